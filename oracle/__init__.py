@@ -1,0 +1,304 @@
+"""Plain FP64 CPU oracle for the embedded-atom force loop (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does: the two
+share no code, header, table or constant.
+
+The arithmetic lives in ``eam_oracle.c`` (brute force O(N^2), FP64); this module
+compiles it with gcc and marshals numpy arrays through ctypes.  Every function
+follows the paper (MOLDY, "Theoretical background" Eq. Ucoh for the energy,
+"Boundary conditions" for the image vector, "Time integration" and "Fixed
+atoms" for the integrator, "Units" for the time unit).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "eam_oracle.c")
+_LIB = os.path.join(_HERE, "_eam_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over atoms) and return the .so path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Pot(ctypes.Structure):
+    _fields_ = [
+        ("ns", ctypes.c_int32),
+        ("npk", ctypes.c_int32),
+        ("ndk", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("pair_a", ctypes.c_void_p),
+        ("pair_r", ctypes.c_void_p),
+        ("dens_A", ctypes.c_void_p),
+        ("dens_R", ctypes.c_void_p),
+        ("emb_c", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    vp, i64, d, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER(_Pot)
+    lib.or_time_unit_fs.restype = d
+    lib.or_boltzmann_ev.restype = d
+    lib.or_pressure_unit_gpa.restype = d
+    lib.or_num_threads.restype = i32
+    lib.or_knot_sum.restype = d
+    lib.or_knot_sum.argtypes = [vp, vp, i32, d, vp]
+    lib.or_pair.restype = d
+    lib.or_pair.argtypes = [P, i32, i32, d, vp]
+    lib.or_density.restype = d
+    lib.or_density.argtypes = [P, i32, i32, d, vp]
+    lib.or_embed.restype = d
+    lib.or_embed.argtypes = [P, i32, d, vp]
+    lib.or_cutoff.restype = d
+    lib.or_cutoff.argtypes = [P]
+    lib.or_forces.restype = i32
+    lib.or_forces.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, P, vp, vp, vp, vp, vp]
+    lib.or_energy.restype = d
+    lib.or_energy.argtypes = [i64, vp, vp, vp, vp, vp, vp, P]
+    lib.or_forces_sampled.restype = i32
+    lib.or_forces_sampled.argtypes = [i64, vp, vp, vp, vp, vp, vp, P, i64, vp, vp, vp, vp]
+    lib.or_kinetic.restype = d
+    lib.or_kinetic.argtypes = [i64, vp, vp, vp, vp, vp, P]
+    lib.or_run_verlet.restype = i32
+    lib.or_run_verlet.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Potential:
+    """Cubic-knot EAM/FS potential in the layout the oracle reads.
+
+    ``pot`` is a mapping with numpy arrays ``pair_a, pair_r`` [ns,ns,npk],
+    ``dens_A, dens_R`` [ns,ns,ndk] (density at an a-site from a b-neighbour),
+    ``emb_c`` [ns] and ``mass`` [ns] (amu).
+    """
+
+    def __init__(self, pot):
+        self.pair_a = _f64(pot["pair_a"])
+        self.pair_r = _f64(pot["pair_r"])
+        self.dens_A = _f64(pot["dens_A"])
+        self.dens_R = _f64(pot["dens_R"])
+        self.emb_c = _f64(pot["emb_c"])
+        self.mass = _f64(pot["mass"])
+        ns = self.emb_c.shape[0]
+        assert self.pair_a.shape[:2] == (ns, ns) and self.dens_A.shape[:2] == (ns, ns)
+        self.s = _Pot(
+            ns,
+            self.pair_a.shape[2],
+            self.dens_A.shape[2],
+            0,
+            self.pair_a.ctypes.data,
+            self.pair_r.ctypes.data,
+            self.dens_A.ctypes.data,
+            self.dens_R.ctypes.data,
+            self.emb_c.ctypes.data,
+            self.mass.ctypes.data,
+        )
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def time_unit_fs() -> float:
+    """Internal time unit sqrt(amu A^2 / eV) in fs (paper, "Units")."""
+    return _load().or_time_unit_fs()
+
+
+def boltzmann_ev() -> float:
+    return _load().or_boltzmann_ev()
+
+
+def pressure_unit_gpa() -> float:
+    return _load().or_pressure_unit_gpa()
+
+
+def num_threads() -> int:
+    return _load().or_num_threads()
+
+
+def knot_sum(a, rk, r):
+    """Cubic-knot sum sum_k a_k (r_k - r)^3 H(r_k - r) and its derivative."""
+    a, rk = _f64(a), _f64(rk)
+    out = ctypes.c_double()
+    v = _load().or_knot_sum(a.ctypes.data, rk.ctypes.data, a.shape[0], float(r), ctypes.addressof(out))
+    return v, out.value
+
+
+def pair(pot: Potential, a: int, b: int, r: float):
+    out = ctypes.c_double()
+    v = _load().or_pair(pot.ref, a, b, float(r), ctypes.addressof(out))
+    return v, out.value
+
+
+def density(pot: Potential, a: int, b: int, r: float):
+    out = ctypes.c_double()
+    v = _load().or_density(pot.ref, a, b, float(r), ctypes.addressof(out))
+    return v, out.value
+
+
+def embed(pot: Potential, a: int, rho: float):
+    out = ctypes.c_double()
+    v = _load().or_embed(pot.ref, a, float(rho), ctypes.addressof(out))
+    return v, out.value
+
+
+def cutoff(pot: Potential) -> float:
+    return _load().or_cutoff(pot.ref)
+
+
+@dataclass
+class ForceResult:
+    f: np.ndarray  # [n,3] eV/A
+    e_atom: np.ndarray  # [n] eV
+    rho: np.ndarray  # [n]
+    virial: np.ndarray  # [6] eV (xx,yy,zz,xy,xz,yz)
+    pe: float  # eV
+
+
+def _split(pos):
+    pos = _f64(pos)
+    return _f64(pos[:, 0]), _f64(pos[:, 1]), _f64(pos[:, 2])
+
+
+def forces(pos, species, box, periodic, pot: Potential, rigid=None) -> ForceResult:
+    """Brute-force forces, per-atom energies, densities and virial of one system."""
+    x, y, z = _split(pos)
+    n = x.shape[0]
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    box = _f64(box)
+    per = _u8(periodic)
+    f = np.zeros((n, 3))
+    e = np.zeros(n)
+    rho = np.zeros(n)
+    w = np.zeros(6)
+    pe = ctypes.c_double()
+    rc = _load().or_forces(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, sp.ctypes.data, _ptr(rg), box.ctypes.data,
+        per.ctypes.data, pot.ref, f.ctypes.data, e.ctypes.data, rho.ctypes.data, w.ctypes.data,
+        ctypes.addressof(pe),
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return ForceResult(f, e, rho, w, pe.value)
+
+
+def energy(pos, species, box, periodic, pot: Potential) -> float:
+    """Total energy of Eq. Ucoh alone (no derivatives)."""
+    x, y, z = _split(pos)
+    sp = _u8(species)
+    box = _f64(box)
+    per = _u8(periodic)
+    e = _load().or_energy(x.shape[0], x.ctypes.data, y.ctypes.data, z.ctypes.data, sp.ctypes.data,
+                          box.ctypes.data, per.ctypes.data, pot.ref)
+    if np.isnan(e):
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return e
+
+
+def forces_sampled(pos, species, box, periodic, pot: Potential, sample):
+    """Forces, per-atom energies and densities of the atoms in ``sample`` only."""
+    x, y, z = _split(pos)
+    sp = _u8(species)
+    box = _f64(box)
+    per = _u8(periodic)
+    idx = np.ascontiguousarray(sample, dtype=np.int64)
+    m = idx.shape[0]
+    f = np.zeros((m, 3))
+    e = np.zeros(m)
+    rho = np.zeros(m)
+    rc = _load().or_forces_sampled(
+        x.shape[0], x.ctypes.data, y.ctypes.data, z.ctypes.data, sp.ctypes.data, box.ctypes.data,
+        per.ctypes.data, pot.ref, m, idx.ctypes.data, f.ctypes.data, e.ctypes.data, rho.ctypes.data,
+    )
+    if rc:
+        raise ValueError(f"oracle: sampled evaluation failed ({rc})")
+    return ForceResult(f, e, rho, np.full(6, np.nan), float("nan"))
+
+
+def kinetic(vel, species, pot: Potential, rigid=None) -> float:
+    """Kinetic energy (eV) of the mobile atoms; velocities in A/fs."""
+    vx, vy, vz = _split(vel)
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    return _load().or_kinetic(vx.shape[0], vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
+                              sp.ctypes.data, _ptr(rg), pot.ref)
+
+
+@dataclass
+class RunResult:
+    pos: np.ndarray
+    vel: np.ndarray
+    f: np.ndarray
+    pe: np.ndarray  # [nsteps+1]
+    ke: np.ndarray  # [nsteps+1]
+    work: np.ndarray  # [nsteps+1]
+
+
+def run_verlet(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps,
+               rigid=None, rigid_velocity=None) -> RunResult:
+    """Velocity-Verlet NVE run with brute-force forces at every step."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    vp = None if rigid_velocity is None else _f64(rigid_velocity)
+    box = _f64(box)
+    per = _u8(periodic)
+    f = np.zeros((n, 3))
+    pe = np.zeros(nsteps + 1)
+    ke = np.zeros(nsteps + 1)
+    wk = np.zeros(nsteps + 1)
+    rc = _load().or_run_verlet(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data,
+        vz.ctypes.data, sp.ctypes.data, _ptr(rg), box.ctypes.data, per.ctypes.data, pot.ref,
+        float(dt_fs), _ptr(vp), int(nsteps), f.ctypes.data, pe.ctypes.data, ke.ctypes.data,
+        wk.ctypes.data,
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return RunResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, wk)
+
+
+def temperature(ke: float, n_mobile: int, has_rigid: bool) -> float:
+    """T from the kinetic energy: 3N-3 degrees of freedom once total momentum is
+    fixed ("Thermostat NVTp"); 3N when a moving rigid block breaks momentum
+    conservation."""
+    dof = 3 * n_mobile if has_rigid else 3 * n_mobile - 3
+    return 0.0 if dof <= 0 else 2.0 * ke / (dof * boltzmann_ev())

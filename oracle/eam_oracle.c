@@ -1,0 +1,474 @@
+/*
+ * Plain FP64 CPU oracle for the embedded-atom (EAM / Finnis-Sinclair) force
+ * loop and velocity-Verlet integration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header or constant with the GPU path.
+ *
+ * Everything is brute force O(N^2): no cell list, no neighbour list, no
+ * reordering.  Each function states the passage of the paper it follows.
+ *
+ * Notation (paper, "Theoretical background", Eq. Ucoh):
+ *   U = sum_i ( 1/2 sum_{j!=i} phi_{s_i s_j}(r_ij) + F_{s_i}(rho_i) ),
+ *   rho_i = sum_{j!=i} rho_{s_i s_j}(r_ij).
+ * The paper writes the pair term V and the density term phi; here phi is the
+ * pair potential and rho the density function.  The pair double sum is read
+ * as counting each unordered pair once (the factor 1/2), which is the only
+ * reading under which the force carries phi' once per pair.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- Units (paper, section "Units") -------------------------------------
+ * Length in Angstrom, mass in amu (1 u = 1.66053886e-27 kg, as printed), energy
+ * in eV.  The time unit is sqrt(M L^2 / E), about 1.018e-14 s.  The eV in
+ * joules and Boltzmann's constant are not printed; the CODATA-2002 values that
+ * go with the printed amu are used. */
+#define OR_AMU_KG 1.66053886e-27
+#define OR_EV_J 1.60217653e-19
+#define OR_KB_EV_PER_K 8.617343e-5
+#define OR_EV_PER_A3_IN_GPA 160.217653
+
+double or_time_unit_fs(void) { return sqrt(OR_AMU_KG * 1.0e-20 / OR_EV_J) * 1.0e15; }
+double or_boltzmann_ev(void) { return OR_KB_EV_PER_K; }
+double or_pressure_unit_gpa(void) { return OR_EV_PER_A3_IN_GPA; }
+
+/* ---- Potential description ------------------------------------------------
+ * Cubic-knot form (paper, "Available potentials", coefficient-file example):
+ *   f(r) = sum_k a_k (r_k - r)^3 H(r_k - r).
+ * pair_a/pair_r: [ns][ns][npk]  phi between species a and b (symmetric).
+ * dens_A/dens_R: [ns][ns][ndk]  density at an a-site from a b-neighbour.
+ *   (EAM: depends on b only; Finnis-Sinclair: symmetric - "Theoretical
+ *   background", the paragraph on the two interpretations.)
+ * emb_c: [ns]  F_a(rho) = -emb_c[a] * sqrt(rho) (the FS square root).
+ * mass:  [ns]  amu.  */
+typedef struct {
+    int32_t ns, npk, ndk, pad_;
+    const double *pair_a, *pair_r, *dens_A, *dens_R, *emb_c, *mass;
+} or_potential;
+
+/* One cubic-knot sum and its derivative with respect to r.  Terms with
+ * r_k - r <= 0 are switched off by the Heaviside step (the value, slope and
+ * curvature of each term vanish at r = r_k, so the side taken at equality
+ * does not matter). */
+double or_knot_sum(const double *a, const double *rk, int n, double r, double *deriv)
+{
+    double v = 0.0, d = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double t = rk[k] - r;
+        if (t > 0.0) {
+            v += a[k] * t * t * t;
+            d += -3.0 * a[k] * t * t;
+        }
+    }
+    if (deriv) *deriv = d;
+    return v;
+}
+
+double or_pair(const or_potential *p, int a, int b, double r, double *dphi)
+{
+    const int off = (a * p->ns + b) * p->npk;
+    return or_knot_sum(p->pair_a + off, p->pair_r + off, p->npk, r, dphi);
+}
+
+double or_density(const or_potential *p, int a, int b, double r, double *drho)
+{
+    const int off = (a * p->ns + b) * p->ndk;
+    return or_knot_sum(p->dens_A + off, p->dens_R + off, p->ndk, r, drho);
+}
+
+/* F(rho) = -c sqrt(rho), F'(rho) = -c / (2 sqrt(rho)).  An atom with no
+ * density (isolated) has F = F' = 0: the square root is singular there and
+ * the paper is silent; zero is the limit of the energy. */
+double or_embed(const or_potential *p, int a, double rho, double *dF)
+{
+    if (rho <= 0.0) {
+        if (dF) *dF = 0.0;
+        return 0.0;
+    }
+    double s = sqrt(rho);
+    if (dF) *dF = -p->emb_c[a] / (2.0 * s);
+    return -p->emb_c[a] * s;
+}
+
+/* Largest knot over every function: beyond it every term is exactly zero. */
+double or_cutoff(const or_potential *p)
+{
+    double rc = 0.0;
+    int n2 = p->ns * p->ns;
+    for (int i = 0; i < n2 * p->npk; ++i)
+        if (p->pair_r[i] > rc) rc = p->pair_r[i];
+    for (int i = 0; i < n2 * p->ndk; ++i)
+        if (p->dens_R[i] > rc) rc = p->dens_R[i];
+    return rc;
+}
+
+/* ---- Geometry (paper, "Boundary conditions") -----------------------------
+ * Positions are stored unwrapped.  The separation used in Eq. Ucoh is the
+ * shortest vector between i and j or any periodic image of j, taken only
+ * along periodic axes; free axes use the plain difference. */
+static void image_vector(const double *xi, const double *xj, const double *box,
+                         const uint8_t *periodic, double d[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double v = xj[a] - xi[a];
+        if (periodic[a]) v -= box[a] * rint(v / box[a]);
+        d[a] = v;
+    }
+}
+
+static void load_pos(const double *x, const double *y, const double *z, int64_t i, double out[3])
+{
+    out[0] = x[i];
+    out[1] = y[i];
+    out[2] = z[i];
+}
+
+/* Returns 0 when every periodic length exceeds twice the cutoff (so one image
+ * at most lies in range), -1 otherwise. */
+static int check_box(const double *box, const uint8_t *periodic, double rc)
+{
+    for (int a = 0; a < 3; ++a)
+        if (periodic[a] && !(box[a] > 2.0 * rc)) return -1;
+    return 0;
+}
+
+/* Host density rho_i of one atom by brute force over all atoms. */
+static double density_of(int64_t i, int64_t n, const double *x, const double *y,
+                         const double *z, const uint8_t *species, const double *box,
+                         const uint8_t *periodic, const or_potential *p, double rc)
+{
+    double xi[3], xj[3], d[3];
+    load_pos(x, y, z, i, xi);
+    double rho = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (j == i) continue;
+        load_pos(x, y, z, j, xj);
+        image_vector(xi, xj, box, periodic, d);
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r >= rc) continue;
+        rho += or_density(p, species[i], species[j], r, NULL);
+    }
+    return rho;
+}
+
+/*
+ * Full evaluation (Eq. Ucoh and its gradient).
+ *   rho_i   = sum_{j!=i} rho_{s_i s_j}(r_ij)
+ *   F_i     = F_{s_i}(rho_i),  F'_i its derivative
+ *   g_ij    = phi'_{s_i s_j}(r) + F'_i rho'_{s_i s_j}(r) + F'_j rho'_{s_j s_i}(r)
+ *   f_i     = sum_{j!=i} g_ij d_ij / r_ij,   d_ij = r_j - r_i (image vector)
+ *   e_i     = 1/2 sum_{j!=i} phi_{s_i s_j}(r_ij) + F_i   (the per-atom split of
+ *             "Theoretical background", last paragraph: halves of each pair)
+ *   W_ab    = - sum_{i<j} g_ij d_a d_b / r, skipping pairs of two fixed atoms
+ *             ("Fixed atoms": the stress ignores forces between fixed atoms)
+ * Outputs (any may be NULL except f): f[3n] interleaved (fx,fy,fz per atom),
+ * e_atom[n], rho[n], virial[6] (xx,yy,zz,xy,xz,yz), pe (sum of e_atom).
+ * rigid may be NULL (no fixed atoms).  Returns 0, or -1 if a periodic length
+ * is not larger than twice the cutoff.
+ */
+int or_forces(int64_t n, const double *x, const double *y, const double *z,
+              const uint8_t *species, const uint8_t *rigid, const double *box,
+              const uint8_t *periodic, const or_potential *p, double *f,
+              double *e_atom, double *rho_out, double *virial, double *pe)
+{
+    const double rc = or_cutoff(p);
+    if (check_box(box, periodic, rc)) return -1;
+
+    double *rho = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *dF = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *Fe = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *eat = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *wrow = (double *)calloc((size_t)(n > 0 ? n : 1) * 6, sizeof(double));
+
+    /* Pass 1: densities and embedding. */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        rho[i] = density_of(i, n, x, y, z, species, box, periodic, p, rc);
+        Fe[i] = or_embed(p, species[i], rho[i], &dF[i]);
+    }
+
+    /* Pass 2: forces, per-atom energies, virial rows (j > i only). */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[3], xj[3], d[3];
+        load_pos(x, y, z, i, xi);
+        double fi[3] = {0.0, 0.0, 0.0};
+        double epair = 0.0;
+        const int si = species[i];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            load_pos(x, y, z, j, xj);
+            image_vector(xi, xj, box, periodic, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r >= rc) continue;
+            const int sj = species[j];
+            double dphi, drho_ij, drho_ji;
+            double phi = or_pair(p, si, sj, r, &dphi);
+            or_density(p, si, sj, r, &drho_ij);
+            or_density(p, sj, si, r, &drho_ji);
+            double g = dphi + dF[i] * drho_ij + dF[j] * drho_ji;
+            for (int a = 0; a < 3; ++a) fi[a] += g * d[a] / r;
+            epair += phi;
+            if (j > i && !(rigid && rigid[i] && rigid[j])) {
+                double *w = wrow + 6 * i;
+                w[0] -= g * d[0] * d[0] / r;
+                w[1] -= g * d[1] * d[1] / r;
+                w[2] -= g * d[2] * d[2] / r;
+                w[3] -= g * d[0] * d[1] / r;
+                w[4] -= g * d[0] * d[2] / r;
+                w[5] -= g * d[1] * d[2] / r;
+            }
+        }
+        f[3 * i + 0] = fi[0];
+        f[3 * i + 1] = fi[1];
+        f[3 * i + 2] = fi[2];
+        eat[i] = 0.5 * epair + Fe[i];
+        if (e_atom) e_atom[i] = eat[i];
+        if (rho_out) rho_out[i] = rho[i];
+    }
+
+    if (pe) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i) s += eat[i];
+        *pe = s;
+    }
+    if (virial) {
+        for (int c = 0; c < 6; ++c) virial[c] = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < 6; ++c) virial[c] += wrow[6 * i + c];
+    }
+    free(rho);
+    free(dF);
+    free(Fe);
+    free(eat);
+    free(wrow);
+    return 0;
+}
+
+/* Total energy only (Eq. Ucoh), computed without any derivative: used by the
+ * finite-difference pins.  Returns NAN on a bad box. */
+double or_energy(int64_t n, const double *x, const double *y, const double *z,
+                 const uint8_t *species, const double *box, const uint8_t *periodic,
+                 const or_potential *p)
+{
+    const double rc = or_cutoff(p);
+    if (check_box(box, periodic, rc)) return NAN;
+    double total = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[3], xj[3], d[3];
+        load_pos(x, y, z, i, xi);
+        double rho = 0.0, epair = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            load_pos(x, y, z, j, xj);
+            image_vector(xi, xj, box, periodic, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r >= rc) continue;
+            rho += or_density(p, species[i], species[j], r, NULL);
+            epair += or_pair(p, species[i], species[j], r, NULL);
+        }
+        total += 0.5 * epair + or_embed(p, species[i], rho, NULL);
+    }
+    return total;
+}
+
+/*
+ * Sampled evaluation for large systems: forces, per-atom energies and host
+ * densities of the atoms listed in sample[0..m), each from a brute-force scan
+ * over all n atoms.  F'_j of every neighbour j is itself found by a
+ * brute-force density scan, so the cost is about (1 + neighbours) * n distance
+ * tests per sampled atom.  Same definitions as or_forces.
+ * Outputs: f[3m], e_atom[m], rho_out[m] (any of the last two may be NULL).
+ */
+int or_forces_sampled(int64_t n, const double *x, const double *y, const double *z,
+                      const uint8_t *species, const double *box, const uint8_t *periodic,
+                      const or_potential *p, int64_t m, const int64_t *sample, double *f,
+                      double *e_atom, double *rho_out)
+{
+    const double rc = or_cutoff(p);
+    if (check_box(box, periodic, rc)) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int64_t s = 0; s < m; ++s) {
+        const int64_t i = sample[s];
+        if (i < 0 || i >= n) {
+            bad |= 1;
+            continue;
+        }
+        double xi[3], xj[3], d[3];
+        load_pos(x, y, z, i, xi);
+        const int si = species[i];
+        /* neighbours of i within the cutoff */
+        int64_t cap = 256, cnt = 0;
+        int64_t *nb = (int64_t *)malloc(sizeof(int64_t) * cap);
+        double rho_i = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            load_pos(x, y, z, j, xj);
+            image_vector(xi, xj, box, periodic, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r >= rc) continue;
+            rho_i += or_density(p, si, species[j], r, NULL);
+            if (cnt == cap) {
+                cap *= 2;
+                nb = (int64_t *)realloc(nb, sizeof(int64_t) * cap);
+            }
+            nb[cnt++] = j;
+        }
+        double dFi;
+        double Fi = or_embed(p, si, rho_i, &dFi);
+        double fi[3] = {0.0, 0.0, 0.0}, epair = 0.0;
+        for (int64_t q = 0; q < cnt; ++q) {
+            const int64_t j = nb[q];
+            const int sj = species[j];
+            double rho_j = density_of(j, n, x, y, z, species, box, periodic, p, rc);
+            double dFj;
+            or_embed(p, sj, rho_j, &dFj);
+            load_pos(x, y, z, j, xj);
+            image_vector(xi, xj, box, periodic, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double dphi, drho_ij, drho_ji;
+            double phi = or_pair(p, si, sj, r, &dphi);
+            or_density(p, si, sj, r, &drho_ij);
+            or_density(p, sj, si, r, &drho_ji);
+            double g = dphi + dFi * drho_ij + dFj * drho_ji;
+            for (int a = 0; a < 3; ++a) fi[a] += g * d[a] / r;
+            epair += phi;
+        }
+        free(nb);
+        f[3 * s + 0] = fi[0];
+        f[3 * s + 1] = fi[1];
+        f[3 * s + 2] = fi[2];
+        if (e_atom) e_atom[s] = 0.5 * epair + Fi;
+        if (rho_out) rho_out[s] = rho_i;
+    }
+    return bad ? -2 : 0;
+}
+
+/* Kinetic energy (eV) of the mobile atoms, velocities in Angstrom/fs:
+ * KE = sum 1/2 m v^2 with v converted to Angstrom per time unit. */
+double or_kinetic(int64_t n, const double *vx, const double *vy, const double *vz,
+                  const uint8_t *species, const uint8_t *rigid, const or_potential *p)
+{
+    const double t0 = or_time_unit_fs();
+    double ke = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rigid && rigid[i]) continue;
+        double v2 = (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) * t0 * t0;
+        ke += 0.5 * p->mass[species[i]] * v2;
+    }
+    return ke;
+}
+
+/* Sum of the forces on the rigid atoms dotted with their prescribed velocity
+ * (Angstrom per time unit): the rate at which the system does work on the
+ * moving rigid block, whose negative is the power the block delivers. */
+static double rigid_power(int64_t n, const double *f, const uint8_t *rigid, const double *vp)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (rigid && rigid[i]) s += f[3 * i] * vp[0] + f[3 * i + 1] * vp[1] + f[3 * i + 2] * vp[2];
+    return s;
+}
+
+/*
+ * Velocity-Verlet molecular dynamics (paper, "Time integration"; "Fixed
+ * atoms"; NVEp ensemble), in the internal unit of time:
+ *   v <- v + (dt/2) f/m;   x <- x + dt v;   f <- forces(x);   v <- v + (dt/2) f/m.
+ * Fixed atoms (rigid[i] = 1) follow a prescribed straight line
+ * x(t) = x(0) + vp t with the velocity vp (Angstrom/fs) instead.
+ * Velocities in and out are Angstrom/fs, dt in fs.
+ * Per step s = 0..nsteps the function records, if the pointers are non-NULL:
+ *   pe[s], ke[s], work[s] = energy delivered by the moving rigid block up to
+ *   step s (trapezoid rule over -sum_{rigid} f_i . vp).
+ * On return x,y,z,vx,vy,vz hold the final state and f[3n] the final forces.
+ */
+int or_run_verlet(int64_t n, double *x, double *y, double *z, double *vx, double *vy,
+                  double *vz, const uint8_t *species, const uint8_t *rigid, const double *box,
+                  const uint8_t *periodic, const or_potential *p, double dt_fs,
+                  const double *vp_fs, int64_t nsteps, double *f, double *pe_out,
+                  double *ke_out, double *work_out)
+{
+    const double t0 = or_time_unit_fs();
+    const double dt = dt_fs / t0;
+    double vp[3] = {0.0, 0.0, 0.0};
+    if (vp_fs)
+        for (int a = 0; a < 3; ++a) vp[a] = vp_fs[a] * t0;
+    double *v[3] = {vx, vy, vz};
+    double *r[3] = {x, y, z};
+    /* internal velocities in Angstrom per time unit */
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] *= t0;
+    double *rigid0 = NULL;
+    if (rigid) {
+        rigid0 = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) rigid0[3 * i + a] = r[a][i];
+    }
+    double pe;
+    int rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+    if (rc) goto done;
+    double work = 0.0;
+    double power_prev = -rigid_power(n, f, rigid, vp);
+    for (int64_t s = 0;; ++s) {
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) {
+            double ke = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (rigid && rigid[i]) continue;
+                ke += 0.5 * p->mass[species[i]] *
+                      (v[0][i] * v[0][i] + v[1][i] * v[1][i] + v[2][i] * v[2][i]);
+            }
+            ke_out[s] = ke;
+        }
+        if (work_out) work_out[s] = work;
+        if (s == nsteps) break;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) {
+                double t = (double)(s + 1) * dt;
+                for (int a = 0; a < 3; ++a) r[a][i] = rigid0[3 * i + a] + vp[a] * t;
+                continue;
+            }
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) {
+                v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+                r[a][i] += dt * v[a][i];
+            }
+        }
+        rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+        if (rc) goto done;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) continue;
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+        }
+        double power = -rigid_power(n, f, rigid, vp);
+        work += 0.5 * dt * (power_prev + power);
+        power_prev = power;
+    }
+done:
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+        if (rigid && rigid[i])
+            for (int a = 0; a < 3; ++a) v[a][i] = vp_fs ? vp_fs[a] : 0.0;
+    }
+    free(rigid0);
+    return rc;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

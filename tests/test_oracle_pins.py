@@ -1,0 +1,419 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each checks a closed form, an
+invariant, a limiting case, a library routine or a finite difference, chosen so
+that a dropped term, a wrong sign or index, or a transposed operand fails at
+least one of them.  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist
+
+from paper_1107_2619_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+GPA = 160.217653
+
+
+# ----------------------------------------------------------------------------- units
+def test_time_unit_matches_paper(orc):
+    """Paper, "Units": the derived time unit is about 1.018e-14 s."""
+    t0 = orc.time_unit_fs() * 1e-15
+    assert abs(t0 - 1.018e-14) < 0.0005e-14
+
+
+def test_constants_shared_by_inputs_and_oracle(orc):
+    # value-identical constants on the two sides (the inputs module draws velocities)
+    assert orc.time_unit_fs() == pytest.approx(inputs.TIME_UNIT_FS, rel=1e-15)
+    assert orc.boltzmann_ev() == inputs.KB_EV
+
+
+# ----------------------------------------------------------------------------- knot evaluator
+def _golden_ni_al():
+    with open(os.path.join(GOLDEN, "ni_al_atvf.json")) as fh:
+        return json.load(fh)
+
+
+def test_knot_sum_vanishes_beyond_largest_knot(orc):
+    g = _golden_ni_al()
+    for r in (g["rmax"], g["rmax"] + 1e-9, 4.5, 7.0):
+        v, d = orc.knot_sum(g["pair_a"], g["pair_r"], r)
+        assert v == 0.0 and d == 0.0
+
+
+def test_knot_sum_outermost_interval_is_single_monomial(orc):
+    """Between the two largest printed knots only the outermost term is on."""
+    g = _golden_ni_al()
+    a, rk = np.array(g["pair_a"]), np.array(g["pair_r"])
+    order = np.argsort(rk)[::-1]
+    k0, k1 = order[0], order[1]
+    for r in np.linspace(rk[k1] + 1e-3, rk[k0] - 1e-3, 7):
+        v, _ = orc.knot_sum(a, rk, r)
+        assert v / (rk[k0] - r) ** 3 == pytest.approx(a[k0], rel=1e-12)
+
+
+def test_knot_sum_piecewise_cubic_third_derivative(orc):
+    """On each interval the function is a cubic whose r^3 coefficient is
+    -(sum of the amplitudes of the knots still switched on)."""
+    g = _golden_ni_al()
+    a, rk = np.array(g["pair_a"]), np.array(g["pair_r"])
+    edges = np.concatenate([[1.5], np.sort(rk)])
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        rs = np.linspace(lo + 0.01 * (hi - lo), hi - 0.01 * (hi - lo), 9)
+        vs = np.array([orc.knot_sum(a, rk, r)[0] for r in rs])
+        c = np.polyfit(rs, vs, 3)
+        assert np.max(np.abs(np.polyval(c, rs) - vs)) < 1e-10
+        active = rk > 0.5 * (lo + hi)
+        assert c[0] == pytest.approx(-a[active].sum(), rel=1e-6, abs=1e-9)
+
+
+def test_knot_sum_c2_at_knots_and_derivative(orc):
+    """Value, slope and curvature are continuous at every knot (one-sided cubic
+    fits agree there); the third derivative jumps by 6 a_k at r_k.  The
+    returned derivative equals a Richardson-extrapolated central difference."""
+    g = _golden_ni_al()
+    a, rk = np.array(g["pair_a"]), np.array(g["pair_r"])
+    f = lambda x: orc.knot_sum(a, rk, x)[0]  # noqa: E731
+    edges = np.concatenate([[1.5], np.sort(rk), [5.0]])
+    for q in range(1, len(edges) - 1):
+        k = edges[q]
+        lo, hi = edges[q - 1], edges[q + 1]
+        left = np.polyfit(np.linspace(lo + 0.05 * (k - lo), k - 0.05 * (k - lo), 9),
+                          [f(x) for x in np.linspace(lo + 0.05 * (k - lo), k - 0.05 * (k - lo), 9)], 3)
+        right = np.polyfit(np.linspace(k + 0.05 * (hi - k), hi - 0.05 * (hi - k), 9),
+                           [f(x) for x in np.linspace(k + 0.05 * (hi - k), hi - 0.05 * (hi - k), 9)], 3)
+        for order in range(3):
+            dl = np.polyval(np.polyder(left, order) if order else left, k)
+            dr = np.polyval(np.polyder(right, order) if order else right, k)
+            assert abs(dl - dr) < 1e-7 * (1 + abs(dl))
+        jump = 6 * (right[0] - left[0])
+        amp = a[np.argmin(np.abs(rk - k))]
+        assert jump == pytest.approx(6 * amp, rel=1e-6)
+    for r in (2.5, 2.86, 3.0, 3.5, 4.0, 4.3):
+        h = 1e-4
+        d1 = (f(r + h) - f(r - h)) / (2 * h)
+        d2 = (f(r + h / 2) - f(r - h / 2)) / h
+        rich = (4 * d2 - d1) / 3
+        assert orc.knot_sum(a, rk, r)[1] == pytest.approx(rich, rel=1e-9, abs=1e-12)
+
+
+# ----------------------------------------------------------------------------- lattices
+def _bcc_shells(a):
+    return [(a * math.sqrt(3) / 2, 8), (a, 6), (a * math.sqrt(2), 12), (a * math.sqrt(11) / 2, 24),
+            (a * math.sqrt(3), 8), (2 * a, 6)]
+
+
+def _fcc_shells(a):
+    return [(a / math.sqrt(2), 12), (a, 6), (a * math.sqrt(1.5), 24), (a * math.sqrt(2), 12),
+            (a * math.sqrt(2.5), 24), (a * math.sqrt(3), 8)]
+
+
+@pytest.mark.parametrize("a", [2.75, 2.80, 2.87, 2.95, 3.02])
+def test_bcc_perfect_lattice_closed_form(orc, fe_pot, a):
+    """Every atom of an ideal bcc crystal has e = 1/2 sum_s n_s phi(d_s) +
+    F(sum_s n_s rho(d_s)) over the neighbour shells; forces vanish by
+    inversion symmetry."""
+    n = 4
+    pos = inputs.bcc(n, n, n, a)
+    sp = np.zeros(len(pos), np.uint8)
+    res = orc.forces(pos, sp, [n * a] * 3, [1, 1, 1], fe_pot)
+    rho = sum(m * orc.density(fe_pot, 0, 0, d)[0] for d, m in _bcc_shells(a))
+    e = 0.5 * sum(m * orc.pair(fe_pot, 0, 0, d)[0] for d, m in _bcc_shells(a)) + orc.embed(fe_pot, 0, rho)[0]
+    assert np.allclose(res.rho, rho, rtol=1e-13, atol=0)
+    assert np.allclose(res.e_atom, e, rtol=1e-13, atol=0)
+    assert res.pe == pytest.approx(len(pos) * e, rel=1e-13)
+    assert np.max(np.abs(res.f)) <= 1e-12
+
+
+def test_fcc_perfect_lattice_closed_form(orc):
+    pot = orc.Potential(inputs.perturbed_potential("cu_fs", 3))
+    a, n = 3.615, 3
+    pos = inputs.fcc(n, n, n, a)
+    res = orc.forces(pos, np.zeros(len(pos), np.uint8), [n * a] * 3, [1, 1, 1], pot)
+    rho = sum(m * orc.density(pot, 0, 0, d)[0] for d, m in _fcc_shells(a))
+    e = 0.5 * sum(m * orc.pair(pot, 0, 0, d)[0] for d, m in _fcc_shells(a)) + orc.embed(pot, 0, rho)[0]
+    assert np.allclose(res.e_atom, e, rtol=1e-13, atol=0)
+    assert np.max(np.abs(res.f)) <= 1e-12
+
+
+def test_b2_two_species_closed_form(orc, fec_pot):
+    """Ordered CsCl-type crystal of species 0 at cube corners and species 1 at
+    centres: the first shell of each atom is the other species, the next two
+    its own.  Pins the [site, neighbour] index order of the density and the
+    per-species embedding (an asymmetric EAM density, "Theoretical background")."""
+    a, n = 2.87, 4
+    corners = inputs.bcc(n, n, n, a)[0::2]
+    centres = inputs.bcc(n, n, n, a)[1::2]
+    pos = np.concatenate([corners, centres])
+    sp = np.concatenate([np.zeros(len(corners)), np.ones(len(centres))]).astype(np.uint8)
+    res = orc.forces(pos, sp, [n * a] * 3, [1, 1, 1], fec_pot)
+    d1, d2, d3 = a * math.sqrt(3) / 2, a, a * math.sqrt(2)
+    for s, o in ((0, 1), (1, 0)):
+        rho = 8 * orc.density(fec_pot, s, o, d1)[0] + 6 * orc.density(fec_pot, s, s, d2)[0] + \
+            12 * orc.density(fec_pot, s, s, d3)[0]
+        e = 0.5 * (8 * orc.pair(fec_pot, s, o, d1)[0] + 6 * orc.pair(fec_pot, s, s, d2)[0] +
+                   12 * orc.pair(fec_pot, s, s, d3)[0]) + orc.embed(fec_pot, s, rho)[0]
+        assert np.allclose(res.rho[sp == s], rho, rtol=1e-13)
+        assert np.allclose(res.e_atom[sp == s], e, rtol=1e-13)
+    # the two densities really differ, so a transposed index would be caught
+    assert abs(orc.density(fec_pot, 0, 1, d1)[0] - orc.density(fec_pot, 1, 0, d1)[0]) > 1e-3
+    assert np.max(np.abs(res.f)) <= 1e-12
+
+
+# ----------------------------------------------------------------------------- forces
+def _displaced_bcc(n, a, amp, rng):
+    pos = inputs.bcc(n, n, n, a)
+    return pos + amp * (2 * rng.random(pos.shape) - 1)
+
+
+def _fd_forces(orc, pos, sp, box, per, pot, atoms, h=2e-3):
+    out = np.zeros((len(atoms), 3))
+    for q, i in enumerate(atoms):
+        for c in range(3):
+            def e_at(s):
+                p = pos.copy()
+                p[i, c] += s
+                return orc.energy(p, sp, box, per, pot)
+            d1 = (e_at(h) - e_at(-h)) / (2 * h)
+            d2 = (e_at(h / 2) - e_at(-h / 2)) / h
+            out[q, c] = -(4 * d2 - d1) / 3
+    return out
+
+
+def test_forces_are_minus_energy_gradient_fe(orc, fe_pot, rng):
+    pos = _displaced_bcc(4, 2.87, 0.12, rng)
+    sp = np.zeros(len(pos), np.uint8)
+    box, per = [4 * 2.87] * 3, [1, 1, 1]
+    res = orc.forces(pos, sp, box, per, fe_pot)
+    atoms = [0, 17, 63, 127]
+    fd = _fd_forces(orc, pos, sp, box, per, fe_pot, atoms)
+    scale = np.sqrt(np.mean(np.sum(res.f**2, 1)))
+    assert np.max(np.abs(fd - res.f[atoms])) / scale < 1e-8
+    assert res.pe == pytest.approx(orc.energy(pos, sp, box, per, fe_pot), rel=1e-13)
+
+
+def test_forces_are_minus_energy_gradient_two_species_free_axis(orc, fec_pot, rng):
+    """Two species with asymmetric densities, one free axis."""
+    pos = _displaced_bcc(4, 2.87, 0.1, rng)
+    sp = (rng.random(len(pos)) < 0.3).astype(np.uint8)
+    box, per = [4 * 2.87, 4 * 2.87, 4 * 2.87], [1, 1, 0]
+    res = orc.forces(pos, sp, box, per, fec_pot)
+    atoms = [i for i in range(len(pos)) if sp[i] == 1][:2] + [i for i in range(len(pos)) if sp[i] == 0][:2]
+    fd = _fd_forces(orc, pos, sp, box, per, fec_pot, atoms)
+    scale = np.sqrt(np.mean(np.sum(res.f**2, 1)))
+    assert np.max(np.abs(fd - res.f[atoms])) / scale < 1e-8
+
+
+def test_net_force_vanishes(orc, fec_pot, rng):
+    pos = _displaced_bcc(4, 2.87, 0.15, rng)
+    sp = (rng.random(len(pos)) < 0.2).astype(np.uint8)
+    res = orc.forces(pos, sp, [4 * 2.87] * 3, [1, 1, 1], fec_pot)
+    assert np.max(np.abs(res.f.sum(0))) < 1e-11 * np.abs(res.f).max() * len(pos)
+
+
+def test_dimer(orc, fe_pot):
+    """Two atoms in open space: E = phi(r) + 2 F(rho(r)), equal and opposite
+    forces along the bond with magnitude |phi' + 2 F'(rho) rho'|."""
+    big = [100.0, 100.0, 100.0]
+    for r in (2.0, 2.4, 2.9, 3.4, 3.9):
+        pos = np.array([[10.0, 10.0, 10.0], [10.0 + r / math.sqrt(3)] * 3])
+        sp = np.zeros(2, np.uint8)
+        res = orc.forces(pos, sp, big, [0, 0, 0], fe_pot)
+        rho, drho = orc.density(fe_pot, 0, 0, r)
+        phi, dphi = orc.pair(fe_pot, 0, 0, r)
+        F, dF = orc.embed(fe_pot, 0, rho)
+        assert res.pe == pytest.approx(phi + 2 * F, rel=1e-14)
+        g = dphi + 2 * dF * drho
+        unit = (pos[1] - pos[0]) / r
+        assert np.allclose(res.f[0], g * unit, rtol=1e-13, atol=1e-15)
+        assert np.allclose(res.f[1], -g * unit, rtol=1e-13, atol=1e-15)
+
+
+def test_isolated_atom_has_no_energy(orc, fe_pot):
+    pos = np.array([[5.0, 5.0, 5.0], [20.0, 20.0, 20.0]])
+    res = orc.forces(pos, np.zeros(2, np.uint8), [40.0] * 3, [0, 0, 0], fe_pot)
+    assert res.pe == 0.0 and np.all(res.f == 0.0) and np.all(res.rho == 0.0)
+
+
+def test_pair_only_limit_matches_pdist(orc, rng):
+    """With F = 0 the model is a plain pair potential (paper: Morse or
+    Lennard-Jones cast into the EAM form by setting F = 0): the energy is the
+    sum of phi over all unordered pairs, distances from scipy's pdist."""
+    arr = inputs.perturbed_potential("fe_fs", 7)
+    arr["emb_c"] = np.zeros(1)
+    pot = orc.Potential(arr)
+    pos = rng.random((60, 3)) * 9.0 + 20.0  # a free cluster
+    res = orc.forces(pos, np.zeros(60, np.uint8), [100.0] * 3, [0, 0, 0], pot)
+    d = pdist(pos)
+    ref = sum(orc.pair(pot, 0, 0, r)[0] for r in d)
+    assert res.pe == pytest.approx(ref, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------- virial
+def test_virial_trace_is_minus_volume_derivative(orc, fe_pot):
+    """On the ideal lattice P = W/(3V) = -dE/dV (T = 0)."""
+    for a in (2.80, 2.87, 2.95):
+        n = 4
+        pos = inputs.bcc(n, n, n, a)
+        sp = np.zeros(len(pos), np.uint8)
+        res = orc.forces(pos, sp, [n * a] * 3, [1, 1, 1], fe_pot)
+        h = 1e-5
+        e = lambda s: orc.energy(pos * (1 + s), sp, [n * a * (1 + s)] * 3, [1, 1, 1], fe_pot)  # noqa: E731
+        vol = (n * a) ** 3
+        dEdV = (e(h) - e(-h)) / (2 * h) / (3 * vol)
+        p_virial = (res.virial[0] + res.virial[1] + res.virial[2]) / (3 * vol)
+        assert p_virial == pytest.approx(-dEdV, rel=1e-7, abs=1e-10)
+
+
+def test_virial_tensor_is_minus_strain_derivative_cluster(orc, fec_pot, rng):
+    """For a free cluster, W_ab = -dE/d(eps_ab) under the homogeneous strain
+    x -> (1 + eps) x, for all six components."""
+    pos = _displaced_bcc(3, 2.87, 0.1, rng) + 30.0
+    sp = (rng.random(len(pos)) < 0.25).astype(np.uint8)
+    box, per = [100.0] * 3, [0, 0, 0]
+    res = orc.forces(pos, sp, box, per, fec_pot)
+    comps = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    h = 1e-5
+    centre = pos.mean(0)
+    for c, (p, q) in enumerate(comps):
+        def e_at(s):
+            eps = np.zeros((3, 3))
+            eps[p, q] += s / (1 if p == q else 2)
+            eps[q, p] += 0 if p == q else s / 2
+            return orc.energy(centre + (pos - centre) @ (np.eye(3) + eps).T, sp, box, per, fec_pot)
+        dE = (e_at(h) - e_at(-h)) / (2 * h)
+        assert res.virial[c] == pytest.approx(-dE, rel=1e-6, abs=1e-8)
+
+
+def test_virial_skips_fixed_pairs(orc, fe_pot, rng):
+    """Paper, "Fixed atoms": the stress ignores forces between fixed atoms."""
+    pos = _displaced_bcc(4, 2.87, 0.1, rng)
+    sp = np.zeros(len(pos), np.uint8)
+    rigid = np.zeros(len(pos), np.uint8)
+    rigid[:40] = 1
+    box = [4 * 2.87] * 3
+    full = orc.forces(pos, sp, box, [1, 1, 1], fe_pot)
+    part = orc.forces(pos, sp, box, [1, 1, 1], fe_pot, rigid=rigid)
+    assert np.array_equal(full.f, part.f)
+    assert not np.allclose(full.virial, part.virial)
+    all_rigid = orc.forces(pos, sp, box, [1, 1, 1], fe_pot, rigid=np.ones(len(pos), np.uint8))
+    assert np.all(all_rigid.virial == 0.0)
+
+
+# ----------------------------------------------------------------------------- invariances
+def test_translation_image_and_permutation_invariance(orc, fec_pot, rng):
+    pos = _displaced_bcc(4, 2.87, 0.12, rng)
+    sp = (rng.random(len(pos)) < 0.2).astype(np.uint8)
+    L = 4 * 2.87
+    box, per = [L] * 3, [1, 1, 1]
+    ref = orc.forces(pos, sp, box, per, fec_pot)
+    scale = np.abs(ref.f).max()
+    t = orc.forces(pos + np.array([3.3, -17.1, 0.77]), sp, box, per, fec_pot)
+    assert np.max(np.abs(t.f - ref.f)) < 1e-10 * scale
+    assert np.allclose(t.e_atom, ref.e_atom, rtol=1e-12)
+    shifted = pos.copy()
+    shifted[5] += np.array([L, -2 * L, 3 * L])  # unwrapped positions
+    s = orc.forces(shifted, sp, box, per, fec_pot)
+    assert np.max(np.abs(s.f - ref.f)) < 1e-10 * scale
+    perm = rng.permutation(len(pos))
+    p = orc.forces(pos[perm], sp[perm], box, per, fec_pot)
+    assert np.max(np.abs(p.f - ref.f[perm])) < 1e-12 * scale
+    assert np.allclose(p.e_atom, ref.e_atom[perm], rtol=1e-13)
+
+
+def test_box_too_small_is_rejected(orc, fe_pot):
+    pos = inputs.bcc(2, 2, 2, 2.87)
+    with pytest.raises(ValueError):
+        orc.forces(pos, np.zeros(len(pos), np.uint8), [5.74] * 3, [1, 1, 1], fe_pot)
+
+
+def test_sampled_mode_matches_full(orc, fec_pot, rng):
+    pos = _displaced_bcc(5, 2.87, 0.1, rng)
+    sp = (rng.random(len(pos)) < 0.2).astype(np.uint8)
+    box, per = [5 * 2.87] * 3, [1, 1, 1]
+    full = orc.forces(pos, sp, box, per, fec_pot)
+    idx = rng.choice(len(pos), 20, replace=False)
+    sm = orc.forces_sampled(pos, sp, box, per, fec_pot, idx)
+    assert np.max(np.abs(sm.f - full.f[idx])) < 1e-12 * np.abs(full.f).max()
+    assert np.allclose(sm.e_atom, full.e_atom[idx], rtol=1e-13)
+    assert np.allclose(sm.rho, full.rho[idx], rtol=1e-13)
+
+
+# ----------------------------------------------------------------------------- integrator
+def _small_md(seed=3, n=4, T=300.0):
+    return inputs.bcc_fe(n, temperature=T, seed=seed, displace=0.05, dt_fs=1.0)
+
+
+def test_momentum_conserved(orc):
+    s = _small_md()
+    pot = orc.Potential(s.potential)
+    m = s.potential["mass"][s.species]
+    p0 = (m[:, None] * s.vel).sum(0)
+    assert np.max(np.abs(p0)) < 1e-12
+    r = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 50)
+    p1 = (m[:, None] * r.vel).sum(0)
+    assert np.max(np.abs(p1)) < 1e-11
+
+
+def test_verlet_time_reversible(orc):
+    """Velocity Verlet is time-reversible (paper, "Time integration")."""
+    s = _small_md()
+    pot = orc.Potential(s.potential)
+    fwd = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100)
+    back = orc.run_verlet(fwd.pos, -fwd.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100)
+    assert np.max(np.abs(back.pos - s.pos)) < 1e-10
+    assert np.max(np.abs(back.vel + s.vel)) < 1e-10
+
+
+def test_verlet_second_order(orc):
+    """Global error of the trajectory falls as dt^2."""
+    s = _small_md(T=600.0)
+    pot = orc.Potential(s.potential)
+    t_end = 20.0
+    ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 0.125, int(t_end / 0.125))
+    errs = []
+    for dt in (1.0, 0.5):
+        r = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, dt, int(t_end / dt))
+        errs.append(np.max(np.abs(r.pos - ref.pos)))
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_nve_energy_bounded_without_drift(orc):
+    """NVE velocity Verlet: total energy fluctuates within a bounded band with
+    no secular drift (paper, "Integration error")."""
+    s = _small_md(T=600.0)
+    pot = orc.Potential(s.potential)
+    r = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 2000)
+    e = (r.pe + r.ke) / s.n_atoms
+    de = e - e[0]
+    assert np.max(np.abs(de)) < 2e-4
+    slope = np.polyfit(np.arange(len(e)), e, 1)[0]
+    assert abs(slope) * len(e) < 2e-5
+    # a genuine exchange between kinetic and potential energy took place
+    assert np.std(r.ke / s.n_atoms) > 50 * np.std(e)
+
+
+def test_piston_work_energy_balance(orc):
+    """A rigid block moving at a prescribed velocity ("Fixed atoms") does work
+    W = -integral of sum_{block} f.v_p dt, and E_tot(t) - E_tot(0) = W."""
+    s = inputs.fcc_piston(nx=3, ny=3, nz=6, piston_cells=1, piston_speed_a_per_fs=0.02, steps=0)
+    pot = orc.Potential(s.potential)
+    r = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 0.5, 400,
+                       rigid=s.rigid, rigid_velocity=s.rigid_velocity[0])
+    e = r.pe + r.ke
+    assert abs(r.work[-1]) > 0.05  # the piston really did work
+    assert np.max(np.abs(e - e[0] - r.work)) < 2e-3 * abs(r.work).max()
+    zr = r.pos[s.rigid == 1, 2] - s.pos[s.rigid == 1, 2]
+    assert np.allclose(zr, 400 * 0.5 * 0.02, rtol=1e-12)
+
+
+def test_temperature_degrees_of_freedom(orc):
+    """3N-3 degrees of freedom once momentum is fixed (paper, NVTp section);
+    3N when a moving rigid block breaks momentum conservation."""
+    kb = orc.boltzmann_ev()
+    assert orc.temperature(0.5 * 99 * kb * 300.0, 34, False) == pytest.approx(300.0, rel=1e-14)
+    assert orc.temperature(0.5 * 102 * kb * 300.0, 34, True) == pytest.approx(300.0, rel=1e-14)
