@@ -1,0 +1,230 @@
+"""Benchmark: EAM atom-steps/s of the MI355X force loop (one JSON line).
+
+Default workload: bcc Fe, 80^3 cells with 1% random vacancies (N = 1,013,760),
+600 K, neighbour list rebuilt every 10 steps.  A step is one pass of the whole
+hot path: (scheduled) cell sort + list build, density pass with embedding,
+force pass with velocity-Verlet update, and - on the last step of each
+md_step call - the energy/virial reductions.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bcc1m]
+
+`value` is the mixed-precision rate (FP32 pair terms, FP64 accumulation and
+integration) gated on its force error against the FP64 path; the FP64 rate is
+reported beside it.  Inputs are seeded and synthetic and already resident in
+HBM when the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EAM atom-steps/s: mixed vs FP64 (force err ≤1e-5), batched vs one-by-one"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def force_kernel_bytes_per_atom(nbar: float) -> float:
+    """Algorithmic HBM bytes of one force-pass launch per atom: read x and F'_i
+    (32), read and write v (48), write the drifted x (24), and the neighbour
+    list counted once per unordered pair as a 32-bit index (2 n_bar)."""
+    return 32.0 + 48.0 + 24.0 + 2.0 * nbar
+
+
+def step_bytes_per_atom(nbar: float, k: int) -> float:
+    """Algorithmic bytes of a whole step per atom (both passes plus the list
+    build amortised over the rebuild period k)."""
+    return 136.0 + 4.0 * nbar + (56.0 + 2.0 * nbar) / k
+
+
+def run_precision(md, system, precision, steps, warmup, timing):
+    import torch
+
+    sim = md.Simulation(system, precision=precision, want_e_atom=False)
+    sim.step(warmup)
+    sim.energy()
+    sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)
+    if timing:
+        sim.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    en = sim.energy()
+    kt = sim.kernel_times(reset=True) if timing else None
+    return sim, ms, wall, en, kt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="bcc1m")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1107_2619_amd import inputs, md
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    log(f"building workload {args.workload}")
+    system = inputs.workload(args.workload)
+    n = system.n_atoms
+
+    results = {}
+    for prec in ("fp64", "mixed"):
+        log(f"{prec}: warmup {args.warmup}, timed {args.steps} steps")
+        sim, ms, wall, en, _ = run_precision(md, system, prec, args.steps, args.warmup, timing=False)
+        log(f"{prec}: {ms / args.steps * 1e3:.1f} us/step  (wall {wall:.3f} s)")
+        # a second timed pass with per-kernel HIP events for the roofline
+        sim_t, ms_t, _, _, kt = run_precision(md, system, prec, args.steps, args.warmup, timing=True)
+        results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt}
+        del sim_t
+
+    # mixed-vs-FP64 force error on one shared state (the FP64 run's final state)
+    ref_sim = results["fp64"]["sim"]
+    pos, vel = ref_sim.positions(), ref_sim.velocities()
+    ref_sim.eam_forces(want_energy=True)
+    f64 = ref_sim.forces()
+    mix_sim = results["mixed"]["sim"]
+    mix_sim.set_state(pos, vel)
+    mix_sim.build_neighbours()
+    mix_sim.eam_forces(want_energy=True)
+    fmix = mix_sim.forces()
+    mix_err = float(np.max(np.linalg.norm(fmix - f64, axis=1)) / np.sqrt(np.mean(np.sum(f64**2, 1))))
+    log(f"mixed vs fp64 force error {mix_err:.3e}")
+
+    # neighbour statistics for the byte model
+    counts, _ = ref_sim.neighbours()
+    nbar = float(counts.mean())
+
+    rec = {}
+    for prec in ("fp64", "mixed"):
+        r = results[prec]
+        ms_step = r["ms"] / args.steps
+        kt = r["kt"]
+        f_ms, f_n = kt["force"]
+        d_ms, d_n = kt["density"]
+        b_ms, b_n = kt["build"]
+        rec[prec] = {
+            "value": n * args.steps / (r["ms"] * 1e-3),
+            "ms_per_step": ms_step,
+            "force_kernel_us": 1e3 * f_ms / f_n,
+            "density_kernel_us": 1e3 * d_ms / d_n,
+            "build_us_per_rebuild": 1e3 * b_ms / max(b_n, 1),
+            "timing_overhead_frac": r["ms_timed"] / r["ms"] - 1.0,
+            "temperature_K": float(r["en"].temperature[0]),
+        }
+    gate_ok = mix_err <= 1e-5
+    head = rec["mixed"] if gate_ok else rec["fp64"]
+    force_us = head["force_kernel_us"]
+    fbytes = force_kernel_bytes_per_atom(nbar) * n
+    achieved = fbytes / (force_us * 1e-6) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "k_force (force pass + velocity Verlet)",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None,
+        "bytes_per_atom": force_kernel_bytes_per_atom(nbar),
+        "step_bytes_per_atom": step_bytes_per_atom(nbar, system.rebuild_every),
+        "step_frac": step_bytes_per_atom(nbar, system.rebuild_every) * head["value"] / 1e9 / HBM_PEAK_GBS,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(system, ref_sim, pos, f64, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if gate_ok else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: bcc Fe 80^3 cells, 1% vacancies, N={n}, 600 K, "
+                        f"rebuild every {system.rebuild_every}, dt {system.dt_fs} fs",
+            "n_atoms": n,
+            "mean_neighbours": nbar,
+            "precision": "mixed" if gate_ok else "fp64",
+            "parallelism": "single GPU",
+        },
+        "mixed_force_err_vs_fp64": mix_err,
+        "fp64": rec["fp64"],
+        "mixed": rec["mixed"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(system, sim, pos, f_gpu, seconds):
+    """The FP64 oracle as it stands, on a bounded sample of atoms of the same
+    state: brute-force forces of S sampled atoms over all N atoms (each needs
+    the densities of its neighbours, also by brute force).  Also a full-size
+    parity check of the GPU FP64 forces at those atoms."""
+    import oracle
+
+    pot = oracle.Potential(system.potential)
+    rng = np.random.default_rng(77)
+    probe = rng.choice(system.n_atoms, 16, replace=False)
+    t = time.perf_counter()
+    oracle.forces_sampled(pos, system.species, system.box[0], system.periodic[0], pot, probe)
+    per_atom = (time.perf_counter() - t) / len(probe)
+    s = int(max(16, min(4096, seconds / max(per_atom, 1e-6))))
+    sample = rng.choice(system.n_atoms, s, replace=False)
+    log(f"cpu baseline: {s} sampled atoms (~{per_atom * s:.1f} s)")
+    t = time.perf_counter()
+    ref = oracle.forces_sampled(pos, system.species, system.box[0], system.periodic[0], pot, sample)
+    dt = time.perf_counter() - t
+    fr = f_gpu[sample]
+    err = float(np.max(np.linalg.norm(fr - ref.f, axis=1)) / np.sqrt(np.mean(np.sum(ref.f**2, 1))))
+    return {
+        "value": s / dt,
+        "unit": "atom-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"forces of {s} random atoms of the same {system.n_atoms}-atom state, brute force O(N) each "
+                  f"(O(N^2) algorithm), FP64, OpenMP; {dt:.1f} s",
+        "gpu_fp64_force_err_on_sample": err,
+    }
+
+
+if __name__ == "__main__":
+    main()

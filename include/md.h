@@ -1,0 +1,215 @@
+/*
+ * md.h - C ABI of the MI355X embedded-atom molecular-dynamics hot path.
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the per-timestep
+ * force loop of a short-range embedded-atom / Finnis-Sinclair model as
+ * described in the MOLDY paper (Ackland et al., arXiv 1107.2619):
+ *
+ *   - link-cell binning and the Verlet neighbour list built from adjacent
+ *     link cells ("The Neighbourlist calculation");
+ *   - the density pass rho_i = sum_j rho_{s_i s_j}(r_ij) and the embedding
+ *     F(rho_i) = -c sqrt(rho_i) with its derivative (Eq. Ucoh and the
+ *     Finnis-Sinclair square root, "Theoretical background");
+ *   - the force pass f_i = sum_j [phi'(r) + F'_i rho'_{ij}(r) + F'_j rho'_{ji}(r)] d_ij / r
+ *     (the gradient of Eq. Ucoh);
+ *   - velocity-Verlet integration ("Time integration"), rigid atoms moving on
+ *     a prescribed line ("Fixed atoms"), and the energy, kinetic-energy and
+ *     virial reductions ("Thermodynamic Quantities").
+ *
+ * Units at the boundary (paper, "Units"): Angstrom, amu, eV, fs; velocities in
+ * Angstrom/fs, forces in eV/Angstrom, pressure in GPa.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns an int status: MD_OK (0) or a negative MD_ERR_*.
+ *     On failure md_last_error(ctx) returns a message.
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     HIP device memory owned by the caller and must stay valid while bound.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued asynchronously on it; only md_energy synchronises.
+ *   - Errors raised on the device (neighbour overflow, skin violation,
+ *     non-finite energies) are sticky and reported by the next md_energy.
+ *   - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef MDEAM_MD_H
+#define MDEAM_MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx; /* opaque; created by md_create, freed by md_destroy */
+
+enum {
+    MD_OK = 0,
+    MD_ERR_ARG = -1,          /* NULL pointer, bad size or bad enum value            */
+    MD_ERR_BOX = -2,          /* periodic length <= 2 (cutoff + skin), or bad box    */
+    MD_ERR_POTENTIAL = -3,    /* unsupported species count, knots, or coefficients   */
+    MD_ERR_NBR_OVERFLOW = -4, /* an atom has more list entries than max_neighbours   */
+    MD_ERR_SKIN = -5,         /* an atom moved more than skin/2 between list builds  */
+    MD_ERR_NONFINITE = -6,    /* NaN or Inf in the energies                          */
+    MD_ERR_DEVICE = -7,       /* a HIP runtime call failed                           */
+    MD_ERR_STATE = -8         /* call out of order (e.g. md_step before md_bind)     */
+};
+
+enum { MD_FP64 = 0, MD_MIXED = 1 };              /* md_config.precision */
+enum { MD_NBR_FULL = 0, MD_NBR_HALF_ATOMIC = 1 }; /* md_config.nbr_mode  */
+
+#define MD_MAX_SPECIES 4
+#define MD_MAX_KNOTS 8
+
+/*
+ * Cubic-knot potential (paper, "Available potentials": the generic ATVF form
+ * f(r) = sum_k a_k (r_k - r)^3 H(r_k - r)), one function per species pair.
+ *   pair_a, pair_r  [ns][ns][n_pair_knots]  pair potential phi_ab; must be
+ *                   symmetric in (a, b).
+ *   dens_A, dens_R  [ns][ns][n_dens_knots]  [a][b] = density at an a-site
+ *                   from a b-neighbour (EAM: depends on b only; FS:
+ *                   symmetric).  Every amplitude must be > 0 so that rho >= 0.
+ *   emb_c           [ns]  F_a(rho) = -emb_c[a] sqrt(rho); F = F' = 0 at rho = 0.
+ *   mass_amu        [ns]  > 0.
+ * All host pointers; md_create copies them.  The cutoff r_c is the largest knot.
+ */
+typedef struct {
+    int32_t n_species;    /* 1..MD_MAX_SPECIES */
+    int32_t n_pair_knots; /* 1..MD_MAX_KNOTS */
+    int32_t n_dens_knots; /* 1..MD_MAX_KNOTS */
+    int32_t reserved;     /* must be 0 */
+    const double *pair_a, *pair_r;
+    const double *dens_A, *dens_R;
+    const double *emb_c;
+    const double *mass_amu;
+} md_potential;
+
+/*
+ * Run configuration: R >= 1 independent replicas ("statistics must be gathered
+ * over a number of equivalent runs", Introduction), each an orthorhombic box
+ * with per-axis periodic or free boundaries ("Boundary conditions").  Replica
+ * r owns atoms [atom_offset[r], atom_offset[r+1]) of the state arrays.
+ * All pointers are host pointers, copied by md_create.
+ */
+typedef struct {
+    int32_t n_replicas;     /* R >= 1 */
+    int32_t max_neighbours; /* per-atom list capacity (the paper's nnbrs), >= 1 */
+    int32_t rebuild_every;  /* list rebuild period in steps (nbrupdate), >= 1 */
+    int32_t precision;      /* MD_FP64 or MD_MIXED */
+    int32_t nbr_mode;       /* MD_NBR_FULL or MD_NBR_HALF_ATOMIC */
+    int32_t lanes_per_atom; /* 0 = choose automatically; else 1, 2, 4 or 8 */
+    const int64_t *atom_offset;   /* [R+1], atom_offset[0] = 0, non-decreasing */
+    const double *box;            /* [R][3] edge lengths, Angstrom, > 0 */
+    const double *origin;         /* [R][3] lower corner (matters on free axes); NULL = 0 */
+    const uint8_t *periodic;      /* [R][3] 1 = periodic (minimum image), 0 = free */
+    const double *rigid_velocity; /* [R][3] Angstrom/fs of rigid atoms; NULL = 0 */
+    double skin;                  /* list padding beyond r_c (the paper's rpad), >= 0 */
+    double dt_fs;                 /* time step, fs, > 0 */
+} md_config;
+
+/*
+ * Per-atom state: device pointers, caller-owned, in the caller's atom order
+ * (which the library never changes; it keeps its own cell-sorted copy).
+ * Positions are unwrapped ("Boundary conditions": no wraparound).
+ *   x,y,z     [N] Angstrom (read at each call, written by md_step)
+ *   vx,vy,vz  [N] Angstrom/fs (read at each call, written by md_step)
+ *   fx,fy,fz  [N] eV/Angstrom (written)
+ *   species   [N] uint8 < n_species (read at md_bind)
+ *   rigid     [N] uint8, 1 = moves at rigid_velocity of its replica; NULL = none
+ *   e_atom    [N] eV per-atom energy 1/2 sum_j phi + F_i (written when
+ *             energies are computed), or NULL
+ */
+typedef struct {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *fx, *fy, *fz;
+    const uint8_t *species;
+    const uint8_t *rigid;
+    double *e_atom;
+} md_state;
+
+/* Per-replica thermodynamic quantities of the last evaluated state. */
+typedef struct {
+    double pe;           /* potential energy, eV (Eq. Ucoh, pairs counted once) */
+    double ke;           /* kinetic energy of the mobile atoms, eV */
+    double temperature;  /* K; 3N-3 degrees of freedom, 3N_mobile with rigid atoms */
+    double pressure_gpa; /* (2 KE + tr W) / (3 V) */
+    double volume;       /* box volume, Angstrom^3 */
+    double piston_work;  /* energy delivered by rigid atoms since md_bind, eV */
+    double virial[6];    /* W_ab = -sum_{i<j} g_ij d_a d_b / r, eV (xx,yy,zz,xy,xz,yz);
+                            pairs of two rigid atoms are skipped ("Fixed atoms") */
+    int64_t step;        /* time step index of this state */
+    int64_t n_atoms, n_mobile;
+} md_energies;
+
+/* Validates the configuration and potential on the host (no device work)
+ * and returns a new context in *out.  Box lengths on periodic axes must
+ * exceed 2 (r_c + skin). */
+int md_create(const md_config *cfg, const md_potential *pot, md_ctx **out);
+
+/* Bytes of device workspace md_bind needs for this context. */
+int md_workspace_bytes(const md_ctx *ctx, size_t *bytes);
+
+/* Attaches caller state and a caller-allocated device workspace of at least
+ * md_workspace_bytes (256-byte aligned).  Neither is owned by the library.
+ * Resets the step counter, the piston work and the neighbour list. */
+int md_bind(md_ctx *ctx, const md_state *state, void *workspace, size_t bytes);
+
+/* Reads the positions, sorts the atoms by link cell and builds the Verlet
+ * list of all pairs closer than r_c + skin (paper, "The Neighbourlist
+ * calculation"; full list, or the half list in MD_NBR_HALF_ATOMIC mode). */
+int md_build_neighbours(md_ctx *ctx, void *stream);
+
+/* Evaluates rho, F, F' and the forces at the caller's current positions
+ * (building the list first if none exists) and writes fx,fy,fz.  With
+ * want_energy != 0 also the energies (read with md_energy) and e_atom. */
+int md_eam_forces(md_ctx *ctx, int want_energy, void *stream);
+
+/* Advances nsteps >= 1 velocity-Verlet steps from the caller's x, v; forces at
+ * the starting positions are recomputed first.  Rebuilds the list whenever
+ * the step index is a multiple of rebuild_every.  On completion x, v, f (and
+ * e_atom) hold the final state and the energies of that state are ready. */
+int md_step(md_ctx *ctx, int32_t nsteps, void *stream);
+
+/* Synchronises the stream, checks the device error flags and copies the
+ * per-replica energies of the last evaluated state to out[0..R). */
+int md_energy(md_ctx *ctx, md_energies *out, void *stream);
+
+/* Test and tuning helpers.
+ * md_copy_neighbours: synchronises and copies the current list to host memory
+ *   in the caller's atom numbering: counts[N] and list[N][cap] (row-major,
+ *   entries beyond counts[i] unspecified).  cap must be >= max_neighbours.
+ * md_set_option / md_get_option: integer knobs (see MD_OPT_*). */
+int md_copy_neighbours(md_ctx *ctx, int32_t *counts, int32_t *list, int32_t cap, void *stream);
+
+enum {
+    MD_OPT_LANES_PER_ATOM = 1, /* 1, 2, 4 or 8 lanes cooperate on one atom           */
+    MD_OPT_USE_GRAPH = 2,      /* 1 = replay md_step from captured HIP graphs         */
+    MD_OPT_MAX_COUNT = 3,      /* read only: largest list length seen (at md_energy)  */
+    MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind                */
+    MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
+    MD_OPT_EVALUATOR = 6       /* 0 = exact local-polynomial tables (default when all
+                                  knots lie on a common grid), 1 = term-by-term knot
+                                  sums (the paper's explicit evaluation)             */
+};
+int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
+int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);
+
+/* Kernel groups timed when MD_OPT_TIMING is on. */
+enum { MD_KT_BUILD = 0, MD_KT_DENSITY = 1, MD_KT_FORCE = 2, MD_KT_REDUCE = 3, MD_KT_COUNT = 4 };
+
+/* Synchronises the stream and returns, per kernel group, the summed elapsed
+ * milliseconds (HIP events recorded on the launch stream around each launch
+ * group) and the number of launches since timing was last reset; reset != 0
+ * clears the totals afterwards.  ms[MD_KT_COUNT], launches[MD_KT_COUNT]. */
+int md_kernel_times(md_ctx *ctx, double *ms, int64_t *launches, int reset, void *stream);
+
+/* Frees the context (not the caller's state or workspace).  NULL is a no-op. */
+void md_destroy(md_ctx *ctx);
+
+/* Message describing the last failure on ctx (never NULL). */
+const char *md_last_error(const md_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDEAM_MD_H */

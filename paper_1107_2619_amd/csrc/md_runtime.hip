@@ -1,0 +1,758 @@
+// Host runtime behind include/md.h: validation, workspace layout, the step
+// schedule and the error flags.  Device work is enqueued on the caller's
+// stream; nothing here allocates device memory (the caller provides the
+// workspace).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "md_internal.h"
+
+using namespace mdk;
+
+struct md_ctx {
+    // configuration (copied)
+    int32_t R = 0, cap = 0, rebuild_every = 1, precision = MD_FP64, nbr_mode = MD_NBR_FULL, lanes = 1;
+    std::vector<int64_t> atom_off;
+    std::vector<double> box, origin, vp;
+    std::vector<uint8_t> periodic;
+    double skin = 0.0, dt_fs = 1.0, rc = 0.0, rlist = 0.0, t0_fs = 0.0;
+    // potential
+    DevPotential pot{};
+    bool single = false;
+    PotArgs args{};
+    // local-polynomial tables (host copies, uploaded at md_bind)
+    bool table_ok = false;
+    int32_t evaluator = 0;  // 0 = tables when the knots share a grid, 1 = explicit knot sums
+    std::vector<double> tf64, te64, td64;
+    std::vector<float> tf32, te32, td32;
+    // derived layout
+    int64_t N = 0, Np = 0;
+    int32_t C = 0, scan_nb = 0;
+    std::vector<DevReplica> reps;
+    std::vector<int32_t> rep_of_wave, cell_shift;
+    size_t ws_bytes = 0;
+    std::vector<size_t> off;  // workspace offsets, in Buffers field order
+    // binding and run state
+    md_state st{};
+    void* ws = nullptr;
+    bool bound = false, have_slots = false, have_list = false, have_energy = false;
+    Buffers buf{};
+    int p = 0, q = 0;
+    int64_t step = 0, built_at = -1, n_builds = 0, max_count = 0;
+    std::vector<int64_t> n_mobile;
+    std::string err;
+    // optional kernel timing: event pairs per group, resolved lazily
+    bool timing = false;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double kt_ms[MD_KT_COUNT] = {0, 0, 0, 0};
+    int64_t kt_n[MD_KT_COUNT] = {0, 0, 0, 0};
+    ~md_ctx()
+    {
+        for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+int fail(md_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+bool hip_ok(md_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return true;
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+KernelShape shape(const md_ctx* c)
+{
+    KernelShape k;
+    k.n_slots = c->Np;
+    k.n_cells = c->C;
+    k.n_replicas = c->R;
+    k.cap = c->cap;
+    k.lanes = c->lanes;
+    k.npk = c->pot.npk;
+    k.ndk = c->pot.ndk;
+    k.table = c->table_ok && c->evaluator == 0;
+    return k;
+}
+
+// Exact re-expansion of every cubic-knot sum on a grid of bins of width w
+// whose edges contain all knots: inside a bin the set of switched-on knots is
+// fixed, so f(b w + u) = sum_k a_k (D_k - u)^3 with D_k = r_k - b w is one
+// cubic c0 + c1 u + c2 u^2 + c3 u^3.  Returns false when no candidate width
+// puts every knot on the grid (the explicit knot sums are used then).
+bool build_tables(md_ctx* c)
+{
+    const DevPotential& P = c->pot;
+    const int n2 = P.ns * P.ns;
+    auto knots_on_grid = [&](double w) {
+        auto on = [&](double rk) {
+            const double x = rk / w;
+            return std::fabs(x - std::nearbyint(x)) <= 1e-9 * std::max(1.0, x);
+        };
+        for (int ab = 0; ab < n2; ++ab) {
+            for (int k = 0; k < P.npk; ++k)
+                if (P.pair_a[ab][k] != 0.0 && !on(P.pair_r[ab][k])) return false;
+            for (int k = 0; k < P.ndk; ++k)
+                if (!on(P.dens_r[ab][k])) return false;
+        }
+        return true;
+    };
+    static const double cand[] = {0.02, 0.025, 0.01, 0.05, 0.04, 0.0125, 0.005, 0.002, 0.001};
+    double w = 0.0;
+    for (double wc : cand)
+        if (c->rc / wc <= 4096.0 && knots_on_grid(wc)) {
+            w = wc;
+            break;
+        }
+    if (w == 0.0) return false;
+    const int nb = (int)std::ceil(c->rc / w - 1e-9);
+    const int nbt = nb + 2;  // two all-zero bins beyond the cutoff absorb rounding at r -> r_c
+    c->args.w = w;
+    c->args.inv_w = 1.0 / w;
+    c->args.nbt = nbt;
+    c->tf64.assign((size_t)n2 * nbt * 8, 0.0);
+    c->te64.assign((size_t)n2 * nbt * 4, 0.0);
+    c->td64.assign((size_t)n2 * nbt * 4, 0.0);
+    auto expand = [&](const double* amp, const double* rk, int nk, int b, double out[4]) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        const double base = b * w;
+        for (int k = 0; k < nk; ++k) {
+            if (amp[k] == 0.0 || std::llround(rk[k] / w) < b + 1) continue;
+            const double D = rk[k] - base, a = amp[k];
+            out[0] += a * D * D * D;
+            out[1] += -3.0 * a * D * D;
+            out[2] += 3.0 * a * D;
+            out[3] += -a;
+        }
+    };
+    for (int ab = 0; ab < n2; ++ab)
+        for (int b = 0; b < nbt; ++b) {
+            double ph[4], rh[4];
+            expand(P.pair_a[ab], P.pair_r[ab], P.npk, b, ph);
+            expand(P.dens_a[ab], P.dens_r[ab], P.ndk, b, rh);
+            double* f = &c->tf64[((size_t)ab * nbt + b) * 8];
+            f[0] = ph[1];
+            f[1] = 2.0 * ph[2];
+            f[2] = 3.0 * ph[3];
+            f[3] = rh[1];
+            f[4] = 2.0 * rh[2];
+            f[5] = 3.0 * rh[3];
+            for (int i = 0; i < 4; ++i) {
+                c->te64[((size_t)ab * nbt + b) * 4 + i] = ph[i];
+                c->td64[((size_t)ab * nbt + b) * 4 + i] = rh[i];
+            }
+        }
+    c->tf32.assign(c->tf64.begin(), c->tf64.end());
+    c->te32.assign(c->te64.begin(), c->te64.end());
+    c->td32.assign(c->td64.begin(), c->td64.end());
+    return true;
+}
+
+// Workspace layout: every array 256-byte aligned.  The order here is the
+// order of the assignments in bind_buffers.
+void plan_workspace(md_ctx* c)
+{
+    const size_t Np = (size_t)c->Np, C = (size_t)c->C;
+    std::vector<size_t> sizes = {
+        Np * 32, Np * 32,                                    // pos[2]
+        Np * 8, Np * 8, Np * 8, Np * 8, Np * 8, Np * 8,      // vel[2][3]
+        Np * 4, Np * 4,                                      // id[2]
+        Np, Np,                                              // type[2]
+        Np * 8, Np * 8,                                      // pwork[2]
+        Np * 32,                                             // xbuild
+        Np * 8,                                              // femb
+        Np * 4 * (size_t)c->cap,                             // nbr
+        Np * 4,                                              // ncount
+        Np * 4,                                              // cell_of
+        Np * 4,                                              // perm
+        C * 4, C * 4, C * 4, C * 4,                          // cell start/count/cursor/shift
+        (size_t)c->scan_nb * 4,                              // scan_blocks
+        Np / kWave * 4,                                      // rep_of_wave
+        (size_t)c->R * sizeof(DevReplica),                   // reps
+        sizeof(DevPotential),                                // pot
+        Np / kWave * kEnergySlots * 8,                       // partial
+        (size_t)c->R * kEnergySlots * 8,                     // energies
+        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // fhalf[3]
+        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
+        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
+        F_COUNT * 4,                                         // flags
+        c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
+        c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
+    };
+    c->off.clear();
+    size_t o = 0;
+    for (size_t s : sizes) {
+        c->off.push_back(o);
+        o = align_up(o + std::max<size_t>(s, 1), 256);
+    }
+    c->ws_bytes = o;
+}
+
+void bind_buffers(md_ctx* c)
+{
+    char* w = static_cast<char*>(c->ws);
+    size_t i = 0;
+    auto at = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(w + c->off[i++]); };
+    Buffers& b = c->buf;
+    at(b.pos[0]);
+    at(b.pos[1]);
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 3; ++a) at(b.vel[k][a]);
+    at(b.id[0]);
+    at(b.id[1]);
+    at(b.type[0]);
+    at(b.type[1]);
+    at(b.pwork[0]);
+    at(b.pwork[1]);
+    at(b.xbuild);
+    at(b.femb);
+    at(b.nbr);
+    at(b.ncount);
+    at(b.cell_of);
+    at(b.perm);
+    at(b.cell_start);
+    at(b.cell_count);
+    at(b.cell_cursor);
+    at(b.cell_shift);
+    at(b.scan_blocks);
+    at(b.rep_of_wave);
+    at(b.reps);
+    at(b.pot);
+    at(b.partial);
+    at(b.energies);
+    for (int a = 0; a < 3; ++a) at(b.fhalf[a]);
+    at(b.flags);
+    at(b.tab_force64);
+    at(b.tab_energy64);
+    at(b.tab_dens64);
+    at(b.tab_force32);
+    at(b.tab_energy32);
+    at(b.tab_dens32);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_launch(md_ctx* c)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, MD_ERR_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return MD_OK;
+}
+
+// Kernel-group timing (MD_OPT_TIMING): an event before and after each group.
+hipEvent_t next_event(md_ctx* c)
+{
+    if (c->event_next == c->event_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->event_pool.push_back(e);
+    }
+    return c->event_pool[c->event_next++];
+}
+
+struct Timed {
+    md_ctx* c;
+    int group;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(md_ctx* c_, int g, hipStream_t s_) : c(c_), group(g), s(s_)
+    {
+        if (!c->timing) return;
+        a = next_event(c);
+        b = next_event(c);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~Timed()
+    {
+        if (!c->timing || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        c->pending.push_back({group, {a, b}});
+    }
+};
+
+// Resolve recorded event pairs (the stream has been synchronised).
+void collect_times(md_ctx* c)
+{
+    for (auto& pr : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, pr.second.first, pr.second.second) == hipSuccess) {
+            c->kt_ms[pr.first] += ms;
+            c->kt_n[pr.first] += 1;
+        }
+    }
+    c->pending.clear();
+    c->event_next = 0;
+}
+
+void ensure_slots(md_ctx* c, hipStream_t s)
+{
+    if (c->have_slots) return;
+    launch_init_slots(c->buf, c->q, c->st, shape(c), s);
+    c->have_slots = true;
+}
+
+void rebuild(md_ctx* c, hipStream_t s)
+{
+    const KernelShape k = shape(c);
+    const double half_skin2 = c->have_list ? 0.25 * c->skin * c->skin : -1.0;
+    Timed tm(c, MD_KT_BUILD, s);
+    launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    c->p ^= 1;
+    c->q ^= 1;
+    launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    c->have_list = true;
+    c->built_at = c->step;
+    ++c->n_builds;
+}
+
+void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
+{
+    const KernelShape k = shape(c);
+    const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
+    {
+        Timed tm(c, MD_KT_DENSITY, s);
+        launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fl.energy, s);
+    }
+    {
+        Timed tm(c, MD_KT_FORCE, s);
+        launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
+    }
+    if (fl.open) c->p ^= 1;
+    if (fl.energy) {
+        Timed tm(c, MD_KT_REDUCE, s);
+        launch_reduce_energies(c->buf, k, s);
+        c->have_energy = true;
+    }
+}
+
+bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
+
+}  // namespace
+
+extern "C" {
+
+int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
+{
+    if (!out) return MD_ERR_ARG;
+    *out = nullptr;
+    if (!cfg || !pot) return MD_ERR_ARG;
+    md_ctx* c = new md_ctx();
+    auto reject = [&](int code, const std::string& msg) {
+        // keep the context so md_last_error can explain; the caller destroys it
+        c->err = msg;
+        *out = c;
+        return code;
+    };
+    // ---- configuration
+    if (cfg->n_replicas < 1) return reject(MD_ERR_ARG, "n_replicas must be >= 1");
+    if (!cfg->atom_offset || !cfg->box || !cfg->periodic) return reject(MD_ERR_ARG, "atom_offset, box and periodic are required");
+    if (cfg->max_neighbours < 1) return reject(MD_ERR_ARG, "max_neighbours must be >= 1");
+    if (cfg->rebuild_every < 1) return reject(MD_ERR_ARG, "rebuild_every must be >= 1");
+    if (cfg->precision != MD_FP64 && cfg->precision != MD_MIXED) return reject(MD_ERR_ARG, "precision must be MD_FP64 or MD_MIXED");
+    if (cfg->nbr_mode != MD_NBR_FULL && cfg->nbr_mode != MD_NBR_HALF_ATOMIC) return reject(MD_ERR_ARG, "nbr_mode must be MD_NBR_FULL or MD_NBR_HALF_ATOMIC");
+    if (!(cfg->lanes_per_atom == 0 || cfg->lanes_per_atom == 1 || cfg->lanes_per_atom == 2 ||
+          cfg->lanes_per_atom == 4 || cfg->lanes_per_atom == 8))
+        return reject(MD_ERR_ARG, "lanes_per_atom must be 0, 1, 2, 4 or 8");
+    if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return reject(MD_ERR_ARG, "skin must be finite and >= 0");
+    if (!(cfg->dt_fs > 0.0) || !std::isfinite(cfg->dt_fs)) return reject(MD_ERR_ARG, "dt_fs must be finite and > 0");
+    c->R = cfg->n_replicas;
+    c->cap = cfg->max_neighbours;
+    c->rebuild_every = cfg->rebuild_every;
+    c->precision = cfg->precision;
+    c->nbr_mode = cfg->nbr_mode;
+    c->lanes = cfg->lanes_per_atom ? cfg->lanes_per_atom : 1;
+    c->skin = cfg->skin;
+    c->dt_fs = cfg->dt_fs;
+    c->atom_off.assign(cfg->atom_offset, cfg->atom_offset + c->R + 1);
+    if (c->atom_off[0] != 0) return reject(MD_ERR_ARG, "atom_offset[0] must be 0");
+    for (int r = 0; r < c->R; ++r)
+        if (c->atom_off[r + 1] < c->atom_off[r]) return reject(MD_ERR_ARG, "atom_offset must be non-decreasing");
+    c->N = c->atom_off[c->R];
+    c->box.assign(cfg->box, cfg->box + 3 * c->R);
+    c->periodic.assign(cfg->periodic, cfg->periodic + 3 * c->R);
+    c->origin.assign(3 * c->R, 0.0);
+    if (cfg->origin) c->origin.assign(cfg->origin, cfg->origin + 3 * c->R);
+    c->vp.assign(3 * c->R, 0.0);
+    if (cfg->rigid_velocity) c->vp.assign(cfg->rigid_velocity, cfg->rigid_velocity + 3 * c->R);
+    for (int i = 0; i < 3 * c->R; ++i) {
+        if (!(c->box[i] > 0.0) || !std::isfinite(c->box[i])) return reject(MD_ERR_BOX, "box lengths must be finite and > 0");
+        if (c->periodic[i] > 1) return reject(MD_ERR_ARG, "periodic flags must be 0 or 1");
+        if (!std::isfinite(c->origin[i]) || !std::isfinite(c->vp[i])) return reject(MD_ERR_ARG, "origin and rigid_velocity must be finite");
+    }
+
+    // ---- potential (paper: the material module must accept the species, else
+    // the run halts before it starts - the analogue of a non-zero ierror)
+    const int ns = pot->n_species, npk = pot->n_pair_knots, ndk = pot->n_dens_knots;
+    if (ns < 1 || ns > MD_MAX_SPECIES) return reject(MD_ERR_POTENTIAL, "n_species must be 1..4");
+    if (npk < 1 || npk > MD_MAX_KNOTS || ndk < 1 || ndk > MD_MAX_KNOTS) return reject(MD_ERR_POTENTIAL, "knot counts must be 1..8");
+    if (pot->reserved != 0) return reject(MD_ERR_POTENTIAL, "reserved must be 0");
+    if (!pot->pair_a || !pot->pair_r || !pot->dens_A || !pot->dens_R || !pot->emb_c || !pot->mass_amu)
+        return reject(MD_ERR_POTENTIAL, "potential arrays are required");
+    DevPotential& P = c->pot;
+    P.ns = ns;
+    P.npk = npk;
+    P.ndk = ndk;
+    double rc = 0.0;
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            const int ab = a * ns + b, ba = b * ns + a;
+            for (int k = 0; k < npk; ++k) {
+                const double A = pot->pair_a[ab * npk + k], Rk = pot->pair_r[ab * npk + k];
+                if (!std::isfinite(A) || !std::isfinite(Rk) || Rk < 0.0) return reject(MD_ERR_POTENTIAL, "pair coefficients must be finite, knots >= 0");
+                if (A != pot->pair_a[ba * npk + k] || Rk != pot->pair_r[ba * npk + k])
+                    return reject(MD_ERR_POTENTIAL, "pair potential must be symmetric in the two species");
+                P.pair_a[ab][k] = A;
+                P.pair_d[ab][k] = -3.0 * A;
+                P.pair_r[ab][k] = Rk;
+                rc = std::max(rc, Rk);
+            }
+            for (int k = 0; k < ndk; ++k) {
+                const double A = pot->dens_A[ab * ndk + k], Rk = pot->dens_R[ab * ndk + k];
+                if (!(A > 0.0) || !std::isfinite(A) || !std::isfinite(Rk) || !(Rk > 0.0))
+                    return reject(MD_ERR_POTENTIAL, "density amplitudes and knots must be finite and > 0 (rho must stay >= 0)");
+                P.dens_a[ab][k] = A;
+                P.dens_d[ab][k] = -3.0 * A;
+                P.dens_r[ab][k] = Rk;
+                rc = std::max(rc, Rk);
+            }
+        }
+    c->t0_fs = std::sqrt(kAmuKg * 1.0e-20 / kEvJ) * 1.0e15;
+    for (int a = 0; a < ns; ++a) {
+        const double m = pot->mass_amu[a], ec = pot->emb_c[a];
+        if (!(m > 0.0) || !std::isfinite(m)) return reject(MD_ERR_POTENTIAL, "masses must be finite and > 0");
+        if (!(ec >= 0.0) || !std::isfinite(ec)) return reject(MD_ERR_POTENTIAL, "emb_c must be finite and >= 0");
+        P.emb_c[a] = ec;
+        P.accel[a] = 1.0 / (m * c->t0_fs * c->t0_fs);
+        P.half_m[a] = 0.5 * m * c->t0_fs * c->t0_fs;
+    }
+    if (!(rc > 0.0)) return reject(MD_ERR_POTENTIAL, "cutoff (largest knot) must be > 0");
+    c->rc = rc;
+    c->rlist = rc + c->skin;
+    P.rc = rc;
+    P.rc2 = rc * rc;
+    P.rlist2 = c->rlist * c->rlist;
+    c->single = ns == 1;
+    c->args.ns = ns;
+    c->args.rc2 = P.rc2;
+    c->table_ok = build_tables(c);
+    if (c->single) {
+        PotArgs& A = c->args;
+        for (int k = 0; k < MD_MAX_KNOTS; ++k) {
+            A.pair_a[k] = P.pair_a[0][k];
+            A.pair_d[k] = P.pair_d[0][k];
+            A.pair_r[k] = P.pair_r[0][k];
+            A.dens_a[k] = P.dens_a[0][k];
+            A.dens_d[k] = P.dens_d[0][k];
+            A.dens_r[k] = P.dens_r[0][k];
+            A.pair_af[k] = (float)A.pair_a[k];
+            A.pair_df[k] = (float)A.pair_d[k];
+            A.dens_af[k] = (float)A.dens_a[k];
+            A.dens_df[k] = (float)A.dens_d[k];
+        }
+        A.emb_c = P.emb_c[0];
+        A.accel = P.accel[0];
+        A.half_m = P.half_m[0];
+    }
+
+    // ---- replicas, wavefront-aligned slot ranges, link-cell grids
+    // (paper: link cells at least the potential range plus the padding rpad)
+    int64_t slot = 0, cells = 0;
+    c->reps.resize(c->R);
+    for (int r = 0; r < c->R; ++r) {
+        DevReplica& D = c->reps[r];
+        const int64_t n = c->atom_off[r + 1] - c->atom_off[r];
+        D.slot_off = (int32_t)slot;
+        D.n_atoms = (int32_t)n;
+        D.atom_off = (int32_t)c->atom_off[r];
+        D.cell_off = (int32_t)cells;
+        D.periodic_mask = 0;
+        int64_t ncell = 1;
+        for (int a = 0; a < 3; ++a) {
+            const double L = c->box[3 * r + a];
+            const bool per = c->periodic[3 * r + a];
+            if (per && !(L > 2.0 * c->rlist)) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "replica %d axis %d: periodic length %.6g must exceed 2*(cutoff+skin) = %.6g", r, a, L,
+                              2.0 * c->rlist);
+                return reject(MD_ERR_BOX, msg);
+            }
+            D.box[a] = L;
+            D.inv_box[a] = 1.0 / L;
+            D.origin[a] = c->origin[3 * r + a];
+            D.vp[a] = c->vp[3 * r + a];
+            int64_t nc = (int64_t)std::floor(L / c->rlist);
+            nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
+            D.nc[a] = (int32_t)nc;
+            if (per) D.periodic_mask |= 1 << a;
+            ncell *= nc;
+        }
+        slot += (n + kWave - 1) / kWave * kWave;
+        cells += ncell;
+        if (slot > (int64_t)INT32_MAX / 2 || cells > (int64_t)INT32_MAX / 2) return reject(MD_ERR_ARG, "system too large for 32-bit slot or cell indices");
+    }
+    c->Np = std::max<int64_t>(slot, kWave);
+    c->C = (int32_t)std::max<int64_t>(cells, 1);
+    c->scan_nb = (c->C + 1023) / 1024;
+    if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
+    c->rep_of_wave.assign(c->Np / kWave, 0);
+    for (int r = 0; r < c->R; ++r) {
+        const int64_t w0 = c->reps[r].slot_off / kWave;
+        const int64_t w1 = (c->reps[r].slot_off + c->reps[r].n_atoms + kWave - 1) / kWave;
+        for (int64_t w = w0; w < w1; ++w) c->rep_of_wave[w] = r;
+    }
+    c->cell_shift.assign(c->C, 0);
+    for (int r = 0; r < c->R; ++r) {
+        const int64_t nc = (int64_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
+        for (int64_t k = 0; k < nc; ++k) c->cell_shift[c->reps[r].cell_off + k] = c->reps[r].slot_off - c->reps[r].atom_off;
+    }
+    plan_workspace(c);
+    *out = c;
+    return MD_OK;
+}
+
+int md_workspace_bytes(const md_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return MD_ERR_ARG;
+    *bytes = c->ws_bytes;
+    return MD_OK;
+}
+
+int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
+{
+    if (!c || !st || !workspace) return fail(c, MD_ERR_ARG, "md_bind: NULL argument");
+    if (!c->err.empty() && c->ws_bytes == 0) return fail(c, MD_ERR_STATE, "md_bind: context was not created successfully");
+    if (bytes < c->ws_bytes) return fail(c, MD_ERR_ARG, "md_bind: workspace smaller than md_workspace_bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(c, MD_ERR_ARG, "md_bind: workspace must be 256-byte aligned");
+    if (c->N > 0 && (!st->x || !st->y || !st->z || !st->vx || !st->vy || !st->vz || !st->fx || !st->fy || !st->fz || !st->species))
+        return fail(c, MD_ERR_ARG, "md_bind: x, v, f and species are required");
+    c->st = *st;
+    c->ws = workspace;
+    bind_buffers(c);
+    if (!hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "md_bind upload") ||
+        !hip_ok(c, hipMemcpy(c->buf.pot, &c->pot, sizeof(DevPotential), hipMemcpyHostToDevice), "md_bind upload") ||
+        !hip_ok(c, hipMemcpy(c->buf.rep_of_wave, c->rep_of_wave.data(), c->rep_of_wave.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
+        !hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
+        !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags"))
+        return MD_ERR_DEVICE;
+    if (c->table_ok &&
+        (!hip_ok(c, hipMemcpy(c->buf.tab_force64, c->tf64.data(), c->tf64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
+         !hip_ok(c, hipMemcpy(c->buf.tab_energy64, c->te64.data(), c->te64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
+         !hip_ok(c, hipMemcpy(c->buf.tab_dens64, c->td64.data(), c->td64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
+         !hip_ok(c, hipMemcpy(c->buf.tab_force32, c->tf32.data(), c->tf32.size() * 4, hipMemcpyHostToDevice), "md_bind tables") ||
+         !hip_ok(c, hipMemcpy(c->buf.tab_energy32, c->te32.data(), c->te32.size() * 4, hipMemcpyHostToDevice), "md_bind tables") ||
+         !hip_ok(c, hipMemcpy(c->buf.tab_dens32, c->td32.data(), c->td32.size() * 4, hipMemcpyHostToDevice), "md_bind tables")))
+        return MD_ERR_DEVICE;
+    // species range and mobile counts per replica, checked once on the host
+    std::vector<uint8_t> sp(c->N), rg(c->N, 0);
+    if (c->N > 0) {
+        if (!hip_ok(c, hipMemcpy(sp.data(), st->species, c->N, hipMemcpyDeviceToHost), "md_bind species")) return MD_ERR_DEVICE;
+        if (st->rigid && !hip_ok(c, hipMemcpy(rg.data(), st->rigid, c->N, hipMemcpyDeviceToHost), "md_bind rigid")) return MD_ERR_DEVICE;
+    }
+    for (int64_t i = 0; i < c->N; ++i)
+        if (sp[i] >= c->pot.ns) return fail(c, MD_ERR_POTENTIAL, "md_bind: species index out of range of the potential");
+    c->n_mobile.assign(c->R, 0);
+    for (int r = 0; r < c->R; ++r)
+        for (int64_t i = c->atom_off[r]; i < c->atom_off[r + 1]; ++i) c->n_mobile[r] += rg[i] ? 0 : 1;
+    c->bound = true;
+    c->have_slots = c->have_list = c->have_energy = false;
+    c->p = c->q = 0;
+    c->step = 0;
+    c->built_at = -1;
+    c->n_builds = 0;
+    c->max_count = 0;
+    c->err.clear();
+    return MD_OK;
+}
+
+int md_build_neighbours(md_ctx* c, void* stream)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_build_neighbours: call md_bind first");
+    hipStream_t s = as_stream(stream);
+    ensure_slots(c, s);
+    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+    rebuild(c, s);
+    return check_launch(c);
+}
+
+int md_eam_forces(md_ctx* c, int want_energy, void* stream)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_eam_forces: call md_bind first");
+    hipStream_t s = as_stream(stream);
+    ensure_slots(c, s);
+    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+    if (!c->have_list) rebuild(c, s);
+    forces(c, ForceFlags{want_energy ? 1 : 0, 0, 0, 1}, s);
+    return check_launch(c);
+}
+
+int md_step(md_ctx* c, int32_t nsteps, void* stream)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_step: call md_bind first");
+    if (nsteps < 1) return fail(c, MD_ERR_ARG, "md_step: nsteps must be >= 1");
+    hipStream_t s = as_stream(stream);
+    ensure_slots(c, s);
+    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+    if (!c->have_list || due(c)) rebuild(c, s);
+    forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        ++c->step;
+        if (due(c)) rebuild(c, s);
+        if (k < nsteps) forces(c, ForceFlags{0, 1, 1, 0}, s);
+        else forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
+    }
+    return check_launch(c);
+}
+
+int md_energy(md_ctx* c, md_energies* out, void* stream)
+{
+    if (!c || !out) return fail(c, MD_ERR_ARG, "md_energy: NULL argument");
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_energy: call md_bind first");
+    hipStream_t s = as_stream(stream);
+    std::vector<double> e((size_t)c->R * kEnergySlots, 0.0);
+    int32_t flags[F_COUNT] = {0, 0, 0, 0};
+    if (!hip_ok(c, hipStreamSynchronize(s), "md_energy sync")) return MD_ERR_DEVICE;
+    collect_times(c);
+    if (!hip_ok(c, hipMemcpy(flags, c->buf.flags, sizeof flags, hipMemcpyDeviceToHost), "md_energy flags")) return MD_ERR_DEVICE;
+    if (c->have_energy && !hip_ok(c, hipMemcpy(e.data(), c->buf.energies, e.size() * 8, hipMemcpyDeviceToHost), "md_energy copy"))
+        return MD_ERR_DEVICE;
+    c->max_count = flags[F_MAX_COUNT];
+    for (int r = 0; r < c->R; ++r) {
+        const double* v = e.data() + (size_t)r * kEnergySlots;
+        md_energies& o = out[r];
+        std::memset(&o, 0, sizeof o);
+        const DevReplica& D = c->reps[r];
+        const bool has_rigid = c->n_mobile[r] < D.n_atoms;
+        const int64_t dof = has_rigid ? 3 * c->n_mobile[r] : 3 * c->n_mobile[r] - 3;
+        o.pe = v[E_PE];
+        o.ke = v[E_KE];
+        o.temperature = dof > 0 ? 2.0 * o.ke / ((double)dof * kBoltzmannEv) : 0.0;
+        o.volume = D.box[0] * D.box[1] * D.box[2];
+        for (int k = 0; k < 6; ++k) o.virial[k] = v[E_W0 + k];
+        o.pressure_gpa = (2.0 * o.ke + o.virial[0] + o.virial[1] + o.virial[2]) / (3.0 * o.volume) * kEvPerA3InGpa;
+        o.piston_work = v[E_PW];
+        o.step = c->step;
+        o.n_atoms = D.n_atoms;
+        o.n_mobile = c->n_mobile[r];
+    }
+    if (flags[F_MAX_COUNT] > c->cap) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "neighbour list overflow: an atom has %d entries, max_neighbours is %d (set it >= %d)",
+                      flags[F_MAX_COUNT], c->cap, flags[F_MAX_COUNT]);
+        return fail(c, MD_ERR_NBR_OVERFLOW, msg);
+    }
+    if (flags[F_SKIN] > 0) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved more than skin/2 = %.4g A between list builds", flags[F_SKIN],
+                      0.5 * c->skin);
+        return fail(c, MD_ERR_SKIN, msg);
+    }
+    for (int r = 0; r < c->R; ++r) {
+        const double* v = e.data() + (size_t)r * kEnergySlots;
+        if (v[E_NONFINITE] != 0.0 || !std::isfinite(v[E_PE]) || !std::isfinite(v[E_KE]))
+            return fail(c, MD_ERR_NONFINITE, "non-finite energy or force in replica " + std::to_string(r));
+    }
+    return MD_OK;
+}
+
+int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, void* stream)
+{
+    if (!c || !counts || !list) return fail(c, MD_ERR_ARG, "md_copy_neighbours: NULL argument");
+    if (!c->bound || !c->have_list) return fail(c, MD_ERR_STATE, "md_copy_neighbours: no list built");
+    if (cap < c->cap) return fail(c, MD_ERR_ARG, "md_copy_neighbours: cap smaller than max_neighbours");
+    if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_copy_neighbours sync")) return MD_ERR_DEVICE;
+    const size_t Np = (size_t)c->Np;
+    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * (size_t)c->cap);
+    if (!hip_ok(c, hipMemcpy(cnt.data(), c->buf.ncount, Np * 4, hipMemcpyDeviceToHost), "copy") ||
+        !hip_ok(c, hipMemcpy(ids.data(), c->buf.id[c->q], Np * 4, hipMemcpyDeviceToHost), "copy") ||
+        !hip_ok(c, hipMemcpy(nb.data(), c->buf.nbr, nb.size() * 4, hipMemcpyDeviceToHost), "copy"))
+        return MD_ERR_DEVICE;
+    for (size_t t = 0; t < Np; ++t) {
+        const int32_t a = ids[t];
+        if (a < 0) continue;
+        counts[a] = cnt[t];
+        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[(size_t)k * Np + t]];
+    }
+    return MD_OK;
+}
+
+int md_set_option(md_ctx* c, int32_t option, int64_t value)
+{
+    if (!c) return MD_ERR_ARG;
+    switch (option) {
+    case MD_OPT_LANES_PER_ATOM:
+        if (value != 1 && value != 2 && value != 4 && value != 8) return fail(c, MD_ERR_ARG, "lanes per atom must be 1, 2, 4 or 8");
+        c->lanes = (int32_t)value;
+        return MD_OK;
+    case MD_OPT_USE_GRAPH:
+        if (value != 0) return fail(c, MD_ERR_ARG, "graph replay is not available in this build");
+        return MD_OK;
+    case MD_OPT_TIMING:
+        if (!value && !c->pending.empty()) return fail(c, MD_ERR_STATE, "read md_kernel_times before turning timing off");
+        c->timing = value != 0;
+        return MD_OK;
+    case MD_OPT_EVALUATOR:
+        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "evaluator must be 0 (tables) or 1 (knot sums)");
+        if (value == 0 && !c->table_ok) return fail(c, MD_ERR_ARG, "the knots share no tabulation grid");
+        c->evaluator = (int32_t)value;
+        return MD_OK;
+    default:
+        return fail(c, MD_ERR_ARG, "unknown or read-only option");
+    }
+}
+
+int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
+{
+    if (!c || !value) return MD_ERR_ARG;
+    switch (option) {
+    case MD_OPT_LANES_PER_ATOM: *value = c->lanes; return MD_OK;
+    case MD_OPT_USE_GRAPH: *value = 0; return MD_OK;
+    case MD_OPT_MAX_COUNT: *value = c->max_count; return MD_OK;
+    case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
+    case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;
+    case MD_OPT_EVALUATOR: *value = (c->table_ok && c->evaluator == 0) ? 0 : 1; return MD_OK;
+    default: return MD_ERR_ARG;
+    }
+}
+
+int md_kernel_times(md_ctx* c, double* ms, int64_t* launches, int reset, void* stream)
+{
+    if (!c || !ms || !launches) return fail(c, MD_ERR_ARG, "md_kernel_times: NULL argument");
+    if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_kernel_times sync")) return MD_ERR_DEVICE;
+    collect_times(c);
+    for (int g = 0; g < MD_KT_COUNT; ++g) {
+        ms[g] = c->kt_ms[g];
+        launches[g] = c->kt_n[g];
+        if (reset) {
+            c->kt_ms[g] = 0.0;
+            c->kt_n[g] = 0;
+        }
+    }
+    return MD_OK;
+}
+
+void md_destroy(md_ctx* c) { delete c; }
+
+const char* md_last_error(const md_ctx* c)
+{
+    if (!c) return "NULL context";
+    return c->err.empty() ? "no error" : c->err.c_str();
+}
+
+}  // extern "C"

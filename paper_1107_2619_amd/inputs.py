@@ -329,10 +329,12 @@ def _concat(name, parts, pot, dt, skin, every, steps, cap, meta):
 def fec_replicas(n_replicas: int = 256, nmin: int = 250, nmax: int = 16000, a: float = 2.87,
                  c_frac: float = 0.005, tmin: float = 300.0, tmax: float = 1200.0,
                  seed0: int = 4000, pot_seed: int = 4, steps: int = 500, dt_fs: float = 1.0,
-                 skin: float = 0.3, rebuild_every: int = 10, name: str = "fec_replicas") -> System:
+                 skin: float = 0.5, rebuild_every: int = 5, name: str = "fec_replicas") -> System:
     """Independent bcc Fe-C replicas: size ~ U{nmin..nmax}, near-cubic cells,
     round(c_frac * N_Fe) carbon atoms on distinct random octahedral sites,
-    temperature ~ U[tmin, tmax].  Replica r uses seed seed0 + r."""
+    temperature ~ U[tmin, tmax].  Replica r uses seed seed0 + r.  Carbon at
+    1200 K moves up to ~0.33 A in 10 fs, so the list uses a 0.5 A skin rebuilt
+    every 5 steps."""
     pot = perturbed_potential("fec_eam", pot_seed)
     parts = []
     for r in range(n_replicas):
@@ -381,6 +383,10 @@ def workload(name: str, **kw) -> System:
     if name == "bcc2000":  # 2000-atom bcc Fe, 300 K, 100 steps
         return bcc_fe(10, temperature=300.0, seed=1, steps=100, name=name, **kw)
     if name == "bcc1m":  # 80^3 cells, 1% vacancies -> 1,013,760 atoms, 600 K
+        # Over 10 fs at 600 K the per-axis displacement has sigma ~0.03 A; with
+        # 10^6 atoms a 0.3 A skin (guard at 0.15 A = 5 sigma) is crossed by a
+        # handful of atoms per interval, 0.4 A (6.7 sigma) is not.
+        kw.setdefault("skin", 0.4)
         return bcc_fe(80, temperature=600.0, vacancy_frac=0.01, seed=2, steps=1000, name=name, **kw)
     if name == "fcc_piston":
         return fcc_piston(**kw)

@@ -1,0 +1,315 @@
+"""Thin ctypes binding of ``include/md.h`` (argument marshalling only).
+
+Every step of the force loop runs in the gfx950 kernels of ``libmdeam.so``;
+this module only allocates device tensors with PyTorch, passes their
+pointers and the current HIP stream, and converts results.  There is no CPU
+fallback: if the library is missing, importing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdeam.so")
+
+MD_OK = 0
+MD_ERR_ARG = -1
+MD_ERR_BOX = -2
+MD_ERR_POTENTIAL = -3
+MD_ERR_NBR_OVERFLOW = -4
+MD_ERR_SKIN = -5
+MD_ERR_NONFINITE = -6
+MD_ERR_DEVICE = -7
+MD_ERR_STATE = -8
+ERROR_NAMES = {
+    MD_ERR_ARG: "MD_ERR_ARG", MD_ERR_BOX: "MD_ERR_BOX", MD_ERR_POTENTIAL: "MD_ERR_POTENTIAL",
+    MD_ERR_NBR_OVERFLOW: "MD_ERR_NBR_OVERFLOW", MD_ERR_SKIN: "MD_ERR_SKIN",
+    MD_ERR_NONFINITE: "MD_ERR_NONFINITE", MD_ERR_DEVICE: "MD_ERR_DEVICE", MD_ERR_STATE: "MD_ERR_STATE",
+}
+MD_FP64, MD_MIXED = 0, 1
+MD_NBR_FULL, MD_NBR_HALF_ATOMIC = 0, 1
+MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_OPT_TIMING = 1, 2, 3, 4, 5
+MD_OPT_EVALUATOR = 6
+KERNEL_GROUPS = ("build", "density", "force", "reduce")
+
+EXPORTED = [
+    "md_create", "md_workspace_bytes", "md_bind", "md_build_neighbours", "md_eam_forces", "md_step",
+    "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_destroy",
+    "md_last_error",
+]
+
+
+class MDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Potential(ctypes.Structure):
+    _fields_ = [
+        ("n_species", ctypes.c_int32), ("n_pair_knots", ctypes.c_int32),
+        ("n_dens_knots", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("pair_a", ctypes.c_void_p), ("pair_r", ctypes.c_void_p),
+        ("dens_A", ctypes.c_void_p), ("dens_R", ctypes.c_void_p),
+        ("emb_c", ctypes.c_void_p), ("mass_amu", ctypes.c_void_p),
+    ]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [
+        ("n_replicas", ctypes.c_int32), ("max_neighbours", ctypes.c_int32),
+        ("rebuild_every", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("nbr_mode", ctypes.c_int32), ("lanes_per_atom", ctypes.c_int32),
+        ("atom_offset", ctypes.c_void_p), ("box", ctypes.c_void_p), ("origin", ctypes.c_void_p),
+        ("periodic", ctypes.c_void_p), ("rigid_velocity", ctypes.c_void_p),
+        ("skin", ctypes.c_double), ("dt_fs", ctypes.c_double),
+    ]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "species", "rigid", "e_atom")]
+
+
+class _Energies(ctypes.Structure):
+    _fields_ = [
+        ("pe", ctypes.c_double), ("ke", ctypes.c_double), ("temperature", ctypes.c_double),
+        ("pressure_gpa", ctypes.c_double), ("volume", ctypes.c_double),
+        ("piston_work", ctypes.c_double), ("virial", ctypes.c_double * 6),
+        ("step", ctypes.c_int64), ("n_atoms", ctypes.c_int64), ("n_mobile", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load libmdeam.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1107_2619_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.md_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(_Potential), ctypes.POINTER(vp)]
+    lib.md_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.md_bind.argtypes = [vp, ctypes.POINTER(_State), vp, ctypes.c_size_t]
+    lib.md_build_neighbours.argtypes = [vp, vp]
+    lib.md_eam_forces.argtypes = [vp, ctypes.c_int, vp]
+    lib.md_step.argtypes = [vp, i32, vp]
+    lib.md_energy.argtypes = [vp, ctypes.POINTER(_Energies), vp]
+    lib.md_copy_neighbours.argtypes = [vp, vp, vp, i32, vp]
+    lib.md_set_option.argtypes = [vp, i32, i64]
+    lib.md_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.md_kernel_times.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.md_destroy.argtypes = [vp]
+    lib.md_destroy.restype = None
+    lib.md_last_error.argtypes = [vp]
+    lib.md_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED[:-2]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Context:
+    """Owns one ``md_ctx`` (host side only until ``bind``)."""
+
+    def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
+                 skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
+                 nbr_mode="full", lanes_per_atom=0):
+        self.lib = library()
+        pa = _c(potential["pair_a"], np.float64)
+        ns = pa.shape[0]
+        self._keep = {
+            "pair_a": pa, "pair_r": _c(potential["pair_r"], np.float64),
+            "dens_A": _c(potential["dens_A"], np.float64), "dens_R": _c(potential["dens_R"], np.float64),
+            "emb_c": _c(potential["emb_c"], np.float64), "mass": _c(potential["mass"], np.float64),
+            "off": _c(atom_offset, np.int64), "box": _c(box, np.float64).reshape(-1, 3),
+            "periodic": _c(periodic, np.uint8).reshape(-1, 3),
+        }
+        k = self._keep
+        k["origin"] = None if origin is None else _c(origin, np.float64).reshape(-1, 3)
+        k["vp"] = None if rigid_velocity is None else _c(rigid_velocity, np.float64).reshape(-1, 3)
+        pot = _Potential(ns, pa.shape[2], k["dens_A"].shape[2], 0, pa.ctypes.data, k["pair_r"].ctypes.data,
+                         k["dens_A"].ctypes.data, k["dens_R"].ctypes.data, k["emb_c"].ctypes.data,
+                         k["mass"].ctypes.data)
+        prec = {"fp64": MD_FP64, "mixed": MD_MIXED}[precision] if isinstance(precision, str) else precision
+        mode = {"full": MD_NBR_FULL, "half": MD_NBR_HALF_ATOMIC}[nbr_mode] if isinstance(nbr_mode, str) else nbr_mode
+        cfg = _Config(
+            len(k["off"]) - 1, int(max_neighbours), int(rebuild_every), prec, mode, int(lanes_per_atom),
+            k["off"].ctypes.data, k["box"].ctypes.data,
+            None if k["origin"] is None else k["origin"].ctypes.data, k["periodic"].ctypes.data,
+            None if k["vp"] is None else k["vp"].ctypes.data, float(skin), float(dt_fs),
+        )
+        h = ctypes.c_void_p()
+        rc = self.lib.md_create(ctypes.byref(cfg), ctypes.byref(pot), ctypes.byref(h))
+        self.handle = h.value
+        if rc != MD_OK:
+            msg = self.lib.md_last_error(self.handle).decode() if self.handle else "md_create failed"
+            if self.handle:
+                self.lib.md_destroy(self.handle)
+                self.handle = None
+            raise MDError(rc, msg)
+        self.n_replicas = len(k["off"]) - 1
+        self.n_atoms = int(k["off"][-1])
+
+    def _check(self, rc):
+        if rc != MD_OK:
+            raise MDError(rc, self.lib.md_last_error(self.handle).decode())
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.md_workspace_bytes(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self.lib.md_destroy(h)
+            self.handle = None
+
+
+@dataclass
+class Energies:
+    pe: np.ndarray
+    ke: np.ndarray
+    temperature: np.ndarray
+    pressure_gpa: np.ndarray
+    volume: np.ndarray
+    piston_work: np.ndarray
+    virial: np.ndarray  # [R, 6]
+    step: int
+    n_atoms: np.ndarray
+    n_mobile: np.ndarray
+
+
+class Simulation:
+    """Device state (torch tensors) bound to a Context."""
+
+    def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
+                 device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None):
+        import torch
+
+        self.torch = torch
+        self.system = system
+        self.device = torch.device(device)
+        self.cap = int(system.max_neighbours if max_neighbours is None else max_neighbours)
+        self.ctx = Context(
+            system.potential, system.atom_offset, system.box, system.periodic, origin=system.origin,
+            rigid_velocity=system.rigid_velocity, skin=system.skin if skin is None else skin,
+            dt_fs=system.dt_fs, rebuild_every=system.rebuild_every if rebuild_every is None else rebuild_every,
+            max_neighbours=self.cap,
+            precision=precision, nbr_mode=nbr_mode, lanes_per_atom=lanes_per_atom,
+        )
+        d = self.device
+        f64 = dict(dtype=torch.float64, device=d)
+        n = system.n_atoms
+        self.x = torch.tensor(system.pos[:, 0], **f64)
+        self.y = torch.tensor(system.pos[:, 1], **f64)
+        self.z = torch.tensor(system.pos[:, 2], **f64)
+        self.vx = torch.tensor(system.vel[:, 0], **f64)
+        self.vy = torch.tensor(system.vel[:, 1], **f64)
+        self.vz = torch.tensor(system.vel[:, 2], **f64)
+        self.fx = torch.zeros(n, **f64)
+        self.fy = torch.zeros(n, **f64)
+        self.fz = torch.zeros(n, **f64)
+        self.species = torch.tensor(system.species, dtype=torch.uint8, device=d)
+        self.rigid = torch.tensor(system.rigid, dtype=torch.uint8, device=d) if system.rigid.any() else None
+        self.e_atom = torch.zeros(n, **f64) if want_e_atom else None
+        nbytes = self.ctx.workspace_bytes()
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=d)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._bind()
+
+    def _ptr(self, t):
+        return None if t is None else t.data_ptr()
+
+    def _bind(self):
+        st = _State(*(self._ptr(t) for t in (self.x, self.y, self.z, self.vx, self.vy, self.vz, self.fx, self.fy,
+                                             self.fz, self.species, self.rigid, self.e_atom)))
+        self.ctx._check(self.ctx.lib.md_bind(self.ctx.handle, ctypes.byref(st), self._ws_ptr,
+                                             self.ctx.workspace_bytes()))
+
+    def set_state(self, pos=None, vel=None):
+        """Overwrite positions/velocities (caller order) on the device."""
+        t = self.torch
+        if pos is not None:
+            p = t.as_tensor(np.asarray(pos, np.float64), device=self.device)
+            self.x.copy_(p[:, 0]), self.y.copy_(p[:, 1]), self.z.copy_(p[:, 2])
+        if vel is not None:
+            v = t.as_tensor(np.asarray(vel, np.float64), device=self.device)
+            self.vx.copy_(v[:, 0]), self.vy.copy_(v[:, 1]), self.vz.copy_(v[:, 2])
+
+    def rebind(self):
+        """Re-attach the same buffers (resets step counter, list and piston work)."""
+        self._bind()
+
+    @property
+    def stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def build_neighbours(self):
+        self.ctx._check(self.ctx.lib.md_build_neighbours(self.ctx.handle, self.stream))
+
+    def eam_forces(self, want_energy=True):
+        self.ctx._check(self.ctx.lib.md_eam_forces(self.ctx.handle, int(bool(want_energy)), self.stream))
+
+    def step(self, nsteps: int):
+        self.ctx._check(self.ctx.lib.md_step(self.ctx.handle, int(nsteps), self.stream))
+
+    def energy(self) -> Energies:
+        R = self.ctx.n_replicas
+        out = (_Energies * R)()
+        self.ctx._check(self.ctx.lib.md_energy(self.ctx.handle, out, self.stream))
+        g = lambda name: np.array([getattr(o, name) for o in out])  # noqa: E731
+        return Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"), g("piston_work"),
+                        np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"))
+
+    def neighbours(self):
+        """(counts[N], list[N, cap]) in caller numbering."""
+        cap = self.cap
+        n = self.ctx.n_atoms
+        counts = np.zeros(n, np.int32)
+        lst = np.full((n, cap), -1, np.int32)
+        self.ctx._check(self.ctx.lib.md_copy_neighbours(self.ctx.handle, counts.ctypes.data, lst.ctypes.data,
+                                                        cap, self.stream))
+        return counts, lst
+
+    def set_option(self, opt, value):
+        self.ctx._check(self.ctx.lib.md_set_option(self.ctx.handle, int(opt), int(value)))
+
+    def get_option(self, opt) -> int:
+        v = ctypes.c_int64()
+        self.ctx._check(self.ctx.lib.md_get_option(self.ctx.handle, int(opt), ctypes.byref(v)))
+        return v.value
+
+    def kernel_times(self, reset=True):
+        """{group: (total ms, launches)} recorded with MD_OPT_TIMING on."""
+        ms = np.zeros(4)
+        n = np.zeros(4, np.int64)
+        self.ctx._check(self.ctx.lib.md_kernel_times(self.ctx.handle, ms.ctypes.data, n.ctypes.data, int(reset),
+                                                     self.stream))
+        return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(KERNEL_GROUPS)}
+
+    def positions(self) -> np.ndarray:
+        return self.torch.stack([self.x, self.y, self.z], 1).cpu().numpy()
+
+    def velocities(self) -> np.ndarray:
+        return self.torch.stack([self.vx, self.vy, self.vz], 1).cpu().numpy()
+
+    def forces(self) -> np.ndarray:
+        return self.torch.stack([self.fx, self.fy, self.fz], 1).cpu().numpy()
+
+    def atom_energies(self) -> np.ndarray:
+        return self.e_atom.cpu().numpy()

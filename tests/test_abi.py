@@ -1,0 +1,103 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, and md_create validates its arguments on the host (no device
+work happens before md_bind)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1107_2619_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_1107_2619_amd import md as _md
+
+    try:
+        _md.library()
+    except ImportError:
+        pytest.fail("libmdeam.so is not built (run python -m paper_1107_2619_amd.build)")
+    return _md
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "md.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(md_\w+)\s*\(", text, re.M)))
+
+
+def test_header_symbols_exported(md):
+    lib = md.library()
+    declared = _declared()
+    assert declared == sorted(md.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _ctx(md, **over):
+    s = inputs.workload("bcc2000")
+    kw = dict(skin=0.3, max_neighbours=48)
+    kw.update(over)
+    pot = over.pop("potential", None) or s.potential
+    kw.pop("potential", None)
+    box = kw.pop("box", s.box)
+    per = kw.pop("periodic", s.periodic)
+    off = kw.pop("atom_offset", s.atom_offset)
+    return md.Context(pot, off, box, per, **kw)
+
+
+def test_create_ok_and_workspace(md):
+    c = _ctx(md)
+    assert c.workspace_bytes() > 2000 * 48 * 4
+
+
+def test_box_too_small(md):
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, box=[[8.7, 28.7, 28.7]])
+    assert e.value.code == md.MD_ERR_BOX
+    # a free axis may be small
+    _ctx(md, box=[[8.7, 28.7, 28.7]], periodic=[[0, 1, 1]])
+
+
+@pytest.mark.parametrize(
+    "field,value,code",
+    [("max_neighbours", 0, -1), ("rebuild_every", 0, -1), ("precision", 7, -1), ("nbr_mode", 3, -1),
+     ("lanes_per_atom", 3, -1), ("skin", -0.1, -1), ("dt_fs", 0.0, -1)],
+)
+def test_config_validation(md, field, value, code):
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, **{field: value})
+    assert e.value.code == code
+
+
+def test_potential_validation(md):
+    s = inputs.workload("bcc2000")
+    bad = dict(s.potential)
+    bad["dens_A"] = -np.abs(bad["dens_A"])
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, potential=bad)
+    assert e.value.code == md.MD_ERR_POTENTIAL
+    pot2 = inputs.perturbed_potential("fec_eam", 1)
+    pot2["pair_a"][0, 1, 0] += 1.0  # break the pair symmetry
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, potential=pot2)
+    assert e.value.code == md.MD_ERR_POTENTIAL
+    heavy = dict(s.potential)
+    heavy["mass"] = np.array([0.0])
+    with pytest.raises(md.MDError):
+        _ctx(md, potential=heavy)
+
+
+def test_atom_offset_validation(md):
+    with pytest.raises(md.MDError):
+        _ctx(md, atom_offset=[1, 2000])
+    with pytest.raises(md.MDError):
+        md.Context(inputs.workload("bcc2000").potential, [0, 10, 5], [[28.7] * 3] * 2, [[1, 1, 1]] * 2)
+
+
+def test_small_boxes_get_at_least_one_cell(md):
+    s = inputs.liquid_replicas(3, nmin=128, nmax=140, seed0=5300)
+    c = md.Context(s.potential, s.atom_offset, s.box, s.periodic, skin=0.5, max_neighbours=96)
+    assert c.workspace_bytes() > 0
