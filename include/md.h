@@ -96,7 +96,7 @@ typedef struct {
     int32_t rebuild_every;  /* list rebuild period in steps (nbrupdate), >= 1 */
     int32_t precision;      /* MD_FP64 or MD_MIXED */
     int32_t nbr_mode;       /* MD_NBR_FULL or MD_NBR_HALF_ATOMIC */
-    int32_t lanes_per_atom; /* 0 = choose automatically; else 1, 2, 4 or 8 */
+    int32_t lanes_per_atom; /* lanes sharing one atom's neighbours: 0 = automatic, 1, 2 or 4 */
     const int64_t *atom_offset;   /* [R+1], atom_offset[0] = 0, non-decreasing */
     const double *box;            /* [R][3] edge lengths, Angstrom, > 0 */
     const double *origin;         /* [R][3] lower corner (matters on free axes); NULL = 0 */
@@ -182,14 +182,23 @@ int md_energy(md_ctx *ctx, md_energies *out, void *stream);
 int md_copy_neighbours(md_ctx *ctx, int32_t *counts, int32_t *list, int32_t cap, void *stream);
 
 enum {
-    MD_OPT_LANES_PER_ATOM = 1, /* 1, 2, 4 or 8 lanes cooperate on one atom           */
+    MD_OPT_LANES_PER_ATOM = 1, /* 0 (automatic), 1, 2 or 4 lanes share one atom      */
     MD_OPT_USE_GRAPH = 2,      /* 1 = replay md_step from captured HIP graphs         */
     MD_OPT_MAX_COUNT = 3,      /* read only: largest list length seen (at md_energy)  */
     MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind                */
     MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
-    MD_OPT_EVALUATOR = 6       /* 0 = exact local-polynomial tables (default when all
+    MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default when all
                                   knots lie on a common grid), 1 = term-by-term knot
                                   sums (the paper's explicit evaluation)             */
+    MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (default, full list),
+                                  1 = one thread per atom with global gathers        */
+    MD_OPT_BRICK_DIMS = 8,     /* 0 = automatic, else bx + 10 by + 100 bz cells (1..4) */
+    MD_OPT_BRICK_BLOCK = 9,    /* threads per brick workgroup: 64..1024             */
+    MD_OPT_HALO_CAP = 10,      /* atoms one brick's LDS staging area holds (set
+                                  smaller to shrink LDS use; larger halos fall back) */
+    MD_OPT_HALO_OVERFLOWS = 11 /* read only: brick passes whose halo exceeded the
+                                  staging area and read global memory instead
+                                  (counted since md_bind, read at md_energy)         */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);

@@ -25,6 +25,17 @@ constexpr int kEnergySlots = 12;  // per-wave partial record, see EnergyIndex
 constexpr int kNumXcd = 8;      // MI355X: 8 accelerator dies, one L2 each
 
 enum EnergyIndex { E_PE = 0, E_KE = 1, E_W0 = 2, E_PW = 8, E_NONFINITE = 9 };
+constexpr int kEnergyTerms = 10;       // per-atom terms written on energy steps
+constexpr int kReduceChunk = 16384;    // slots per first-stage reduction chunk
+constexpr int kHaloMax = 216;          // halo cells of a brick: (4 + 2)^3 at most
+constexpr int kBrickMaxDim = 4;
+
+// Neighbour-list entry: slot index in the low kIndexBits bits, the periodic
+// image shift (2 bits per axis) above.
+constexpr int kIndexBits = 26;
+constexpr int kIndexMask = (1 << kIndexBits) - 1;
+constexpr int kChunk = 4;  // neighbours whose loads are issued together
+constexpr int kForceStride = 6;  // coefficients per bin of the force table (phi', rho' quadratics)
 
 // Slot type byte: species in bits 0..5, rigid flag in bit 6; 0xFF = empty slot.
 constexpr uint8_t kRigidBit = 0x40;
@@ -34,12 +45,28 @@ constexpr uint8_t kEmptySlot = 0xFF;
 // [slot_off, slot_off + n_atoms); slot_off is a multiple of the wavefront, so
 // a wavefront never mixes replicas and the replica of a slot is a per-wave
 // (scalar) value.  Cells of replica r are [cell_off, cell_off + nc.x*nc.y*nc.z).
+//
+// Link cells are numbered brick-major: the nc[0] x nc[1] x nc[2] grid is cut
+// into bricks of bd[0] x bd[1] x bd[2] cells (nbk[a] bricks per axis, the last
+// one possibly partial), cell (cx,cy,cz) has index
+//   cell_off + brick * cpb + local,  brick = (bz*nbk[1] + by)*nbk[0] + bx,
+//   local = (lz*bd[1] + ly)*bd[0] + lx,  c = b*bd + l,  cpb = bd[0]*bd[1]*bd[2],
+// so after the cell sort the atoms of a brick occupy one contiguous slot range.
 struct DevReplica {
     int32_t slot_off, n_atoms, cell_off, periodic_mask;  // bit a = axis a periodic
     int32_t nc[3], atom_off;                              // atom_off: caller index base
+    int32_t bd[3], cpb;                                   // brick shape, cells per brick
+    int32_t nbk[3], brick_off;                            // bricks per axis, first global brick
     double box[3], inv_box[3], origin[3];
     double vp[3];  // rigid velocity, A/fs
 };
+
+__host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)
+{
+    const int bx = cx / R.bd[0], by = cy / R.bd[1], bz = cz / R.bd[2];
+    const int lx = cx - bx * R.bd[0], ly = cy - by * R.bd[1], lz = cz - bz * R.bd[2];
+    return R.cell_off + ((bz * R.nbk[1] + by) * R.nbk[0] + bx) * R.cpb + (lz * R.bd[1] + ly) * R.bd[0] + lx;
+}
 
 // Potential evaluated in the kernels.  Amplitudes are stored premultiplied
 // for the derivative (-3 a) beside the value amplitudes.
@@ -74,7 +101,9 @@ struct PotArgs {
 // F_MAX_COUNT: largest list length found by any build (overflow when > cap);
 // F_SKIN: atoms whose net displacement between builds exceeded skin/2;
 // F_OUTSIDE: atoms beyond the grid extent of a free axis (clamped; legal).
-enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_COUNT = 4 };
+// F_HALO: brick passes whose halo did not fit the LDS staging area (those
+// read their neighbours from global memory instead).
+enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COUNT = 4 };
 
 // Pointers into the workspace.
 struct Buffers {
@@ -83,9 +112,16 @@ struct Buffers {
     int32_t* id[2];       // [Np] caller index of the slot, -1 = empty
     uint8_t* type[2];     // [Np]
     double* pwork[2];     // [Np] piston work accumulated per rigid atom, eV
+    int32_t* img[2][3];   // [Np] periodic image count per axis (caller x = x + img L)
     double4* xbuild;      // [Np] positions at the last list build
     double* femb;         // [Np] F_i (energy steps)
-    int32_t* nbr;         // [cap][Np] transposed list
+    int32_t* nbr;         // [cap][Np] transposed list (global slots + shift code)
+    uint16_t* nbr16;      // [Np][rowlen] rows of staging (LDS) indices (brick path)
+    int32_t* cell_sorted; // [Np] link cell of each slot after the sort
+    int32_t* brick_rep;   // [n_bricks] replica of each brick
+    int4* brick_info;     // [n_bricks] own slot range [x, y) and halo atoms z at the last build
+    int32_t* stage_src;   // [n_bricks][halo_cap] slot | shift code of each staging position
+    uint16_t* own_li;     // [Np] staging position of each atom within its own brick
     int32_t* ncount;      // [Np]
     int32_t* cell_of;     // [Np]
     int32_t* perm;        // [Np] new slot -> old slot
@@ -97,10 +133,13 @@ struct Buffers {
     int32_t* rep_of_wave; // [Np / 64]
     DevReplica* reps;     // [R]
     DevPotential* pot;    // 1
-    double* partial;      // [Np / 64][kEnergySlots]
+    double* eslot;        // [kEnergyTerms][Np] per-atom energy terms (energy steps)
     double* energies;     // [R][kEnergySlots]
+    int32_t* chunk_rep;   // [n_chunks] replica of each reduction chunk
+    int32_t* chunk_off;   // [R+1] first chunk of each replica
+    double* chunk_partial;  // [n_chunks][kEnergySlots]
     double* fhalf[3];     // [Np] half-list force accumulators (MD_NBR_HALF_ATOMIC)
-    // local-polynomial tables, [ns*ns][nbt][8] (phi' and rho' quadratics),
+    // local-polynomial tables, [ns*ns][nbt][kForceStride] (phi' and rho' quadratics),
     // [ns*ns][nbt][4] (phi cubic), [ns*ns][nbt][4] (rho cubic)
     double *tab_force64, *tab_energy64, *tab_dens64;
     float *tab_force32, *tab_energy32, *tab_dens32;
@@ -112,9 +151,15 @@ struct KernelShape {
     int32_t n_cells;
     int32_t n_replicas;
     int32_t cap;
-    int32_t lanes;    // lanes per atom
     int32_t npk, ndk; // knots per pair / density function
     int32_t table;    // 1 = local-polynomial tables, 0 = explicit knot sums
+    int32_t n_chunks; // energy-reduction chunks over all replicas
+    int32_t n_bricks; // bricks over all replicas
+    int32_t brick;    // 1 = LDS brick kernels, 0 = global-gather kernels
+    int32_t halo_cap; // atoms the LDS staging area holds
+    int32_t block;    // threads per brick workgroup
+    int32_t lanes;    // lanes sharing one atom's neighbour list (brick path)
+    int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
 };
 
 // Launchers (kernels.hip).  All enqueue on `s`.
@@ -133,6 +178,14 @@ struct ForceFlags {
 };
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
-void launch_reduce_energies(const Buffers& b, const KernelShape& k, hipStream_t s);
+void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
+// Brick path (kernels_brick.hip).
+void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, hipStream_t s);
+void launch_brick_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
+                          int energy, hipStream_t s);
+void launch_brick_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
+                        ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
+void launch_brick_list_to_slots(const Buffers& b, const KernelShape& k, hipStream_t s);
+size_t brick_lds_bytes(const KernelShape& k, const PotArgs& P, int precision, int pass, int energy);
 
 }  // namespace mdk

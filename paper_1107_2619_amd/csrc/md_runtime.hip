@@ -31,9 +31,18 @@ struct md_ctx {
     std::vector<float> tf32, te32, td32;
     // derived layout
     int64_t N = 0, Np = 0;
-    int32_t C = 0, scan_nb = 0;
+    int32_t C = 0, C_alloc = 0, scan_nb = 0;
+    // brick path
+    int32_t kernel_path = 0;  // 0 = LDS bricks, 1 = global gathers
+    int32_t brick_dims = 0;   // 0 = automatic, else bd[0] + 10 bd[1] + 100 bd[2]
+    int32_t brick_block = 512;
+    int32_t lds_limit = 65536;
+    int32_t halo_cap = 0;
+    int32_t halo_cap_max = 0;
+    int64_t halo_overflows = 0;  // bricks evaluated from global memory (last md_energy)
+    std::vector<int32_t> brick_rep;
     std::vector<DevReplica> reps;
-    std::vector<int32_t> rep_of_wave, cell_shift;
+    std::vector<int32_t> rep_of_wave, cell_shift, chunk_rep, chunk_off;
     size_t ws_bytes = 0;
     std::vector<size_t> off;  // workspace offsets, in Buffers field order
     // binding and run state
@@ -82,11 +91,114 @@ KernelShape shape(const md_ctx* c)
     k.n_cells = c->C;
     k.n_replicas = c->R;
     k.cap = c->cap;
-    k.lanes = c->lanes;
+    k.lanes = c->lanes > 0 ? std::min(c->lanes, 4) : 4;
     k.npk = c->pot.npk;
     k.ndk = c->pot.ndk;
     k.table = c->table_ok && c->evaluator == 0;
+    k.n_chunks = (int32_t)c->chunk_rep.size();
+    k.n_bricks = (int32_t)c->brick_rep.size();
+    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL;
+    k.halo_cap = c->halo_cap;
+    k.block = c->brick_block;
+    k.rowlen = (c->cap + 7) / 8 * 8;
     return k;
+}
+
+// Staging records of all bricks: n_bricks x halo_cap entries.  Every atom lies
+// in the halo of at most 27 bricks, and the automatic capacity is 1.25 times
+// the expected halo rounded up to 64, so 34 Np + 64 (bricks) entries bound it;
+// choose_bricks clamps explicit settings to this size.
+size_t stage_entries(const md_ctx* c)
+{
+    size_t max_bricks = 0;
+    for (int r = 0; r < c->R; ++r) max_bricks += (size_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
+    return 34 * (size_t)c->Np + 64 * max_bricks;
+}
+
+// Brick geometry (LDS path).  One workgroup's LDS holds the halo table, the
+// staged atoms (32 bytes each plus a type byte) and the tables of the pass.
+// Budget: kLdsBudget per workgroup (two workgroups per CU on 160 KB of LDS) or
+// the device limit if lower; a shape set through MD_OPT_BRICK_DIMS may use the
+// whole device limit.  Automatic shape: the largest candidate whose
+// expected halo, with 25% headroom for density fluctuations, fits the budget;
+// the staging area is then sized to that halo, not to the budget, so that as
+// many workgroups as possible stay resident.
+constexpr int64_t kLdsBudget = 80 * 1024;
+constexpr double kHaloHeadroom = 1.25;
+
+void choose_bricks(md_ctx* c, int32_t dims)
+{
+    const size_t rsz = c->precision == MD_MIXED ? 4 : 8;
+    const size_t tables = c->table_ok && c->pot.ns == 1 ? (size_t)c->args.nbt * (kForceStride + 4) * rsz : 0;
+    // an explicit shape may use all the LDS a workgroup can have
+    const int64_t budget = dims > 0 ? (int64_t)c->lds_limit : std::min<int64_t>(kLdsBudget, c->lds_limit);
+    const int64_t max_cap = std::max<int64_t>(64, std::min<int64_t>(65535, (budget - 4608 - (int64_t)tables) / 33));
+    static const int cand[][3] = {{4, 4, 4}, {4, 4, 3}, {4, 4, 2}, {4, 3, 2}, {4, 2, 2}, {3, 2, 2},
+                                  {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
+    int64_t cells = 0, bricks = 0;
+    double need = 0.0;
+    c->brick_rep.clear();
+    for (int r = 0; r < c->R; ++r) {
+        DevReplica& D = c->reps[r];
+        const double vol_cell = (D.box[0] / D.nc[0]) * (D.box[1] / D.nc[1]) * (D.box[2] / D.nc[2]);
+        const double vol = D.box[0] * D.box[1] * D.box[2];
+        const double apc = D.n_atoms > 0 ? D.n_atoms / vol * vol_cell : 0.0;
+        auto halo_of = [&](const int* bd) {
+            double h = kHaloHeadroom * apc;
+            for (int a = 0; a < 3; ++a) h *= std::min(bd[a], D.nc[a]) + 2;
+            return h;
+        };
+        int bd[3] = {1, 1, 1};
+        if (dims > 0) {
+            bd[0] = dims % 10;
+            bd[1] = (dims / 10) % 10;
+            bd[2] = (dims / 100) % 10;
+        } else {
+            for (const auto& cd : cand)
+                if (halo_of(cd) <= max_cap) {
+                    for (int a = 0; a < 3; ++a) bd[a] = cd[a];
+                    break;
+                }
+        }
+        for (int a = 0; a < 3; ++a) {
+            bd[a] = std::max(1, std::min(bd[a], std::min(kBrickMaxDim, D.nc[a])));
+            D.bd[a] = bd[a];
+            D.nbk[a] = (D.nc[a] + bd[a] - 1) / bd[a];
+        }
+        need = std::max(need, halo_of(bd));
+        D.cpb = bd[0] * bd[1] * bd[2];
+        D.cell_off = (int32_t)cells;
+        D.brick_off = (int32_t)bricks;
+        const int64_t nb = (int64_t)D.nbk[0] * D.nbk[1] * D.nbk[2];
+        for (int64_t k = 0; k < nb; ++k) c->brick_rep.push_back(r);
+        bricks += nb;
+        cells += nb * D.cpb;
+    }
+    // staging capacity: the largest expected halo (with headroom), whole wavefronts
+    int64_t cap = ((int64_t)std::ceil(need) + 63) / 64 * 64;
+    const int64_t rec_cap = (int64_t)(stage_entries(c) / std::max<size_t>(c->brick_rep.size(), 1));
+    c->halo_cap_max = (int32_t)std::max<int64_t>(64, std::min<int64_t>(max_cap, rec_cap));
+    c->halo_cap = (int32_t)std::max<int64_t>(64, std::min<int64_t>(cap, c->halo_cap_max));
+    c->C = (int32_t)std::max<int64_t>(cells, 1);
+    c->cell_shift.assign(c->C_alloc, 0);
+    for (int r = 0; r < c->R; ++r) {
+        const DevReplica& D = c->reps[r];
+        const int64_t nc = (int64_t)D.nbk[0] * D.nbk[1] * D.nbk[2] * D.cpb;
+        for (int64_t k = 0; k < nc; ++k) c->cell_shift[D.cell_off + k] = D.slot_off - D.atom_off;
+    }
+    c->brick_dims = dims;
+}
+
+// Upload the replica table and the brick/cell maps (after md_bind or a
+// change of brick shape); the next call rebuilds the list.
+bool upload_geometry(md_ctx* c)
+{
+    if (!c->bound) return true;
+    c->have_list = false;
+    return hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "upload") &&
+           hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "upload") &&
+           (c->brick_rep.empty() ||
+            hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "upload"));
 }
 
 // Exact re-expansion of every cubic-knot sum on a grid of bins of width w
@@ -124,7 +236,7 @@ bool build_tables(md_ctx* c)
     c->args.w = w;
     c->args.inv_w = 1.0 / w;
     c->args.nbt = nbt;
-    c->tf64.assign((size_t)n2 * nbt * 8, 0.0);
+    c->tf64.assign((size_t)n2 * nbt * kForceStride, 0.0);
     c->te64.assign((size_t)n2 * nbt * 4, 0.0);
     c->td64.assign((size_t)n2 * nbt * 4, 0.0);
     auto expand = [&](const double* amp, const double* rk, int nk, int b, double out[4]) {
@@ -144,7 +256,7 @@ bool build_tables(md_ctx* c)
             double ph[4], rh[4];
             expand(P.pair_a[ab], P.pair_r[ab], P.npk, b, ph);
             expand(P.dens_a[ab], P.dens_r[ab], P.ndk, b, rh);
-            double* f = &c->tf64[((size_t)ab * nbt + b) * 8];
+            double* f = &c->tf64[((size_t)ab * nbt + b) * kForceStride];
             f[0] = ph[1];
             f[1] = 2.0 * ph[2];
             f[2] = 3.0 * ph[3];
@@ -166,32 +278,44 @@ bool build_tables(md_ctx* c)
 // order of the assignments in bind_buffers.
 void plan_workspace(md_ctx* c)
 {
-    const size_t Np = (size_t)c->Np, C = (size_t)c->C;
+    const size_t Np = (size_t)c->Np, C = (size_t)c->C_alloc;
+    size_t max_bricks = 0;
+    for (int r = 0; r < c->R; ++r)
+        max_bricks += (size_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
     std::vector<size_t> sizes = {
         Np * 32, Np * 32,                                    // pos[2]
         Np * 8, Np * 8, Np * 8, Np * 8, Np * 8, Np * 8,      // vel[2][3]
         Np * 4, Np * 4,                                      // id[2]
         Np, Np,                                              // type[2]
         Np * 8, Np * 8,                                      // pwork[2]
+        Np * 4, Np * 4, Np * 4, Np * 4, Np * 4, Np * 4,      // img[2][3]
         Np * 32,                                             // xbuild
         Np * 8,                                              // femb
-        Np * 4 * (size_t)c->cap,                             // nbr
+        Np * 4 * (size_t)((c->cap + 7) / 8 * 8),             // nbr rows (global path), rowlen entries each
         Np * 4,                                              // ncount
         Np * 4,                                              // cell_of
         Np * 4,                                              // perm
-        C * 4, C * 4, C * 4, C * 4,                          // cell start/count/cursor/shift
+        C * 4, C * 4, C * 4, C * 4,                          // cell start/count/cursor/shift (C_alloc)
         (size_t)c->scan_nb * 4,                              // scan_blocks
         Np / kWave * 4,                                      // rep_of_wave
         (size_t)c->R * sizeof(DevReplica),                   // reps
         sizeof(DevPotential),                                // pot
-        Np / kWave * kEnergySlots * 8,                       // partial
+        Np * kEnergyTerms * 8,                               // eslot
         (size_t)c->R * kEnergySlots * 8,                     // energies
+        c->chunk_rep.size() * 4, c->chunk_off.size() * 4,     // reduction chunks
+        c->chunk_rep.size() * kEnergySlots * 8,
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // fhalf[3]
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
         F_COUNT * 4,                                         // flags
         c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
         c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
+        (Np * (size_t)((c->cap + 7) / 8 * 8) + 64) * 2,     // nbr16 rows (+ one padding row for prefetches)
+        Np * 4,                                              // cell_sorted
+        std::max<size_t>(max_bricks, 1) * 4,                 // brick_rep (bricks <= cells)
+        std::max<size_t>(max_bricks, 1) * 16,                // brick_info
+        stage_entries(c) * 4,                                // stage_src
+        Np * 2,                                              // own_li
     };
     c->off.clear();
     size_t o = 0;
@@ -218,6 +342,8 @@ void bind_buffers(md_ctx* c)
     at(b.type[1]);
     at(b.pwork[0]);
     at(b.pwork[1]);
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 3; ++a) at(b.img[k][a]);
     at(b.xbuild);
     at(b.femb);
     at(b.nbr);
@@ -232,8 +358,11 @@ void bind_buffers(md_ctx* c)
     at(b.rep_of_wave);
     at(b.reps);
     at(b.pot);
-    at(b.partial);
+    at(b.eslot);
     at(b.energies);
+    at(b.chunk_rep);
+    at(b.chunk_off);
+    at(b.chunk_partial);
     for (int a = 0; a < 3; ++a) at(b.fhalf[a]);
     at(b.flags);
     at(b.tab_force64);
@@ -242,6 +371,12 @@ void bind_buffers(md_ctx* c)
     at(b.tab_force32);
     at(b.tab_energy32);
     at(b.tab_dens32);
+    at(b.nbr16);
+    at(b.cell_sorted);
+    at(b.brick_rep);
+    at(b.brick_info);
+    at(b.stage_src);
+    at(b.own_li);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -305,15 +440,19 @@ void ensure_slots(md_ctx* c, hipStream_t s)
     c->have_slots = true;
 }
 
-void rebuild(md_ctx* c, hipStream_t s)
+// List build.  Scheduled builds (check_skin) verify that no atom moved more
+// than skin/2 since the previous build, i.e. that the list just retired was
+// complete; an explicit md_build_neighbours starts afresh.
+void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
 {
     const KernelShape k = shape(c);
-    const double half_skin2 = c->have_list ? 0.25 * c->skin * c->skin : -1.0;
+    const double half_skin2 = (c->have_list && check_skin) ? 0.25 * c->skin * c->skin : -1.0;
     Timed tm(c, MD_KT_BUILD, s);
     launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
     c->p ^= 1;
     c->q ^= 1;
-    launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    if (k.brick) launch_brick_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, s);
+    else launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
     c->have_list = true;
     c->built_at = c->step;
     ++c->n_builds;
@@ -325,16 +464,18 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
     {
         Timed tm(c, MD_KT_DENSITY, s);
-        launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fl.energy, s);
+        if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fl.energy, s);
+        else launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fl.energy, s);
     }
     {
         Timed tm(c, MD_KT_FORCE, s);
-        launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
+        if (k.brick) launch_brick_force(c->buf, c->p, c->q, k, c->args, c->precision, fl, c->dt_fs, c->st, s);
+        else launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
     }
     if (fl.open) c->p ^= 1;
     if (fl.energy) {
         Timed tm(c, MD_KT_REDUCE, s);
-        launch_reduce_energies(c->buf, k, s);
+        launch_reduce_energies(c->buf, k, -0.5, s);  // full list: each pair seen from both atoms
         c->have_energy = true;
     }
 }
@@ -364,9 +505,8 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     if (cfg->rebuild_every < 1) return reject(MD_ERR_ARG, "rebuild_every must be >= 1");
     if (cfg->precision != MD_FP64 && cfg->precision != MD_MIXED) return reject(MD_ERR_ARG, "precision must be MD_FP64 or MD_MIXED");
     if (cfg->nbr_mode != MD_NBR_FULL && cfg->nbr_mode != MD_NBR_HALF_ATOMIC) return reject(MD_ERR_ARG, "nbr_mode must be MD_NBR_FULL or MD_NBR_HALF_ATOMIC");
-    if (!(cfg->lanes_per_atom == 0 || cfg->lanes_per_atom == 1 || cfg->lanes_per_atom == 2 ||
-          cfg->lanes_per_atom == 4 || cfg->lanes_per_atom == 8))
-        return reject(MD_ERR_ARG, "lanes_per_atom must be 0, 1, 2, 4 or 8");
+    if (!(cfg->lanes_per_atom == 0 || cfg->lanes_per_atom == 1 || cfg->lanes_per_atom == 2 || cfg->lanes_per_atom == 4))
+        return reject(MD_ERR_ARG, "lanes_per_atom must be 0, 1, 2 or 4");
     if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return reject(MD_ERR_ARG, "skin must be finite and >= 0");
     if (!(cfg->dt_fs > 0.0) || !std::isfinite(cfg->dt_fs)) return reject(MD_ERR_ARG, "dt_fs must be finite and > 0");
     c->R = cfg->n_replicas;
@@ -374,7 +514,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     c->rebuild_every = cfg->rebuild_every;
     c->precision = cfg->precision;
     c->nbr_mode = cfg->nbr_mode;
-    c->lanes = cfg->lanes_per_atom ? cfg->lanes_per_atom : 1;
+    c->lanes = cfg->lanes_per_atom;  // 0 = automatic
     c->skin = cfg->skin;
     c->dt_fs = cfg->dt_fs;
     c->atom_off.assign(cfg->atom_offset, cfg->atom_offset + c->R + 1);
@@ -470,7 +610,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
 
     // ---- replicas, wavefront-aligned slot ranges, link-cell grids
     // (paper: link cells at least the potential range plus the padding rpad)
-    int64_t slot = 0, cells = 0;
+    int64_t slot = 0, cells_alloc = 0;
     c->reps.resize(c->R);
     for (int r = 0; r < c->R; ++r) {
         DevReplica& D = c->reps[r];
@@ -478,9 +618,8 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
         D.slot_off = (int32_t)slot;
         D.n_atoms = (int32_t)n;
         D.atom_off = (int32_t)c->atom_off[r];
-        D.cell_off = (int32_t)cells;
         D.periodic_mask = 0;
-        int64_t ncell = 1;
+        int64_t worst = 1;
         for (int a = 0; a < 3; ++a) {
             const double L = c->box[3 * r + a];
             const bool per = c->periodic[3 * r + a];
@@ -498,15 +637,16 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
             D.nc[a] = (int32_t)nc;
             if (per) D.periodic_mask |= 1 << a;
-            ncell *= nc;
+            worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
         }
         slot += (n + kWave - 1) / kWave * kWave;
-        cells += ncell;
-        if (slot > (int64_t)INT32_MAX / 2 || cells > (int64_t)INT32_MAX / 2) return reject(MD_ERR_ARG, "system too large for 32-bit slot or cell indices");
+        cells_alloc += worst;
+        if (slot > (int64_t)kIndexMask || cells_alloc > (int64_t)INT32_MAX / 2)
+            return reject(MD_ERR_ARG, "system too large: at most 2^26 atom slots and 2^30 link cells");
     }
     c->Np = std::max<int64_t>(slot, kWave);
-    c->C = (int32_t)std::max<int64_t>(cells, 1);
-    c->scan_nb = (c->C + 1023) / 1024;
+    c->C_alloc = (int32_t)std::max<int64_t>(cells_alloc, 1);
+    c->scan_nb = (c->C_alloc + 1023) / 1024;
     if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
     c->rep_of_wave.assign(c->Np / kWave, 0);
     for (int r = 0; r < c->R; ++r) {
@@ -514,11 +654,23 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
         const int64_t w1 = (c->reps[r].slot_off + c->reps[r].n_atoms + kWave - 1) / kWave;
         for (int64_t w = w0; w < w1; ++w) c->rep_of_wave[w] = r;
     }
-    c->cell_shift.assign(c->C, 0);
+    // energy-reduction chunks of kReduceChunk slots, per replica
+    c->chunk_off.assign(c->R + 1, 0);
+    c->chunk_rep.clear();
     for (int r = 0; r < c->R; ++r) {
-        const int64_t nc = (int64_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
-        for (int64_t k = 0; k < nc; ++k) c->cell_shift[c->reps[r].cell_off + k] = c->reps[r].slot_off - c->reps[r].atom_off;
+        const int64_t nch = (c->reps[r].n_atoms + kReduceChunk - 1) / kReduceChunk;
+        for (int64_t k = 0; k < nch; ++k) c->chunk_rep.push_back(r);
+        c->chunk_off[r + 1] = (int32_t)c->chunk_rep.size();
     }
+    // LDS available to one workgroup (a device query when a GPU is visible)
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            c->lds_limit = lds;
+        (void)hipGetLastError();
+    }
+    choose_bricks(c, 0);
     plan_workspace(c);
     *out = c;
     return MD_OK;
@@ -546,6 +698,11 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         !hip_ok(c, hipMemcpy(c->buf.pot, &c->pot, sizeof(DevPotential), hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.rep_of_wave, c->rep_of_wave.data(), c->rep_of_wave.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
+        (!c->brick_rep.empty() &&
+         !hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
+        !hip_ok(c, hipMemcpy(c->buf.chunk_off, c->chunk_off.data(), c->chunk_off.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
+        (!c->chunk_rep.empty() &&
+         !hip_ok(c, hipMemcpy(c->buf.chunk_rep, c->chunk_rep.data(), c->chunk_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
         !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags"))
         return MD_ERR_DEVICE;
     if (c->table_ok &&
@@ -585,7 +742,7 @@ int md_build_neighbours(md_ctx* c, void* stream)
     hipStream_t s = as_stream(stream);
     ensure_slots(c, s);
     launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
-    rebuild(c, s);
+    rebuild(c, s, false);
     return check_launch(c);
 }
 
@@ -596,7 +753,7 @@ int md_eam_forces(md_ctx* c, int want_energy, void* stream)
     hipStream_t s = as_stream(stream);
     ensure_slots(c, s);
     launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
-    if (!c->have_list) rebuild(c, s);
+    if (!c->have_list) rebuild(c, s, false);
     forces(c, ForceFlags{want_energy ? 1 : 0, 0, 0, 1}, s);
     return check_launch(c);
 }
@@ -609,11 +766,11 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     hipStream_t s = as_stream(stream);
     ensure_slots(c, s);
     launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
-    if (!c->have_list || due(c)) rebuild(c, s);
+    if (!c->have_list || due(c)) rebuild(c, s, true);
     forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
     for (int32_t k = 1; k <= nsteps; ++k) {
         ++c->step;
-        if (due(c)) rebuild(c, s);
+        if (due(c)) rebuild(c, s, true);
         if (k < nsteps) forces(c, ForceFlags{0, 1, 1, 0}, s);
         else forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
     }
@@ -657,6 +814,7 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
                       flags[F_MAX_COUNT], c->cap, flags[F_MAX_COUNT]);
         return fail(c, MD_ERR_NBR_OVERFLOW, msg);
     }
+    c->halo_overflows = flags[F_HALO];
     if (flags[F_SKIN] > 0) {
         char msg[200];
         std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved more than skin/2 = %.4g A between list builds", flags[F_SKIN],
@@ -676,9 +834,11 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
     if (!c || !counts || !list) return fail(c, MD_ERR_ARG, "md_copy_neighbours: NULL argument");
     if (!c->bound || !c->have_list) return fail(c, MD_ERR_STATE, "md_copy_neighbours: no list built");
     if (cap < c->cap) return fail(c, MD_ERR_ARG, "md_copy_neighbours: cap smaller than max_neighbours");
+    if (shape(c).brick) launch_brick_list_to_slots(c->buf, shape(c), as_stream(stream));
     if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_copy_neighbours sync")) return MD_ERR_DEVICE;
     const size_t Np = (size_t)c->Np;
-    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * (size_t)c->cap);
+    const size_t rowlen = (size_t)((c->cap + 7) / 8 * 8);
+    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * rowlen);
     if (!hip_ok(c, hipMemcpy(cnt.data(), c->buf.ncount, Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(ids.data(), c->buf.id[c->q], Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(nb.data(), c->buf.nbr, nb.size() * 4, hipMemcpyDeviceToHost), "copy"))
@@ -687,7 +847,7 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
         const int32_t a = ids[t];
         if (a < 0) continue;
         counts[a] = cnt[t];
-        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[(size_t)k * Np + t]];
+        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[t * rowlen + k] & kIndexMask];
     }
     return MD_OK;
 }
@@ -697,7 +857,7 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
     if (!c) return MD_ERR_ARG;
     switch (option) {
     case MD_OPT_LANES_PER_ATOM:
-        if (value != 1 && value != 2 && value != 4 && value != 8) return fail(c, MD_ERR_ARG, "lanes per atom must be 1, 2, 4 or 8");
+        if (value != 0 && value != 1 && value != 2 && value != 4) return fail(c, MD_ERR_ARG, "lanes per atom must be 0 (automatic), 1, 2 or 4");
         c->lanes = (int32_t)value;
         return MD_OK;
     case MD_OPT_USE_GRAPH:
@@ -712,6 +872,31 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
         if (value == 0 && !c->table_ok) return fail(c, MD_ERR_ARG, "the knots share no tabulation grid");
         c->evaluator = (int32_t)value;
         return MD_OK;
+    case MD_OPT_KERNEL:
+        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "kernel path must be 0 (LDS bricks) or 1 (global gathers)");
+        if (value != c->kernel_path) {
+            c->kernel_path = (int32_t)value;
+            c->have_list = false;  // the two paths keep different list formats
+        }
+        return MD_OK;
+    case MD_OPT_BRICK_DIMS: {
+        const int64_t d0 = value % 10, d1 = (value / 10) % 10, d2 = (value / 100) % 10;
+        if (value != 0 && (value >= 1000 || d0 < 1 || d1 < 1 || d2 < 1 || d0 > kBrickMaxDim || d1 > kBrickMaxDim || d2 > kBrickMaxDim))
+            return fail(c, MD_ERR_ARG, "brick dims: 0 (automatic) or bx + 10 by + 100 bz with each in 1..4");
+        choose_bricks(c, (int32_t)value);
+        return upload_geometry(c) ? MD_OK : MD_ERR_DEVICE;
+    }
+    case MD_OPT_HALO_CAP:
+        // shrink the staging area (testing the global fallback, tuning occupancy)
+        if (value < 64 || value > c->halo_cap_max) return fail(c, MD_ERR_ARG, "halo capacity out of range");
+        c->halo_cap = (int32_t)value;
+        c->have_list = false;  // staging records are laid out by capacity
+        return MD_OK;
+    case MD_OPT_BRICK_BLOCK:
+        if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
+            return fail(c, MD_ERR_ARG, "brick workgroup size must be 64, 128, 256, 512 or 1024");
+        c->brick_block = (int32_t)value;
+        return MD_OK;
     default:
         return fail(c, MD_ERR_ARG, "unknown or read-only option");
     }
@@ -721,12 +906,17 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
 {
     if (!c || !value) return MD_ERR_ARG;
     switch (option) {
-    case MD_OPT_LANES_PER_ATOM: *value = c->lanes; return MD_OK;
+    case MD_OPT_LANES_PER_ATOM: *value = shape(c).lanes; return MD_OK;
     case MD_OPT_USE_GRAPH: *value = 0; return MD_OK;
     case MD_OPT_MAX_COUNT: *value = c->max_count; return MD_OK;
     case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
     case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;
     case MD_OPT_EVALUATOR: *value = (c->table_ok && c->evaluator == 0) ? 0 : 1; return MD_OK;
+    case MD_OPT_KERNEL: *value = shape(c).brick ? 0 : 1; return MD_OK;
+    case MD_OPT_BRICK_DIMS: *value = c->reps.empty() ? 0 : c->reps[0].bd[0] + 10 * c->reps[0].bd[1] + 100 * c->reps[0].bd[2]; return MD_OK;
+    case MD_OPT_BRICK_BLOCK: *value = c->brick_block; return MD_OK;
+    case MD_OPT_HALO_CAP: *value = c->halo_cap; return MD_OK;
+    case MD_OPT_HALO_OVERFLOWS: *value = c->halo_overflows; return MD_OK;
     default: return MD_ERR_ARG;
     }
 }

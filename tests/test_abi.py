@@ -64,7 +64,7 @@ def test_box_too_small(md):
 @pytest.mark.parametrize(
     "field,value,code",
     [("max_neighbours", 0, -1), ("rebuild_every", 0, -1), ("precision", 7, -1), ("nbr_mode", 3, -1),
-     ("lanes_per_atom", 3, -1), ("skin", -0.1, -1), ("dt_fs", 0.0, -1)],
+     ("lanes_per_atom", 3, -1), ("lanes_per_atom", 8, -1), ("skin", -0.1, -1), ("dt_fs", 0.0, -1)],
 )
 def test_config_validation(md, field, value, code):
     with pytest.raises(md.MDError) as e:

@@ -99,6 +99,45 @@ def test_explicit_knot_evaluator(md, orc, workload):
     _check_snapshot(md, orc, s, "mixed", options={md.MD_OPT_EVALUATOR: 1}, check_energy=False)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_global_gather_path(md, orc, precision):
+    """The one-thread-per-atom global-gather kernels (int32 list with periodic
+    shift codes) on single- and two-species systems."""
+    s = inputs.bcc_fe(8, temperature=600.0, seed=8, displace=0.07)
+    _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: 1})
+    s2 = inputs.fec_replicas(2, nmin=300, nmax=900, seed0=4400)
+    s2.pos = s2.pos + 0.04 * (2 * np.random.default_rng(7).random(s2.pos.shape) - 1)
+    _check_snapshot(md, orc, s2, precision, options={md.MD_OPT_KERNEL: 1})
+
+
+@pytest.mark.parametrize("dims", [111, 211, 222, 432, 444])
+def test_brick_shapes(md, orc, dims):
+    """Every brick shape stages the same neighbourhoods: parity for 1x1x1 up to
+    4x4x4 cells per brick (edge bricks partial: 9 cells per axis)."""
+    s = inputs.bcc_fe(12, temperature=600.0, seed=9, displace=0.07)
+    _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_BRICK_DIMS: dims})
+
+
+@pytest.mark.parametrize("lanes,block", [(1, 256), (2, 512), (4, 1024), (4, 128)])
+def test_brick_lanes_and_blocks(md, orc, lanes, block):
+    """Lanes sharing one atom's list and workgroup sizes: same results (two
+    species exercise the staged type bytes)."""
+    s = inputs.fec_replicas(2, nmin=600, nmax=1400, seed0=4500)
+    s.pos = s.pos + 0.04 * (2 * np.random.default_rng(11).random(s.pos.shape) - 1)
+    for prec in ("fp64", "mixed"):
+        _check_snapshot(md, orc, s, prec, options={md.MD_OPT_LANES_PER_ATOM: lanes, md.MD_OPT_BRICK_BLOCK: block})
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_brick_global_fallback(md, orc, precision):
+    """Bricks whose halo exceeds the LDS staging area read their neighbours
+    from global memory through the same halo order: identical results."""
+    s = inputs.fec_replicas(2, nmin=800, nmax=1500, seed0=4600)
+    s.pos = s.pos + 0.04 * (2 * np.random.default_rng(12).random(s.pos.shape) - 1)
+    sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_HALO_CAP: 64})
+    assert sim.get_option(md.MD_OPT_HALO_OVERFLOWS) > 0
+
+
 def test_free_axis_piston_snapshot(md, orc):
     s = inputs.fcc_piston(nx=4, ny=4, nz=8, piston_cells=2, steps=0)
     s.pos = s.pos + 0.03 * (2 * np.random.default_rng(3).random(s.pos.shape) - 1)
