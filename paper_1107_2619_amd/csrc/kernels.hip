@@ -257,8 +257,35 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
 // adjacent cells").  Full list: every j != i with r < r_c + skin.  Half list:
 // only j with a larger slot index.  Overflow keeps counting, so the required
 // capacity can be reported.
+// Compact record of a slot: cell-local coordinates in 2^-27 A units (the
+// mixed mode's gather image of the FP64 positions).  Returns false if a
+// coordinate is too far outside the link cell to encode.
+__device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[3], double x, double y, double z,
+                                               int4& out)
+{
+    const double xs[3] = {x, y, z};
+    int q[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double local = xs[a] - (R.origin[a] + c[a] * R.cell[a]);
+        ok = ok && fabs(local) < kCompactLimit;
+        q[a] = ok ? (int)rint(local * kInvQuantum) : 0;
+    }
+    out = make_int4(q[0], q[1], q[2], 0);
+    return ok;
+}
+
+// Step 6: the Verlet list from the 27 (or fewer, on boxes under three cells
+// per axis) adjacent link cells ("a nested loop over link-cells and their
+// adjacent cells").  Full list: every j != i with r < r_c + skin.  Half list:
+// only j with a larger slot index.  Entries: slot | code << kIndexBits, the
+// code being the periodic image shift (FP64 mode) or the unwrapped link-cell
+// offset (compact mixed mode), 2 bits per axis.  Transposed layout
+// nbr[k * Np + slot]: the k-th entries of a wavefront's atoms are contiguous.
+// Overflow keeps counting so the required capacity can be reported.
 __global__ void k_build_list(Buffers b, int p, int q, int64_t n_slots, int32_t cap, double rlist2,
-                             int half_list, int rowlen)
+                             int half_list, int compact)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -268,6 +295,12 @@ __global__ void k_build_list(Buffers b, int p, int q, int64_t n_slots, int32_t c
     const double3 xi = load_xyz(b.pos[p], t);
     int c[3];
     cell_coords(bx, xi.x, xi.y, xi.z, c);
+    b.cellxyz[t] = make_int4(c[0], c[1], c[2], 0);
+    if (compact) {
+        int4 rq;
+        if (!compact_coords(R, c, xi.x, xi.y, xi.z, rq) && valid) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
     int lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -281,8 +314,6 @@ __global__ void k_build_list(Buffers b, int p, int q, int64_t n_slots, int32_t c
         }
     }
     int count = 0;
-    int4* row = reinterpret_cast<int4*>(b.nbr + t * (int64_t)rowlen);
-    int pk[4] = {0, 0, 0, 0};  // entries buffered until a 16-byte store
     if (!valid) lo[2] = 1, hi[2] = 0;  // empty slot: no cells, count stays 0
     for (int dz = lo[2]; dz <= hi[2]; ++dz) {
         int cz = c[2] + dz;
@@ -298,44 +329,85 @@ __global__ void k_build_list(Buffers b, int p, int q, int64_t n_slots, int32_t c
                 if (cx >= bx.nc[0]) cx -= bx.nc[0];
                 const int cell = cell_index(R, cx, cy, cz);
                 const int beg = b.cell_start[cell], end = beg + b.cell_count[cell];
+                const int cj[3] = {cx, cy, cz};
 #pragma unroll 4
                 for (int j = beg; j < end; ++j) {
                     if (j == t || (half_list && j < t)) continue;
                     const double3 xj = load_xyz(b.pos[p], j);
                     double ddx = xj.x - xi.x, ddy = xj.y - xi.y, ddz = xj.z - xi.z;
-                    const int code = image_code(bx, ddx, ddy, ddz);
+                    int code = image_code(bx, ddx, ddy, ddz);
                     if (ddx * ddx + ddy * ddy + ddz * ddz < rlist2) {
-                        if (count < cap) {
-                            pk[count & 3] = j | (code << kIndexBits);
-                            if ((count & 3) == 3) row[count >> 2] = make_int4(pk[0], pk[1], pk[2], pk[3]);
+                        if (compact) {
+                            // unwrapped link-cell offset: c_j - c_i + (image shift) * nc
+                            int dc = 0;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const int s = (code >> (2 * a)) & 3;
+                                const int off = cj[a] - c[a] + (s == 1 ? bx.nc[a] : (s == 2 ? -bx.nc[a] : 0));
+                                dc |= (off + 1) << (2 * a);
+                            }
+                            code = dc;
                         }
+                        if (count < cap) b.nbr[(int64_t)count * n_slots + t] = j | (code << kIndexBits);
                         ++count;
                     }
                 }
             }
         }
     }
-    const int stored = count < cap ? count : cap;
-    if (stored & 3) row[stored >> 2] = make_int4(pk[0], pk[1], pk[2], pk[3]);
-    b.ncount[t] = stored;
+    b.ncount[t] = count < cap ? count : cap;
     wave_max_flag(count, &b.flags[F_MAX_COUNT]);
+}
+
+// Compact records of all slots from the FP64 positions (mixed mode, at the
+// start of a call when the list is kept).
+__global__ void k_compact_records(Buffers b, int p, int64_t n_slots)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const int4 c4 = b.cellxyz[t];
+    const int c[3] = {c4.x, c4.y, c4.z};
+    const double3 x = load_xyz(b.pos[p], t);
+    int4 rq;
+    if (!compact_coords(R, c, x.x, x.y, x.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+    b.rec[0][t] = rq;
+}
+
+// Pair separation from compact records: d = q_j 2^-27 - q_i 2^-27 + dc h.
+// The first two terms are multiples of 2^-27 below 16 A in magnitude, so
+// their difference is exact in FP64; only the cell offset adds a rounding.
+// `base` holds -q_i 2^-27 per axis.
+__device__ __forceinline__ void compact_delta(const DevReplica& R, const double3& base, const int4& qj, int code,
+                                              double& dx, double& dy, double& dz)
+{
+    dx = fma((double)((code & 3) - 1), R.cell[0], fma((double)qj.x, kQuantum, base.x));
+    dy = fma((double)(((code >> 2) & 3) - 1), R.cell[1], fma((double)qj.y, kQuantum, base.y));
+    dz = fma((double)(((code >> 4) & 3) - 1), R.cell[2], fma((double)qj.z, kQuantum, base.z));
+}
+
+__device__ __forceinline__ double3 compact_base(const int4& q)
+{
+    return make_double3(-(double)q.x * kQuantum, -(double)q.y * kQuantum, -(double)q.z * kQuantum);
 }
 
 // ---------------------------------------------------------------------------
 // Global-gather kernels: one thread per atom reads its neighbours straight
-// from HBM/L2 through the int32 list (slot index + periodic shift code).  They
-// serve the half-list variant and systems whose brick halo would not fit LDS.
+// from the cache hierarchy through the transposed int32 list.  Neighbours go
+// in chunks of kChunk: all index loads, then all gathers, then the
+// arithmetic.  Entries past the end point at the atom itself (masked).
+//
+// The cost of these loops is set by the number of vector-memory accesses per
+// neighbour (the L1 resolves about one cache-line access per clock per CU),
+// not by bytes or arithmetic: FP64 mode gathers a 32-byte {x, y, z, F'} record
+// (two accesses), the compact mixed mode a 16-byte record (one access).
 //
 // Density pass (Eq. Ucoh, the argument of F): rho_i = sum_j rho_{s_i s_j}(r_ij),
 // then F_i and F'_i.  The sum is accumulated in FP64 in both precision modes.
-// L lanes share an atom: lane l takes the 8-entry blocks l, l + L, ... of the
-// atom's list row, loads the 8 indices with two 16-byte loads and then issues
-// all 8 position gathers before using any of them, so one wavefront keeps 8
-// gathers per lane in flight (memory-level parallelism is what bounds this
-// loop: the arithmetic is a small fraction of the wait).
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, int L>
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool CMP>
 __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
-                                                     int energy, int rowlen)
+                                                     int energy)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const R* tab = tables<R>(b).dens;
@@ -345,32 +417,48 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
         __syncthreads();
         tab = s;
     }
-    const int64_t gid = global_thread();
-    const int64_t t = gid / L;
-    const int lane = (int)(gid % L);
-    if (t >= n_slots) return;  // whole wavefronts
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
     const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
-    const bool valid = t - Rp.slot_off < Rp.n_atoms;
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
     const Box bx = load_box(Rp);
     const DevPotential& G = *b.pot;
     const double4* __restrict__ pos = b.pos[p];
-    const double3 xi = load_xyz(pos, t);
+    const int4* __restrict__ rec = b.rec[0];
+    const int32_t* __restrict__ nbr = b.nbr;
+    const double3 xi = CMP ? make_double3(0.0, 0.0, 0.0) : load_xyz(pos, t);
+    const int4 qi = CMP ? rec[t] : make_int4(0, 0, 0, 0);
+    const double3 qb = compact_base(qi);
     const int si = b.type[q][t] & 0x3F;
-    const int n = valid ? b.ncount[t] : 0;
-    const int4* row = reinterpret_cast<const int4*>(b.nbr + t * (int64_t)rowlen);
+    const int n = b.ncount[t];
     double rho = 0.0;
-    for (int blk = lane; blk * 8 < n; blk += L) {
-        const int4 v0 = row[2 * blk], v1 = row[2 * blk + 1];
-        const int e[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        double3 xs[8];
+    for (int k0 = 0; k0 < n; k0 += kChunk) {
+        int e[kChunk];
+        double3 xs[kChunk];
+        int4 qs[kChunk];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xs[u] = load_xyz(pos, blk * 8 + u < n ? (e[u] & kIndexMask) : t);
+        for (int u = 0; u < kChunk; ++u) {
+            const int v = nbr[(int64_t)(k0 + u) * n_slots + t];  // rows past cap are padding
+            e[u] = k0 + u < n ? v : (int)t;
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (blk * 8 + u >= n) break;
-            double dx = xs[u].x - xi.x, dy = xs[u].y - xi.y, dz = xs[u].z - xi.z;
+        for (int u = 0; u < kChunk; ++u) {
+            if (CMP) qs[u] = rec[e[u] & kIndexMask];
+            else xs[u] = load_xyz(pos, e[u] & kIndexMask);
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (k0 + u >= n) break;
             const int code = (unsigned)e[u] >> kIndexBits;
-            if (code) apply_shift(bx, code, dx, dy, dz);
+            double dx, dy, dz;
+            if (CMP) {
+                compact_delta(Rp, qb, qs[u], code, dx, dy, dz);
+            } else {
+                dx = xs[u].x - xi.x;
+                dy = xs[u].y - xi.y;
+                dz = xs[u].z - xi.z;
+                if (code) apply_shift(bx, code, dx, dy, dz);
+            }
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (!(r2 < P.rc2)) continue;
             const double r = r2 * inv_dist<R>(r2);
@@ -378,19 +466,18 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
             rho += (double)density_term<R, SINGLE, NDK, EV>(P, G, tab, si, sj, r);
         }
     }
-    rho = lane_sum<L>(rho);
-    if (valid && lane == 0) {
-        double F, dF;
-        embed(SINGLE ? P.emb_c : G.emb_c[si], rho, F, dF);
-        reinterpret_cast<double*>(b.pos[p] + t)[3] = dF;
-        if (energy) b.femb[t] = F;
-    }
+    double F, dF;
+    embed(SINGLE ? P.emb_c : G.emb_c[si], rho, F, dF);
+    if (CMP) b.rec[1][t] = make_int4(qi.x, qi.y, qi.z, __float_as_int((float)dF));
+    else reinterpret_cast<double*>(b.pos[p] + t)[3] = dF;
+    if (energy) b.femb[t] = F;
 }
 
-// Force pass + velocity Verlet (global gathers, lanes as in k_density).
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK, int L>
+// Force pass + velocity Verlet (global gathers).
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
+          bool CMP>
 __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
-                                                   double dt, md_state st, int rowlen)
+                                                   double dt, md_state st)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tabs<R> T = tables<R>(b);
@@ -404,57 +491,74 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
         tf = s;
         te = s + P.nbt * kForceStride;
     }
-    const int64_t gid = global_thread();
-    const int64_t t = gid / L;
-    const int lane = (int)(gid % L);
-    if (t >= n_slots) return;  // whole wavefronts
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
     const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
-    const bool valid = t - Rp.slot_off < Rp.n_atoms;
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
     const Box bx = load_box(Rp);
     const DevPotential& G = *b.pot;
     const double4* __restrict__ pos = b.pos[p];
+    const int4* __restrict__ rec = b.rec[1];
+    const int32_t* __restrict__ nbr = b.nbr;
     const double4 pi = pos[t];
+    const int4 qi = CMP ? rec[t] : make_int4(0, 0, 0, 0);
+    const double3 qb = compact_base(qi);
     const uint8_t ti = b.type[q][t];
     const int si = ti & 0x3F;
     const bool rigid_i = ti & kRigidBit;
-    const int n = valid ? b.ncount[t] : 0;
-    const R fpi = (R)pi.w;
-    const int4* row = reinterpret_cast<const int4*>(b.nbr + t * (int64_t)rowlen);
+    const int n = b.ncount[t];
+    const R fpi = CMP ? (R)__int_as_float(qi.w) : (R)pi.w;
     PairAcc A;
-    for (int blk = lane; blk * 8 < n; blk += L) {
-        const int4 v0 = row[2 * blk], v1 = row[2 * blk + 1];
-        const int e[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        double4 ps[8];
+    for (int k0 = 0; k0 < n; k0 += kChunk) {
+        int e[kChunk];
+        double4 ps[kChunk];
+        int4 qs[kChunk];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ps[u] = pos[blk * 8 + u < n ? (e[u] & kIndexMask) : t];
+        for (int u = 0; u < kChunk; ++u) {
+            const int v = nbr[(int64_t)(k0 + u) * n_slots + t];  // rows past cap are padding
+            e[u] = k0 + u < n ? v : (int)t;
+        }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (blk * 8 + u >= n) break;
-            const double4 pj = ps[u];
-            double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        for (int u = 0; u < kChunk; ++u) {
+            if (CMP) qs[u] = rec[e[u] & kIndexMask];
+            else ps[u] = pos[e[u] & kIndexMask];
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            if (k0 + u >= n) break;
             const int code = (unsigned)e[u] >> kIndexBits;
-            if (code) apply_shift(bx, code, dx, dy, dz);
+            double dx, dy, dz;
+            R fpj;
+            if (CMP) {
+                compact_delta(Rp, qb, qs[u], code, dx, dy, dz);
+                fpj = (R)__int_as_float(qs[u].w);
+            } else {
+                dx = ps[u].x - pi.x;
+                dy = ps[u].y - pi.y;
+                dz = ps[u].z - pi.z;
+                if (code) apply_shift(bx, code, dx, dy, dz);
+                fpj = (R)ps[u].w;
+            }
             const double r2 = dx * dx + dy * dy + dz * dz;
             if (!(r2 < P.rc2)) continue;
             const double ri = inv_dist<R>(r2);
             const double r = r2 * ri;
             const uint8_t tj = (!SINGLE || ENERGY) ? b.type[q][e[u] & kIndexMask] : 0;
             R g, phi;
-            pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, (R)pj.w, g, phi);
+            pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, fpj, g, phi);
             accumulate<ENERGY>(A, (double)g * ri, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
         }
     }
-    if (L > 1) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) A.f[c] = lane_sum<L>(A.f[c]);
-        if (ENERGY) {
-            A.epair = lane_sum<L>(A.epair);
-#pragma unroll
-            for (int c = 0; c < 6; ++c) A.w[c] = lane_sum<L>(A.w[c]);
-        }
+    atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK>(b, p, q, t, n_slots, Rp, P, G, dt, st, pi, ti, A);
+    if (CMP && OPEN) {
+        // the compact record of the drifted position, for the next density pass
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        const double3 xn = load_xyz(b.pos[p ^ 1], t);
+        int4 rq;
+        if (!compact_coords(Rp, c, xn.x, xn.y, xn.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
     }
-    if (valid && lane == 0)
-        atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK>(b, p, q, t, n_slots, Rp, P, G, dt, st, pi, ti, A);
 }
 
 // Per-replica totals of the per-atom energy terms, in two stages with a fixed
@@ -558,7 +662,12 @@ void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, dou
                        hipStream_t s)
 {
     hipLaunchKernelGGL(k_build_list, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots,
-                       k.cap, rlist2, half_list, k.rowlen);
+                       k.cap, rlist2, half_list, k.compact);
+}
+
+void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact_records, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, k.n_slots);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>
@@ -566,21 +675,13 @@ static void density_variant(const Buffers& b, int p, int q, const KernelShape& k
                             hipStream_t s)
 {
     const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * 4 * sizeof(R) : 0;
-    const dim3 grid(blocks_for(k.n_slots * k.lanes));
-    if (k.lanes == 4)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 4>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy,
-                           k.rowlen);
-    else if (k.lanes == 2)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy,
-                           k.rowlen);
+    const dim3 grid(blocks_for(k.n_slots));
+    if (k.compact)
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
     else
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy,
-                           k.rowlen);
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, false>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
 }
 
-// Knot counts are compile-time so the explicit sums unroll: the 6-pair /
-// 2-density shape of every table used here, and a padded 8 / 8 fallback (zero
-// amplitudes contribute nothing).  The table evaluator does not depend on them.
 template <typename R, bool S>
 static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                              hipStream_t s)
@@ -609,16 +710,13 @@ static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, c
                          const md_state& st, hipStream_t s)
 {
     const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (E ? 4 : 0)) * sizeof(R) : 0;
-    const dim3 grid(blocks_for(k.n_slots * k.lanes));
-    if (k.lanes == 4)
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 4>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           dt_fs, st, k.rowlen);
-    else if (k.lanes == 2)
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           dt_fs, st, k.rowlen);
+    const dim3 grid(blocks_for(k.n_slots));
+    if (k.compact)
+        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
+                           P, dt_fs, st);
     else
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           dt_fs, st, k.rowlen);
+        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, false>), grid, dim3(kBlock), lds, s, b, p, q,
+                           k.n_slots, P, dt_fs, st);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>

@@ -530,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_brick_list_to_slots(Buffers b, int64_t
                 if (M.start[mid] <= i) lo = mid;
                 else hi = mid - 1;
             }
-            b.nbr[t * (int64_t)rowlen + k] = M.cstart[lo] + (i - M.start[lo]);
+            b.nbr[(int64_t)k * n_slots + t] = M.cstart[lo] + (i - M.start[lo]);
         }
     }
 }

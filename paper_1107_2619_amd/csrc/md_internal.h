@@ -36,6 +36,11 @@ constexpr int kIndexBits = 26;
 constexpr int kIndexMask = (1 << kIndexBits) - 1;
 constexpr int kChunk = 4;  // neighbours whose loads are issued together
 constexpr int kForceStride = 6;  // coefficients per bin of the force table (phi', rho' quadratics)
+// Compact gather record of the mixed mode: cell-local coordinates in units of
+// kQuantum (32-bit fixed point, |local| < 16 A) and F' as FP32, 16 bytes.
+constexpr double kQuantum = 1.0 / 134217728.0;  // 2^-27 A
+constexpr double kInvQuantum = 134217728.0;
+constexpr double kCompactLimit = 15.5;           // A, largest cell-local coordinate
 
 // Slot type byte: species in bits 0..5, rigid flag in bit 6; 0xFF = empty slot.
 constexpr uint8_t kRigidBit = 0x40;
@@ -58,7 +63,8 @@ struct DevReplica {
     int32_t bd[3], cpb;                                   // brick shape, cells per brick
     int32_t nbk[3], brick_off;                            // bricks per axis, first global brick
     double box[3], inv_box[3], origin[3];
-    double vp[3];  // rigid velocity, A/fs
+    double vp[3];    // rigid velocity, A/fs
+    double cell[3];  // link-cell edge per axis, box / nc
 };
 
 __host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)
@@ -102,8 +108,9 @@ struct PotArgs {
 // F_SKIN: atoms whose net displacement between builds exceeded skin/2;
 // F_OUTSIDE: atoms beyond the grid extent of a free axis (clamped; legal).
 // F_HALO: brick passes whose halo did not fit the LDS staging area (those
-// read their neighbours from global memory instead).
-enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COUNT = 4 };
+// read their neighbours from global memory instead).  F_COMPACT: atoms too far
+// outside their link cell for the compact mixed-mode record.
+enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_COUNT = 8 };
 
 // Pointers into the workspace.
 struct Buffers {
@@ -114,6 +121,8 @@ struct Buffers {
     double* pwork[2];     // [Np] piston work accumulated per rigid atom, eV
     int32_t* img[2][3];   // [Np] periodic image count per axis (caller x = x + img L)
     double4* xbuild;      // [Np] positions at the last list build
+    int4* rec[2];         // [Np] compact records (mixed): [0] coordinates, [1] coordinates + F'
+    int4* cellxyz;        // [Np] link cell (cx, cy, cz) of each slot at the last build
     double* femb;         // [Np] F_i (energy steps)
     int32_t* nbr;         // [cap][Np] transposed list (global slots + shift code)
     uint16_t* nbr16;      // [Np][rowlen] rows of staging (LDS) indices (brick path)
@@ -160,6 +169,7 @@ struct KernelShape {
     int32_t block;    // threads per brick workgroup
     int32_t lanes;    // lanes sharing one atom's neighbour list (brick path)
     int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
+    int32_t compact;  // 1 = mixed mode with compact records (global path)
 };
 
 // Launchers (kernels.hip).  All enqueue on `s`.
@@ -171,6 +181,7 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
                     int half_list, hipStream_t s);
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
                        hipStream_t s);
+void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
 struct ForceFlags {

@@ -16,6 +16,7 @@ using namespace mdk;
 struct md_ctx {
     // configuration (copied)
     int32_t R = 0, cap = 0, rebuild_every = 1, precision = MD_FP64, nbr_mode = MD_NBR_FULL, lanes = 1;
+    bool compact_ok = false;
     std::vector<int64_t> atom_off;
     std::vector<double> box, origin, vp;
     std::vector<uint8_t> periodic;
@@ -101,6 +102,7 @@ KernelShape shape(const md_ctx* c)
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
+    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok;
     return k;
 }
 
@@ -291,7 +293,7 @@ void plan_workspace(md_ctx* c)
         Np * 4, Np * 4, Np * 4, Np * 4, Np * 4, Np * 4,      // img[2][3]
         Np * 32,                                             // xbuild
         Np * 8,                                              // femb
-        Np * 4 * (size_t)((c->cap + 7) / 8 * 8),             // nbr rows (global path), rowlen entries each
+        Np * 4 * (size_t)(c->cap + kChunk),                  // nbr, transposed, kChunk padding rows
         Np * 4,                                              // ncount
         Np * 4,                                              // cell_of
         Np * 4,                                              // perm
@@ -316,6 +318,8 @@ void plan_workspace(md_ctx* c)
         std::max<size_t>(max_bricks, 1) * 16,                // brick_info
         stage_entries(c) * 4,                                // stage_src
         Np * 2,                                              // own_li
+        Np * 16, Np * 16,                                    // rec[2]
+        Np * 16,                                             // cellxyz
     };
     c->off.clear();
     size_t o = 0;
@@ -377,6 +381,9 @@ void bind_buffers(md_ctx* c)
     at(b.brick_info);
     at(b.stage_src);
     at(b.own_li);
+    at(b.rec[0]);
+    at(b.rec[1]);
+    at(b.cellxyz);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -456,6 +463,17 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
     c->have_list = true;
     c->built_at = c->step;
     ++c->n_builds;
+}
+
+// Caller state -> internal slots at the start of every call.  Compact records
+// (mixed mode, global path) follow the positions unless a list build, which
+// writes them, comes next.
+void load_state(md_ctx* c, hipStream_t s, bool build_next)
+{
+    const KernelShape k = shape(c);
+    ensure_slots(c, s);
+    launch_load_state(c->buf, c->p, c->q, c->st, k, s);
+    if (k.compact && c->have_list && !build_next) launch_compact_records(c->buf, c->p, k, s);
 }
 
 void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
@@ -611,6 +629,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     // ---- replicas, wavefront-aligned slot ranges, link-cell grids
     // (paper: link cells at least the potential range plus the padding rpad)
     int64_t slot = 0, cells_alloc = 0;
+    double cell_max = 0.0;
     c->reps.resize(c->R);
     for (int r = 0; r < c->R; ++r) {
         DevReplica& D = c->reps[r];
@@ -636,6 +655,8 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             int64_t nc = (int64_t)std::floor(L / c->rlist);
             nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
             D.nc[a] = (int32_t)nc;
+            D.cell[a] = L / (double)nc;
+            cell_max = std::max(cell_max, D.cell[a]);
             if (per) D.periodic_mask |= 1 << a;
             worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
         }
@@ -645,6 +666,9 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             return reject(MD_ERR_ARG, "system too large: at most 2^26 atom slots and 2^30 link cells");
     }
     c->Np = std::max<int64_t>(slot, kWave);
+    // compact records need every cell-local coordinate below kCompactLimit:
+    // cells up to 12 A leave 3.5 A of travel between list builds
+    c->compact_ok = cell_max <= kCompactLimit - 3.5;
     c->C_alloc = (int32_t)std::max<int64_t>(cells_alloc, 1);
     c->scan_nb = (c->C_alloc + 1023) / 1024;
     if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
@@ -740,8 +764,7 @@ int md_build_neighbours(md_ctx* c, void* stream)
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_build_neighbours: call md_bind first");
     hipStream_t s = as_stream(stream);
-    ensure_slots(c, s);
-    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+    load_state(c, s, true);
     rebuild(c, s, false);
     return check_launch(c);
 }
@@ -751,8 +774,7 @@ int md_eam_forces(md_ctx* c, int want_energy, void* stream)
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_eam_forces: call md_bind first");
     hipStream_t s = as_stream(stream);
-    ensure_slots(c, s);
-    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+    load_state(c, s, !c->have_list);
     if (!c->have_list) rebuild(c, s, false);
     forces(c, ForceFlags{want_energy ? 1 : 0, 0, 0, 1}, s);
     return check_launch(c);
@@ -764,9 +786,9 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_step: call md_bind first");
     if (nsteps < 1) return fail(c, MD_ERR_ARG, "md_step: nsteps must be >= 1");
     hipStream_t s = as_stream(stream);
-    ensure_slots(c, s);
-    launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
-    if (!c->have_list || due(c)) rebuild(c, s, true);
+    const bool build = !c->have_list || due(c);
+    load_state(c, s, build);
+    if (build) rebuild(c, s, true);
     forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
     for (int32_t k = 1; k <= nsteps; ++k) {
         ++c->step;
@@ -783,7 +805,7 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_energy: call md_bind first");
     hipStream_t s = as_stream(stream);
     std::vector<double> e((size_t)c->R * kEnergySlots, 0.0);
-    int32_t flags[F_COUNT] = {0, 0, 0, 0};
+    int32_t flags[F_COUNT] = {};
     if (!hip_ok(c, hipStreamSynchronize(s), "md_energy sync")) return MD_ERR_DEVICE;
     collect_times(c);
     if (!hip_ok(c, hipMemcpy(flags, c->buf.flags, sizeof flags, hipMemcpyDeviceToHost), "md_energy flags")) return MD_ERR_DEVICE;
@@ -821,6 +843,12 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
                       0.5 * c->skin);
         return fail(c, MD_ERR_SKIN, msg);
     }
+    if (flags[F_COMPACT] > 0) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved %.4g A or more outside their link cell between list builds",
+                      flags[F_COMPACT], kCompactLimit);
+        return fail(c, MD_ERR_SKIN, msg);
+    }
     for (int r = 0; r < c->R; ++r) {
         const double* v = e.data() + (size_t)r * kEnergySlots;
         if (v[E_NONFINITE] != 0.0 || !std::isfinite(v[E_PE]) || !std::isfinite(v[E_KE]))
@@ -837,8 +865,7 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
     if (shape(c).brick) launch_brick_list_to_slots(c->buf, shape(c), as_stream(stream));
     if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_copy_neighbours sync")) return MD_ERR_DEVICE;
     const size_t Np = (size_t)c->Np;
-    const size_t rowlen = (size_t)((c->cap + 7) / 8 * 8);
-    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * rowlen);
+    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * (size_t)c->cap);
     if (!hip_ok(c, hipMemcpy(cnt.data(), c->buf.ncount, Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(ids.data(), c->buf.id[c->q], Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(nb.data(), c->buf.nbr, nb.size() * 4, hipMemcpyDeviceToHost), "copy"))
@@ -847,7 +874,7 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
         const int32_t a = ids[t];
         if (a < 0) continue;
         counts[a] = cnt[t];
-        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[t * rowlen + k] & kIndexMask];
+        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[k * Np + t] & kIndexMask];
     }
     return MD_OK;
 }
