@@ -78,6 +78,27 @@ __global__ void k_load_state(Buffers b, int p, int q, md_state st, int64_t n_slo
     }
 }
 
+// counter[key] += 1 for every lane with key >= 0; returns the lane's old value
+// plus its rank among the lanes of its run.  Lanes with equal keys usually sit
+// side by side (the slots are cell-sorted from the previous build), so each
+// run of equal keys issues one atomic instead of one per lane.  Must be called
+// by every lane of the wavefront.
+__device__ __forceinline__ int wave_run_add(int32_t* counter, int key)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int prev = __shfl_up(key, 1, kWave);
+    const uint64_t heads = __ballot(lane == 0 || key != prev);
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+    const int head = 63 - __clzll(heads & upto);  // first lane of this run
+    const uint64_t later = heads & ~upto;
+    const int next = later ? __ffsll((unsigned long long)later) - 1 : kWave;
+    int base = 0;
+    if (lane == head && key >= 0) base = atomicAdd(&counter[key], next - lane);
+    base = __shfl(base, head, kWave);
+    return base + (lane - head);
+}
+
+
 // ---------------------------------------------------------------------------
 // List build, step 1: link cell of every atom, cell populations, and the skin
 // guard (net displacement since the previous build must stay below skin/2).
@@ -86,17 +107,15 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
     const int64_t t = global_thread();
     if (t >= n_slots) return;
     const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
-    if (b.id[q][t] < 0) {
-        b.cell_of[t] = -1;
-        return;
-    }
+    const bool valid = b.id[q][t] >= 0;
     const Box bx = load_box(R);
     const double3 x = load_xyz(b.pos[p], t);
     int c[3];
     cell_coords(bx, x.x, x.y, x.z, c);
-    const int cell = cell_index(R, c[0], c[1], c[2]);
+    const int cell = valid ? cell_index(R, c[0], c[1], c[2]) : -1;
     b.cell_of[t] = cell;
-    atomicAdd(&b.cell_count[cell], 1);
+    wave_run_add(b.cell_count, cell);
+    if (!valid) return;
     if (check_skin) {
         const double3 x0 = load_xyz(b.xbuild, t);
         const double dx = x.x - x0.x, dy = x.y - x0.y, dz = x.z - x0.z;
@@ -177,9 +196,8 @@ __global__ void k_scatter(Buffers b, int64_t n_slots)
     const int64_t t = global_thread();
     if (t >= n_slots) return;
     const int c = b.cell_of[t];
-    if (c < 0) return;
-    const int k = atomicAdd(&b.cell_cursor[c], 1);
-    b.perm[b.cell_start[c] + k] = (int32_t)t;
+    const int k = wave_run_add(b.cell_cursor, c);
+    if (c >= 0) b.perm[b.cell_start[c] + k] = (int32_t)t;
 }
 
 // Step 4: order each cell's members by caller index, making the slot order
@@ -252,11 +270,6 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
     }
 }
 
-// Step 6: the Verlet list from the 27 (or fewer, on boxes under three cells
-// per axis) adjacent link cells ("a nested loop over link-cells and their
-// adjacent cells").  Full list: every j != i with r < r_c + skin.  Half list:
-// only j with a larger slot index.  Overflow keeps counting, so the required
-// capacity can be reported.
 // Compact record of a slot: cell-local coordinates in 2^-27 A units (the
 // mixed mode's gather image of the FP64 positions).  Returns false if a
 // coordinate is too far outside the link cell to encode.
@@ -276,87 +289,168 @@ __device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[
     return ok;
 }
 
-// Step 6: the Verlet list from the 27 (or fewer, on boxes under three cells
-// per axis) adjacent link cells ("a nested loop over link-cells and their
-// adjacent cells").  Full list: every j != i with r < r_c + skin.  Half list:
-// only j with a larger slot index.  Entries: slot | code << kIndexBits, the
-// code being the periodic image shift (FP64 mode) or the unwrapped link-cell
-// offset (compact mixed mode), 2 bits per axis.  Transposed layout
-// nbr[k * Np + slot]: the k-th entries of a wavefront's atoms are contiguous.
-// Overflow keeps counting so the required capacity can be reported.
-__global__ void k_build_list(Buffers b, int p, int q, int64_t n_slots, int32_t cap, double rlist2,
-                             int half_list, int compact)
+// Verlet list from the link cells (paper, "The Neighbourlist calculation":
+// a loop over link cells and their adjacent cells).  One wavefront per link
+// cell.  The up to 27 adjacent cells (fewer on free faces; on a periodic axis
+// with under three cells each distinct cell once) become one candidate
+// sequence: cell by cell (x fastest), atoms in slot order.  The wavefront
+// holds 64 x kCandPasses candidates in registers, shifted by the periodic
+// image of their cell, and tests every atom of its own cell against them;
+// the in-range lanes of each test are packed with a ballot, so list entries
+// come out in candidate order.  Full list: every j != i with r < r_c + skin;
+// half list: only j with a larger slot index.
+//
+// Entries: slot | code << kIndexBits, 2 bits per axis.  FP64 mode: the
+// periodic image (0 none, 1 +L, 2 -L); compact mixed mode: the unwrapped
+// link-cell offset plus one.  Axes with one or two periodic cells have no
+// unique image per cell; there the image is the minimum one of each pair.
+// Transposed layout nbr[k * Np + slot].  Overflow keeps counting, so the
+// required capacity can be reported.
+constexpr int kCandPasses = 4;
+
+__device__ __forceinline__ double select_shift(int s, double L) { return s == 1 ? L : (s == 2 ? -L : 0.0); }
+
+__global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t n_slots, int32_t n_cells,
+                                                      int32_t cap, double rlist2, int half_list, int compact)
 {
-    const int64_t t = global_thread();
-    if (t >= n_slots) return;
-    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
-    const bool valid = t - R.slot_off < R.n_atoms;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cell = uniform((int)(logical_block() * (kBlock / kWave) + threadIdx.x / kWave));
+    if (cell >= n_cells) return;
+    const int r = uniform(b.cell_rep[cell]);
+    if (r < 0) return;
+    const int n_own = uniform(b.cell_count[cell]);
+    if (n_own == 0) return;
+    const int s_own = uniform(b.cell_start[cell]);
+    const DevReplica& R = b.reps[r];
     const Box bx = load_box(R);
-    const double3 xi = load_xyz(b.pos[p], t);
+    // coordinates of this cell from its brick-major index
     int c[3];
-    cell_coords(bx, xi.x, xi.y, xi.z, c);
-    b.cellxyz[t] = make_int4(c[0], c[1], c[2], 0);
-    if (compact) {
-        int4 rq;
-        if (!compact_coords(R, c, xi.x, xi.y, xi.z, rq) && valid) atomicAdd(&b.flags[F_COMPACT], 1);
-        b.rec[0][t] = rq;
+    {
+        const int local = cell - R.cell_off;
+        const int brick = local / R.cpb, in = local - brick * R.cpb;
+        c[0] = (brick % R.nbk[0]) * R.bd[0] + in % R.bd[0];
+        c[1] = ((brick / R.nbk[0]) % R.nbk[1]) * R.bd[1] + (in / R.bd[0]) % R.bd[1];
+        c[2] = (brick / (R.nbk[0] * R.nbk[1])) * R.bd[2] + in / (R.bd[0] * R.bd[1]);
     }
-    int lo[3], hi[3];
+    int amb = 0;  // periodic axes with fewer than three cells
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (bx.pmask & (1 << a)) {
-            // distinct neighbours only: {-1,0,1}, {0,1} or {0} cells
-            lo[a] = bx.nc[a] >= 3 ? -1 : 0;
-            hi[a] = bx.nc[a] >= 2 ? 1 : 0;
-        } else {
-            lo[a] = c[a] > 0 ? -1 : 0;
-            hi[a] = c[a] < bx.nc[a] - 1 ? 1 : 0;
-        }
-    }
-    int count = 0;
-    if (!valid) lo[2] = 1, hi[2] = 0;  // empty slot: no cells, count stays 0
-    for (int dz = lo[2]; dz <= hi[2]; ++dz) {
-        int cz = c[2] + dz;
-        if (cz < 0) cz += bx.nc[2];
-        if (cz >= bx.nc[2]) cz -= bx.nc[2];
-        for (int dy = lo[1]; dy <= hi[1]; ++dy) {
-            int cy = c[1] + dy;
-            if (cy < 0) cy += bx.nc[1];
-            if (cy >= bx.nc[1]) cy -= bx.nc[1];
-            for (int dx = lo[0]; dx <= hi[0]; ++dx) {
-                int cx = c[0] + dx;
-                if (cx < 0) cx += bx.nc[0];
-                if (cx >= bx.nc[0]) cx -= bx.nc[0];
-                const int cell = cell_index(R, cx, cy, cz);
-                const int beg = b.cell_start[cell], end = beg + b.cell_count[cell];
-                const int cj[3] = {cx, cy, cz};
-#pragma unroll 4
-                for (int j = beg; j < end; ++j) {
-                    if (j == t || (half_list && j < t)) continue;
-                    const double3 xj = load_xyz(b.pos[p], j);
-                    double ddx = xj.x - xi.x, ddy = xj.y - xi.y, ddz = xj.z - xi.z;
-                    int code = image_code(bx, ddx, ddy, ddz);
-                    if (ddx * ddx + ddy * ddy + ddz * ddz < rlist2) {
-                        if (compact) {
-                            // unwrapped link-cell offset: c_j - c_i + (image shift) * nc
-                            int dc = 0;
+    for (int a = 0; a < 3; ++a)
+        if ((bx.pmask >> a & 1) && bx.nc[a] < 3) amb |= 1 << a;
+
+    // lane k < 27: adjacent cell k, offset (k % 3 - 1, k / 3 % 3 - 1, k / 9 - 1)
+    int nb_start = 0, nb_count = 0, nb_wrap = 0, nb_code = 0;
+    if (lane < 27) {
+        const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+        int cc[3];
+        bool ok = true;
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                const int s = (code >> (2 * a)) & 3;
-                                const int off = cj[a] - c[a] + (s == 1 ? bx.nc[a] : (s == 2 ? -bx.nc[a] : 0));
-                                dc |= (off + 1) << (2 * a);
-                            }
-                            code = dc;
-                        }
-                        if (count < cap) b.nbr[(int64_t)count * n_slots + t] = j | (code << kIndexBits);
-                        ++count;
-                    }
-                }
+        for (int a = 0; a < 3; ++a) {
+            int v = c[a] + o[a];
+            int wrap = 0;
+            if (bx.pmask >> a & 1) {
+                if (bx.nc[a] == 1) ok = ok && o[a] == 0;
+                if (bx.nc[a] == 2) ok = ok && o[a] >= 0;
+                if (v < 0) v += bx.nc[a], wrap = 2;
+                if (v >= bx.nc[a]) v -= bx.nc[a], wrap = 1;
+            } else {
+                ok = ok && v >= 0 && v < bx.nc[a];
+            }
+            cc[a] = v;
+            if (amb >> a & 1) {
+                nb_code |= (compact ? v - c[a] + 1 : 0) << (2 * a);  // raw offset; the image comes per pair
+            } else {
+                nb_wrap |= wrap << (2 * a);
+                nb_code |= (compact ? o[a] + 1 : wrap) << (2 * a);
             }
         }
+        if (ok) {
+            const int nc = cell_index(R, cc[0], cc[1], cc[2]);
+            nb_start = b.cell_start[nc];
+            nb_count = b.cell_count[nc];
+        }
     }
-    b.ncount[t] = count < cap ? count : cap;
-    wave_max_flag(count, &b.flags[F_MAX_COUNT]);
+    // exclusive prefix of the candidate counts over the 27 lanes
+    int incl = nb_count;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int v = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += v;
+    }
+    const int excl = incl - nb_count;
+    const int total = uniform(__shfl(incl, kWave - 1, kWave));
+
+    const double4* __restrict__ pos = b.pos[p];
+    for (int i0 = 0; i0 < n_own; i0 += kWave) {
+        const int n_chunk = min(kWave, n_own - i0);
+        int my_count = 0;  // lane l: entries of atom s_own + i0 + l so far
+        for (int g0 = 0; g0 < total; g0 += kWave * kCandPasses) {
+            double cx[kCandPasses], cy[kCandPasses], cz[kCandPasses];
+            int ce[kCandPasses];
+#pragma unroll
+            for (int u = 0; u < kCandPasses; ++u) {
+                const int m = min(g0 + u * kWave + lane, total - 1);
+                // the adjacent cell holding candidate m: the last k with excl_k <= m
+                int k = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    if (__shfl(excl, k + step, kWave) <= m) k += step;
+                const int j = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
+                const int w = __shfl(nb_wrap, k, kWave);
+                const double3 xj = load_xyz(pos, j);
+                cx[u] = xj.x + select_shift(w & 3, bx.L[0]);
+                cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
+                cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
+                ce[u] = j | (__shfl(nb_code, k, kWave) << kIndexBits);
+            }
+            for (int ii = 0; ii < n_chunk; ++ii) {
+                const int i = s_own + i0 + ii;
+                const double3 xi = load_xyz(pos, i);
+                int base = __builtin_amdgcn_readlane(my_count, ii);
+#pragma unroll
+                for (int u = 0; u < kCandPasses; ++u) {
+                    const int m = g0 + u * kWave + lane;
+                    double dx = cx[u] - xi.x, dy = cy[u] - xi.y, dz = cz[u] - xi.z;
+                    int e = ce[u];
+                    if (amb) {  // minimum image per pair
+                        double* d[3] = {&dx, &dy, &dz};
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            if (!(amb >> a & 1)) continue;
+                            const double s = rint(*d[a] * bx.iL[a]);
+                            *d[a] -= s * bx.L[a];
+                            const int f = (e >> (kIndexBits + 2 * a)) & 3;
+                            const int nf = compact ? f - (int)s * bx.nc[a] : (s < 0.0 ? 1 : (s > 0.0 ? 2 : 0));
+                            e = (e & ~(3 << (kIndexBits + 2 * a))) | (nf << (kIndexBits + 2 * a));
+                        }
+                    }
+                    const int j = e & kIndexMask;
+                    const bool take = m < total && j != i && (!half_list || j > i) &&
+                                      dx * dx + dy * dy + dz * dz < rlist2;
+                    const uint64_t mask = __ballot(take);
+                    if (take) {
+                        const int idx = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+                        if (idx < cap) b.nbr[(int64_t)idx * n_slots + i] = e;
+                    }
+                    base += __popcll(mask);
+                }
+                if (lane == ii) my_count = base;
+            }
+        }
+        // per-atom epilogue: count, overflow flag, compact record
+        const int i = s_own + i0 + lane;
+        if (lane < n_chunk) {
+            b.ncount[i] = min(my_count, cap);
+            b.cellxyz[i] = make_int4(c[0], c[1], c[2], 0);
+            if (compact) {
+                const double3 xi = load_xyz(pos, i);
+                int4 rq;
+                if (!compact_coords(R, c, xi.x, xi.y, xi.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+                b.rec[0][i] = rq;
+            }
+        }
+        wave_max_flag(lane < n_chunk ? my_count : 0, &b.flags[F_MAX_COUNT]);
+    }
 }
 
 // Compact records of all slots from the FP64 positions (mixed mode, at the
@@ -661,8 +755,10 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_build_list, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots,
-                       k.cap, rlist2, half_list, k.compact);
+    (void)q;
+    const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
+    hipLaunchKernelGGL(k_cell_list, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap, rlist2,
+                       half_list, k.compact);
 }
 
 void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s)

@@ -270,7 +270,8 @@ __global__ __launch_bounds__(1024) void k_brick_list(Buffers b, int p, int64_t n
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && most > 0) atomicMax(&b.flags[F_MAX_COUNT], most);
+    if ((threadIdx.x & (kWave - 1)) == 0 && most > 0 && most > b.flags[F_MAX_COUNT])
+        atomicMax(&b.flags[F_MAX_COUNT], most);
 }
 
 // LDS layout of the density / force kernels: Halo | staged atoms | tables.

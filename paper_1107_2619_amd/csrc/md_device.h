@@ -230,7 +230,10 @@ __device__ __forceinline__ void wave_max_flag(int v, int32_t* flag)
 {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && v > 0) atomicMax(flag, v);
+    // The flag only grows, so a plain (possibly stale) read filters out the
+    // atomics that cannot raise it: a kernel with many wavefronts would
+    // otherwise serialise on one address.
+    if ((threadIdx.x & (kWave - 1)) == 0 && v > 0 && v > *flag) atomicMax(flag, v);
 }
 
 // ---------------------------------------------------------------------------

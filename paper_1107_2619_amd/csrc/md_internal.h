@@ -138,6 +138,7 @@ struct Buffers {
     int32_t* cell_count;  // [C]
     int32_t* cell_cursor; // [C]
     int32_t* cell_shift;  // [C] slot_off - atom_off of the cell's replica
+    int32_t* cell_rep;    // [C] replica of each link cell (-1: unused)
     int32_t* scan_blocks; // [scan blocks]
     int32_t* rep_of_wave; // [Np / 64]
     DevReplica* reps;     // [R]

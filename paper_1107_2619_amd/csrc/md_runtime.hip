@@ -43,7 +43,7 @@ struct md_ctx {
     int64_t halo_overflows = 0;  // bricks evaluated from global memory (last md_energy)
     std::vector<int32_t> brick_rep;
     std::vector<DevReplica> reps;
-    std::vector<int32_t> rep_of_wave, cell_shift, chunk_rep, chunk_off;
+    std::vector<int32_t> rep_of_wave, cell_shift, cell_rep, chunk_rep, chunk_off;
     size_t ws_bytes = 0;
     std::vector<size_t> off;  // workspace offsets, in Buffers field order
     // binding and run state
@@ -183,10 +183,14 @@ void choose_bricks(md_ctx* c, int32_t dims)
     c->halo_cap = (int32_t)std::max<int64_t>(64, std::min<int64_t>(cap, c->halo_cap_max));
     c->C = (int32_t)std::max<int64_t>(cells, 1);
     c->cell_shift.assign(c->C_alloc, 0);
+    c->cell_rep.assign(c->C_alloc, -1);
     for (int r = 0; r < c->R; ++r) {
         const DevReplica& D = c->reps[r];
         const int64_t nc = (int64_t)D.nbk[0] * D.nbk[1] * D.nbk[2] * D.cpb;
-        for (int64_t k = 0; k < nc; ++k) c->cell_shift[D.cell_off + k] = D.slot_off - D.atom_off;
+        for (int64_t k = 0; k < nc; ++k) {
+            c->cell_shift[D.cell_off + k] = D.slot_off - D.atom_off;
+            c->cell_rep[D.cell_off + k] = r;
+        }
     }
     c->brick_dims = dims;
 }
@@ -199,6 +203,7 @@ bool upload_geometry(md_ctx* c)
     c->have_list = false;
     return hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "upload") &&
            hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "upload") &&
+           hip_ok(c, hipMemcpy(c->buf.cell_rep, c->cell_rep.data(), c->cell_rep.size() * 4, hipMemcpyHostToDevice), "upload") &&
            (c->brick_rep.empty() ||
             hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "upload"));
 }
@@ -320,6 +325,7 @@ void plan_workspace(md_ctx* c)
         Np * 2,                                              // own_li
         Np * 16, Np * 16,                                    // rec[2]
         Np * 16,                                             // cellxyz
+        C * 4,                                               // cell_rep (C_alloc)
     };
     c->off.clear();
     size_t o = 0;
@@ -384,6 +390,7 @@ void bind_buffers(md_ctx* c)
     at(b.rec[0]);
     at(b.rec[1]);
     at(b.cellxyz);
+    at(b.cell_rep);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -722,6 +729,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         !hip_ok(c, hipMemcpy(c->buf.pot, &c->pot, sizeof(DevPotential), hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.rep_of_wave, c->rep_of_wave.data(), c->rep_of_wave.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
+        !hip_ok(c, hipMemcpy(c->buf.cell_rep, c->cell_rep.data(), c->cell_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
         (!c->brick_rep.empty() &&
          !hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
         !hip_ok(c, hipMemcpy(c->buf.chunk_off, c->chunk_off.data(), c->chunk_off.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
