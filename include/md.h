@@ -190,8 +190,9 @@ enum {
     MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default when all
                                   knots lie on a common grid), 1 = term-by-term knot
                                   sums (the paper's explicit evaluation)             */
-    MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (default, full list),
-                                  1 = one thread per atom with global gathers        */
+    MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (full list only),
+                                  1 = one thread per atom with global gathers
+                                      (default)                                      */
     MD_OPT_BRICK_DIMS = 8,     /* 0 = automatic, else bx + 10 by + 100 bz cells (1..4) */
     MD_OPT_BRICK_BLOCK = 9,    /* threads per brick workgroup: 64..1024             */
     MD_OPT_HALO_CAP = 10,      /* atoms one brick's LDS staging area holds (set

@@ -306,9 +306,120 @@ __device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[
 // unique image per cell; there the image is the minimum one of each pair.
 // Transposed layout nbr[k * Np + slot].  Overflow keeps counting, so the
 // required capacity can be reported.
+// Adjacency of every link cell, once per geometry: entry k of cell c is the
+// cell at offset (k % 3 - 1, k / 3 % 3 - 1, k / 9 - 1), or -1 where a free
+// face ends the grid or a periodic axis of under three cells would list a
+// cell twice.  .y: periodic image of that cell (2 bits per axis, 1 = +L,
+// 2 = -L) and, from bit 8, its unwrapped offset plus one.  On periodic axes
+// with under three cells the image is left to the pair (minimum image) and
+// the offset is the plain one between the two cells.
+__global__ void k_cell_table(Buffers b, int32_t n_cells)
+{
+    const int64_t t = global_thread();
+    if (t >= (int64_t)n_cells * 27) return;
+    const int cell = (int)(t / 27), k = (int)(t - (int64_t)cell * 27);
+    const int r = b.cell_rep[cell];
+    if (r < 0) {
+        b.cell_adj[t] = make_int2(-1, 0);
+        if (k == 13) b.cell_coord[cell] = 0;
+        return;
+    }
+    const DevReplica& R = b.reps[r];
+    const int local = cell - R.cell_off;
+    const int brick = local / R.cpb, in = local - brick * R.cpb;
+    const int c[3] = {(brick % R.nbk[0]) * R.bd[0] + in % R.bd[0],
+                      ((brick / R.nbk[0]) % R.nbk[1]) * R.bd[1] + (in / R.bd[0]) % R.bd[1],
+                      (brick / (R.nbk[0] * R.nbk[1])) * R.bd[2] + in / (R.bd[0] * R.bd[1])};
+    const int o[3] = {k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1};
+    bool ok = true;
+    int cc[3], wrap = 0, code = 0;
+    for (int a = 0; a < 3; ++a) {
+        int v = c[a] + o[a], w = 0;
+        ok = ok && c[a] < R.nc[a];  // padding cells of the brick grid have no atoms
+        if (R.periodic_mask >> a & 1) {
+            if (R.nc[a] == 1) ok = ok && o[a] == 0;
+            if (R.nc[a] == 2) ok = ok && o[a] >= 0;
+            if (v < 0) v += R.nc[a], w = 2;
+            if (v >= R.nc[a]) v -= R.nc[a], w = 1;
+        } else {
+            ok = ok && v >= 0 && v < R.nc[a];
+        }
+        cc[a] = v;
+        const bool few = (R.periodic_mask >> a & 1) && R.nc[a] < 3;
+        wrap |= (few ? 0 : w) << (2 * a);
+        code |= (few ? v - c[a] + 1 : o[a] + 1) << (2 * a);
+    }
+    b.cell_adj[t] = make_int2(ok ? cell_index(R, cc[0], cc[1], cc[2]) : -1, wrap | (code << 8));
+    if (k == 13) b.cell_coord[cell] = c[0] | (c[1] << 10) | (c[2] << 20);
+}
+
 constexpr int kCandPasses = 4;
 
 __device__ __forceinline__ double select_shift(int s, double L) { return s == 1 ? L : (s == 2 ? -L : 0.0); }
+
+// Value of lane `l` (wave-uniform) of a double.
+__device__ __forceinline__ double bcast_lane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Minimum image of one pair along the axes in `amb` (periodic axes with fewer
+// than three cells), with the entry's code field updated: the image shift in
+// FP64 mode, the unwrapped link-cell offset plus one in compact mode.
+__device__ __forceinline__ void min_image_axis(double& d, double L, double iL, int nc, int a, int compact, int& e)
+{
+    const double s = rint(d * iL);
+    d -= s * L;
+    const int sh = kIndexBits + 2 * a;
+    const int f = (e >> sh) & 3;
+    const int nf = compact ? f - (int)s * nc : (s < 0.0 ? 1 : (s > 0.0 ? 2 : 0));
+    e = (e & ~(3 << sh)) | (nf << sh);
+}
+
+__device__ __forceinline__ void min_image_pair(const Box& bx, int amb, int compact, double& dx, double& dy, double& dz,
+                                               int& e)
+{
+    if (amb & 1) min_image_axis(dx, bx.L[0], bx.iL[0], bx.nc[0], 0, compact, e);
+    if (amb & 2) min_image_axis(dy, bx.L[1], bx.iL[1], bx.nc[1], 1, compact, e);
+    if (amb & 4) min_image_axis(dz, bx.L[2], bx.iL[2], bx.nc[2], 2, compact, e);
+}
+
+// Tests atoms s0 .. s0 + n - 1 (lane l holds atom s0 + l in xl) against the
+// candidates in registers and appends the in-range ones to their rows.
+template <int P, bool AMB>
+__device__ __forceinline__ void test_candidates(int32_t* __restrict__ nbr, int64_t n_slots, int32_t cap, double rlist2,
+                                                int half_list, int compact, const Box& bx, int amb, int s0, int n,
+                                                const double3& xl, const double (&cx)[P], const double (&cy)[P],
+                                                const double (&cz)[P], const int (&ce)[P], const int (&cj)[P],
+                                                const bool (&live)[P], int& my_count)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int ii = 0; ii < n; ++ii) {
+        const int i = s0 + ii;
+        const double xi = bcast_lane(xl.x, ii), yi = bcast_lane(xl.y, ii), zi = bcast_lane(xl.z, ii);
+        int base = __builtin_amdgcn_readlane(my_count, ii);
+#pragma unroll
+        for (int u = 0; u < P; ++u) {
+            double dx = cx[u] - xi, dy = cy[u] - yi, dz = cz[u] - zi;
+            int e = ce[u];
+            if (AMB) min_image_pair(bx, amb, compact, dx, dy, dz, e);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            bool take = live[u] & (cj[u] != i) & (r2 < rlist2);
+            if (half_list) take = take & (cj[u] > i);
+            const uint64_t mask = __ballot(take);
+            if (mask == 0) continue;
+            const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+            // row `base` of atom i, then `rank` rows further
+            int32_t* row = nbr + ((int64_t)base * n_slots + i);
+            if (take && base + rank < cap) row[(uint32_t)rank * (uint32_t)n_slots] = e;
+            base += __popcll(mask);
+        }
+        if (lane == ii) my_count = base;
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t n_slots, int32_t n_cells,
                                                       int32_t cap, double rlist2, int half_list, int compact)
@@ -323,50 +434,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
     const int s_own = uniform(b.cell_start[cell]);
     const DevReplica& R = b.reps[r];
     const Box bx = load_box(R);
-    // coordinates of this cell from its brick-major index
-    int c[3];
-    {
-        const int local = cell - R.cell_off;
-        const int brick = local / R.cpb, in = local - brick * R.cpb;
-        c[0] = (brick % R.nbk[0]) * R.bd[0] + in % R.bd[0];
-        c[1] = ((brick / R.nbk[0]) % R.nbk[1]) * R.bd[1] + (in / R.bd[0]) % R.bd[1];
-        c[2] = (brick / (R.nbk[0] * R.nbk[1])) * R.bd[2] + in / (R.bd[0] * R.bd[1]);
-    }
+    const int cpk = uniform(b.cell_coord[cell]);
+    int c[3] = {cpk & 1023, (cpk >> 10) & 1023, cpk >> 20};
     int amb = 0;  // periodic axes with fewer than three cells
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         if ((bx.pmask >> a & 1) && bx.nc[a] < 3) amb |= 1 << a;
 
-    // lane k < 27: adjacent cell k, offset (k % 3 - 1, k / 3 % 3 - 1, k / 9 - 1)
+    // lane k < 27: adjacent cell k
     int nb_start = 0, nb_count = 0, nb_wrap = 0, nb_code = 0;
     if (lane < 27) {
-        const int o[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
-        int cc[3];
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int v = c[a] + o[a];
-            int wrap = 0;
-            if (bx.pmask >> a & 1) {
-                if (bx.nc[a] == 1) ok = ok && o[a] == 0;
-                if (bx.nc[a] == 2) ok = ok && o[a] >= 0;
-                if (v < 0) v += bx.nc[a], wrap = 2;
-                if (v >= bx.nc[a]) v -= bx.nc[a], wrap = 1;
-            } else {
-                ok = ok && v >= 0 && v < bx.nc[a];
-            }
-            cc[a] = v;
-            if (amb >> a & 1) {
-                nb_code |= (compact ? v - c[a] + 1 : 0) << (2 * a);  // raw offset; the image comes per pair
-            } else {
-                nb_wrap |= wrap << (2 * a);
-                nb_code |= (compact ? o[a] + 1 : wrap) << (2 * a);
-            }
-        }
-        if (ok) {
-            const int nc = cell_index(R, cc[0], cc[1], cc[2]);
-            nb_start = b.cell_start[nc];
-            nb_count = b.cell_count[nc];
+        const int2 adj = b.cell_adj[(int64_t)cell * 27 + lane];
+        nb_wrap = adj.y & 63;
+        nb_code = compact ? (adj.y >> 8) & 63 : nb_wrap;
+        if (adj.x >= 0) {
+            nb_start = b.cell_start[adj.x];
+            nb_count = b.cell_count[adj.x];
         }
     }
     // exclusive prefix of the candidate counts over the 27 lanes
@@ -382,13 +465,17 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
     const double4* __restrict__ pos = b.pos[p];
     for (int i0 = 0; i0 < n_own; i0 += kWave) {
         const int n_chunk = min(kWave, n_own - i0);
-        int my_count = 0;  // lane l: entries of atom s_own + i0 + l so far
+        // lane l holds atom s_own + i0 + l; the test loop broadcasts it
+        const double3 xl = load_xyz(pos, s_own + i0 + min(lane, n_chunk - 1));
+        int my_count = 0;  // lane l: entries of that atom so far
         for (int g0 = 0; g0 < total; g0 += kWave * kCandPasses) {
             double cx[kCandPasses], cy[kCandPasses], cz[kCandPasses];
-            int ce[kCandPasses];
+            int ce[kCandPasses], cj[kCandPasses];
+            bool live[kCandPasses];
 #pragma unroll
             for (int u = 0; u < kCandPasses; ++u) {
-                const int m = min(g0 + u * kWave + lane, total - 1);
+                const int m0 = g0 + u * kWave + lane;
+                const int m = min(m0, total - 1);
                 // the adjacent cell holding candidate m: the last k with excl_k <= m
                 int k = 0;
 #pragma unroll
@@ -401,41 +488,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                 cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
                 cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
                 ce[u] = j | (__shfl(nb_code, k, kWave) << kIndexBits);
+                cj[u] = j;
+                live[u] = m0 < total;
             }
-            for (int ii = 0; ii < n_chunk; ++ii) {
-                const int i = s_own + i0 + ii;
-                const double3 xi = load_xyz(pos, i);
-                int base = __builtin_amdgcn_readlane(my_count, ii);
-#pragma unroll
-                for (int u = 0; u < kCandPasses; ++u) {
-                    const int m = g0 + u * kWave + lane;
-                    double dx = cx[u] - xi.x, dy = cy[u] - xi.y, dz = cz[u] - xi.z;
-                    int e = ce[u];
-                    if (amb) {  // minimum image per pair
-                        double* d[3] = {&dx, &dy, &dz};
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            if (!(amb >> a & 1)) continue;
-                            const double s = rint(*d[a] * bx.iL[a]);
-                            *d[a] -= s * bx.L[a];
-                            const int f = (e >> (kIndexBits + 2 * a)) & 3;
-                            const int nf = compact ? f - (int)s * bx.nc[a] : (s < 0.0 ? 1 : (s > 0.0 ? 2 : 0));
-                            e = (e & ~(3 << (kIndexBits + 2 * a))) | (nf << (kIndexBits + 2 * a));
-                        }
-                    }
-                    const int j = e & kIndexMask;
-                    const bool take = m < total && j != i && (!half_list || j > i) &&
-                                      dx * dx + dy * dy + dz * dz < rlist2;
-                    const uint64_t mask = __ballot(take);
-                    if (take) {
-                        const int idx = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-                        if (idx < cap) b.nbr[(int64_t)idx * n_slots + i] = e;
-                    }
-                    base += __popcll(mask);
-                }
-                if (lane == ii) my_count = base;
-            }
+            if (amb)
+                test_candidates<kCandPasses, true>(b.nbr, n_slots, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                                                   n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
+            else
+                test_candidates<kCandPasses, false>(b.nbr, n_slots, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                                                    n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
         }
         // per-atom epilogue: count, overflow flag, compact record
         const int i = s_own + i0 + lane;
@@ -443,9 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
             b.ncount[i] = min(my_count, cap);
             b.cellxyz[i] = make_int4(c[0], c[1], c[2], 0);
             if (compact) {
-                const double3 xi = load_xyz(pos, i);
                 int4 rq;
-                if (!compact_coords(R, c, xi.x, xi.y, xi.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+                if (!compact_coords(R, c, xl.x, xl.y, xl.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
                 b.rec[0][i] = rq;
             }
         }
@@ -711,6 +771,156 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double vi
     }
 }
 
+// ---------------------------------------------------------------------------
+// Half-list variant (MD_NBR_HALF_ATOMIC): the comparison form in which every
+// unordered pair is evaluated once, by its lower slot, and the partner's share
+// goes to memory with FP64 atomics; the paper's own OpenMP code resolves the
+// same write conflict with link-cell locks (section "OpenMP Parallelisation").
+// Density: rho_i and rho_j both receive their term; the embedding then runs as
+// its own pass.  Forces: f_i += s d, f_j -= s d; pair energies split in halves;
+// the virial counts every pair once.  Integration follows as a separate pass.
+
+// Density pass, half list: accumulates into rhalf (zeroed beforehand).
+template <typename R, bool SINGLE, int NPK, int NDK, int EV>
+__global__ __launch_bounds__(kBlock) void k_density_half(Buffers b, int p, int q, int64_t n_slots, PotArgs P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const R* tab = tables<R>(b).dens;
+    if (EV == EV_TABLE && SINGLE) {
+        R* s = reinterpret_cast<R*>(smem);
+        lds_fill(s, tab, P.nbt * 4);
+        __syncthreads();
+        tab = s;
+    }
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
+    const Box bx = load_box(Rp);
+    const DevPotential& G = *b.pot;
+    const double4* __restrict__ pos = b.pos[p];
+    const int32_t* __restrict__ nbr = b.nbr;
+    const double3 xi = load_xyz(pos, t);
+    const int si = b.type[q][t] & 0x3F;
+    const int n = b.ncount[t];
+    double rho = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int e = nbr[(int64_t)k * n_slots + t];
+        const int j = e & kIndexMask;
+        const double3 xj = load_xyz(pos, j);
+        double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+        const int code = (unsigned)e >> kIndexBits;
+        if (code) apply_shift(bx, code, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < P.rc2)) continue;
+        const double r = r2 * inv_dist<R>(r2);
+        const int sj = SINGLE ? 0 : (b.type[q][j] & 0x3F);
+        const R to_i = density_term<R, SINGLE, NDK, EV>(P, G, tab, si, sj, r);
+        const R to_j = SINGLE ? to_i : density_term<R, SINGLE, NDK, EV>(P, G, tab, sj, si, r);
+        rho += (double)to_i;
+        atomicAdd(&b.rhalf[j], (double)to_j);
+    }
+    atomicAdd(&b.rhalf[t], rho);
+}
+
+// Embedding after the half-list density pass: F_i, F'_i from rho_i.
+template <bool SINGLE>
+__global__ void k_embed_half(Buffers b, int p, int q, int64_t n_slots, PotArgs P, int energy)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const int si = b.type[q][t] & 0x3F;
+    double F, dF;
+    embed(SINGLE ? P.emb_c : G.emb_c[si], b.rhalf[t], F, dF);
+    reinterpret_cast<double*>(b.pos[p] + t)[3] = dF;
+    if (energy) b.femb[t] = F;
+}
+
+// Force pass, half list: forces and pair energies into fhalf / ehalf (zeroed
+// beforehand); the virial of the pairs an atom owns into its energy slots.
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_force_half(Buffers b, int p, int q, int64_t n_slots, PotArgs P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Tabs<R> T = tables<R>(b);
+    const R* tf = T.force;
+    const R* te = T.energy;
+    if (EV == EV_TABLE && SINGLE) {
+        R* s = reinterpret_cast<R*>(smem);
+        lds_fill(s, tf, P.nbt * kForceStride);
+        if (ENERGY) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        __syncthreads();
+        tf = s;
+        te = s + P.nbt * kForceStride;
+    }
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
+    const Box bx = load_box(Rp);
+    const DevPotential& G = *b.pot;
+    const double4* __restrict__ pos = b.pos[p];
+    const int32_t* __restrict__ nbr = b.nbr;
+    const double4 pi = pos[t];
+    const uint8_t ti = b.type[q][t];
+    const int si = ti & 0x3F;
+    const bool rigid_i = ti & kRigidBit;
+    const int n = b.ncount[t];
+    PairAcc A;
+    for (int k = 0; k < n; ++k) {
+        const int e = nbr[(int64_t)k * n_slots + t];
+        const int j = e & kIndexMask;
+        const double4 pj = pos[j];
+        double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+        const int code = (unsigned)e >> kIndexBits;
+        if (code) apply_shift(bx, code, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < P.rc2)) continue;
+        const double ri = inv_dist<R>(r2);
+        const double r = r2 * ri;
+        const uint8_t tj = (!SINGLE || ENERGY) ? b.type[q][j] : 0;
+        R g, phi;
+        pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, (R)pi.w, (R)pj.w, g, phi);
+        const double s = (double)g * ri;
+        accumulate<ENERGY>(A, s, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
+        atomicAdd(&b.fhalf[0][j], -s * dx);
+        atomicAdd(&b.fhalf[1][j], -s * dy);
+        atomicAdd(&b.fhalf[2][j], -s * dz);
+        if (ENERGY) atomicAdd(&b.ehalf[j], 0.5 * (double)phi);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) atomicAdd(&b.fhalf[a][t], A.f[a]);
+    if (ENERGY) {
+        atomicAdd(&b.ehalf[t], 0.5 * A.epair);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
+    }
+}
+
+// Velocity Verlet and energy terms after the half-list force pass.
+template <bool SINGLE, bool ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK>
+__global__ void k_integrate_half(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double dt, md_state st)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - Rp.slot_off >= Rp.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    PairAcc A;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) A.f[a] = b.fhalf[a][t];
+    if (ENERGY) {
+        A.epair = 2.0 * b.ehalf[t];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) A.w[k] = b.eslot[(int64_t)(E_W0 + k) * n_slots + t];
+    }
+    atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK>(b, p, q, t, n_slots, Rp, P, G, dt, st, b.pos[p][t],
+                                                         b.type[q][t], A);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -761,6 +971,11 @@ void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, dou
                        half_list, k.compact);
 }
 
+void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cell_table, dim3(blocks_for((int64_t)k.n_cells * 27)), dim3(kBlock), 0, s, b, k.n_cells);
+}
+
 void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s)
 {
     hipLaunchKernelGGL(k_compact_records, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, k.n_slots);
@@ -778,10 +993,27 @@ static void density_variant(const Buffers& b, int p, int q, const KernelShape& k
         hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, false>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
 }
 
-template <typename R, bool S>
-static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
-                             hipStream_t s)
+template <typename R, bool S, int NP, int ND, int EV>
+static void density_half_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
+                                 hipStream_t s)
 {
+    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * 4 * sizeof(R) : 0;
+    const dim3 grid(blocks_for(k.n_slots));
+    hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.rhalf, 0.0, k.n_slots);
+    hipLaunchKernelGGL((k_density_half<R, S, NP, ND, EV>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
+    hipLaunchKernelGGL((k_embed_half<S>), grid, dim3(kBlock), 0, s, b, p, q, k.n_slots, P, energy);
+}
+
+template <typename R, bool S>
+static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int half_list,
+                             int energy, hipStream_t s)
+{
+    if (half_list) {
+        if (k.table) density_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
+        else if (k.npk == 6 && k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
+        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+        return;
+    }
     if (k.table) density_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
     else if (k.npk == 6 && k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
     else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
@@ -790,14 +1022,13 @@ static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& 
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s)
 {
-    (void)half_list;
     const bool one = P.ns == 1;
     if (precision == MD_MIXED) {
-        if (one) density_dispatch<float, true>(b, p, q, k, P, energy, s);
-        else density_dispatch<float, false>(b, p, q, k, P, energy, s);
+        if (one) density_dispatch<float, true>(b, p, q, k, P, half_list, energy, s);
+        else density_dispatch<float, false>(b, p, q, k, P, half_list, energy, s);
     } else {
-        if (one) density_dispatch<double, true>(b, p, q, k, P, energy, s);
-        else density_dispatch<double, false>(b, p, q, k, P, energy, s);
+        if (one) density_dispatch<double, true>(b, p, q, k, P, half_list, energy, s);
+        else density_dispatch<double, false>(b, p, q, k, P, half_list, energy, s);
     }
 }
 
@@ -831,10 +1062,48 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
     }
 }
 
-template <typename R, bool S>
-static void force_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, ForceFlags fl,
-                           double dt_fs, const md_state& st, hipStream_t s)
+template <bool S, bool E, bool C, bool O, bool W>
+static void integrate_half(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                           const md_state& st, hipStream_t s)
 {
+    hipLaunchKernelGGL((k_integrate_half<S, E, C, O, W>), dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q,
+                       k.n_slots, P, dt_fs, st);
+}
+
+template <typename R, bool S, int NP, int ND, int EV>
+static void force_half_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, ForceFlags fl,
+                               double dt_fs, const md_state& st, hipStream_t s)
+{
+    const dim3 grid(blocks_for(k.n_slots));
+    for (int a = 0; a < 3; ++a) hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.fhalf[a], 0.0, k.n_slots);
+    if (fl.energy) hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.ehalf, 0.0, k.n_slots);
+    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (fl.energy ? 4 : 0)) * sizeof(R) : 0;
+    if (fl.energy)
+        hipLaunchKernelGGL((k_force_half<R, S, NP, ND, EV, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
+    else
+        hipLaunchKernelGGL((k_force_half<R, S, NP, ND, EV, false>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
+    if (!fl.close && !fl.open) {
+        if (fl.energy) integrate_half<S, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
+        else integrate_half<S, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.close && fl.open) {
+        integrate_half<S, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (fl.close && fl.open) {
+        integrate_half<S, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else {
+        integrate_half<S, true, true, false, true>(b, p, q, k, P, dt_fs, st, s);
+    }
+}
+
+template <typename R, bool S>
+static void force_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int half_list,
+                           ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s)
+{
+    if (half_list) {
+        if (k.table) force_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if (k.npk == 6 && k.ndk == 2) force_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        else force_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        return;
+    }
     if (k.table) force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
     else if (k.npk == 6 && k.ndk == 2) force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
     else force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
@@ -843,14 +1112,13 @@ static void force_dispatch(const Buffers& b, int p, int q, const KernelShape& k,
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s)
 {
-    (void)half_list;
     const bool one = P.ns == 1;
     if (precision == MD_MIXED) {
-        if (one) force_dispatch<float, true>(b, p, q, k, P, fl, dt_fs, st, s);
-        else force_dispatch<float, false>(b, p, q, k, P, fl, dt_fs, st, s);
+        if (one) force_dispatch<float, true>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
+        else force_dispatch<float, false>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
     } else {
-        if (one) force_dispatch<double, true>(b, p, q, k, P, fl, dt_fs, st, s);
-        else force_dispatch<double, false>(b, p, q, k, P, fl, dt_fs, st, s);
+        if (one) force_dispatch<double, true>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
+        else force_dispatch<double, false>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
     }
 }
 

@@ -139,6 +139,8 @@ struct Buffers {
     int32_t* cell_cursor; // [C]
     int32_t* cell_shift;  // [C] slot_off - atom_off of the cell's replica
     int32_t* cell_rep;    // [C] replica of each link cell (-1: unused)
+    int2* cell_adj;       // [C][27] adjacent cell (-1: none), image and offset codes
+    int32_t* cell_coord;  // [C] cell coordinates, 10 bits per axis
     int32_t* scan_blocks; // [scan blocks]
     int32_t* rep_of_wave; // [Np / 64]
     DevReplica* reps;     // [R]
@@ -149,6 +151,8 @@ struct Buffers {
     int32_t* chunk_off;   // [R+1] first chunk of each replica
     double* chunk_partial;  // [n_chunks][kEnergySlots]
     double* fhalf[3];     // [Np] half-list force accumulators (MD_NBR_HALF_ATOMIC)
+    double* rhalf;        // [Np] half-list density accumulator
+    double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
     // local-polynomial tables, [ns*ns][nbt][kForceStride] (phi' and rho' quadratics),
     // [ns*ns][nbt][4] (phi cubic), [ns*ns][nbt][4] (rho cubic)
     double *tab_force64, *tab_energy64, *tab_dens64;
@@ -183,6 +187,7 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
                        hipStream_t s);
 void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s);
+void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
 struct ForceFlags {

@@ -34,7 +34,7 @@ struct md_ctx {
     int64_t N = 0, Np = 0;
     int32_t C = 0, C_alloc = 0, scan_nb = 0;
     // brick path
-    int32_t kernel_path = 0;  // 0 = LDS bricks, 1 = global gathers
+    int32_t kernel_path = 1;  // 0 = LDS bricks, 1 = global gathers
     int32_t brick_dims = 0;   // 0 = automatic, else bd[0] + 10 bd[1] + 100 bd[2]
     int32_t brick_block = 512;
     int32_t lds_limit = 65536;
@@ -102,7 +102,7 @@ KernelShape shape(const md_ctx* c)
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
-    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok;
+    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->nbr_mode == MD_NBR_FULL;
     return k;
 }
 
@@ -197,6 +197,13 @@ void choose_bricks(md_ctx* c, int32_t dims)
 
 // Upload the replica table and the brick/cell maps (after md_bind or a
 // change of brick shape); the next call rebuilds the list.
+// Link-cell adjacency table on the device (once per geometry; synchronous).
+bool build_cell_table(md_ctx* c)
+{
+    launch_cell_table(c->buf, shape(c), nullptr);
+    return hip_ok(c, hipGetLastError(), "cell table") && hip_ok(c, hipStreamSynchronize(nullptr), "cell table");
+}
+
 bool upload_geometry(md_ctx* c)
 {
     if (!c->bound) return true;
@@ -205,7 +212,8 @@ bool upload_geometry(md_ctx* c)
            hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "upload") &&
            hip_ok(c, hipMemcpy(c->buf.cell_rep, c->cell_rep.data(), c->cell_rep.size() * 4, hipMemcpyHostToDevice), "upload") &&
            (c->brick_rep.empty() ||
-            hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "upload"));
+            hip_ok(c, hipMemcpy(c->buf.brick_rep, c->brick_rep.data(), c->brick_rep.size() * 4, hipMemcpyHostToDevice), "upload")) &&
+           build_cell_table(c);
 }
 
 // Exact re-expansion of every cubic-knot sum on a grid of bins of width w
@@ -314,6 +322,8 @@ void plan_workspace(md_ctx* c)
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // fhalf[3]
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
+        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // rhalf
+        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // ehalf
         F_COUNT * 4,                                         // flags
         c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
         c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
@@ -326,6 +336,8 @@ void plan_workspace(md_ctx* c)
         Np * 16, Np * 16,                                    // rec[2]
         Np * 16,                                             // cellxyz
         C * 4,                                               // cell_rep (C_alloc)
+        C * 27 * 8,                                          // cell_adj
+        C * 4,                                               // cell_coord
     };
     c->off.clear();
     size_t o = 0;
@@ -374,6 +386,8 @@ void bind_buffers(md_ctx* c)
     at(b.chunk_off);
     at(b.chunk_partial);
     for (int a = 0; a < 3; ++a) at(b.fhalf[a]);
+    at(b.rhalf);
+    at(b.ehalf);
     at(b.flags);
     at(b.tab_force64);
     at(b.tab_energy64);
@@ -391,6 +405,8 @@ void bind_buffers(md_ctx* c)
     at(b.rec[1]);
     at(b.cellxyz);
     at(b.cell_rep);
+    at(b.cell_adj);
+    at(b.cell_coord);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -500,7 +516,8 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
     if (fl.open) c->p ^= 1;
     if (fl.energy) {
         Timed tm(c, MD_KT_REDUCE, s);
-        launch_reduce_energies(c->buf, k, -0.5, s);  // full list: each pair seen from both atoms
+        // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
+        launch_reduce_energies(c->buf, k, half ? -1.0 : -0.5, s);
         c->have_energy = true;
     }
 }
@@ -660,7 +677,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             D.origin[a] = c->origin[3 * r + a];
             D.vp[a] = c->vp[3 * r + a];
             int64_t nc = (int64_t)std::floor(L / c->rlist);
-            nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
+            nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1023));
             D.nc[a] = (int32_t)nc;
             D.cell[a] = L / (double)nc;
             cell_max = std::max(cell_max, D.cell[a]);
@@ -757,6 +774,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     for (int r = 0; r < c->R; ++r)
         for (int64_t i = c->atom_off[r]; i < c->atom_off[r + 1]; ++i) c->n_mobile[r] += rg[i] ? 0 : 1;
     c->bound = true;
+    if (!build_cell_table(c)) return MD_ERR_DEVICE;
     c->have_slots = c->have_list = c->have_energy = false;
     c->p = c->q = 0;
     c->step = 0;

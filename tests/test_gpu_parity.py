@@ -102,7 +102,8 @@ def test_explicit_knot_evaluator(md, orc, workload):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_global_gather_path(md, orc, precision):
     """The one-thread-per-atom global-gather kernels (int32 list with periodic
-    shift codes) on single- and two-species systems."""
+    shift codes, compact records in mixed mode) on single- and two-species
+    systems."""
     s = inputs.bcc_fe(8, temperature=600.0, seed=8, displace=0.07)
     _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: 1})
     s2 = inputs.fec_replicas(2, nmin=300, nmax=900, seed0=4400)
@@ -110,12 +111,49 @@ def test_global_gather_path(md, orc, precision):
     _check_snapshot(md, orc, s2, precision, options={md.MD_OPT_KERNEL: 1})
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_half_list_atomics(md, orc, precision):
+    """Half list with FP64 atomics (each pair evaluated once): parity with the
+    oracle on one species, two species and a free-axis piston with rigid atoms
+    (whose mutual pairs stay out of the virial)."""
+    s = inputs.bcc_fe(8, temperature=600.0, seed=21, displace=0.07)
+    _check_snapshot(md, orc, s, precision, nbr_mode="half")
+    s2 = inputs.fec_replicas(2, nmin=300, nmax=900, seed0=4700)
+    s2.pos = s2.pos + 0.04 * (2 * np.random.default_rng(21).random(s2.pos.shape) - 1)
+    _check_snapshot(md, orc, s2, precision, nbr_mode="half")
+    s3 = inputs.fcc_piston(nx=4, ny=4, nz=8, piston_cells=2, steps=0)
+    s3.pos = s3.pos + 0.03 * (2 * np.random.default_rng(22).random(s3.pos.shape) - 1)
+    _check_snapshot(md, orc, s3, precision, nbr_mode="half")
+
+
+def test_half_list_matches_full(md):
+    """FP64: half list + atomics and full list agree to rounding (only the
+    summation order differs); the half list holds every pair exactly once."""
+    s = inputs.fec_replicas(2, nmin=500, nmax=1200, seed0=4800)
+    s.pos = s.pos + 0.04 * (2 * np.random.default_rng(23).random(s.pos.shape) - 1)
+    out = {}
+    for mode in ("full", "half"):
+        sim = md.Simulation(s, nbr_mode=mode)
+        sim.eam_forces(want_energy=True)
+        en = sim.energy()
+        out[mode] = (sim.forces(), sim.atom_energies(), en, sim.neighbours())
+    (ff, ef, enf, (cf, lf)), (fh, eh, enh, (ch, lh)) = out["full"], out["half"]
+    assert force_error(fh, ff) < 1e-12
+    assert energy_error(eh, ef) < 1e-13
+    assert np.allclose(enh.virial, enf.virial, rtol=1e-12, atol=1e-10)
+    assert int(ch.sum()) * 2 == int(cf.sum())
+    full_pairs = {(i, int(j)) for i in range(s.n_atoms) for j in lf[i, : cf[i]]}
+    half_pairs = [(i, int(j)) for i in range(s.n_atoms) for j in lh[i, : ch[i]]]
+    assert len(set(half_pairs)) == len(half_pairs)
+    assert {(min(a, b), max(a, b)) for a, b in half_pairs} == {(min(a, b), max(a, b)) for a, b in full_pairs}
+
+
 @pytest.mark.parametrize("dims", [111, 211, 222, 432, 444])
 def test_brick_shapes(md, orc, dims):
     """Every brick shape stages the same neighbourhoods: parity for 1x1x1 up to
     4x4x4 cells per brick (edge bricks partial: 9 cells per axis)."""
     s = inputs.bcc_fe(12, temperature=600.0, seed=9, displace=0.07)
-    _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_BRICK_DIMS: dims})
+    _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_KERNEL: 0, md.MD_OPT_BRICK_DIMS: dims})
 
 
 @pytest.mark.parametrize("lanes,block", [(1, 256), (2, 512), (4, 1024), (4, 128)])
@@ -125,7 +163,7 @@ def test_brick_lanes_and_blocks(md, orc, lanes, block):
     s = inputs.fec_replicas(2, nmin=600, nmax=1400, seed0=4500)
     s.pos = s.pos + 0.04 * (2 * np.random.default_rng(11).random(s.pos.shape) - 1)
     for prec in ("fp64", "mixed"):
-        _check_snapshot(md, orc, s, prec, options={md.MD_OPT_LANES_PER_ATOM: lanes, md.MD_OPT_BRICK_BLOCK: block})
+        _check_snapshot(md, orc, s, prec, options={md.MD_OPT_KERNEL: 0, md.MD_OPT_LANES_PER_ATOM: lanes, md.MD_OPT_BRICK_BLOCK: block})
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -134,7 +172,7 @@ def test_brick_global_fallback(md, orc, precision):
     from global memory through the same halo order: identical results."""
     s = inputs.fec_replicas(2, nmin=800, nmax=1500, seed0=4600)
     s.pos = s.pos + 0.04 * (2 * np.random.default_rng(12).random(s.pos.shape) - 1)
-    sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_HALO_CAP: 64})
+    sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: 0, md.MD_OPT_HALO_CAP: 64})
     assert sim.get_option(md.MD_OPT_HALO_OVERFLOWS) > 0
 
 
@@ -166,13 +204,13 @@ def test_neighbour_list_complete(md, orc):
         assert all(r[i, j] < rc + s.skin for j in listed)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_trajectory_100_steps(md, orc, precision):
+@pytest.mark.parametrize("precision,mode", [("fp64", "full"), ("mixed", "full"), ("fp64", "half")])
+def test_trajectory_100_steps(md, orc, precision, mode):
     """100 velocity-Verlet steps with list rebuilds every 10 steps against the
     oracle's brute-force trajectory (FP64: positions within 1e-8 A)."""
     s = inputs.workload("bcc2000")
-    announce(f"trajectory bcc2000 {precision}")
-    sim = md.Simulation(s, precision=precision)
+    announce(f"trajectory bcc2000 {precision} {mode}")
+    sim = md.Simulation(s, precision=precision, nbr_mode=mode)
     sim.step(100)
     en = sim.energy()
     ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), s.dt_fs, 100)
