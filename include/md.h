@@ -183,7 +183,12 @@ int md_copy_neighbours(md_ctx *ctx, int32_t *counts, int32_t *list, int32_t cap,
 
 enum {
     MD_OPT_LANES_PER_ATOM = 1, /* 0 (automatic), 1, 2 or 4 lanes share one atom      */
-    MD_OPT_USE_GRAPH = 2,      /* 1 = replay md_step from captured HIP graphs         */
+    MD_OPT_USE_GRAPH = 2,      /* 1 = md_step replays its middle steps, two list
+                                  rebuild periods at a time, from captured HIP
+                                  graphs (launched on a library stream ordered after
+                                  and before the caller's stream by events; not with
+                                  MD_OPT_TIMING).  Any md_set_option or md_bind
+                                  drops the captured graphs.                         */
     MD_OPT_MAX_COUNT = 3,      /* read only: largest list length seen (at md_energy)  */
     MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind                */
     MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
@@ -197,12 +202,26 @@ enum {
     MD_OPT_BRICK_BLOCK = 9,    /* threads per brick workgroup: 64..1024             */
     MD_OPT_HALO_CAP = 10,      /* atoms one brick's LDS staging area holds (set
                                   smaller to shrink LDS use; larger halos fall back) */
-    MD_OPT_HALO_OVERFLOWS = 11 /* read only: brick passes whose halo exceeded the
+    MD_OPT_HALO_OVERFLOWS = 11, /* read only: brick passes whose halo exceeded the
                                   staging area and read global memory instead
                                   (counted since md_bind, read at md_energy)         */
+    MD_OPT_GRAPH_LAUNCHES = 12, /* read only: graph replays since md_create          */
+    MD_OPT_TUNED_NS = 13       /* read only: md_autotune's estimate of one step of
+                                  the chosen configuration, ns                       */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);
+
+/* Autotuner for the kernel configuration of the bound system (the paper finds
+ * the best settings machine dependent; section "Parallel benchmarks").  Times,
+ * on the current positions, the global-gather kernels and (full list only)
+ * LDS-brick shapes {automatic, 4x4x4, 2x2x2} x lanes per atom {1, 2} x
+ * workgroup sizes {512, 1024}: one list build plus `trials` density + force
+ * passes each (forces are written to the caller's arrays; positions and
+ * velocities are untouched), and keeps the configuration with the lowest
+ * force-pass time plus build time / rebuild_every, readable through
+ * md_get_option.  Synchronises the stream.  trials: 1..1000. */
+int md_autotune(md_ctx *ctx, int32_t trials, void *stream);
 
 /* Kernel groups timed when MD_OPT_TIMING is on. */
 enum { MD_KT_BUILD = 0, MD_KT_DENSITY = 1, MD_KT_FORCE = 2, MD_KT_REDUCE = 3, MD_KT_COUNT = 4 };

@@ -62,8 +62,28 @@ struct md_ctx {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     double kt_ms[MD_KT_COUNT] = {0, 0, 0, 0};
     int64_t kt_n[MD_KT_COUNT] = {0, 0, 0, 0};
+    // HIP graph replay of md_step (MD_OPT_USE_GRAPH): one executable graph per
+    // ping-pong state (p + 2 q), each covering two list-rebuild periods
+    bool use_graph = false;
+    hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};
+    int64_t graph_launches = 0;
+    double tuned_us = 0.0;  // md_autotune's estimate of one step of the chosen configuration
+    void drop_graphs()
+    {
+        for (auto& g : graph_exec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+    }
     ~md_ctx()
     {
+        drop_graphs();
+        for (hipEvent_t e : graph_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (graph_stream) (void)hipStreamDestroy(graph_stream);
         for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     }
 };
@@ -524,6 +544,60 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
 
 bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
 
+// The middle steps of md_step (closing kick, list rebuild on schedule, force
+// pass, opening kick and drift), `n` of them.
+void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        ++c->step;
+        if (due(c)) rebuild(c, s, true);
+        forces(c, ForceFlags{0, 1, 1, 0}, s);
+    }
+}
+
+// Two rebuild periods of middle steps from a step that is a multiple of
+// 2 * rebuild_every, replayed from a captured graph.  Over such a span every
+// ping-pong index flips an even number of times and the rebuild pattern is
+// fixed, so one graph per (p, q) state serves every replay.  Capture runs the
+// host logic once (advancing the counters as a real run would) without
+// executing; a replay advances the counters by the same amounts.
+bool replay_period(md_ctx* c, hipStream_t s)
+{
+    const int64_t P = 2 * (int64_t)c->rebuild_every;
+    if (!c->graph_stream) {
+        if (!hip_ok(c, hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking), "graph stream") ||
+            !hip_ok(c, hipEventCreateWithFlags(&c->graph_ev[0], hipEventDisableTiming), "graph event") ||
+            !hip_ok(c, hipEventCreateWithFlags(&c->graph_ev[1], hipEventDisableTiming), "graph event"))
+            return false;
+    }
+    hipStream_t gs = c->graph_stream;
+    const int key = c->p + 2 * c->q;
+    const int64_t step0 = c->step, builds0 = c->n_builds;
+    if (!c->graph_exec[key]) {
+        hipGraph_t g = nullptr;
+        if (!hip_ok(c, hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed), "graph capture")) return false;
+        middle_steps(c, P, gs);
+        if (!hip_ok(c, hipStreamEndCapture(gs, &g), "graph capture")) return false;
+        const bool ok = hip_ok(c, hipGraphInstantiate(&c->graph_exec[key], g, nullptr, nullptr, 0), "graph instantiate");
+        (void)hipGraphDestroy(g);
+        if (!ok) {
+            c->graph_exec[key] = nullptr;
+            return false;
+        }
+        if (c->p + 2 * c->q != key) return fail(c, MD_ERR_STATE, "graph period changed the ping-pong state") == MD_OK;
+    } else {
+        c->step = step0 + P;
+        c->n_builds = builds0 + 2;
+        c->built_at = c->step;
+    }
+    ++c->graph_launches;
+    return hip_ok(c, hipEventRecord(c->graph_ev[0], s), "graph launch") &&
+           hip_ok(c, hipStreamWaitEvent(gs, c->graph_ev[0], 0), "graph launch") &&
+           hip_ok(c, hipGraphLaunch(c->graph_exec[key], gs), "graph launch") &&
+           hip_ok(c, hipEventRecord(c->graph_ev[1], gs), "graph launch") &&
+           hip_ok(c, hipStreamWaitEvent(s, c->graph_ev[1], 0), "graph launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -774,6 +848,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     for (int r = 0; r < c->R; ++r)
         for (int64_t i = c->atom_off[r]; i < c->atom_off[r + 1]; ++i) c->n_mobile[r] += rg[i] ? 0 : 1;
     c->bound = true;
+    c->drop_graphs();
     if (!build_cell_table(c)) return MD_ERR_DEVICE;
     c->have_slots = c->have_list = c->have_energy = false;
     c->p = c->q = 0;
@@ -816,12 +891,22 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     load_state(c, s, build);
     if (build) rebuild(c, s, true);
     forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
-    for (int32_t k = 1; k <= nsteps; ++k) {
-        ++c->step;
-        if (due(c)) rebuild(c, s, true);
-        if (k < nsteps) forces(c, ForceFlags{0, 1, 1, 0}, s);
-        else forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
+    const int64_t P = 2 * (int64_t)c->rebuild_every;
+    int64_t left = nsteps - 1;  // middle steps
+    while (left > 0) {
+        if (c->use_graph && !c->timing && c->step % P == 0 && left >= P) {
+            if (!replay_period(c, s)) return c->err.empty() ? fail(c, MD_ERR_DEVICE, "graph replay") : MD_ERR_DEVICE;
+            left -= P;
+            continue;
+        }
+        // eager steps up to the next period boundary (or the end)
+        const int64_t n = c->use_graph ? std::min(left, P - c->step % P) : left;
+        middle_steps(c, n, s);
+        left -= n;
     }
+    ++c->step;
+    if (due(c)) rebuild(c, s, true);
+    forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
     return check_launch(c);
 }
 
@@ -908,13 +993,15 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
 int md_set_option(md_ctx* c, int32_t option, int64_t value)
 {
     if (!c) return MD_ERR_ARG;
+    if (option != MD_OPT_TIMING) c->drop_graphs();  // captured launches hold the old settings
     switch (option) {
     case MD_OPT_LANES_PER_ATOM:
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(c, MD_ERR_ARG, "lanes per atom must be 0 (automatic), 1, 2 or 4");
         c->lanes = (int32_t)value;
         return MD_OK;
     case MD_OPT_USE_GRAPH:
-        if (value != 0) return fail(c, MD_ERR_ARG, "graph replay is not available in this build");
+        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "use_graph must be 0 or 1");
+        c->use_graph = value != 0;
         return MD_OK;
     case MD_OPT_TIMING:
         if (!value && !c->pending.empty()) return fail(c, MD_ERR_STATE, "read md_kernel_times before turning timing off");
@@ -955,12 +1042,72 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
     }
 }
 
+int md_autotune(md_ctx* c, int32_t trials, void* stream)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_autotune: call md_bind first");
+    if (trials < 1 || trials > 1000) return fail(c, MD_ERR_ARG, "md_autotune: trials must be 1..1000");
+    if (c->timing) return fail(c, MD_ERR_STATE, "md_autotune: turn MD_OPT_TIMING off first");
+    hipStream_t s = as_stream(stream);
+    struct Cand {
+        int32_t kernel, dims, lanes, block;
+    };
+    std::vector<Cand> cands = {{1, 0, 0, 512}};
+    if (c->nbr_mode == MD_NBR_FULL)
+        for (int32_t dims : {0, 444, 222})
+            for (int32_t lanes : {1, 2})
+                for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block});
+    hipEvent_t ev[3];
+    for (auto& e : ev)
+        if (!hip_ok(c, hipEventCreate(&e), "md_autotune events")) return MD_ERR_DEVICE;
+    double best = 1e300;
+    Cand choice = cands[0];
+    int rc = MD_OK;
+    for (const Cand& cd : cands) {
+        if ((rc = md_set_option(c, MD_OPT_KERNEL, cd.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, cd.dims)) != MD_OK ||
+            (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, cd.lanes)) != MD_OK ||
+            (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK)
+            break;
+        ensure_slots(c, s);
+        launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+        (void)hipEventRecord(ev[0], s);
+        rebuild(c, s, false);
+        (void)hipEventRecord(ev[1], s);
+        for (int32_t t = 0; t < trials; ++t) forces(c, ForceFlags{0, 0, 0, 1}, s);
+        (void)hipEventRecord(ev[2], s);
+        if ((rc = check_launch(c)) != MD_OK) break;
+        float t_build = 0.0f, t_force = 0.0f;
+        if (!hip_ok(c, hipEventSynchronize(ev[2]), "md_autotune") || !hip_ok(c, hipEventElapsedTime(&t_build, ev[0], ev[1]), "md_autotune") ||
+            !hip_ok(c, hipEventElapsedTime(&t_force, ev[1], ev[2]), "md_autotune")) {
+            rc = MD_ERR_DEVICE;
+            break;
+        }
+        // cost of one step: force passes plus the list build spread over its period
+        const double cost = t_force / trials + t_build / c->rebuild_every;
+        if (cost < best) {
+            best = cost;
+            choice = cd;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc != MD_OK) return rc;
+    if ((rc = md_set_option(c, MD_OPT_KERNEL, choice.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, choice.dims)) != MD_OK ||
+        (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, choice.lanes)) != MD_OK ||
+        (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, choice.block)) != MD_OK)
+        return rc;
+    c->tuned_us = best * 1e3;
+    c->have_list = false;  // the next call builds the list of the chosen configuration
+    return MD_OK;
+}
+
 int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
 {
     if (!c || !value) return MD_ERR_ARG;
     switch (option) {
     case MD_OPT_LANES_PER_ATOM: *value = shape(c).lanes; return MD_OK;
-    case MD_OPT_USE_GRAPH: *value = 0; return MD_OK;
+    case MD_OPT_USE_GRAPH: *value = c->use_graph ? 1 : 0; return MD_OK;
+    case MD_OPT_GRAPH_LAUNCHES: *value = c->graph_launches; return MD_OK;
+    case MD_OPT_TUNED_NS: *value = (int64_t)(c->tuned_us * 1e3); return MD_OK;
     case MD_OPT_MAX_COUNT: *value = c->max_count; return MD_OK;
     case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
     case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;

@@ -35,12 +35,13 @@ MD_NBR_FULL, MD_NBR_HALF_ATOMIC = 0, 1
 MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_OPT_TIMING = 1, 2, 3, 4, 5
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
+MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS = 12, 13
 KERNEL_GROUPS = ("build", "density", "force", "reduce")
 
 EXPORTED = [
     "md_create", "md_workspace_bytes", "md_bind", "md_build_neighbours", "md_eam_forces", "md_step",
-    "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_destroy",
-    "md_last_error",
+    "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_autotune",
+    "md_destroy", "md_last_error",
 ]
 
 
@@ -108,6 +109,7 @@ def library():
     lib.md_set_option.argtypes = [vp, i32, i64]
     lib.md_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.md_kernel_times.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.md_autotune.argtypes = [vp, i32, vp]
     lib.md_destroy.argtypes = [vp]
     lib.md_destroy.restype = None
     lib.md_last_error.argtypes = [vp]
@@ -302,6 +304,16 @@ class Simulation:
         self.ctx._check(self.ctx.lib.md_kernel_times(self.ctx.handle, ms.ctypes.data, n.ctypes.data, int(reset),
                                                      self.stream))
         return {g: (float(ms[i]), int(n[i])) for i, g in enumerate(KERNEL_GROUPS)}
+
+    def autotune(self, trials=5):
+        """Pick the fastest kernel configuration for this system (md_autotune);
+        returns the chosen settings and the estimated step time in us."""
+        self.ctx._check(self.ctx.lib.md_autotune(self.ctx.handle, int(trials), self.stream))
+        opts = {name: self.get_option(opt) for name, opt in (
+            ("kernel", MD_OPT_KERNEL), ("brick_dims", MD_OPT_BRICK_DIMS), ("lanes", MD_OPT_LANES_PER_ATOM),
+            ("block", MD_OPT_BRICK_BLOCK))}
+        opts["step_us"] = self.get_option(MD_OPT_TUNED_NS) / 1e3
+        return opts
 
     def positions(self) -> np.ndarray:
         return self.torch.stack([self.x, self.y, self.z], 1).cpu().numpy()

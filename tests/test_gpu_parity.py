@@ -148,6 +148,45 @@ def test_half_list_matches_full(md):
     assert {(min(a, b), max(a, b)) for a, b in half_pairs} == {(min(a, b), max(a, b)) for a, b in full_pairs}
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_matches_eager(md, precision):
+    """md_step with captured-graph replay gives bitwise the eager results.  The
+    graphs are replayed over several calls, with the program's own eager work
+    and synchronisations in between, and every call is compared."""
+    s = inputs.fec_replicas(3, nmin=300, nmax=900, seed0=4900)
+    eager = md.Simulation(s, precision=precision)
+    graph = md.Simulation(s, precision=precision)
+    graph.set_option(md.MD_OPT_USE_GRAPH, 1)
+    for nsteps in (47, 31, 60, 5):
+        eager.step(nsteps)
+        graph.step(nsteps)
+        e1, e2 = eager.energy(), graph.energy()
+        assert np.array_equal(eager.positions(), graph.positions())
+        assert np.array_equal(eager.velocities(), graph.velocities())
+        assert np.array_equal(eager.forces(), graph.forces())
+        assert np.array_equal(e1.pe, e2.pe) and np.array_equal(e1.virial, e2.virial)
+        assert graph.get_option(md.MD_OPT_N_BUILDS) == eager.get_option(md.MD_OPT_N_BUILDS)
+    assert graph.get_option(md.MD_OPT_GRAPH_LAUNCHES) >= 4
+
+
+def test_autotune_then_parity(md, orc):
+    """md_autotune leaves positions and velocities untouched and the chosen
+    configuration keeps oracle parity."""
+    s = inputs.fec_replicas(2, nmin=600, nmax=1200, seed0=5000)
+    s.pos = s.pos + 0.04 * (2 * np.random.default_rng(24).random(s.pos.shape) - 1)
+    sim = md.Simulation(s, precision="mixed")
+    x0, v0 = sim.positions(), sim.velocities()
+    choice = sim.autotune(trials=2)
+    assert choice["kernel"] in (0, 1) and choice["step_us"] > 0
+    assert np.array_equal(sim.positions(), x0) and np.array_equal(sim.velocities(), v0)
+    sim.eam_forces(want_energy=True)
+    sim.energy()
+    for r in range(s.n_replicas):
+        a, b = int(s.atom_offset[r]), int(s.atom_offset[r + 1])
+        ref = _oracle_snapshot(orc, s, r)
+        assert force_error(sim.forces()[a:b], ref.f) <= TOL["mixed"]["force"]
+
+
 @pytest.mark.parametrize("dims", [111, 211, 222, 432, 444])
 def test_brick_shapes(md, orc, dims):
     """Every brick shape stages the same neighbourhoods: parity for 1x1x1 up to
