@@ -49,15 +49,11 @@ def step_bytes_per_atom(nbar: float, k: int) -> float:
     return 136.0 + 4.0 * nbar + (56.0 + 2.0 * nbar) / k
 
 
-def run_precision(md, system, precision, steps, warmup, timing):
+def timed_steps(sim, steps):
+    """Milliseconds of one md_step(steps) call between HIP events on the
+    caller's stream (barriers on both sides), and the wall time."""
     import torch
 
-    sim = md.Simulation(system, precision=precision, want_e_atom=False)
-    sim.step(warmup)
-    sim.energy()
-    sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)
-    if timing:
-        sim.kernel_times(reset=True)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -67,11 +63,81 @@ def run_precision(md, system, precision, steps, warmup, timing):
     sim.step(steps)
     t1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1)
+    return t0.elapsed_time(t1), time.perf_counter() - wall0
+
+
+def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None):
+    """A warmed-up timed run.  tune: options to apply (e.g. an autotuner's
+    choice); graph replay is used unless per-kernel timing is requested."""
+    sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode)
+    for opt, val in (tune or {}).items():
+        sim.set_option(opt, val)
+    if not timing:
+        sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+        # two warmup calls long enough to capture the graphs of both ping-pong
+        # states a call can start in (a graph spans two rebuild periods)
+        calls = [max(warmup, 4 * system.rebuild_every + 2)] * 2
+    else:
+        calls = [warmup]
+    for w in calls:
+        sim.step(w)
+        sim.energy()
+    sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)
+    if timing:
+        sim.kernel_times(reset=True)
+    ms, wall = timed_steps(sim, steps)
     en = sim.energy()
     kt = sim.kernel_times(reset=True) if timing else None
+    sim.warmup_steps = sum(calls)
     return sim, ms, wall, en, kt
+
+
+def tune_options(md, system, precision):
+    """md_autotune on the workload; returns the options it chose."""
+    sim = md.Simulation(system, precision=precision, want_e_atom=False)
+    ch = sim.autotune(trials=3)
+    log(f"autotune {precision}: {ch}")
+    opts = {md.MD_OPT_KERNEL: ch["kernel"], md.MD_OPT_BRICK_DIMS: ch["brick_dims"] if ch["kernel"] == 0 else 0,
+            md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"]}
+    del sim
+    return opts, ch
+
+
+def batched_vs_one_by_one(md, inputs, name, steps, warmup, precision="mixed"):
+    """The replicas of a batched workload run (a) together, one launch per
+    kernel per step, autotuned, with graph replay, and (b) one by one through
+    the single-system path with the same kernel settings and their own graphs.
+    atom-steps/s of both."""
+    t = time.perf_counter()
+    system = inputs.workload(name)
+    log(f"{name}: {system.n_replicas} replicas, {system.n_atoms} atoms (built in {time.perf_counter() - t:.1f} s)")
+    opts, ch = tune_options(md, system, precision)
+    sim, ms, _, en, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts)
+    batched = system.n_atoms * steps / (ms * 1e-3)
+    del sim
+    total_ms = 0.0
+    for r in range(system.n_replicas):
+        sub = system.replica(r)
+        if sub.n_atoms == 0:
+            continue
+        s1, ms1, _, _, _ = run_precision(md, sub, precision, steps, warmup, timing=False, tune=opts)
+        total_ms += ms1
+        del s1
+    one = system.n_atoms * steps / (total_ms * 1e-3)
+    log(f"{name}: batched {batched:.3e}, one-by-one {one:.3e} atom-steps/s")
+    return {
+        "workload": name,
+        "n_replicas": system.n_replicas,
+        "n_atoms": system.n_atoms,
+        "precision": precision,
+        "steps": steps,
+        "batched": batched,
+        "one_by_one": one,
+        "speedup": batched / one,
+        "batched_ms_per_step": ms / steps,
+        "autotuned": {k: v for k, v in ch.items()},
+        "pe_per_atom_eV": float(np.sum(en.pe) / system.n_atoms),
+    }
 
 
 def main():
@@ -82,6 +148,10 @@ def main():
     ap.add_argument("--workload", default="bcc1m")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", default="fec256",
+                    help="comma-separated batched workloads to run together and one by one ('' = none)")
+    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -99,14 +169,30 @@ def main():
     n = system.n_atoms
 
     results = {}
+    tuned = {}
     for prec in ("fp64", "mixed"):
-        log(f"{prec}: warmup {args.warmup}, timed {args.steps} steps")
-        sim, ms, wall, en, _ = run_precision(md, system, prec, args.steps, args.warmup, timing=False)
+        opts, ch = tune_options(md, system, prec)
+        tuned[prec] = ch
+        log(f"{prec}: warmup 2 x {args.warmup}, timed {args.steps} steps")
+        sim, ms, wall, en, _ = run_precision(md, system, prec, args.steps, args.warmup, timing=False, tune=opts)
         log(f"{prec}: {ms / args.steps * 1e3:.1f} us/step  (wall {wall:.3f} s)")
         # a second timed pass with per-kernel HIP events for the roofline
-        sim_t, ms_t, _, _, kt = run_precision(md, system, prec, args.steps, args.warmup, timing=True)
-        results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt}
+        sim_t, ms_t, _, _, kt = run_precision(md, system, prec, args.steps, args.warmup, timing=True, tune=opts)
+        results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt, "warmup_run": sim.warmup_steps}
         del sim_t
+
+    # the half-list + FP64-atomics variant on the same workload (comparison)
+    half = {}
+    if args.half_steps > 0:
+        for prec in ("fp64", "mixed"):
+            sim_h, ms_h, _, _, _ = run_precision(md, system, prec, args.half_steps, args.warmup, timing=False,
+                                                 nbr_mode="half", tune={md.MD_OPT_KERNEL: 1})
+            half[prec] = {"value": n * args.half_steps / (ms_h * 1e-3), "ms_per_step": ms_h / args.half_steps}
+            log(f"half list {prec}: {ms_h / args.half_steps * 1e3:.1f} us/step")
+            del sim_h
+
+    batched = [batched_vs_one_by_one(md, inputs, w, args.batched_steps, args.warmup)
+               for w in args.batched.split(",") if w]
 
     # mixed-vs-FP64 force error on one shared state (the FP64 run's final state)
     ref_sim = results["fp64"]["sim"]
@@ -141,6 +227,9 @@ def main():
             "build_us_per_rebuild": 1e3 * b_ms / max(b_n, 1),
             "timing_overhead_frac": r["ms_timed"] / r["ms"] - 1.0,
             "temperature_K": float(r["en"].temperature[0]),
+            "autotuned": tuned[prec],
+            "graph_replay": True,
+            "warmup_steps_run": r["warmup_run"],
         }
     gate_ok = mix_err <= 1e-5
     head = rec["mixed"] if gate_ok else rec["fp64"]
@@ -188,6 +277,8 @@ def main():
         "mixed_force_err_vs_fp64": mix_err,
         "fp64": rec["fp64"],
         "mixed": rec["mixed"],
+        "half_list_atomics": half,
+        "batched_vs_one_by_one": batched,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

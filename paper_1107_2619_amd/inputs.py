@@ -138,40 +138,35 @@ def bcc_octahedral_sites(nx: int, ny: int, nz: int, a: float) -> np.ndarray:
     return _lattice(nx, ny, nz, a, basis)
 
 
-def random_liquid(n: int, box: float, dmin: float, rng: np.random.Generator) -> np.ndarray:
-    """Random sequential addition of n points in a periodic cube with minimum
-    separation dmin (batched proposals, periodic k-d tree)."""
+def random_liquid(n: int, box: float, dmin: float, rng: np.random.Generator, spread: float = 1.15,
+                  max_iter: int = 1000) -> np.ndarray:
+    """n random points in a periodic cube with every pair at least dmin apart:
+    uniform random positions, then overlap relaxation (every pair closer than
+    spread * dmin is pushed apart symmetrically along its separation, all pairs
+    at once) until no pair is closer than dmin.  The push target above dmin
+    gives nearest-neighbour distances spread over [dmin, spread * dmin] instead
+    of piling up at dmin."""
     from scipy.spatial import cKDTree
 
-    pts = np.empty((0, 3))
-    tries = 0
-    while pts.shape[0] < n:
-        tries += 1
-        if tries > 10000:
-            raise RuntimeError("random packing did not converge")
-        m = max(64, 2 * (n - pts.shape[0]))
-        cand = rng.random((m, 3)) * box
-        if pts.shape[0]:
-            tree = cKDTree(pts, boxsize=box)
-            d, _ = tree.query(cand, k=1)
-            cand = cand[d >= dmin]
-        # resolve conflicts among the surviving candidates in proposal order
-        keep = []
-        if cand.shape[0]:
-            ctree = cKDTree(cand, boxsize=box)
-            pairs = ctree.query_pairs(dmin, output_type="ndarray")
-            bad = np.zeros(cand.shape[0], bool)
-            if pairs.size:
-                conflicts = [[] for _ in range(cand.shape[0])]
-                for p, q in pairs:
-                    conflicts[max(p, q)].append(min(p, q))
-                for idx in range(cand.shape[0]):
-                    if any(not bad[c] for c in conflicts[idx]):
-                        bad[idx] = True
-            keep = np.nonzero(~bad)[0]
-        take = cand[keep][: n - pts.shape[0]]
-        pts = np.concatenate([pts, take], 0)
-    return pts
+    pts = rng.random((n, 3)) * box
+    target = dmin * spread
+    for _ in range(max_iter):
+        tree = cKDTree(pts, boxsize=box)
+        if not len(tree.query_pairs(dmin, output_type="ndarray")):
+            return pts
+        pairs = tree.query_pairs(target, output_type="ndarray")
+        i, j = pairs[:, 0], pairs[:, 1]
+        d = pts[j] - pts[i]
+        d -= box * np.rint(d / box)
+        r = np.linalg.norm(d, axis=1)
+        zero = r < 1e-12
+        if zero.any():
+            d[zero] = rng.normal(size=(int(zero.sum()), 3))
+            r[zero] = np.linalg.norm(d[zero], axis=1)
+        push = (0.5 * (target - r) / r)[:, None] * d
+        disp = np.stack([np.bincount(j, push[:, a], n) - np.bincount(i, push[:, a], n) for a in range(3)], 1)
+        pts = (pts + disp) % box
+    raise RuntimeError("random packing did not converge")
 
 
 def maxwell_boltzmann(masses: np.ndarray, temperature: float, rng: np.random.Generator,
@@ -362,8 +357,8 @@ def liquid_replicas(n_replicas: int = 4096, nmin: int = 128, nmax: int = 2000,
                     pot_seed: int = 5, steps: int = 1000, dt_fs: float = 1.0, skin: float = 0.5,
                     rebuild_every: int = 5, name: str = "liquid_replicas") -> System:
     """Independent liquid-like Fe replicas: size ~ U{nmin..nmax}, random
-    sequential packing with minimum separation dmin in a periodic cube at 7.0
-    g/cm^3, Maxwell-Boltzmann velocities at ``temperature``."""
+    positions with minimum separation dmin (``random_liquid``) in a periodic
+    cube at 7.0 g/cm^3, Maxwell-Boltzmann velocities at ``temperature``."""
     pot = perturbed_potential("fe_fs", pot_seed)
     parts = []
     for r in range(n_replicas):

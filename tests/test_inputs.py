@@ -1,0 +1,73 @@
+"""The seeded input generators: shapes, sizes and value distributions of the
+synthetic workloads (CPU only)."""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+from paper_1107_2619_amd import inputs
+
+
+def test_bcc_lattice_and_vacancies():
+    s = inputs.bcc_fe(6, vacancy_frac=0.02, seed=3)
+    assert s.n_atoms == 2 * 6**3 - int(round(0.02 * 2 * 6**3))
+    d, _ = cKDTree(s.pos, boxsize=s.box[0]).query(s.pos, k=2)
+    assert np.allclose(d[:, 1], 2.87 * np.sqrt(3) / 2)  # nearest bcc shell
+    s2 = inputs.bcc_fe(6, vacancy_frac=0.02, seed=3)
+    assert np.array_equal(s.pos, s2.pos) and np.array_equal(s.vel, s2.vel)
+
+
+def test_maxwell_boltzmann_moments():
+    rng = np.random.default_rng(0)
+    m = np.full(200000, 55.845)
+    v = inputs.maxwell_boltzmann(m, 600.0, rng)
+    assert np.allclose((m[:, None] * v).sum(0), 0.0, atol=1e-9)
+    # <m v^2> per component = k_B T, in A/fs units
+    kt = inputs.KB_EV * 600.0
+    mv2 = m[:, None] * v**2 * inputs.AMU_KG * 1e10 / inputs.EV_J
+    assert abs(mv2.mean() / kt - 1.0) < 0.01
+
+
+def test_fec_replicas_carbon_on_octahedral_sites():
+    s = inputs.fec_replicas(3, nmin=500, nmax=2000, seed0=4000)
+    assert s.n_replicas == 3 and s.atom_offset[-1] == s.n_atoms
+    for r in range(3):
+        a, b = s.atom_offset[r], s.atom_offset[r + 1]
+        sp = s.species[a:b]
+        n_fe, n_c = int((sp == 0).sum()), int((sp == 1).sum())
+        assert n_c == int(round(0.005 * n_fe))
+        L = s.box[r]
+        fe, c = s.pos[a:b][sp == 0], s.pos[a:b][sp == 1]
+        if n_c:
+            # an octahedral site sits a/2 from its two nearest Fe atoms
+            d, _ = cKDTree(fe, boxsize=L).query(c, k=2)
+            assert np.allclose(d, 2.87 / 2)
+        assert 300.0 <= s.temperature[r] <= 1200.0
+
+
+@pytest.mark.parametrize("n", [128, 700, 2000])
+def test_liquid_density_and_min_separation(n):
+    L = (n * inputs.LIQUID_VOLUME_PER_ATOM) ** (1.0 / 3.0)
+    pos = inputs.random_liquid(n, L, 2.0, np.random.default_rng(n))
+    assert pos.shape == (n, 3) and np.all((pos >= 0) & (pos < L))
+    d, _ = cKDTree(pos, boxsize=L).query(pos, k=2)
+    assert d[:, 1].min() >= 2.0
+    # 7.0 g/cm^3 of Fe: 55.845 amu per 13.2475 A^3
+    rho = n * 55.845 * inputs.AMU_KG * 1e3 / (L**3 * 1e-24)
+    assert abs(rho - 7.0) < 1e-3
+
+
+def test_liquid_replicas_sizes_seeded():
+    s = inputs.liquid_replicas(4, nmin=128, nmax=400, seed0=5000)
+    sizes = np.diff(s.atom_offset)
+    assert np.all((sizes >= 128) & (sizes <= 400))
+    s2 = inputs.liquid_replicas(4, nmin=128, nmax=400, seed0=5000)
+    assert np.array_equal(s.pos, s2.pos)
+
+
+def test_piston_rigid_layer():
+    s = inputs.fcc_piston(nx=4, ny=4, nz=8, piston_cells=2, steps=0)
+    rigid = s.rigid.astype(bool)
+    assert rigid.sum() == 4 * 4 * 2 * 4  # fcc: 4 atoms per cubic cell
+    assert np.all(s.pos[rigid, 2] < 2 * 3.615)
+    assert np.allclose(s.vel[rigid], [0.0, 0.0, 0.01])
+    assert list(s.periodic[0]) == [1, 1, 0]
