@@ -31,6 +31,27 @@ if ROOT not in sys.path:
 METRIC = "EAM atom-steps/s: mixed vs FP64 (force err ≤1e-5), batched vs one-by-one"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of one launch of the mixed-mode force kernel on bcc1m, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of
+# 199 dispatches), each scaled by the reading for a plain 1 GiB device copy
+# (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
+# Valid only for the kernel sources they were taken with (hash below); after
+# any change the bench reports null until the counters are taken again.
+FORCE_TRAFFIC = {"fetch_kib": 112437.0, "write_kib": 71280.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256_16": "3491122853bbad62", "workload": "bcc1m", "precision": "mixed"}
+FORCE_SOURCES = ["paper_1107_2619_amd/csrc/kernels.hip", "paper_1107_2619_amd/csrc/md_device.h",
+                 "paper_1107_2619_amd/csrc/md_internal.h"]
+
+
+def force_sources_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -152,6 +173,8 @@ def main():
                     help="comma-separated batched workloads to run together and one by one ('' = none)")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -164,6 +187,17 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.copy_calibration_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counter readings
+        # calibrate the counters of the force kernel
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
     log(f"building workload {args.workload}")
     system = inputs.workload(args.workload)
     n = system.n_atoms
@@ -236,6 +270,13 @@ def main():
     force_us = head["force_kernel_us"]
     fbytes = force_kernel_bytes_per_atom(nbar) * n
     achieved = fbytes / (force_us * 1e-6) / 1e9
+    traffic = None
+    traffic_bytes = None
+    t = FORCE_TRAFFIC
+    if (gate_ok and args.workload == t["workload"] and force_sources_hash() == t["sources_sha256_16"]
+            and head.get("autotuned", {}).get("kernel") == 1):
+        traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+        traffic = traffic_bytes / (force_us * 1e-6) / 1e9
     roofline = {
         "bound": "hbm",
         "kernel": "k_force (force pass + velocity Verlet)",
@@ -243,7 +284,9 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_bytes_per_launch": traffic_bytes,
+        "algorithmic_bytes_per_launch": fbytes,
         "bytes_per_atom": force_kernel_bytes_per_atom(nbar),
         "step_bytes_per_atom": step_bytes_per_atom(nbar, system.rebuild_every),
         "step_frac": step_bytes_per_atom(nbar, system.rebuild_every) * head["value"] / 1e9 / HBM_PEAK_GBS,

@@ -321,15 +321,39 @@ def _concat(name, parts, pot, dt, skin, every, steps, cap, meta):
     )
 
 
+def _spread_sites(sites: np.ndarray, n: int, box: np.ndarray, min_sep: float,
+                  rng: np.random.Generator) -> np.ndarray:
+    """n distinct sites in random order, skipping any closer than min_sep
+    (periodic) to one already taken."""
+    chosen: list[np.ndarray] = []
+    for idx in rng.permutation(sites.shape[0]):
+        if len(chosen) == n:
+            break
+        s = sites[idx]
+        if chosen:
+            d = np.asarray(chosen) - s
+            d -= box * np.rint(d / box)
+            if np.min(np.sum(d * d, 1)) < min_sep * min_sep:
+                continue
+        chosen.append(s)
+    if len(chosen) < n:
+        raise ValueError("too many carbon atoms for the requested separation")
+    return np.asarray(chosen).reshape(-1, 3)
+
+
 def fec_replicas(n_replicas: int = 256, nmin: int = 250, nmax: int = 16000, a: float = 2.87,
                  c_frac: float = 0.005, tmin: float = 300.0, tmax: float = 1200.0,
                  seed0: int = 4000, pot_seed: int = 4, steps: int = 500, dt_fs: float = 1.0,
-                 skin: float = 0.5, rebuild_every: int = 5, name: str = "fec_replicas") -> System:
+                 skin: float = 0.8, rebuild_every: int = 5, c_min_sep: float = 1.0,
+                 name: str = "fec_replicas") -> System:
     """Independent bcc Fe-C replicas: size ~ U{nmin..nmax}, near-cubic cells,
     round(c_frac * N_Fe) carbon atoms on distinct random octahedral sites,
-    temperature ~ U[tmin, tmax].  Replica r uses seed seed0 + r.  Carbon at
-    1200 K moves up to ~0.33 A in 10 fs, so the list uses a 0.5 A skin rebuilt
-    every 5 steps."""
+    temperature ~ U[tmin, tmax], no two carbons closer than c_min_sep lattice
+    constants (neighbouring octahedral sites are only a/2 apart, and such
+    pairs fly apart at several km/s).  Replica r uses seed seed0 + r.  Carbon at
+    1200 K moves up to ~0.26 A in 5 fs in a 2000-atom replica (further in the
+    tail of a million-atom batch), so the list uses a 0.8 A skin (guard at
+    0.4 A) rebuilt every 5 steps."""
     pot = perturbed_potential("fec_eam", pot_seed)
     parts = []
     for r in range(n_replicas):
@@ -339,7 +363,7 @@ def fec_replicas(n_replicas: int = 256, nmin: int = 250, nmax: int = 16000, a: f
         fe = bcc(nx, ny, nz, a)
         nc = int(round(c_frac * fe.shape[0]))
         sites = bcc_octahedral_sites(nx, ny, nz, a)
-        cpos = sites[rng.choice(sites.shape[0], nc, replace=False)] if nc else np.zeros((0, 3))
+        cpos = _spread_sites(sites, nc, np.array([nx, ny, nz]) * a, c_min_sep * a, rng)
         pos = np.concatenate([fe, cpos], 0)
         sp = np.concatenate([np.zeros(fe.shape[0], np.uint8), np.ones(nc, np.uint8)])
         T = float(rng.uniform(tmin, tmax))
@@ -354,11 +378,13 @@ LIQUID_VOLUME_PER_ATOM = 13.2475  # A^3 per Fe atom at 7.0 g/cm^3
 
 def liquid_replicas(n_replicas: int = 4096, nmin: int = 128, nmax: int = 2000,
                     temperature: float = 2500.0, dmin: float = 2.0, seed0: int = 5000,
-                    pot_seed: int = 5, steps: int = 1000, dt_fs: float = 1.0, skin: float = 0.5,
+                    pot_seed: int = 5, steps: int = 1000, dt_fs: float = 1.0, skin: float = 0.6,
                     rebuild_every: int = 5, name: str = "liquid_replicas") -> System:
     """Independent liquid-like Fe replicas: size ~ U{nmin..nmax}, random
     positions with minimum separation dmin (``random_liquid``) in a periodic
-    cube at 7.0 g/cm^3, Maxwell-Boltzmann velocities at ``temperature``."""
+    cube at 7.0 g/cm^3, Maxwell-Boltzmann velocities at ``temperature``.  At
+    2500-2800 K an atom moves up to ~0.15 A in 5 fs in a 1000-atom replica and
+    ~0.21 A in the tail of a 4-million-atom batch: 0.6 A skin (guard 0.3 A)."""
     pot = perturbed_potential("fe_fs", pot_seed)
     parts = []
     for r in range(n_replicas):

@@ -71,3 +71,13 @@ def test_piston_rigid_layer():
     assert np.all(s.pos[rigid, 2] < 2 * 3.615)
     assert np.allclose(s.vel[rigid], [0.0, 0.0, 0.01])
     assert list(s.periodic[0]) == [1, 1, 0]
+
+
+def test_fec_carbons_kept_apart():
+    s = inputs.fec_replicas(2, nmin=8000, nmax=16000, seed0=4100)
+    for r in range(2):
+        a, b = s.atom_offset[r], s.atom_offset[r + 1]
+        c = s.pos[a:b][s.species[a:b] == 1]
+        if len(c) > 1:
+            d, _ = cKDTree(c, boxsize=s.box[r]).query(c, k=2)
+            assert d[:, 1].min() >= 2.87 - 1e-9
