@@ -941,6 +941,12 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         o.n_atoms = D.n_atoms;
         o.n_mobile = c->n_mobile[r];
     }
+    // a non-finite state first: it also trips the displacement checks
+    for (int r = 0; r < c->R; ++r) {
+        const double* v = e.data() + (size_t)r * kEnergySlots;
+        if (v[E_NONFINITE] != 0.0 || !std::isfinite(v[E_PE]) || !std::isfinite(v[E_KE]))
+            return fail(c, MD_ERR_NONFINITE, "non-finite energy or force in replica " + std::to_string(r));
+    }
     if (flags[F_MAX_COUNT] > c->cap) {
         char msg[200];
         std::snprintf(msg, sizeof msg, "neighbour list overflow: an atom has %d entries, max_neighbours is %d (set it >= %d)",
@@ -959,11 +965,6 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved %.4g A or more outside their link cell between list builds",
                       flags[F_COMPACT], kCompactLimit);
         return fail(c, MD_ERR_SKIN, msg);
-    }
-    for (int r = 0; r < c->R; ++r) {
-        const double* v = e.data() + (size_t)r * kEnergySlots;
-        if (v[E_NONFINITE] != 0.0 || !std::isfinite(v[E_PE]) || !std::isfinite(v[E_KE]))
-            return fail(c, MD_ERR_NONFINITE, "non-finite energy or force in replica " + std::to_string(r));
     }
     return MD_OK;
 }

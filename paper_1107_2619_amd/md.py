@@ -96,6 +96,16 @@ def library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1107_2619_amd.build`")
+    # PyTorch ships its own copy of the HIP runtime under the same soname.  It
+    # has to be loaded (and, with a GPU present, initialised) before this
+    # library, which then binds to it; in the other order PyTorch finds no GPU.
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.md_create.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(_Potential), ctypes.POINTER(vp)]

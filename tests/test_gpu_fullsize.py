@@ -1,0 +1,146 @@
+"""Full-size parity at the benchmark's sizes and launch configurations: the
+oracle computes sampled atoms one by one (brute force over all N), the GPU
+the whole system; plus energy drift over 10^4 steps (GPU, needs the
+library)."""
+import numpy as np
+import pytest
+
+from paper_1107_2619_amd import inputs
+
+from .gpu_helpers import TOL, announce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_1107_2619_amd import md as _md
+
+    _md.library()
+    return _md
+
+
+def _sampled_check(orc, sim, system, precision, n_sample, seed, replicas=None):
+    """Forces and per-atom energies of sampled atoms against the oracle on the
+    GPU's current state (each sampled replica on its own)."""
+    pos, f, e = sim.positions(), sim.forces(), sim.atom_energies()
+    pot = orc.Potential(system.potential)
+    rng = np.random.default_rng(seed)
+    worst_f = worst_e = 0.0
+    for r in (range(system.n_replicas) if replicas is None else replicas):
+        a, b = int(system.atom_offset[r]), int(system.atom_offset[r + 1])
+        sample = rng.choice(b - a, min(n_sample, b - a), replace=False)
+        ref = orc.forces_sampled(pos[a:b], system.species[a:b], system.box[r], system.periodic[r], pot, sample)
+        rms = np.sqrt(np.mean(np.sum(ref.f**2, 1)))
+        worst_f = max(worst_f, np.max(np.linalg.norm(f[a:b][sample] - ref.f, axis=1)) / rms)
+        worst_e = max(worst_e, np.max(np.abs(e[a:b][sample] - ref.e_atom) / np.abs(ref.e_atom)))
+    announce(f"{system.name} {precision}: sampled force err {worst_f:.2e}, energy err {worst_e:.2e}")
+    assert worst_f <= TOL[precision]["force"]
+    assert worst_e <= TOL[precision]["energy"]
+
+
+@pytest.mark.parametrize("precision,config", [
+    ("mixed", "global"), ("fp64", "global"), ("fp64", "brick444"), ("mixed", "brick444")])
+def test_bcc1m_sampled_parity(md, orc, precision, config):
+    """1,013,760 atoms after 30 graph-replayed steps (three list builds)."""
+    s = inputs.workload("bcc1m")
+    announce(f"bcc1m sampled {precision} {config}")
+    sim = md.Simulation(s, precision=precision)
+    if config == "global":
+        sim.set_option(md.MD_OPT_KERNEL, 1)
+    else:
+        for opt, val in ((md.MD_OPT_KERNEL, 0), (md.MD_OPT_BRICK_DIMS, 444), (md.MD_OPT_LANES_PER_ATOM, 2),
+                         (md.MD_OPT_BRICK_BLOCK, 1024)):
+            sim.set_option(opt, val)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(30)
+    sim.energy()
+    assert sim.get_option(md.MD_OPT_N_BUILDS) == 4
+    _sampled_check(orc, sim, s, precision, 64, seed=1)
+
+
+def test_fec256_sampled_parity(md, orc):
+    """256 Fe-C replicas (2.1 M atoms), autotuned, graph replay, mixed."""
+    s = inputs.workload("fec256")
+    announce("fec256 sampled mixed")
+    sim = md.Simulation(s, precision="mixed")
+    sim.autotune(trials=2)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(25)
+    sim.energy()
+    _sampled_check(orc, sim, s, "mixed", 24, seed=2, replicas=[0, 77, 150, 255])
+
+
+def test_piston_full_size_sampled_parity(md, orc):
+    """2.88 M-atom fcc slab with a rigid piston, free z, mixed precision."""
+    s = inputs.workload("fcc_piston")
+    announce(f"fcc_piston sampled mixed N={s.n_atoms}")
+    sim = md.Simulation(s, precision="mixed")
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(25)
+    en = sim.energy()
+    assert en.piston_work[0] != 0.0
+    _sampled_check(orc, sim, s, "mixed", 48, seed=3)
+
+
+def test_liquid_batch_sampled_parity(md, orc):
+    """64 liquid replicas of uneven sizes at 2500 K, FP64 and mixed."""
+    s = inputs.liquid_replicas(64, seed0=5000)
+    for prec in ("fp64", "mixed"):
+        sim = md.Simulation(s, precision=prec)
+        sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+        sim.step(20)
+        sim.energy()
+        _sampled_check(orc, sim, s, prec, 16, seed=4, replicas=[0, 21, 42, 63])
+
+
+def _drift(sim, n_atoms, blocks, per):
+    e = []
+    for _ in range(blocks):
+        sim.step(per)
+        en = sim.energy()
+        e.append(np.asarray(en.pe) + np.asarray(en.ke))
+    e = np.array(e)  # [blocks, replicas]
+    de = (e - e[0]) / n_atoms
+    t = np.arange(blocks) * per
+    slope = np.polyfit(t, de, 1)[0]
+    return np.max(np.abs(de), axis=0), slope
+
+
+def test_nve_drift_10k_steps(md):
+    """10^4 velocity-Verlet steps of the 2000-atom bcc crystal: total energy
+    per atom stays in a bounded band without secular drift, in FP64 and in
+    mixed precision (paper, "Integration error")."""
+    s = inputs.workload("bcc2000")
+    out = {}
+    for prec in ("fp64", "mixed"):
+        sim = md.Simulation(s, precision=prec, want_e_atom=False)
+        sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+        band, slope = _drift(sim, s.n_atoms, 100, 100)
+        out[prec] = (float(band[0]), float(slope[0]) * 1e4)
+        announce(f"bcc2000 {prec}: max |dE|/N {band[0]:.3e} eV, drift over 1e4 steps {slope[0] * 1e4:.3e} eV/atom")
+    for prec, (band, drift) in out.items():
+        assert band < 2e-4
+        assert abs(drift) < 2e-5
+    assert abs(out["mixed"][1] - out["fp64"][1]) < 1e-5
+
+
+def test_liquid_per_replica_drift(md):
+    """Per-replica energy drift of liquid replicas at 2500 K over 10^3 steps
+    (rebuild every 5), FP64 and mixed."""
+    s = inputs.liquid_replicas(16, seed0=5100)
+    n = np.diff(s.atom_offset)
+    for prec in ("fp64", "mixed"):
+        sim = md.Simulation(s, precision=prec, want_e_atom=False)
+        sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+        e0 = None
+        band = np.zeros(s.n_replicas)
+        for _ in range(20):
+            sim.step(50)
+            en = sim.energy()
+            e = (np.asarray(en.pe) + np.asarray(en.ke)) / n
+            e0 = e if e0 is None else e0
+            band = np.maximum(band, np.abs(e - e0))
+        announce(f"liquid16 {prec}: per-replica max |dE|/N over 1e3 steps: median {np.median(band):.2e}, "
+                 f"max {band.max():.2e} eV")
+        assert band.max() < 5e-3
