@@ -124,14 +124,12 @@ def tune_options(md, system, precision):
     return opts, ch
 
 
-def batched_vs_one_by_one(md, inputs, name, steps, warmup, precision="mixed"):
+def batched_vs_one_by_one(md, system, name, steps, warmup, precision="mixed"):
     """The replicas of a batched workload run (a) together, one launch per
     kernel per step, autotuned, with graph replay, and (b) one by one through
     the single-system path with the same kernel settings and their own graphs.
     atom-steps/s of both."""
-    t = time.perf_counter()
-    system = inputs.workload(name)
-    log(f"{name}: {system.n_replicas} replicas, {system.n_atoms} atoms (built in {time.perf_counter() - t:.1f} s)")
+    log(f"{name}: {system.n_replicas} replicas, {system.n_atoms} atoms, {precision}")
     opts, ch = tune_options(md, system, precision)
     sim, ms, _, en, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts)
     batched = system.n_atoms * steps / (ms * 1e-3)
@@ -169,7 +167,8 @@ def main():
     ap.add_argument("--workload", default="bcc1m")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", default="fec256",
+    ap.add_argument("--piston-steps", type=int, default=100, help="steps of the 2.88 M-atom piston slab (0 = skip)")
+    ap.add_argument("--batched", default="fec256,liquid4096",
                     help="comma-separated batched workloads to run together and one by one ('' = none)")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
@@ -180,9 +179,21 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    from paper_1107_2619_amd import inputs
+
+    # batched workloads first, while no GPU context exists (the liquid
+    # generator may use a process pool)
+    batched_sys = {}
+    for w in [w for w in args.batched.split(",") if w]:
+        t = time.perf_counter()
+        kw = {"workers": min(16, os.cpu_count() or 1)} if w == "liquid4096" else {}
+        batched_sys[w] = inputs.workload(w, **kw)
+        log(f"built {w} in {time.perf_counter() - t:.1f} s")
+    piston = inputs.workload("fcc_piston") if args.piston_steps > 0 else None
+
     import torch
 
-    from paper_1107_2619_amd import inputs, md
+    from paper_1107_2619_amd import md
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -225,8 +236,25 @@ def main():
             log(f"half list {prec}: {ms_h / args.half_steps * 1e3:.1f} us/step")
             del sim_h
 
-    batched = [batched_vs_one_by_one(md, inputs, w, args.batched_steps, args.warmup)
-               for w in args.batched.split(",") if w]
+    batched = [batched_vs_one_by_one(md, system_b, w, args.batched_steps, args.warmup)
+               for w, system_b in batched_sys.items()]
+    if "liquid4096" in batched_sys:  # cfg5 also compares FP64 with mixed
+        batched.append(batched_vs_one_by_one(md, batched_sys["liquid4096"], "liquid4096", args.batched_steps,
+                                             args.warmup, precision="fp64"))
+
+    # the free-surface piston slab (2.88 M atoms, mixed)
+    piston_rec = None
+    if piston is not None:
+        opts_p, ch_p = tune_options(md, piston, "mixed")
+        sim_p, ms_p, _, en_p, _ = run_precision(md, piston, "mixed", args.piston_steps, args.warmup, timing=False,
+                                                tune=opts_p)
+        piston_rec = {"workload": "fcc_piston: fcc Cu-like 60x60x200 cells, free z, rigid piston at 1 km/s, "
+                                  f"dt {piston.dt_fs} fs", "n_atoms": piston.n_atoms, "precision": "mixed",
+                      "steps": args.piston_steps, "value": piston.n_atoms * args.piston_steps / (ms_p * 1e-3),
+                      "ms_per_step": ms_p / args.piston_steps, "autotuned": ch_p,
+                      "piston_work_eV": float(en_p.piston_work[0])}
+        log(f"piston: {ms_p / args.piston_steps * 1e3:.1f} us/step")
+        del sim_p
 
     # mixed-vs-FP64 force error on one shared state (the FP64 run's final state)
     ref_sim = results["fp64"]["sim"]
@@ -322,6 +350,7 @@ def main():
         "mixed": rec["mixed"],
         "half_list_atomics": half,
         "batched_vs_one_by_one": batched,
+        "piston_slab": piston_rec,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -376,26 +376,45 @@ def fec_replicas(n_replicas: int = 256, nmin: int = 250, nmax: int = 16000, a: f
 LIQUID_VOLUME_PER_ATOM = 13.2475  # A^3 per Fe atom at 7.0 g/cm^3
 
 
+def _liquid_part(args):
+    r, seed0, nmin, nmax, dmin, temperature, mass = args
+    rng = np.random.default_rng(seed0 + r)
+    n_r = int(rng.integers(nmin, nmax + 1))
+    L = (n_r * LIQUID_VOLUME_PER_ATOM) ** (1.0 / 3.0)
+    pos = random_liquid(n_r, L, dmin, rng)
+    sp = np.zeros(n_r, np.uint8)
+    vel = maxwell_boltzmann(np.full(n_r, mass), temperature, rng)
+    return {"pos": pos, "vel": vel, "species": sp, "rigid": np.zeros(n_r), "box": [L, L, L], "T": temperature}
+
+
+def _gpu_initialised() -> bool:
+    import sys
+
+    torch = sys.modules.get("torch")
+    return bool(torch is not None and torch.cuda.is_initialized())
+
+
 def liquid_replicas(n_replicas: int = 4096, nmin: int = 128, nmax: int = 2000,
                     temperature: float = 2500.0, dmin: float = 2.0, seed0: int = 5000,
                     pot_seed: int = 5, steps: int = 1000, dt_fs: float = 1.0, skin: float = 0.6,
-                    rebuild_every: int = 5, name: str = "liquid_replicas") -> System:
+                    rebuild_every: int = 5, name: str = "liquid_replicas", workers: int = 1) -> System:
     """Independent liquid-like Fe replicas: size ~ U{nmin..nmax}, random
     positions with minimum separation dmin (``random_liquid``) in a periodic
     cube at 7.0 g/cm^3, Maxwell-Boltzmann velocities at ``temperature``.  At
     2500-2800 K an atom moves up to ~0.15 A in 5 fs in a 1000-atom replica and
-    ~0.21 A in the tail of a 4-million-atom batch: 0.6 A skin (guard 0.3 A)."""
+    ~0.21 A in the tail of a 4-million-atom batch: 0.6 A skin (guard 0.3 A).
+    Replica r depends only on seed0 + r, so ``workers`` > 1 (a process pool,
+    used only while no GPU context exists in this process) gives the same
+    result."""
     pot = perturbed_potential("fe_fs", pot_seed)
-    parts = []
-    for r in range(n_replicas):
-        rng = np.random.default_rng(seed0 + r)
-        n_r = int(rng.integers(nmin, nmax + 1))
-        L = (n_r * LIQUID_VOLUME_PER_ATOM) ** (1.0 / 3.0)
-        pos = random_liquid(n_r, L, dmin, rng)
-        sp = np.zeros(n_r, np.uint8)
-        vel = maxwell_boltzmann(pot["mass"][sp], temperature, rng)
-        parts.append({"pos": pos, "vel": vel, "species": sp, "rigid": np.zeros(n_r),
-                      "box": [L, L, L], "T": temperature})
+    jobs = [(r, seed0, nmin, nmax, dmin, temperature, float(pot["mass"][0])) for r in range(n_replicas)]
+    if workers > 1 and n_replicas > 1 and not _gpu_initialised():
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_liquid_part, jobs, chunksize=max(1, n_replicas // (8 * workers)))
+    else:
+        parts = [_liquid_part(j) for j in jobs]
     return _concat(name, parts, pot, dt_fs, skin, rebuild_every, steps, 96, {})
 
 
