@@ -270,9 +270,9 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
     }
 }
 
-// Compact record of a slot: cell-local coordinates in 2^-27 A units (the
+// Compact record of a slot: cell-local coordinates in units of h_a 2^-28 (the
 // mixed mode's gather image of the FP64 positions).  Returns false if a
-// coordinate is too far outside the link cell to encode.
+// coordinate lies too far outside its link cell to encode.
 __device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[3], double x, double y, double z,
                                                int4& out)
 {
@@ -281,9 +281,9 @@ __device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double local = xs[a] - (R.origin[a] + c[a] * R.cell[a]);
-        ok = ok && fabs(local) < kCompactLimit;
-        q[a] = ok ? (int)rint(local * kInvQuantum) : 0;
+        const double u = (xs[a] - (R.origin[a] + c[a] * R.cell[a])) * R.iqs[a];
+        ok = ok && fabs(u) < kCompactCells * (double)(1 << kCompactBits);
+        q[a] = ok ? (int)rint(u) : 0;
     }
     out = make_int4(q[0], q[1], q[2], 0);
     return ok;
@@ -529,21 +529,41 @@ __global__ void k_compact_records(Buffers b, int p, int64_t n_slots)
     b.rec[0][t] = rq;
 }
 
-// Pair separation from compact records: d = q_j 2^-27 - q_i 2^-27 + dc h.
-// The first two terms are multiples of 2^-27 below 16 A in magnitude, so
-// their difference is exact in FP64; only the cell offset adds a rounding.
-// `base` holds -q_i 2^-27 per axis.
-__device__ __forceinline__ void compact_delta(const DevReplica& R, const double3& base, const int4& qj, int code,
-                                              double& dx, double& dy, double& dz)
+// Pair separation from compact records.  With the cell offset dc in {-1,0,1}
+// per axis, d_a = (q_j - q_i + dc 2^28) h_a 2^-28: the integer part is exact
+// in 32 bits (|d| < 8 cells), and the scale is one rounding in FP64.  `qi1`
+// holds q_i + 2^28, so the field c = dc + 1 of the entry adds c 2^28.
+__device__ __forceinline__ double compact_axis(int code_field, int qj, int qi1, double qs)
 {
-    dx = fma((double)((code & 3) - 1), R.cell[0], fma((double)qj.x, kQuantum, base.x));
-    dy = fma((double)(((code >> 2) & 3) - 1), R.cell[1], fma((double)qj.y, kQuantum, base.y));
-    dz = fma((double)(((code >> 4) & 3) - 1), R.cell[2], fma((double)qj.z, kQuantum, base.z));
+    const uint32_t dq = ((uint32_t)code_field << kCompactBits) + (uint32_t)qj - (uint32_t)qi1;
+    return (double)(int32_t)dq * qs;
 }
 
-__device__ __forceinline__ double3 compact_base(const int4& q)
+__device__ __forceinline__ void compact_delta(const DevReplica& R, const int4& qi1, const int4& qj, int code,
+                                              double& dx, double& dy, double& dz)
 {
-    return make_double3(-(double)q.x * kQuantum, -(double)q.y * kQuantum, -(double)q.z * kQuantum);
+    dx = compact_axis(code & 3, qj.x, qi1.x, R.qs[0]);
+    dy = compact_axis((code >> 2) & 3, qj.y, qi1.y, R.qs[1]);
+    dz = compact_axis((code >> 4) & 3, qj.z, qi1.z, R.qs[2]);
+}
+
+__device__ __forceinline__ int4 compact_base(const int4& q)
+{
+    constexpr int one = 1 << kCompactBits;
+    return make_int4(q.x + one, q.y + one, q.z + one, q.w);
+}
+
+// One 16-byte gather through a raw buffer resource: a single load
+// instruction with a 32-bit offset (out-of-range offsets read zero).
+typedef int int4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t record_rsrc(const int4* p, int64_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int4*>(p), (short)0, (int)(n * 16), (int)kBufferWord3);
+}
+__device__ __forceinline__ int4 record_load(__amdgpu_buffer_rsrc_t rs, int j)
+{
+    const int4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, j * 16, 0, 0);
+    return make_int4(v.x, v.y, v.z, v.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,7 +602,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
     const int32_t* __restrict__ nbr = b.nbr;
     const double3 xi = CMP ? make_double3(0.0, 0.0, 0.0) : load_xyz(pos, t);
     const int4 qi = CMP ? rec[t] : make_int4(0, 0, 0, 0);
-    const double3 qb = compact_base(qi);
+    const int4 qb = compact_base(qi);
+    const __amdgpu_buffer_rsrc_t rs = record_rsrc(b.rec[0], n_slots);
     const int si = b.type[q][t] & 0x3F;
     const int n = b.ncount[t];
     double rho = 0.0;
@@ -597,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
         }
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            if (CMP) qs[u] = rec[e[u] & kIndexMask];
+            if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
             else xs[u] = load_xyz(pos, e[u] & kIndexMask);
         }
 #pragma unroll
@@ -656,7 +677,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
     const int32_t* __restrict__ nbr = b.nbr;
     const double4 pi = pos[t];
     const int4 qi = CMP ? rec[t] : make_int4(0, 0, 0, 0);
-    const double3 qb = compact_base(qi);
+    const int4 qb = compact_base(qi);
+    const __amdgpu_buffer_rsrc_t rs = record_rsrc(b.rec[1], n_slots);
     const uint8_t ti = b.type[q][t];
     const int si = ti & 0x3F;
     const bool rigid_i = ti & kRigidBit;
@@ -674,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
         }
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
-            if (CMP) qs[u] = rec[e[u] & kIndexMask];
+            if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
             else ps[u] = pos[e[u] & kIndexMask];
         }
 #pragma unroll

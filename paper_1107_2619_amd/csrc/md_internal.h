@@ -36,11 +36,13 @@ constexpr int kIndexBits = 26;
 constexpr int kIndexMask = (1 << kIndexBits) - 1;
 constexpr int kChunk = 4;  // neighbours whose loads are issued together
 constexpr int kForceStride = 6;  // coefficients per bin of the force table (phi', rho' quadratics)
-// Compact gather record of the mixed mode: cell-local coordinates in units of
-// kQuantum (32-bit fixed point, |local| < 16 A) and F' as FP32, 16 bytes.
-constexpr double kQuantum = 1.0 / 134217728.0;  // 2^-27 A
-constexpr double kInvQuantum = 134217728.0;
-constexpr double kCompactLimit = 15.5;           // A, largest cell-local coordinate
+// Compact gather record of the mixed mode: cell-local coordinates as 32-bit
+// fixed point in units of h_a 2^-kCompactBits (h_a the link-cell edge of axis
+// a) and F' as FP32, 16 bytes.  A coordinate may lie up to kCompactCells cell
+// edges from its cell's origin.
+constexpr int kCompactBits = 28;
+constexpr double kCompactCells = 7.5;
+constexpr uint32_t kBufferWord3 = 0x00020000;  // raw buffer resource, gfx9 family
 
 // Slot type byte: species in bits 0..5, rigid flag in bit 6; 0xFF = empty slot.
 constexpr uint8_t kRigidBit = 0x40;
@@ -65,6 +67,8 @@ struct DevReplica {
     double box[3], inv_box[3], origin[3];
     double vp[3];    // rigid velocity, A/fs
     double cell[3];  // link-cell edge per axis, box / nc
+    double qs[3];    // compact coordinate unit per axis, cell * 2^-kCompactBits
+    double iqs[3];   // its inverse
 };
 
 __host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)

@@ -727,7 +727,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     // ---- replicas, wavefront-aligned slot ranges, link-cell grids
     // (paper: link cells at least the potential range plus the padding rpad)
     int64_t slot = 0, cells_alloc = 0;
-    double cell_max = 0.0;
+    double cell_min = 1e300;
     c->reps.resize(c->R);
     for (int r = 0; r < c->R; ++r) {
         DevReplica& D = c->reps[r];
@@ -754,7 +754,9 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1023));
             D.nc[a] = (int32_t)nc;
             D.cell[a] = L / (double)nc;
-            cell_max = std::max(cell_max, D.cell[a]);
+            D.qs[a] = std::ldexp(D.cell[a], -kCompactBits);
+            D.iqs[a] = std::ldexp(1.0 / D.cell[a], kCompactBits);
+            cell_min = std::min(cell_min, D.cell[a]);
             if (per) D.periodic_mask |= 1 << a;
             worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
         }
@@ -764,9 +766,10 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             return reject(MD_ERR_ARG, "system too large: at most 2^26 atom slots and 2^30 link cells");
     }
     c->Np = std::max<int64_t>(slot, kWave);
-    // compact records need every cell-local coordinate below kCompactLimit:
-    // cells up to 12 A leave 3.5 A of travel between list builds
-    c->compact_ok = cell_max <= kCompactLimit - 3.5;
+    // compact records hold coordinates up to kCompactCells cell edges from
+    // their cell; cells under half the list radius (a free axis of a thin
+    // slab) could see atoms beyond that between builds
+    c->compact_ok = cell_min >= 0.5 * c->rlist;
     c->C_alloc = (int32_t)std::max<int64_t>(cells_alloc, 1);
     c->scan_nb = (c->C_alloc + 1023) / 1024;
     if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
@@ -962,8 +965,8 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     }
     if (flags[F_COMPACT] > 0) {
         char msg[200];
-        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved %.4g A or more outside their link cell between list builds",
-                      flags[F_COMPACT], kCompactLimit);
+        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved %.3g link cells or more from their cell between list builds",
+                      flags[F_COMPACT], kCompactCells);
         return fail(c, MD_ERR_SKIN, msg);
     }
     return MD_OK;
