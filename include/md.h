@@ -206,8 +206,12 @@ enum {
                                   staging area and read global memory instead
                                   (counted since md_bind, read at md_energy)         */
     MD_OPT_GRAPH_LAUNCHES = 12, /* read only: graph replays since md_create          */
-    MD_OPT_TUNED_NS = 13       /* read only: md_autotune's estimate of one step of
+    MD_OPT_TUNED_NS = 13,      /* read only: md_autotune's estimate of one step of
                                   the chosen configuration, ns                       */
+    MD_OPT_COMPACT = 14        /* mixed precision, global kernels, full list: 1 =
+                                  gather 16-byte cell-relative fixed-point records
+                                  (default), 0 = the FP64 position records; reads
+                                  back whether compact records are in use            */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);

@@ -17,6 +17,7 @@ struct md_ctx {
     // configuration (copied)
     int32_t R = 0, cap = 0, rebuild_every = 1, precision = MD_FP64, nbr_mode = MD_NBR_FULL, lanes = 1;
     bool compact_ok = false;
+    bool compact_on = true;  // MD_OPT_COMPACT
     std::vector<int64_t> atom_off;
     std::vector<double> box, origin, vp;
     std::vector<uint8_t> periodic;
@@ -122,7 +123,7 @@ KernelShape shape(const md_ctx* c)
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
-    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->nbr_mode == MD_NBR_FULL;
+    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL;
     return k;
 }
 
@@ -1007,6 +1008,13 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
         if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "use_graph must be 0 or 1");
         c->use_graph = value != 0;
         return MD_OK;
+    case MD_OPT_COMPACT:
+        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "compact must be 0 or 1");
+        if ((value != 0) != c->compact_on) {
+            c->compact_on = value != 0;
+            c->have_list = false;  // the list entries carry a different code
+        }
+        return MD_OK;
     case MD_OPT_TIMING:
         if (!value && !c->pending.empty()) return fail(c, MD_ERR_STATE, "read md_kernel_times before turning timing off");
         c->timing = value != 0;
@@ -1112,6 +1120,7 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
     case MD_OPT_USE_GRAPH: *value = c->use_graph ? 1 : 0; return MD_OK;
     case MD_OPT_GRAPH_LAUNCHES: *value = c->graph_launches; return MD_OK;
     case MD_OPT_TUNED_NS: *value = (int64_t)(c->tuned_us * 1e3); return MD_OK;
+    case MD_OPT_COMPACT: *value = shape(c).compact ? 1 : 0; return MD_OK;
     case MD_OPT_MAX_COUNT: *value = c->max_count; return MD_OK;
     case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
     case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;

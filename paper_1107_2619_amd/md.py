@@ -35,7 +35,7 @@ MD_NBR_FULL, MD_NBR_HALF_ATOMIC = 0, 1
 MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_OPT_TIMING = 1, 2, 3, 4, 5
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
-MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS = 12, 13
+MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS, MD_OPT_COMPACT = 12, 13, 14
 KERNEL_GROUPS = ("build", "density", "force", "reduce")
 
 EXPORTED = [

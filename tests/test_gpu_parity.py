@@ -108,7 +108,12 @@ def test_global_gather_path(md, orc, precision):
     _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: 1})
     s2 = inputs.fec_replicas(2, nmin=300, nmax=900, seed0=4400)
     s2.pos = s2.pos + 0.04 * (2 * np.random.default_rng(7).random(s2.pos.shape) - 1)
-    _check_snapshot(md, orc, s2, precision, options={md.MD_OPT_KERNEL: 1})
+    sim = _check_snapshot(md, orc, s2, precision, options={md.MD_OPT_KERNEL: 1})
+    assert sim.get_option(md.MD_OPT_COMPACT) == (precision == "mixed")
+    if precision == "mixed":  # the FP64 position records in mixed precision
+        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: 1, md.MD_OPT_COMPACT: 0})
+        assert sim.get_option(md.MD_OPT_COMPACT) == 0
+        _check_snapshot(md, orc, s2, precision, options={md.MD_OPT_KERNEL: 1, md.MD_OPT_COMPACT: 0})
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
