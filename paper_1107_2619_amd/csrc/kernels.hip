@@ -100,7 +100,7 @@ __device__ __forceinline__ int wave_run_add(int32_t* counter, int key)
 
 
 // ---------------------------------------------------------------------------
-// List build, step 1: link cell of every atom, cell populations, and the skin
+// Rebuild stage 1 of 5: link cell of every atom, cell populations, and the skin
 // guard (net displacement since the previous build must stay below skin/2).
 __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin2, int check_skin)
 {
@@ -133,7 +133,7 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
     }
 }
 
-// Exclusive scan of cell populations, three phases (block scan, scan of block
+// Rebuild stage 2: exclusive scan of cell populations, three phases (block scan, scan of block
 // sums, add), then shifted into slot numbering with the per-cell replica shift.
 constexpr int kScanBlock = 1024;
 
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(Buffers b, int32_t n)
     if (i < n) b.cell_start[i] += b.scan_blocks[blockIdx.x] + b.cell_shift[i];
 }
 
-// Step 3: place every atom in its cell's slot range (arbitrary order within
+// Rebuild stage 3: place every atom in its cell's slot range (arbitrary order within
 // the cell, fixed by the next kernel).
 __global__ void k_scatter(Buffers b, int64_t n_slots)
 {
@@ -200,7 +200,7 @@ __global__ void k_scatter(Buffers b, int64_t n_slots)
     if (c >= 0) b.perm[b.cell_start[c] + k] = (int32_t)t;
 }
 
-// Step 4: order each cell's members by caller index, making the slot order
+// Rebuild stage 4: order each cell's members by caller index, making the slot order
 // (and so every later floating-point sum) independent of atomics' timing.
 __global__ void k_sort_cells(Buffers b, int q, int32_t n_cells)
 {
@@ -221,7 +221,7 @@ __global__ void k_sort_cells(Buffers b, int q, int32_t n_cells)
     }
 }
 
-// Step 5: gather the whole atom state into the new slot order.
+// Rebuild stage 5: gather the whole atom state into the new slot order.
 __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
 {
     const int64_t u = global_thread();

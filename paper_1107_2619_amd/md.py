@@ -185,6 +185,14 @@ class Context:
         self._check(self.lib.md_workspace_bytes(self.handle, ctypes.byref(n)))
         return n.value
 
+    def set_option(self, opt, value):
+        self._check(self.lib.md_set_option(self.handle, int(opt), int(value)))
+
+    def get_option(self, opt) -> int:
+        v = ctypes.c_int64()
+        self._check(self.lib.md_get_option(self.handle, int(opt), ctypes.byref(v)))
+        return v.value
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
@@ -300,12 +308,10 @@ class Simulation:
         return counts, lst
 
     def set_option(self, opt, value):
-        self.ctx._check(self.ctx.lib.md_set_option(self.ctx.handle, int(opt), int(value)))
+        self.ctx.set_option(opt, value)
 
     def get_option(self, opt) -> int:
-        v = ctypes.c_int64()
-        self.ctx._check(self.ctx.lib.md_get_option(self.ctx.handle, int(opt), ctypes.byref(v)))
-        return v.value
+        return self.ctx.get_option(opt)
 
     def kernel_times(self, reset=True):
         """{group: (total ms, launches)} recorded with MD_OPT_TIMING on."""

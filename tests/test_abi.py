@@ -101,3 +101,27 @@ def test_small_boxes_get_at_least_one_cell(md):
     s = inputs.liquid_replicas(3, nmin=128, nmax=140, seed0=5300)
     c = md.Context(s.potential, s.atom_offset, s.box, s.periodic, skin=0.5, max_neighbours=96)
     assert c.workspace_bytes() > 0
+
+
+def test_size_limits_rejected_on_host(md):
+    """More atom slots than a list entry can index (2^26), and link-cell grids
+    beyond the supported count, are refused before any device work."""
+    s = inputs.workload("bcc2000")
+    n = (1 << 26) + 1
+    with pytest.raises(md.MDError) as e:
+        md.Context(s.potential, [0, n], [[300.0] * 3], [[1, 1, 1]], skin=0.3, max_neighbours=48)
+    assert e.value.code == md.MD_ERR_ARG and "too large" in str(e.value)
+    # one atom slot short of the limit is accepted (no device memory is touched)
+    md.Context(s.potential, [0, (1 << 26) - 64], [[300.0] * 3], [[1, 1, 1]], skin=0.3, max_neighbours=48)
+
+
+def test_options_round_trip_on_host(md):
+    c = _ctx(md)
+    for opt, val in ((md.MD_OPT_USE_GRAPH, 1), (md.MD_OPT_KERNEL, 0), (md.MD_OPT_COMPACT, 0),
+                     (md.MD_OPT_LANES_PER_ATOM, 2)):
+        c.set_option(opt, val)
+        assert c.get_option(opt) == val
+    with pytest.raises(md.MDError):
+        c.set_option(md.MD_OPT_USE_GRAPH, 2)
+    with pytest.raises(md.MDError):
+        c.set_option(999, 1)
