@@ -96,7 +96,8 @@ typedef struct {
     int32_t rebuild_every;  /* list rebuild period in steps (nbrupdate), >= 1 */
     int32_t precision;      /* MD_FP64 or MD_MIXED */
     int32_t nbr_mode;       /* MD_NBR_FULL or MD_NBR_HALF_ATOMIC */
-    int32_t lanes_per_atom; /* lanes sharing one atom's neighbours: 0 = automatic, 1, 2 or 4 */
+    int32_t lanes_per_atom; /* LDS-brick kernels: lanes sharing one atom's neighbours,
+                               0 = automatic, 1, 2 or 4 (the global kernels use one) */
     const int64_t *atom_offset;   /* [R+1], atom_offset[0] = 0, non-decreasing */
     const double *box;            /* [R][3] edge lengths, Angstrom, > 0 */
     const double *origin;         /* [R][3] lower corner (matters on free axes); NULL = 0 */

@@ -113,7 +113,7 @@ KernelShape shape(const md_ctx* c)
     k.n_cells = c->C;
     k.n_replicas = c->R;
     k.cap = c->cap;
-    k.lanes = c->lanes > 0 ? std::min(c->lanes, 4) : 4;
+    k.lanes = c->lanes > 0 ? std::min(c->lanes, 4) : 2;  // automatic: two lanes per atom
     k.npk = c->pot.npk;
     k.ndk = c->pot.ndk;
     k.table = c->table_ok && c->evaluator == 0;

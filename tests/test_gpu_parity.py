@@ -153,15 +153,29 @@ def test_half_list_matches_full(md):
     assert {(min(a, b), max(a, b)) for a, b in half_pairs} == {(min(a, b), max(a, b)) for a, b in full_pairs}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replay_matches_eager(md, precision):
-    """md_step with captured-graph replay gives bitwise the eager results.  The
-    graphs are replayed over several calls, with the program's own eager work
-    and synchronisations in between, and every call is compared."""
+@pytest.mark.parametrize("precision,mode,kernel", [("fp64", "full", 1), ("mixed", "full", 1),
+                                                   ("fp64", "full", 0), ("mixed", "half", 1)])
+def test_graph_replay_matches_eager(md, precision, mode, kernel):
+    """md_step with captured-graph replay gives bitwise the eager results
+    (global and LDS-brick kernels, full and half lists; the half list's FP64
+    atomics make its sums order dependent, so it is compared to rounding).
+    The graphs are replayed over several calls, with the program's own eager
+    work and synchronisations in between, and every call is compared."""
     s = inputs.fec_replicas(3, nmin=300, nmax=900, seed0=4900)
-    eager = md.Simulation(s, precision=precision)
-    graph = md.Simulation(s, precision=precision)
+    eager = md.Simulation(s, precision=precision, nbr_mode=mode)
+    graph = md.Simulation(s, precision=precision, nbr_mode=mode)
+    for sim in (eager, graph):
+        sim.set_option(md.MD_OPT_KERNEL, kernel)
     graph.set_option(md.MD_OPT_USE_GRAPH, 1)
+    if mode == "half":
+        for nsteps in (47, 31):
+            eager.step(nsteps)
+            graph.step(nsteps)
+            e1, e2 = eager.energy(), graph.energy()
+            assert np.max(np.abs(eager.positions() - graph.positions())) < 1e-9
+            assert np.allclose(e1.pe, e2.pe, rtol=1e-10)
+        assert graph.get_option(md.MD_OPT_GRAPH_LAUNCHES) >= 2
+        return
     for nsteps in (47, 31, 60, 5):
         eager.step(nsteps)
         graph.step(nsteps)
