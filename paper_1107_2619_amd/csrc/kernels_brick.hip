@@ -1,5 +1,7 @@
-// LDS brick kernels: the default path for the list build, the density pass and
-// the force pass.
+// LDS brick kernels (MD_OPT_KERNEL = 0): the list build, the density pass and
+// the force pass with neighbour reads from LDS.  The autotuner picks them where
+// they win (FP64 on a large single crystal); the global-gather kernels are the
+// default.
 //
 // The link-cell grid of each replica is cut into bricks (a few cells per axis;
 // see cell_index in md_internal.h) and one workgroup owns one brick.  It first
