@@ -83,6 +83,8 @@ def _load():
     lib.or_kinetic.argtypes = [i64, vp, vp, vp, vp, vp, P]
     lib.or_run_verlet.restype = i32
     lib.or_run_verlet.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
+    lib.or_run_nh.restype = i32
+    lib.or_run_nh.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, d, d, d, vp, vp, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -294,6 +296,45 @@ def run_verlet(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps,
     if rc:
         raise ValueError("oracle: periodic box length must exceed twice the cutoff")
     return RunResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, wk)
+
+
+@dataclass
+class NHResult:
+    pos: np.ndarray
+    vel: np.ndarray
+    f: np.ndarray
+    pe: np.ndarray  # [nsteps+1]
+    ke: np.ndarray
+    work: np.ndarray
+    pi: np.ndarray  # [nsteps+1] thermostat momentum, 1/fs
+    nh_energy: np.ndarray  # [nsteps+1] Q pi^2/2 + g k_B T xi, eV
+
+
+def run_nh(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps, t_target, q_ev_fs2,
+           rigid=None, rigid_velocity=None, pi0=0.0) -> NHResult:
+    """Nose-Hoover NVT run (paper, "Thermostat NVTp") with brute-force forces;
+    Q in eV fs^2, thermostat momentum starting at pi0 (1/fs)."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    vp = None if rigid_velocity is None else _f64(rigid_velocity)
+    box = _f64(box)
+    per = _u8(periodic)
+    f = np.zeros((n, 3))
+    pe, ke, wk = np.zeros(nsteps + 1), np.zeros(nsteps + 1), np.zeros(nsteps + 1)
+    nh = np.zeros(2 * (nsteps + 1))
+    rc = _load().or_run_nh(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
+        sp.ctypes.data, _ptr(rg), box.ctypes.data, per.ctypes.data, pot.ref, float(dt_fs), _ptr(vp),
+        int(nsteps), float(t_target), float(q_ev_fs2), float(pi0), f.ctypes.data, pe.ctypes.data, ke.ctypes.data,
+        wk.ctypes.data, nh.ctypes.data,
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return NHResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, wk, nh[0::2].copy(),
+                    nh[1::2].copy())
 
 
 def temperature(ke: float, n_mobile: int, has_rigid: bool) -> float:

@@ -464,6 +464,132 @@ done:
     return rc;
 }
 
+/*
+ * Nose-Hoover NVT molecular dynamics (paper, "Thermostat NVTp"): the particle
+ * momenta feel the friction -pi_s p_i and the thermostat momentum obeys
+ * Q_s dpi_s/dt = sum_i p_i^2/m_i - g k_B T, with g the degrees of freedom of
+ * the temperature definition (3N - 3; 3N_mobile with rigid atoms).  The
+ * printed right-hand side halves the kinetic term, which would hold the
+ * kinetic energy at twice the one the temperature definition gives; the
+ * reading here keeps the fixed point at that definition.
+ *
+ * The flow is split symmetrically (thermostat half step, velocity half kick,
+ * drift, forces, velocity half kick, thermostat half step).  A thermostat
+ * half step of length h with kinetic energy K:
+ *   pi += (h/2) (2K - g k_B T)/Q;  v *= exp(-pi h);  K *= exp(-2 pi h);
+ *   xi += pi h;  pi += (h/2) (2K - g k_B T)/Q.
+ * The extended energy PE + KE + Q pi^2/2 + g k_B T xi is conserved.
+ * Units: dt in fs, velocities Angstrom/fs, Q in eV fs^2, pi in 1/fs (pi starts
+ * at pi0, xi at 0).
+ * Per step s = 0..nsteps, nh_out[2 s] = pi and nh_out[2 s + 1] =
+ * Q pi^2/2 + g k_B T xi (eV), besides the outputs of or_run_verlet.
+ */
+static double mobile_ke(int64_t n, double *const v[3], const uint8_t *species, const uint8_t *rigid,
+                        const or_potential *p)
+{
+    double ke = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rigid && rigid[i]) continue;
+        ke += 0.5 * p->mass[species[i]] * (v[0][i] * v[0][i] + v[1][i] * v[1][i] + v[2][i] * v[2][i]);
+    }
+    return ke;
+}
+
+static void nh_half_step(int64_t n, double *const v[3], const uint8_t *species, const uint8_t *rigid,
+                         const or_potential *p, double h, double q, double gkt, double *pi, double *xi)
+{
+    double ke = mobile_ke(n, v, species, rigid, p);
+    *pi += 0.5 * h * (2.0 * ke - gkt) / q;
+    const double s = exp(-*pi * h);
+    for (int64_t i = 0; i < n; ++i) {
+        if (rigid && rigid[i]) continue;
+        for (int a = 0; a < 3; ++a) v[a][i] *= s;
+    }
+    ke *= s * s;
+    *xi += *pi * h;
+    *pi += 0.5 * h * (2.0 * ke - gkt) / q;
+}
+
+int or_run_nh(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, const uint8_t *rigid, const double *box, const uint8_t *periodic,
+              const or_potential *p, double dt_fs, const double *vp_fs, int64_t nsteps, double t_target,
+              double q_ev_fs2, double pi0_per_fs, double *f, double *pe_out, double *ke_out, double *work_out,
+              double *nh_out)
+{
+    const double t0 = or_time_unit_fs();
+    const double dt = dt_fs / t0;
+    const double q = q_ev_fs2 / (t0 * t0);
+    double vp[3] = {0.0, 0.0, 0.0};
+    if (vp_fs)
+        for (int a = 0; a < 3; ++a) vp[a] = vp_fs[a] * t0;
+    double *v[3] = {vx, vy, vz};
+    double *r[3] = {x, y, z};
+    int64_t n_mobile = 0;
+    int has_rigid = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (rigid && rigid[i]) has_rigid = 1;
+        else ++n_mobile;
+    }
+    const double dof = has_rigid ? 3.0 * (double)n_mobile : 3.0 * (double)n_mobile - 3.0;
+    const double gkt = dof * OR_KB_EV_PER_K * t_target;
+    double pi = pi0_per_fs * t0, xi = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] *= t0;
+    double *rigid0 = NULL;
+    if (rigid) {
+        rigid0 = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) rigid0[3 * i + a] = r[a][i];
+    }
+    double pe;
+    int rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+    if (rc) goto done;
+    double work = 0.0;
+    double power_prev = -rigid_power(n, f, rigid, vp);
+    for (int64_t s = 0;; ++s) {
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) ke_out[s] = mobile_ke(n, v, species, rigid, p);
+        if (work_out) work_out[s] = work;
+        if (nh_out) {
+            nh_out[2 * s] = pi / t0;
+            nh_out[2 * s + 1] = 0.5 * q * pi * pi + gkt * xi;
+        }
+        if (s == nsteps) break;
+        nh_half_step(n, v, species, rigid, p, 0.5 * dt, q, gkt, &pi, &xi);
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) {
+                double t = (double)(s + 1) * dt;
+                for (int a = 0; a < 3; ++a) r[a][i] = rigid0[3 * i + a] + vp[a] * t;
+                continue;
+            }
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) {
+                v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+                r[a][i] += dt * v[a][i];
+            }
+        }
+        rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+        if (rc) goto done;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) continue;
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+        }
+        nh_half_step(n, v, species, rigid, p, 0.5 * dt, q, gkt, &pi, &xi);
+        double power = -rigid_power(n, f, rigid, vp);
+        work += 0.5 * dt * (power_prev + power);
+        power_prev = power;
+    }
+done:
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+        if (rigid && rigid[i])
+            for (int a = 0; a < 3; ++a) v[a][i] = vp_fs ? vp_fs[a] : 0.0;
+    }
+    free(rigid0);
+    return rc;
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

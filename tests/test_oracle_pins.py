@@ -417,3 +417,62 @@ def test_temperature_degrees_of_freedom(orc):
     kb = orc.boltzmann_ev()
     assert orc.temperature(0.5 * 99 * kb * 300.0, 34, False) == pytest.approx(300.0, rel=1e-14)
     assert orc.temperature(0.5 * 102 * kb * 300.0, 34, True) == pytest.approx(300.0, rel=1e-14)
+
+
+# --- Nose-Hoover NVT (paper, "Thermostat NVTp") -------------------------------
+
+def _nh_system():
+    from paper_1107_2619_amd import inputs
+
+    s = inputs.bcc_fe(4, temperature=600.0, seed=7, displace=0.02)
+    return s
+
+
+def test_nh_large_thermostat_mass_is_nve(orc):
+    """Q -> infinity decouples the thermostat: the NVE trajectory."""
+    s = _nh_system()
+    pot = orc.Potential(s.potential)
+    v = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100)
+    n = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100, 300.0, 1e15)
+    assert np.max(np.abs(v.pos - n.pos)) < 1e-9
+    assert np.max(np.abs(n.pi)) < 1e-12
+
+
+def test_nh_extended_energy_conserved(orc):
+    """PE + KE + Q pi^2/2 + g k_B T xi is a constant of the motion: over 2000
+    steps it stays within a band a thousand times narrower than the swing of
+    PE + KE that the thermostat drives (600 K start, 300 K target)."""
+    s = _nh_system()
+    pot = orc.Potential(s.potential)
+    g = 3 * s.n_atoms - 3
+    q = g * orc.boltzmann_ev() * 300.0 * 50.0**2
+    r = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 2000, 300.0, q)
+    h = r.pe + r.ke + r.nh_energy
+    assert np.ptp(h) < 1e-3 * np.ptp(r.pe + r.ke)
+    assert np.ptp(h) / s.n_atoms < 2e-5
+
+
+def test_nh_fixed_point_is_the_target_temperature(orc):
+    """The time-averaged temperature (2 KE / g k_B) settles at the target: the
+    reading of the thermostat equation with the full kinetic term (the halved
+    term as printed would settle at twice the target)."""
+    s = _nh_system()
+    pot = orc.Potential(s.potential)
+    g = 3 * s.n_atoms - 3
+    q = g * orc.boltzmann_ev() * 300.0 * 50.0**2
+    r = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 3000, 300.0, q)
+    t = 2.0 * r.ke[1000:] / (g * orc.boltzmann_ev())
+    assert abs(t.mean() - 300.0) < 15.0
+
+
+def test_nh_time_reversible(orc):
+    """Reversing velocities and the thermostat momentum retraces the path."""
+    s = _nh_system()
+    pot = orc.Potential(s.potential)
+    q = (3 * s.n_atoms - 3) * orc.boltzmann_ev() * 300.0 * 50.0**2
+    a = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100, 300.0, q)
+    assert abs(a.pi[-1]) > 1e-6
+    b = orc.run_nh(a.pos, -a.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100, 300.0, q, pi0=-a.pi[-1])
+    assert np.max(np.abs(b.pos - s.pos)) < 1e-10
+    assert np.max(np.abs(b.vel + s.vel)) < 1e-12
+    assert abs(b.pi[-1]) < 1e-14
