@@ -105,6 +105,13 @@ typedef struct {
     const double *rigid_velocity; /* [R][3] Angstrom/fs of rigid atoms; NULL = 0 */
     double skin;                  /* list padding beyond r_c (the paper's rpad), >= 0 */
     double dt_fs;                 /* time step, fs, > 0 */
+    /* Nose-Hoover thermostat per replica ("Thermostat NVTp"): md_step then
+     * integrates the NVT equations of motion, the thermostat momentum pi_s
+     * obeying Q dpi_s/dt = 2 KE - g k_B T (g = 3N - 3, or 3N_mobile with rigid
+     * atoms), split symmetrically around the velocity-Verlet step.  Both NULL =
+     * NVE; both set = every replica thermostatted. */
+    const double *nh_temperature; /* [R] target temperature, K, >= 0 */
+    const double *nh_mass;        /* [R] thermostat mass Q, eV fs^2, > 0 */
 } md_config;
 
 /*
@@ -140,6 +147,10 @@ typedef struct {
                             pairs of two rigid atoms are skipped ("Fixed atoms") */
     int64_t step;        /* time step index of this state */
     int64_t n_atoms, n_mobile;
+    double nh_pi;        /* thermostat momentum pi_s, 1/fs (0 without thermostat) */
+    double nh_energy;    /* thermostat energy Q pi_s^2 / 2 + g k_B T xi, eV, with
+                            xi the time integral of pi_s: pe + ke + nh_energy is
+                            conserved by the NVT dynamics */
 } md_energies;
 
 /* Validates the configuration and potential on the host (no device work)

@@ -794,6 +794,130 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double vi
 }
 
 // ---------------------------------------------------------------------------
+// Nose-Hoover thermostat (paper, "Thermostat NVTp").  The flow of a step is
+// split symmetrically: thermostat half step, velocity half kick, drift, forces,
+// velocity half kick, thermostat half step.  A thermostat half step of length
+// h with kinetic energy K updates pi by (h/2)(2K - g k_B T)/Q, scales the
+// velocities by exp(-pi h) (K by its square), advances xi by pi h and updates
+// pi again with the scaled K.  Between two steps the two half steps meet, so
+// one kinetic-energy reduction per step serves both.
+
+// Kinetic energy of the mobile atoms of each reduction chunk (fixed order).
+__global__ __launch_bounds__(kBlock) void k_nh_ke_chunks(Buffers b, int q, int64_t n_slots, PotArgs P)
+{
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.x;
+    const int r = b.chunk_rep[c];
+    const DevReplica& R = b.reps[r];
+    const DevPotential& G = *b.pot;
+    const int64_t s0 = R.slot_off + (int64_t)(c - b.chunk_off[r]) * kReduceChunk;
+    const int64_t s1 = min(s0 + (int64_t)kReduceChunk, (int64_t)R.slot_off + R.n_atoms);
+    double ke = 0.0;
+    for (int64_t t = s0 + threadIdx.x; t < s1; t += kBlock) {
+        const uint8_t ty = b.type[q][t];
+        if (ty & kRigidBit) continue;
+        const double vx = b.vel[q][0][t], vy = b.vel[q][1][t], vz = b.vel[q][2][t];
+        const double hm = P.ns == 1 ? P.half_m : G.half_m[ty & 0x3F];
+        ke += hm * (vx * vx + vy * vy + vz * vz);
+    }
+    sh[threadIdx.x] = ke;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.nh_partial[c] = sh[0];
+}
+
+// Per replica: the kinetic energy, then `halves` thermostat half steps of
+// length dt/2; nh_state = {pi, xi, total velocity scale, kinetic energy after}.
+__global__ void k_nh_update(Buffers b, int n_replicas, int halves, double dt)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_replicas) return;
+    double K = 0.0;
+    for (int c = b.chunk_off[r]; c < b.chunk_off[r + 1]; ++c) K += b.nh_partial[c];
+    double* st = b.nh_state + 4 * (int64_t)r;
+    const double Q = b.nh_param[2 * r], gkt = b.nh_param[2 * r + 1];
+    double pi = st[0], xi = st[1], S = 1.0;
+    const double h = 0.5 * dt;
+    for (int k = 0; k < halves; ++k) {
+        pi += 0.5 * h * (2.0 * K - gkt) / Q;
+        const double s = exp(-pi * h);
+        S *= s;
+        K *= s * s;
+        xi += pi * h;
+        pi += 0.5 * h * (2.0 * K - gkt) / Q;
+    }
+    st[0] = pi;
+    st[1] = xi;
+    st[2] = S;
+    st[3] = K;
+}
+
+// Scaled opening half kick and drift after a thermostatted boundary: for mobile
+// atoms v <- S v + (dt/2) f/m and x <- x + dt v; rigid atoms move on their
+// line and account the opening half of their power.  Writes pos[p^1] (and the
+// compact record of the new position).
+__global__ void k_nh_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double dt, int compact)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const uint8_t ty = b.type[q][t];
+    const double3 x = load_xyz(b.pos[p], t);
+    double xn[3] = {x.x, x.y, x.z};
+    const double f[3] = {b.fhalf[0][t], b.fhalf[1][t], b.fhalf[2][t]};
+    if (ty & kRigidBit) {
+        b.pwork[q][t] += -(f[0] * R.vp[0] + f[1] * R.vp[1] + f[2] * R.vp[2]) * 0.5 * dt;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xn[a] += dt * R.vp[a];
+    } else {
+        const double S = b.nh_state[4 * (int64_t)r + 2];
+        const double acc = P.ns == 1 ? P.accel : G.accel[ty & 0x3F];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double v = fma(0.5 * dt * acc, f[a], S * b.vel[q][a][t]);
+            b.vel[q][a][t] = v;
+            xn[a] = fma(dt, v, xn[a]);
+        }
+    }
+    double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
+    *reinterpret_cast<double2*>(dst) = make_double2(xn[0], xn[1]);
+    dst[2] = xn[2];
+    if (compact) {
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        int4 rq;
+        if (!compact_coords(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
+}
+
+// Final thermostat half step of an md_step call: scale the mobile velocities
+// (internal and the caller's, already written back) and their kinetic-energy
+// terms.
+__global__ void k_nh_scale(Buffers b, int q, int64_t n_slots, md_state st, int energy)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    if (b.type[q][t] & kRigidBit) return;
+    const double S = b.nh_state[4 * (int64_t)r + 2];
+    const int32_t a = b.id[q][t];
+    for (int d = 0; d < 3; ++d) b.vel[q][d][t] *= S;
+    st.vx[a] *= S;
+    st.vy[a] *= S;
+    st.vz[a] *= S;
+    if (energy) b.eslot[(int64_t)E_KE * n_slots + t] *= S * S;
+}
+
+// ---------------------------------------------------------------------------
 // Half-list variant (MD_NBR_HALF_ATOMIC): the comparison form in which every
 // unordered pair is evaluated once, by its lower slot, and the partner's share
 // goes to memory with FP64 atomics; the paper's own OpenMP code resolves the
@@ -1073,12 +1197,15 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
                           double dt_fs, const md_state& st, hipStream_t s)
 {
     if (!fl.close && !fl.open) {
-        if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
+        if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else force_launch<R, S, NP, ND, EV, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.writeback) {
+        force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else {
         force_launch<R, S, NP, ND, EV, true, true, false, true>(b, p, q, k, P, dt_fs, st, s);
     }
@@ -1105,12 +1232,15 @@ static void force_half_variant(const Buffers& b, int p, int q, const KernelShape
     else
         hipLaunchKernelGGL((k_force_half<R, S, NP, ND, EV, false>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
     if (!fl.close && !fl.open) {
-        if (fl.energy) integrate_half<S, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
+        if (!fl.writeback) integrate_half<S, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (fl.energy) integrate_half<S, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else integrate_half<S, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.close && fl.open) {
         integrate_half<S, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         integrate_half<S, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.writeback) {
+        integrate_half<S, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else {
         integrate_half<S, true, true, false, true>(b, p, q, k, P, dt_fs, st, s);
     }
@@ -1142,6 +1272,26 @@ void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const Po
         if (one) force_dispatch<double, true>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
         else force_dispatch<double, false>(b, p, q, k, P, half_list, fl, dt_fs, st, s);
     }
+}
+
+void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int halves, double dt_fs,
+                      hipStream_t s)
+{
+    if (k.n_chunks > 0) hipLaunchKernelGGL(k_nh_ke_chunks, dim3(k.n_chunks), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+    hipLaunchKernelGGL(k_nh_update, dim3((k.n_replicas + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b, k.n_replicas,
+                       halves, dt_fs);
+}
+
+void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nh_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
+                       k.compact);
+}
+
+void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nh_scale, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, st, energy);
 }
 
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)

@@ -623,12 +623,16 @@ static void brick_force_variant(const Buffers& b, int p, int q, const KernelShap
                                 int precision, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s)
 {
     if (!fl.close && !fl.open) {
-        if (fl.energy) brick_force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, precision, dt_fs, st, s);
+        if (!fl.writeback)
+            brick_force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, precision, dt_fs, st, s);
+        else if (fl.energy) brick_force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, precision, dt_fs, st, s);
         else brick_force_launch<R, S, NP, ND, EV, false, false, false, true>(b, p, q, k, P, precision, dt_fs, st, s);
     } else if (!fl.close && fl.open) {
         brick_force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         brick_force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
+    } else if (!fl.writeback) {
+        brick_force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, precision, dt_fs, st, s);
     } else {
         brick_force_launch<R, S, NP, ND, EV, true, true, false, true>(b, p, q, k, P, precision, dt_fs, st, s);
     }

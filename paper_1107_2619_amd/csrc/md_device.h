@@ -448,6 +448,12 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
 #pragma unroll
         for (int k = 0; k < kEnergyTerms; ++k) b.eslot[(int64_t)k * n_slots + t] = vals[k];
     }
+    if (!OPEN && !WRITEBACK) {
+        // thermostatted steps: the opening kick runs after the kinetic-energy
+        // reduction and reads the force from here
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b.fhalf[a][t] = f[a];
+    }
     if (WRITEBACK) {
         const int32_t a = b.id[q][t];
         st.fx[a] = f[0];

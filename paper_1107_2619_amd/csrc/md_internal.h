@@ -156,6 +156,9 @@ struct Buffers {
     double* chunk_partial;  // [n_chunks][kEnergySlots]
     double* fhalf[3];     // [Np] half-list force accumulators (MD_NBR_HALF_ATOMIC)
     double* rhalf;        // [Np] half-list density accumulator
+    double* nh_param;     // [R][2] thermostat mass Q (eV fs^2), g k_B T (eV)
+    double* nh_state;     // [R][4] pi (1/fs), xi, velocity scale of the last update, KE after it (eV)
+    double* nh_partial;   // [n_chunks] kinetic energy per reduction chunk
     double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
     // local-polynomial tables, [ns*ns][nbt][kForceStride] (phi' and rho' quadratics),
     // [ns*ns][nbt][4] (phi cubic), [ns*ns][nbt][4] (rho cubic)
@@ -200,6 +203,14 @@ struct ForceFlags {
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
+// Nose-Hoover thermostat: kinetic energy per replica and `halves` thermostat
+// half steps of length dt/2 (launch_nh_update); then either the scaled opening
+// kick and drift (launch_nh_open) or the final scaling (launch_nh_scale).
+void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int halves, double dt_fs,
+                      hipStream_t s);
+void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                    hipStream_t s);
+void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s);
 // Brick path (kernels_brick.hip).
 void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, hipStream_t s);
 void launch_brick_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

@@ -18,6 +18,9 @@ struct md_ctx {
     int32_t R = 0, cap = 0, rebuild_every = 1, precision = MD_FP64, nbr_mode = MD_NBR_FULL, lanes = 1;
     bool compact_ok = false;
     bool compact_on = true;  // MD_OPT_COMPACT
+    bool nvt = false;        // Nose-Hoover thermostat per replica
+    std::vector<double> nh_T, nh_Q;
+    std::vector<double> nh_gkt;  // host copy of nh_param
     std::vector<int64_t> atom_off;
     std::vector<double> box, origin, vp;
     std::vector<uint8_t> periodic;
@@ -340,11 +343,13 @@ void plan_workspace(md_ctx* c)
         (size_t)c->R * kEnergySlots * 8,                     // energies
         c->chunk_rep.size() * 4, c->chunk_off.size() * 4,     // reduction chunks
         c->chunk_rep.size() * kEnergySlots * 8,
-        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // fhalf[3]
-        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
-        c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,
+        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,  // fhalf[3] (also the thermostat's forces)
+        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,
+        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // rhalf
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // ehalf
+        (size_t)c->R * 16, (size_t)c->R * 32,                // nh_param, nh_state
+        std::max<size_t>(c->chunk_rep.size(), 1) * 8,        // nh_partial
         F_COUNT * 4,                                         // flags
         c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
         c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
@@ -409,6 +414,9 @@ void bind_buffers(md_ctx* c)
     for (int a = 0; a < 3; ++a) at(b.fhalf[a]);
     at(b.rhalf);
     at(b.ehalf);
+    at(b.nh_param);
+    at(b.nh_state);
+    at(b.nh_partial);
     at(b.flags);
     at(b.tab_force64);
     at(b.tab_energy64);
@@ -520,7 +528,17 @@ void load_state(md_ctx* c, hipStream_t s, bool build_next)
     if (k.compact && c->have_list && !build_next) launch_compact_records(c->buf, c->p, k, s);
 }
 
-void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
+void reduce_energies(md_ctx* c, const KernelShape& k, hipStream_t s)
+{
+    Timed tm(c, MD_KT_REDUCE, s);
+    // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
+    launch_reduce_energies(c->buf, k, c->nbr_mode == MD_NBR_HALF_ATOMIC ? -1.0 : -0.5, s);
+    c->have_energy = true;
+}
+
+// Density and force passes.  reduce = false leaves the energy reduction to
+// the caller (the thermostat scales the kinetic terms first).
+void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
 {
     const KernelShape k = shape(c);
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
@@ -535,12 +553,18 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s)
         else launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
     }
     if (fl.open) c->p ^= 1;
-    if (fl.energy) {
-        Timed tm(c, MD_KT_REDUCE, s);
-        // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
-        launch_reduce_energies(c->buf, k, half ? -1.0 : -0.5, s);
-        c->have_energy = true;
-    }
+    if (fl.energy && reduce) reduce_energies(c, k, s);
+}
+
+// Thermostatted step boundary: kinetic energy, `halves` thermostat half steps,
+// then the scaled opening kick and drift (which moves the positions to p^1).
+void nh_boundary(md_ctx* c, int halves, hipStream_t s)
+{
+    const KernelShape k = shape(c);
+    Timed tm(c, MD_KT_FORCE, s);
+    launch_nh_update(c->buf, c->q, k, c->args, halves, c->dt_fs, s);
+    launch_nh_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
+    c->p ^= 1;
 }
 
 bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
@@ -552,7 +576,12 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
     for (int64_t k = 0; k < n; ++k) {
         ++c->step;
         if (due(c)) rebuild(c, s, true);
-        forces(c, ForceFlags{0, 1, 1, 0}, s);
+        if (c->nvt) {
+            forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
+            nh_boundary(c, 2, s);
+        } else {
+            forces(c, ForceFlags{0, 1, 1, 0}, s);
+        }
     }
 }
 
@@ -634,6 +663,17 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     c->lanes = cfg->lanes_per_atom;  // 0 = automatic
     c->skin = cfg->skin;
     c->dt_fs = cfg->dt_fs;
+    if ((cfg->nh_temperature == nullptr) != (cfg->nh_mass == nullptr))
+        return reject(MD_ERR_ARG, "nh_temperature and nh_mass go together (both NULL for NVE)");
+    c->nvt = cfg->nh_temperature != nullptr;
+    if (c->nvt) {
+        c->nh_T.assign(cfg->nh_temperature, cfg->nh_temperature + c->R);
+        c->nh_Q.assign(cfg->nh_mass, cfg->nh_mass + c->R);
+        for (int r = 0; r < c->R; ++r) {
+            if (!(c->nh_T[r] >= 0.0) || !std::isfinite(c->nh_T[r])) return reject(MD_ERR_ARG, "nh_temperature must be finite and >= 0");
+            if (!(c->nh_Q[r] > 0.0) || !std::isfinite(c->nh_Q[r])) return reject(MD_ERR_ARG, "nh_mass must be finite and > 0");
+        }
+    }
     c->atom_off.assign(cfg->atom_offset, cfg->atom_offset + c->R + 1);
     if (c->atom_off[0] != 0) return reject(MD_ERR_ARG, "atom_offset[0] must be 0");
     for (int r = 0; r < c->R; ++r)
@@ -851,6 +891,21 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     c->n_mobile.assign(c->R, 0);
     for (int r = 0; r < c->R; ++r)
         for (int64_t i = c->atom_off[r]; i < c->atom_off[r + 1]; ++i) c->n_mobile[r] += rg[i] ? 0 : 1;
+    {
+        // thermostat: mass Q and g k_B T per replica (g as in the temperature), pi = xi = 0
+        std::vector<double> param(2 * (size_t)c->R, 0.0), state(4 * (size_t)c->R, 0.0);
+        for (int r = 0; r < c->R; ++r) {
+            const bool has_rigid = c->n_mobile[r] < c->reps[r].n_atoms;
+            const double dof = std::max<double>(0.0, has_rigid ? 3.0 * c->n_mobile[r] : 3.0 * c->n_mobile[r] - 3.0);
+            param[2 * r] = c->nvt ? c->nh_Q[r] : 1.0;
+            param[2 * r + 1] = c->nvt ? dof * kBoltzmannEv * c->nh_T[r] : 0.0;
+            state[4 * r + 2] = 1.0;
+        }
+        if (!hip_ok(c, hipMemcpy(c->buf.nh_param, param.data(), param.size() * 8, hipMemcpyHostToDevice), "md_bind thermostat") ||
+            !hip_ok(c, hipMemcpy(c->buf.nh_state, state.data(), state.size() * 8, hipMemcpyHostToDevice), "md_bind thermostat"))
+            return MD_ERR_DEVICE;
+        c->nh_gkt.assign(param.begin(), param.end());
+    }
     c->bound = true;
     c->drop_graphs();
     if (!build_cell_table(c)) return MD_ERR_DEVICE;
@@ -894,7 +949,12 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     const bool build = !c->have_list || due(c);
     load_state(c, s, build);
     if (build) rebuild(c, s, true);
-    forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
+    if (c->nvt) {
+        forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
+        nh_boundary(c, 1, s);                  // thermostat half step, opening kick, drift
+    } else {
+        forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
+    }
     const int64_t P = 2 * (int64_t)c->rebuild_every;
     int64_t left = nsteps - 1;  // middle steps
     while (left > 0) {
@@ -910,7 +970,18 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     }
     ++c->step;
     if (due(c)) rebuild(c, s, true);
-    forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
+    if (c->nvt) {
+        forces(c, ForceFlags{1, 1, 0, 1}, s, false);  // closing kick, energies, write back
+        const KernelShape k = shape(c);
+        {
+            Timed tm(c, MD_KT_FORCE, s);
+            launch_nh_update(c->buf, c->q, k, c->args, 1, c->dt_fs, s);  // closing thermostat half step
+            launch_nh_scale(c->buf, c->q, k, c->st, 1, s);
+        }
+        reduce_energies(c, k, s);
+    } else {
+        forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
+    }
     return check_launch(c);
 }
 
@@ -927,6 +998,9 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     if (c->have_energy && !hip_ok(c, hipMemcpy(e.data(), c->buf.energies, e.size() * 8, hipMemcpyDeviceToHost), "md_energy copy"))
         return MD_ERR_DEVICE;
     c->max_count = flags[F_MAX_COUNT];
+    std::vector<double> nh((size_t)c->R * 4, 0.0);
+    if (c->nvt && !hip_ok(c, hipMemcpy(nh.data(), c->buf.nh_state, nh.size() * 8, hipMemcpyDeviceToHost), "md_energy thermostat"))
+        return MD_ERR_DEVICE;
     for (int r = 0; r < c->R; ++r) {
         const double* v = e.data() + (size_t)r * kEnergySlots;
         md_energies& o = out[r];
@@ -944,6 +1018,11 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         o.step = c->step;
         o.n_atoms = D.n_atoms;
         o.n_mobile = c->n_mobile[r];
+        if (c->nvt) {
+            const double Q = c->nh_gkt[2 * r], gkt = c->nh_gkt[2 * r + 1], pi = nh[4 * r], xi = nh[4 * r + 1];
+            o.nh_pi = pi;
+            o.nh_energy = 0.5 * Q * pi * pi + gkt * xi;
+        }
     }
     // a non-finite state first: it also trips the displacement checks
     for (int r = 0; r < c->R; ++r) {

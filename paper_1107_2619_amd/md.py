@@ -69,6 +69,7 @@ class _Config(ctypes.Structure):
         ("atom_offset", ctypes.c_void_p), ("box", ctypes.c_void_p), ("origin", ctypes.c_void_p),
         ("periodic", ctypes.c_void_p), ("rigid_velocity", ctypes.c_void_p),
         ("skin", ctypes.c_double), ("dt_fs", ctypes.c_double),
+        ("nh_temperature", ctypes.c_void_p), ("nh_mass", ctypes.c_void_p),
     ]
 
 
@@ -83,6 +84,7 @@ class _Energies(ctypes.Structure):
         ("pressure_gpa", ctypes.c_double), ("volume", ctypes.c_double),
         ("piston_work", ctypes.c_double), ("virial", ctypes.c_double * 6),
         ("step", ctypes.c_int64), ("n_atoms", ctypes.c_int64), ("n_mobile", ctypes.c_int64),
+        ("nh_pi", ctypes.c_double), ("nh_energy", ctypes.c_double),
     ]
 
 
@@ -139,7 +141,7 @@ class Context:
 
     def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
                  skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
-                 nbr_mode="full", lanes_per_atom=0):
+                 nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None):
         self.lib = library()
         pa = _c(potential["pair_a"], np.float64)
         ns = pa.shape[0]
@@ -153,6 +155,10 @@ class Context:
         k = self._keep
         k["origin"] = None if origin is None else _c(origin, np.float64).reshape(-1, 3)
         k["vp"] = None if rigid_velocity is None else _c(rigid_velocity, np.float64).reshape(-1, 3)
+        n_rep = len(k["off"]) - 1
+        k["nh_t"] = None if nh_temperature is None else np.broadcast_to(
+            np.asarray(nh_temperature, np.float64), (n_rep,)).copy()
+        k["nh_q"] = None if nh_mass is None else np.broadcast_to(np.asarray(nh_mass, np.float64), (n_rep,)).copy()
         pot = _Potential(ns, pa.shape[2], k["dens_A"].shape[2], 0, pa.ctypes.data, k["pair_r"].ctypes.data,
                          k["dens_A"].ctypes.data, k["dens_R"].ctypes.data, k["emb_c"].ctypes.data,
                          k["mass"].ctypes.data)
@@ -163,6 +169,7 @@ class Context:
             k["off"].ctypes.data, k["box"].ctypes.data,
             None if k["origin"] is None else k["origin"].ctypes.data, k["periodic"].ctypes.data,
             None if k["vp"] is None else k["vp"].ctypes.data, float(skin), float(dt_fs),
+            None if k["nh_t"] is None else k["nh_t"].ctypes.data, None if k["nh_q"] is None else k["nh_q"].ctypes.data,
         )
         h = ctypes.c_void_p()
         rc = self.lib.md_create(ctypes.byref(cfg), ctypes.byref(pot), ctypes.byref(h))
@@ -212,13 +219,16 @@ class Energies:
     step: int
     n_atoms: np.ndarray
     n_mobile: np.ndarray
+    nh_pi: np.ndarray      # thermostat momentum per replica, 1/fs (0 without a thermostat)
+    nh_energy: np.ndarray  # thermostat energy 0.5 Q pi^2 + g k T xi, eV
 
 
 class Simulation:
     """Device state (torch tensors) bound to a Context."""
 
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
-                 device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None):
+                 device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
+                 nh_mass=None):
         import torch
 
         self.torch = torch
@@ -231,6 +241,7 @@ class Simulation:
             dt_fs=system.dt_fs, rebuild_every=system.rebuild_every if rebuild_every is None else rebuild_every,
             max_neighbours=self.cap,
             precision=precision, nbr_mode=nbr_mode, lanes_per_atom=lanes_per_atom,
+            nh_temperature=nh_temperature, nh_mass=nh_mass,
         )
         d = self.device
         f64 = dict(dtype=torch.float64, device=d)
@@ -295,7 +306,8 @@ class Simulation:
         self.ctx._check(self.ctx.lib.md_energy(self.ctx.handle, out, self.stream))
         g = lambda name: np.array([getattr(o, name) for o in out])  # noqa: E731
         return Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"), g("piston_work"),
-                        np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"))
+                        np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"),
+                        g("nh_pi"), g("nh_energy"))
 
     def neighbours(self):
         """(counts[N], list[N, cap]) in caller numbering."""

@@ -125,3 +125,15 @@ def test_options_round_trip_on_host(md):
         c.set_option(md.MD_OPT_USE_GRAPH, 2)
     with pytest.raises(md.MDError):
         c.set_option(999, 1)
+
+
+def test_thermostat_validation(md):
+    """Thermostat arguments: both or neither, T >= 0 and Q > 0, per replica."""
+    _ctx(md, nh_temperature=[300.0], nh_mass=[50.0])
+    _ctx(md, nh_temperature=[0.0], nh_mass=[1e-3])
+    for kw in (dict(nh_temperature=[300.0]), dict(nh_mass=[50.0]), dict(nh_temperature=[-1.0], nh_mass=[50.0]),
+               dict(nh_temperature=[300.0], nh_mass=[0.0]), dict(nh_temperature=[np.nan], nh_mass=[50.0]),
+               dict(nh_temperature=[300.0], nh_mass=[np.inf])):
+        with pytest.raises(md.MDError) as e:
+            _ctx(md, **kw)
+        assert e.value.code == md.MD_ERR_ARG

@@ -1,0 +1,265 @@
+"""GPU parity of the Nose-Hoover NVT path (paper, "Thermostat NVTp") against
+the oracle's NVT integrator: trajectories, thermostat momentum and the
+thermostat energy per replica, on the FP64, mixed, half-list, brick and
+graph-replay forms and in batches with a different target per replica.
+
+The thermostat mass of each case is Q = g k_B T tau^2 with tau = 50 fs (g the
+degrees of freedom of that replica), so the thermostat acts strongly within
+the 100-step runs compared here.
+"""
+import numpy as np
+import pytest
+
+from paper_1107_2619_amd import inputs
+from tests.gpu_helpers import announce, force_error
+
+pytestmark = pytest.mark.gpu
+
+KB = 8.617333262e-5  # eV/K
+TAU_FS = 50.0
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1107_2619_amd import md as _md
+
+    return _md
+
+
+def _dof(s, r):
+    a, b = int(s.atom_offset[r]), int(s.atom_offset[r + 1])
+    n_mobile = int((s.rigid[a:b] == 0).sum())
+    return 3 * n_mobile if n_mobile < b - a else max(3 * n_mobile - 3, 0)
+
+
+def _masses(s, targets):
+    return np.array([max(_dof(s, r), 1) * KB * max(t, 1.0) * TAU_FS**2 for r, t in enumerate(targets)])
+
+
+_ORACLE_RUNS = {}
+
+
+def _oracle(orc, s, r, nsteps, t, q):
+    key = (s.name, s.n_atoms, r, nsteps, float(t), float(q))
+    if key not in _ORACLE_RUNS:
+        _ORACLE_RUNS[key] = _oracle_run(orc, s, r, nsteps, t, q)
+    return _ORACLE_RUNS[key]
+
+
+def _oracle_run(orc, s, r, nsteps, t, q):
+    sub = s.replica(r) if s.n_replicas > 1 else s
+    has_rigid = bool(sub.rigid.any())
+    return orc.run_nh(sub.pos, sub.vel, sub.species, sub.box[0], sub.periodic[0], orc.Potential(sub.potential),
+                      sub.dt_fs, nsteps, t, q, rigid=sub.rigid if has_rigid else None,
+                      rigid_velocity=sub.rigid_velocity[0] if has_rigid else None)
+
+
+def _check_replica(en, r, ref, pos, f, precision, n_atoms):
+    dx = np.max(np.abs(pos - ref.pos)) if len(pos) else 0.0
+    if precision == "fp64":
+        assert dx < 1e-8
+        if len(pos):
+            assert force_error(f, ref.f) < 1e-8
+        assert abs(en.pe[r] - ref.pe[-1]) <= 1e-10 * abs(ref.pe[-1]) + 1e-12
+        assert abs(en.ke[r] - ref.ke[-1]) <= 1e-8 * abs(ref.ke[-1]) + 1e-12
+        assert abs(en.nh_pi[r] - ref.pi[-1]) <= 1e-8 * abs(ref.pi[-1]) + 1e-14
+        assert abs(en.nh_energy[r] - ref.nh_energy[-1]) <= 1e-8 * abs(ref.nh_energy[-1]) + 1e-10
+    else:
+        assert dx < 1e-4
+        h_gpu = en.pe[r] + en.ke[r] + en.nh_energy[r]
+        h_ref = ref.pe[-1] + ref.ke[-1] + ref.nh_energy[-1]
+        assert abs(h_gpu - h_ref) < 1e-5 * max(n_atoms, 1)
+        assert abs(en.nh_pi[r] - ref.pi[-1]) <= 1e-3 * abs(ref.pi[-1]) + 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["full", "half"])
+def test_nvt_trajectory_100_steps(md, orc, precision, mode):
+    """bcc Fe (2000 atoms, 300 K start) driven towards 500 K: 100 thermostatted
+    steps with list rebuilds every 10 against the oracle."""
+    s = inputs.workload("bcc2000")
+    t, q = [500.0], _masses(s, [500.0])
+    announce(f"nvt trajectory bcc2000 {precision} {mode}")
+    sim = md.Simulation(s, precision=precision, nbr_mode=mode, nh_temperature=t, nh_mass=q)
+    sim.step(100)
+    en = sim.energy()
+    ref = _oracle(orc, s, 0, 100, t[0], q[0])
+    assert abs(ref.pi[-1]) > 1e-5  # the thermostat is doing work
+    _check_replica(en, 0, ref, sim.positions(), sim.forces(), precision, s.n_atoms)
+    assert en.step == 100
+
+
+def test_nvt_split_calls_equal_one_call(md):
+    """md_step(40) equals md_step(1) + md_step(13) + md_step(26): the thermostat
+    half steps at call boundaries compose to the same dynamics, bitwise."""
+    s = inputs.workload("bcc2000")
+    t, q = [500.0], _masses(s, [500.0])
+    announce("nvt split calls")
+    a = md.Simulation(s, nh_temperature=t, nh_mass=q)
+    a.step(40)
+    b = md.Simulation(s, nh_temperature=t, nh_mass=q)
+    for n in (1, 13, 26):
+        b.step(n)
+    ea, eb = a.energy(), b.energy()
+    np.testing.assert_allclose(b.positions(), a.positions(), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(b.velocities(), a.velocities(), rtol=0, atol=1e-14)
+    assert eb.nh_pi[0] == pytest.approx(ea.nh_pi[0], rel=1e-10, abs=1e-16)
+    assert eb.nh_energy[0] == pytest.approx(ea.nh_energy[0], rel=1e-10, abs=1e-12)
+
+
+def test_nvt_batched_per_replica_targets(md, orc):
+    """Four Fe-C replicas of uneven sizes, each with its own target
+    temperature and thermostat mass, against the oracle replica by replica."""
+    s = inputs.fec_replicas(4, nmin=250, nmax=1200, seed0=4300)
+    targets = np.array([300.0, 650.0, 900.0, 1400.0])
+    q = _masses(s, targets)
+    announce("nvt batched fec x4 fp64")
+    sim = md.Simulation(s, nh_temperature=targets, nh_mass=q)
+    sim.step(40)
+    en = sim.energy()
+    pos, f = sim.positions(), sim.forces()
+    for r in range(s.n_replicas):
+        a, b = int(s.atom_offset[r]), int(s.atom_offset[r + 1])
+        ref = _oracle(orc, s, r, 40, targets[r], q[r])
+        _check_replica(en, r, ref, pos[a:b], f[a:b], "fp64", b - a)
+
+
+def test_nvt_batched_equals_one_by_one(md):
+    """A thermostatted replica inside a batch is bitwise the same replica run
+    alone: the per-replica kinetic-energy sums keep their order."""
+    s = inputs.fec_replicas(3, nmin=300, nmax=1500, seed0=4400)
+    targets = np.array([400.0, 800.0, 1200.0])
+    q = _masses(s, targets)
+    announce("nvt batched vs one-by-one")
+    sim = md.Simulation(s, nh_temperature=targets, nh_mass=q)
+    sim.step(25)
+    en = sim.energy()
+    pos = sim.positions()
+    for r in range(s.n_replicas):
+        one = md.Simulation(s.replica(r), nh_temperature=targets[r:r + 1], nh_mass=q[r:r + 1])
+        one.step(25)
+        e1 = one.energy()
+        a, b = int(s.atom_offset[r]), int(s.atom_offset[r + 1])
+        assert np.array_equal(one.positions(), pos[a:b])
+        assert e1.nh_pi[0] == en.nh_pi[r] and e1.nh_energy[0] == en.nh_energy[r]
+        assert e1.ke[0] == en.ke[r]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel", ["global", "brick"])
+def test_nvt_graph_replay_matches_eager(md, precision, kernel):
+    """The thermostatted middle steps replayed from a HIP graph give bitwise
+    the eager result (two replays and an eager tail over 60 steps)."""
+    s = inputs.fec_replicas(3, nmin=600, nmax=2000, seed0=4500)
+    targets = np.array([500.0, 700.0, 900.0])
+    q = _masses(s, targets)
+    announce(f"nvt graph replay {precision} {kernel}")
+    out = []
+    for use_graph in (0, 1):
+        sim = md.Simulation(s, precision=precision, nh_temperature=targets, nh_mass=q)
+        if kernel == "brick":
+            sim.set_option(md.MD_OPT_KERNEL, 1)
+            sim.set_option(md.MD_OPT_BRICK_DIMS, 444)
+        sim.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        sim.step(60)
+        e = sim.energy()
+        out.append((sim.positions(), sim.velocities(), e.nh_pi.copy(), e.nh_energy.copy()))
+        if use_graph:
+            assert sim.get_option(md.MD_OPT_GRAPH_LAUNCHES) >= 2
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_nvt_brick_matches_oracle(md, orc):
+    """The LDS-brick kernels in NVT against the oracle."""
+    s = inputs.workload("bcc2000")
+    t, q = [500.0], _masses(s, [500.0])
+    announce("nvt brick fp64")
+    sim = md.Simulation(s, nh_temperature=t, nh_mass=q)
+    sim.set_option(md.MD_OPT_KERNEL, 1)
+    sim.set_option(md.MD_OPT_BRICK_DIMS, 222)
+    sim.step(50)
+    ref = _oracle(orc, s, 0, 50, t[0], q[0])
+    _check_replica(sim.energy(), 0, ref, sim.positions(), sim.forces(), "fp64", s.n_atoms)
+
+
+def test_nvt_piston_rigid_atoms(md, orc):
+    """A rigid moving block on a free axis with the thermostat on the mobile
+    atoms only (g = 3 N_mobile)."""
+    s = inputs.fcc_piston(nx=4, ny=4, nz=8, piston_cells=2, piston_speed_a_per_fs=0.02, steps=0)
+    t, q = [300.0], _masses(s, [300.0])
+    announce("nvt piston")
+    sim = md.Simulation(s, nh_temperature=t, nh_mass=q)
+    sim.step(60)
+    en = sim.energy()
+    ref = _oracle(orc, s, 0, 60, t[0], q[0])
+    _check_replica(en, 0, ref, sim.positions(), sim.forces(), "fp64", s.n_atoms)
+    assert en.piston_work[0] == pytest.approx(ref.work[-1], rel=1e-8, abs=1e-10)
+    rigid = s.rigid.astype(bool)
+    np.testing.assert_allclose(sim.velocities()[rigid], np.broadcast_to(s.rigid_velocity[0], (rigid.sum(), 3)))
+
+
+def test_nvt_zero_target_and_empty_replica(md, orc):
+    """Degenerate cases in one batch: an empty replica, a two-atom replica
+    and a zero target temperature (the thermostat only removes energy)."""
+    base = inputs.liquid_replicas(2, nmin=150, nmax=200, seed0=5200)
+    dimer_pos = np.array([[5.0, 5.0, 5.0], [7.3, 5.0, 5.0]])
+    pos = np.concatenate([base.pos[: base.atom_offset[1]], dimer_pos, base.pos[base.atom_offset[1]:]])
+    dimer_vel = np.array([[0.002, 0.0, 0.0], [-0.002, 0.0, 0.0]])
+    vel = np.concatenate([base.vel[: base.atom_offset[1]], dimer_vel, base.vel[base.atom_offset[1]:]])
+    n0 = int(base.atom_offset[1])
+    n2 = int(base.atom_offset[2] - base.atom_offset[1])
+    off = np.array([0, n0, n0, n0 + 2, n0 + 2 + n2], np.int64)
+    box = np.array([base.box[0], [20.0] * 3, [20.0] * 3, base.box[1]])
+    s = inputs.System(
+        name="nvt_edge", pos=pos, vel=vel, species=np.zeros(len(pos), np.uint8), rigid=np.zeros(len(pos), np.uint8),
+        atom_offset=off, box=box, origin=np.zeros((4, 3)), periodic=np.ones((4, 3), np.uint8),
+        rigid_velocity=np.zeros((4, 3)), potential=base.potential, dt_fs=1.0, skin=0.6, rebuild_every=5, steps=0,
+        temperature=np.zeros(4), max_neighbours=96,
+    )
+    targets = np.array([0.0, 300.0, 300.0, 2500.0])
+    q = _masses(s, targets)
+    announce("nvt zero target, empty and dimer replicas")
+    sim = md.Simulation(s, nh_temperature=targets, nh_mass=q)
+    sim.step(30)
+    en = sim.energy()
+    assert en.nh_pi[1] == 0.0 and en.nh_energy[1] == 0.0 and en.ke[1] == 0.0
+    pos_gpu, f_gpu = sim.positions(), sim.forces()
+    for r in (0, 2, 3):
+        a, b = int(off[r]), int(off[r + 1])
+        ref = _oracle(orc, s, r, 30, targets[r], q[r])
+        _check_replica(en, r, ref, pos_gpu[a:b], f_gpu[a:b], "fp64", b - a)
+    assert en.nh_pi[0] > 0.0  # T = 0: pi only grows while kinetic energy remains
+
+
+def test_nvt_extended_energy_and_mean_temperature(md):
+    """Statistical checks on the GPU alone: over 8000 mixed-precision steps of
+    8 Fe-C replicas, PE + KE + thermostat energy stays within a narrow band
+    while PE + KE swings, and the temperature averaged over the last 6000
+    steps settles at each replica's target.  Integrating the thermostat
+    equation over the window bounds that average's offset from the target by
+    T tau^2 |delta pi| / window, about 1% here."""
+    s = inputs.fec_replicas(8, nmin=1500, nmax=3000, seed0=4600)
+    targets = np.linspace(350.0, 1050.0, 8)
+    q = _masses(s, targets)
+    announce("nvt statistics fec x8 mixed 8000 steps")
+    sim = md.Simulation(s, precision="mixed", nh_temperature=targets, nh_mass=q)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    h, u, temp = [], [], []
+    for k in range(200):
+        sim.step(40)
+        e = sim.energy()
+        h.append(e.pe + e.ke + e.nh_energy)
+        u.append(e.pe + e.ke)
+        if k >= 50:
+            temp.append(e.temperature)
+    h, u, temp = np.array(h), np.array(u), np.array(temp)
+    n = np.diff(s.atom_offset)
+    announce(f"band/N {np.ptp(h, 0) / n} swing/N {np.ptp(u, 0) / n} mean T {temp.mean(0)}")
+    assert np.all(np.ptp(h, 0) < 0.02 * np.ptp(u, 0))
+    assert np.all(np.ptp(h, 0) / n < 1e-4)
+    assert np.all(np.abs(temp.mean(0) - targets) < 0.04 * targets)
