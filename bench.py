@@ -87,10 +87,12 @@ def timed_steps(sim, steps):
     return t0.elapsed_time(t1), time.perf_counter() - wall0
 
 
-def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None):
+def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None, nvt=None):
     """A warmed-up timed run.  tune: options to apply (e.g. an autotuner's
-    choice); graph replay is used unless per-kernel timing is requested."""
-    sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode)
+    choice); graph replay is used unless per-kernel timing is requested.
+    nvt: (targets [R] K, thermostat masses [R] eV fs^2) for a Nose-Hoover run."""
+    kw = {} if nvt is None else {"nh_temperature": nvt[0], "nh_mass": nvt[1]}
+    sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode, **kw)
     for opt, val in (tune or {}).items():
         sim.set_option(opt, val)
     if not timing:
@@ -113,15 +115,45 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
     return sim, ms, wall, en, kt
 
 
+def choice_options(md, ch):
+    """The md_set_option settings of an autotuner choice."""
+    return {md.MD_OPT_KERNEL: ch["kernel"], md.MD_OPT_BRICK_DIMS: ch["brick_dims"] if ch["kernel"] == 0 else 0,
+            md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"]}
+
+
 def tune_options(md, system, precision):
     """md_autotune on the workload; returns the options it chose."""
     sim = md.Simulation(system, precision=precision, want_e_atom=False)
     ch = sim.autotune(trials=3)
     log(f"autotune {precision}: {ch}")
-    opts = {md.MD_OPT_KERNEL: ch["kernel"], md.MD_OPT_BRICK_DIMS: ch["brick_dims"] if ch["kernel"] == 0 else 0,
-            md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"]}
     del sim
-    return opts, ch
+    return choice_options(md, ch), ch
+
+
+def nvt_vs_nve(md, system, name, steps, warmup, ch, precision="mixed", tau_fs=100.0):
+    """A batched workload with a Nose-Hoover thermostat per replica (target:
+    the replica's initial temperature; Q = g k_B T tau^2) timed beside the
+    same run without it, with the same kernel settings: atom-steps/s of both."""
+    opts = choice_options(md, ch)
+    targets = np.asarray(system.temperature, np.float64)
+    n = np.diff(system.atom_offset)
+    n_mobile = np.array([int((system.rigid[a:b] == 0).sum()) for a, b in zip(system.atom_offset[:-1],
+                                                                            system.atom_offset[1:])])
+    dof = np.where(n_mobile < n, 3 * n_mobile, np.maximum(3 * n_mobile - 3, 1))
+    from paper_1107_2619_amd.inputs import KB_EV
+
+    q = dof * KB_EV * np.maximum(targets, 1.0) * tau_fs**2
+    sim, ms_nve, _, _, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts)
+    del sim
+    sim, ms_nvt, _, _, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts,
+                                         nvt=(targets, q))
+    del sim
+    nve = system.n_atoms * steps / (ms_nve * 1e-3)
+    nvt = system.n_atoms * steps / (ms_nvt * 1e-3)
+    log(f"{name} NVT: {nvt:.3e} atom-steps/s, NVE {nve:.3e} ({ms_nvt / ms_nve - 1.0:+.1%})")
+    return {"workload": name, "n_replicas": system.n_replicas, "n_atoms": system.n_atoms, "precision": precision,
+            "steps": steps, "tau_fs": tau_fs, "nvt": nvt, "nve": nve, "overhead": ms_nvt / ms_nve - 1.0,
+            "nvt_ms_per_step": ms_nvt / steps}
 
 
 def batched_vs_one_by_one(md, system, name, steps, warmup, precision="mixed"):
@@ -172,6 +204,8 @@ def main():
                     help="comma-separated batched workloads to run together and one by one ('' = none)")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
+    ap.add_argument("--nvt-steps", type=int, default=100,
+                    help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -238,6 +272,10 @@ def main():
 
     batched = [batched_vs_one_by_one(md, system_b, w, args.batched_steps, args.warmup)
                for w, system_b in batched_sys.items()]
+    nvt_rec = None
+    if "fec256" in batched_sys and args.nvt_steps > 0:
+        ch_fec = next(b["autotuned"] for b in batched if b["workload"] == "fec256")
+        nvt_rec = nvt_vs_nve(md, batched_sys["fec256"], "fec256", args.nvt_steps, args.warmup, ch_fec)
     if "liquid4096" in batched_sys:  # cfg5 also compares FP64 with mixed
         batched.append(batched_vs_one_by_one(md, batched_sys["liquid4096"], "liquid4096", args.batched_steps,
                                              args.warmup, precision="fp64"))
@@ -350,6 +388,7 @@ def main():
         "mixed": rec["mixed"],
         "half_list_atomics": half,
         "batched_vs_one_by_one": batched,
+        "nvt_batched": nvt_rec,
         "piston_slab": piston_rec,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -162,8 +162,10 @@ def test_nvt_graph_replay_matches_eager(md, precision, kernel):
     for use_graph in (0, 1):
         sim = md.Simulation(s, precision=precision, nh_temperature=targets, nh_mass=q)
         if kernel == "brick":
-            sim.set_option(md.MD_OPT_KERNEL, 1)
+            sim.set_option(md.MD_OPT_KERNEL, 0)
             sim.set_option(md.MD_OPT_BRICK_DIMS, 444)
+        else:
+            sim.set_option(md.MD_OPT_KERNEL, 1)
         sim.set_option(md.MD_OPT_USE_GRAPH, use_graph)
         sim.step(60)
         e = sim.energy()
@@ -180,7 +182,7 @@ def test_nvt_brick_matches_oracle(md, orc):
     t, q = [500.0], _masses(s, [500.0])
     announce("nvt brick fp64")
     sim = md.Simulation(s, nh_temperature=t, nh_mass=q)
-    sim.set_option(md.MD_OPT_KERNEL, 1)
+    sim.set_option(md.MD_OPT_KERNEL, 0)
     sim.set_option(md.MD_OPT_BRICK_DIMS, 222)
     sim.step(50)
     ref = _oracle(orc, s, 0, 50, t[0], q[0])
