@@ -8,7 +8,9 @@ The arithmetic lives in ``eam_oracle.c`` (brute force O(N^2), FP64); this module
 compiles it with gcc and marshals numpy arrays through ctypes.  Every function
 follows the paper (MOLDY, "Theoretical background" Eq. Ucoh for the energy,
 "Boundary conditions" for the image vector, "Time integration" and "Fixed
-atoms" for the integrator, "Units" for the time unit).
+atoms" for the integrator, "Thermostat NVTp" for the Nose-Hoover run, "Units"
+for the time unit).  The mean square displacement and the diffusion estimate
+("Self-diffusion in iron") are plain numpy.
 """
 from __future__ import annotations
 
@@ -343,3 +345,40 @@ def temperature(ke: float, n_mobile: int, has_rigid: bool) -> float:
     conservation."""
     dof = 3 * n_mobile if has_rigid else 3 * n_mobile - 3
     return 0.0 if dof <= 0 else 2.0 * ke / (dof * boltzmann_ev())
+
+
+def msd(pos, pos0, species, atom_offset, n_species, rigid=None):
+    """Mean square displacement per replica and species ("Self-diffusion in
+    iron": the displacement squared, averaged over atoms), from unwrapped
+    positions ("Boundary conditions": trajectories are stored without
+    wraparound, so a displacement is a plain difference).  Rigid atoms are not
+    averaged.  Returns (msd [R, n_species] in A^2, count [R, n_species]); a
+    species with no atom in a replica has msd 0."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    pos0 = np.asarray(pos0, np.float64).reshape(-1, 3)
+    species = np.asarray(species).astype(np.int64)
+    mobile = np.ones(len(pos), bool) if rigid is None else np.asarray(rigid) == 0
+    off = np.asarray(atom_offset, np.int64)
+    n_rep = len(off) - 1
+    out = np.zeros((n_rep, n_species))
+    count = np.zeros((n_rep, n_species), np.int64)
+    for r in range(n_rep):
+        for s in range(n_species):
+            total = 0.0
+            for i in range(off[r], off[r + 1]):
+                if species[i] != s or not mobile[i]:
+                    continue
+                d = pos[i] - pos0[i]
+                total += d[0] * d[0] + d[1] * d[1] + d[2] * d[2]
+                count[r, s] += 1
+            out[r, s] = total / count[r, s] if count[r, s] else 0.0
+    return out, count
+
+
+def diffusion_coefficient(t_fs, msd_a2):
+    """D = lim MSD / (6 t) ("Self-diffusion in iron"), estimated as one sixth of
+    the least-squares slope of MSD against t; A^2/fs (x 0.1 gives cm^2/s)."""
+    t = np.asarray(t_fs, np.float64)
+    m = np.asarray(msd_a2, np.float64)
+    tm, mm = t.mean(), m.mean()
+    return float(np.sum((t - tm) * (m - mm)) / np.sum((t - tm) ** 2)) / 6.0

@@ -476,3 +476,69 @@ def test_nh_time_reversible(orc):
     assert np.max(np.abs(b.pos - s.pos)) < 1e-10
     assert np.max(np.abs(b.vel + s.vel)) < 1e-12
     assert abs(b.pi[-1]) < 1e-14
+
+
+# --- Mean square displacement and diffusion ("Self-diffusion in iron") -------
+
+def test_msd_worked_example(orc):
+    """Three atoms displaced by 1, 2 and 3 A along different axes: MSD 14/3 A^2;
+    split by species, (1 + 4) / 2 and 9; a rigid atom is left out."""
+    p0 = np.zeros((3, 3))
+    p = np.array([[1.0, 0, 0], [0, 2.0, 0], [0, 0, 3.0]])
+    m, c = orc.msd(p, p0, [0, 0, 0], [0, 3], 1)
+    assert m[0, 0] == pytest.approx(14.0 / 3.0, rel=1e-15) and c[0, 0] == 3
+    m, c = orc.msd(p, p0, [0, 0, 1], [0, 3], 2)
+    assert m[0].tolist() == [2.5, 9.0] and c[0].tolist() == [2, 1]
+    m, c = orc.msd(p, p0, [0, 0, 0], [0, 3], 2, rigid=[0, 1, 0])
+    assert m[0].tolist() == [5.0, 0.0] and c[0].tolist() == [2, 0]
+
+
+def test_msd_uniform_translation_and_permutation(orc, rng):
+    """A rigid translation d of every atom gives |d|^2 in every replica and
+    species; reordering atoms inside a replica changes nothing."""
+    n = 300
+    p0 = rng.uniform(0, 20, (n, 3))
+    sp = rng.integers(0, 2, n)
+    off = [0, 100, 100, 300]
+    d = np.array([0.3, -1.7, 2.2])
+    m, c = orc.msd(p0 + d, p0, sp, off, 2)
+    nonempty = c > 0
+    assert np.allclose(m[nonempty], d @ d, rtol=1e-14) and np.all(m[~nonempty] == 0.0)
+    assert c[1].sum() == 0
+    p = p0 + rng.normal(0, 0.5, (n, 3))
+    perm = np.concatenate([rng.permutation(100), 100 + rng.permutation(200)])
+    m1, _ = orc.msd(p, p0, sp, off, 2)
+    m2, _ = orc.msd(p[perm], p0[perm], sp[perm], off, 2)
+    assert np.allclose(m1, m2, rtol=1e-13)
+
+
+def test_msd_ballistic_across_periodic_boundaries(orc):
+    """Isolated atoms (beyond the cutoff of each other) fly in straight lines
+    through the periodic box several times: the oracle's trajectory stays
+    unwrapped, so the MSD is |v|^2 t^2."""
+    from paper_1107_2619_amd import inputs
+
+    pot = orc.Potential(inputs.perturbed_potential("fe_fs", 1))
+    g = np.arange(4) * 7.0 + 1.0
+    pos = np.array([[x, y, z] for x in g for y in g for z in g])
+    v = np.array([0.031, -0.017, 0.024])
+    vel = np.tile(v, (len(pos), 1))
+    r = orc.run_verlet(pos, vel, np.zeros(len(pos), np.uint8), [28.0] * 3, [1, 1, 1], pot, 1.0, 2000)
+    m, _ = orc.msd(r.pos, pos, np.zeros(len(pos)), [0, len(pos)], 1)
+    assert np.max(np.abs(r.pos - pos)) > 2 * 28.0
+    assert m[0, 0] == pytest.approx((v @ v) * 2000.0**2, rel=1e-12)
+
+
+def test_diffusion_of_a_random_walk(orc):
+    """Gaussian random walks with per-axis step variance s^2 per dt have
+    MSD(n) = 3 n s^2, so D = s^2 / (2 dt); the estimate from 4000 seeded
+    walkers over 400 steps lands within 3%."""
+    rng = np.random.default_rng(77)
+    s, dt, n_w, n_t = 0.1, 2.0, 4000, 400
+    steps = rng.normal(0.0, s, (n_t, n_w, 3))
+    paths = np.cumsum(steps, 0)
+    t = dt * np.arange(1, n_t + 1)
+    msd_t = np.array([orc.msd(paths[k], np.zeros((n_w, 3)), np.zeros(n_w), [0, n_w], 1)[0][0, 0]
+                      for k in range(0, n_t, 20)])
+    d = orc.diffusion_coefficient(t[::20], msd_t)
+    assert d == pytest.approx(s * s / (2 * dt), rel=0.03)
