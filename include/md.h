@@ -186,6 +186,22 @@ int md_step(md_ctx *ctx, int32_t nsteps, void *stream);
  * per-replica energies of the last evaluated state to out[0..R). */
 int md_energy(md_ctx *ctx, md_energies *out, void *stream);
 
+/* Mean square displacement per replica and species (paper, "Self-diffusion
+ * in iron": D = lim MSD / 6t, the MSD averaged over atoms), from the unwrapped
+ * positions ("Boundary conditions": no wraparound).  msd[r * S + s] (Angstrom^2,
+ * S = n_species) is the mean of |x_i - x0_i|^2 over the mobile atoms i of
+ * replica r with species s, x the positions in the bound state arrays now and
+ * x0 the origin: the positions at md_bind or at the last md_msd_origin.
+ * count[r * S + s] receives the number of such atoms (msd is 0 where it is 0);
+ * count may be NULL.  Rigid atoms are left out.  msd and count are host arrays
+ * of R * S entries, written once the work already on the stream has finished
+ * (the call synchronises the stream). */
+int md_msd(md_ctx *ctx, double *msd, int64_t *count, void *stream);
+
+/* Takes the positions in the bound state arrays as the new origin x0 of md_msd
+ * (device copies enqueued on the stream; md_bind sets the origin as well). */
+int md_msd_origin(md_ctx *ctx, void *stream);
+
 /* Test and tuning helpers.
  * md_copy_neighbours: synchronises and copies the current list to host memory
  *   in the caller's atom numbering: counts[N] and list[N][cap] (row-major,

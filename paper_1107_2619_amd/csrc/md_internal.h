@@ -160,6 +160,10 @@ struct Buffers {
     double* nh_state;     // [R][4] pi (1/fs), xi, velocity scale of the last update, KE after it (eV)
     double* nh_partial;   // [n_chunks] kinetic energy per reduction chunk
     double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
+    double* x0[3];        // [N] origin positions of the mean square displacement, caller order
+    uint8_t* ctype;       // [N] species | rigid bit, caller order
+    double* msd_partial;  // [n_chunks][2 * MD_MAX_SPECIES] sums of d^2 and atom counts
+    double* msd_out;      // [R][2 * MD_MAX_SPECIES] msd per species, then counts
     // local-polynomial tables, [ns*ns][nbt][kForceStride] (phi' and rho' quadratics),
     // [ns*ns][nbt][4] (phi cubic), [ns*ns][nbt][4] (rho cubic)
     double *tab_force64, *tab_energy64, *tab_dens64;
@@ -212,6 +216,9 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
                     hipStream_t s);
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s);
 // Brick path (kernels_brick.hip).
+// Launchers (kernels_analysis.hip).
+void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);
+
 void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, hipStream_t s);
 void launch_brick_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                           int energy, hipStream_t s);

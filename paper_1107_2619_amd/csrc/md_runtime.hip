@@ -364,6 +364,10 @@ void plan_workspace(md_ctx* c)
         C * 4,                                               // cell_rep (C_alloc)
         C * 27 * 8,                                          // cell_adj
         C * 4,                                               // cell_coord
+        (size_t)c->N * 8, (size_t)c->N * 8, (size_t)c->N * 8,  // x0[3]
+        (size_t)c->N,                                        // ctype
+        std::max<size_t>(c->chunk_rep.size(), 1) * 2 * MD_MAX_SPECIES * 8,  // msd_partial
+        (size_t)c->R * 2 * MD_MAX_SPECIES * 8,               // msd_out
     };
     c->off.clear();
     size_t o = 0;
@@ -436,6 +440,10 @@ void bind_buffers(md_ctx* c)
     at(b.cell_rep);
     at(b.cell_adj);
     at(b.cell_coord);
+    for (int a = 0; a < 3; ++a) at(b.x0[a]);
+    at(b.ctype);
+    at(b.msd_partial);
+    at(b.msd_out);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -906,6 +914,18 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
             return MD_ERR_DEVICE;
         c->nh_gkt.assign(param.begin(), param.end());
     }
+    if (c->N > 0) {
+        // mean square displacement: species and rigid flag in caller order, and
+        // the bound positions as the origin
+        std::vector<uint8_t> ct(c->N);
+        for (int64_t i = 0; i < c->N; ++i) ct[i] = (uint8_t)(sp[i] | (rg[i] ? kRigidBit : 0));
+        const size_t nb = (size_t)c->N * 8;
+        if (!hip_ok(c, hipMemcpy(c->buf.ctype, ct.data(), c->N, hipMemcpyHostToDevice), "md_bind msd") ||
+            !hip_ok(c, hipMemcpy(c->buf.x0[0], st->x, nb, hipMemcpyDeviceToDevice), "md_bind msd") ||
+            !hip_ok(c, hipMemcpy(c->buf.x0[1], st->y, nb, hipMemcpyDeviceToDevice), "md_bind msd") ||
+            !hip_ok(c, hipMemcpy(c->buf.x0[2], st->z, nb, hipMemcpyDeviceToDevice), "md_bind msd"))
+            return MD_ERR_DEVICE;
+    }
     c->bound = true;
     c->drop_graphs();
     if (!build_cell_table(c)) return MD_ERR_DEVICE;
@@ -1071,6 +1091,40 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
         counts[a] = cnt[t];
         for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[k * Np + t] & kIndexMask];
     }
+    return MD_OK;
+}
+
+int md_msd(md_ctx* c, double* msd, int64_t* count, void* stream)
+{
+    if (!c || !msd) return fail(c, MD_ERR_ARG, "md_msd: NULL argument");
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_msd: call md_bind first");
+    hipStream_t s = as_stream(stream);
+    launch_msd(c->buf, shape(c), c->st, s);
+    const int ns = c->pot.ns;
+    std::vector<double> out((size_t)c->R * 2 * MD_MAX_SPECIES);
+    if (!hip_ok(c, hipGetLastError(), "md_msd launch") ||
+        !hip_ok(c, hipMemcpyAsync(out.data(), c->buf.msd_out, out.size() * 8, hipMemcpyDeviceToHost, s), "md_msd copy") ||
+        !hip_ok(c, hipStreamSynchronize(s), "md_msd sync"))
+        return MD_ERR_DEVICE;
+    for (int r = 0; r < c->R; ++r)
+        for (int k = 0; k < ns; ++k) {
+            msd[(size_t)r * ns + k] = out[(size_t)r * 2 * MD_MAX_SPECIES + k];
+            if (count) count[(size_t)r * ns + k] = (int64_t)out[(size_t)r * 2 * MD_MAX_SPECIES + MD_MAX_SPECIES + k];
+        }
+    return MD_OK;
+}
+
+int md_msd_origin(md_ctx* c, void* stream)
+{
+    if (!c) return MD_ERR_ARG;
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_msd_origin: call md_bind first");
+    if (c->N == 0) return MD_OK;
+    hipStream_t s = as_stream(stream);
+    const size_t nb = (size_t)c->N * 8;
+    if (!hip_ok(c, hipMemcpyAsync(c->buf.x0[0], c->st.x, nb, hipMemcpyDeviceToDevice, s), "md_msd_origin") ||
+        !hip_ok(c, hipMemcpyAsync(c->buf.x0[1], c->st.y, nb, hipMemcpyDeviceToDevice, s), "md_msd_origin") ||
+        !hip_ok(c, hipMemcpyAsync(c->buf.x0[2], c->st.z, nb, hipMemcpyDeviceToDevice, s), "md_msd_origin"))
+        return MD_ERR_DEVICE;
     return MD_OK;
 }
 

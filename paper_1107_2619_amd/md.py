@@ -41,7 +41,7 @@ KERNEL_GROUPS = ("build", "density", "force", "reduce")
 EXPORTED = [
     "md_create", "md_workspace_bytes", "md_bind", "md_build_neighbours", "md_eam_forces", "md_step",
     "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_autotune",
-    "md_destroy", "md_last_error",
+    "md_msd", "md_msd_origin", "md_destroy", "md_last_error",
 ]
 
 
@@ -122,6 +122,8 @@ def library():
     lib.md_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.md_kernel_times.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.md_autotune.argtypes = [vp, i32, vp]
+    lib.md_msd.argtypes = [vp, vp, vp, vp]
+    lib.md_msd_origin.argtypes = [vp, vp]
     lib.md_destroy.argtypes = [vp]
     lib.md_destroy.restype = None
     lib.md_last_error.argtypes = [vp]
@@ -182,6 +184,7 @@ class Context:
             raise MDError(rc, msg)
         self.n_replicas = len(k["off"]) - 1
         self.n_atoms = int(k["off"][-1])
+        self.n_species = ns
 
     def _check(self, rc):
         if rc != MD_OK:
@@ -308,6 +311,19 @@ class Simulation:
         return Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"), g("piston_work"),
                         np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"),
                         g("nh_pi"), g("nh_energy"))
+
+    def msd(self):
+        """(msd [R, n_species] A^2, count [R, n_species]): mean square displacement
+        of the mobile atoms from the origin positions (md_msd)."""
+        shape = (self.ctx.n_replicas, self.ctx.n_species)
+        out = np.zeros(shape)
+        cnt = np.zeros(shape, np.int64)
+        self.ctx._check(self.ctx.lib.md_msd(self.ctx.handle, out.ctypes.data, cnt.ctypes.data, self.stream))
+        return out, cnt
+
+    def msd_origin(self):
+        """Take the current positions as the origin of msd() (md_msd_origin)."""
+        self.ctx._check(self.ctx.lib.md_msd_origin(self.ctx.handle, self.stream))
 
     def neighbours(self):
         """(counts[N], list[N, cap]) in caller numbering."""

@@ -137,3 +137,13 @@ def test_thermostat_validation(md):
         with pytest.raises(md.MDError) as e:
             _ctx(md, **kw)
         assert e.value.code == md.MD_ERR_ARG
+
+
+def test_msd_needs_a_bound_state(md):
+    """md_msd and md_msd_origin refuse an unbound context before any device work."""
+    c = _ctx(md)
+    out = np.zeros(1)
+    assert c.lib.md_msd(c.handle, out.ctypes.data, None, None) == md.MD_ERR_STATE
+    assert c.lib.md_msd_origin(c.handle, None) == md.MD_ERR_STATE
+    assert c.lib.md_msd(c.handle, None, None, None) == md.MD_ERR_ARG
+    assert c.lib.md_msd(None, out.ctypes.data, None, None) == md.MD_ERR_ARG
