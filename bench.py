@@ -135,14 +135,7 @@ def nvt_vs_nve(md, system, name, steps, warmup, ch, precision="mixed", tau_fs=10
     the replica's initial temperature; Q = g k_B T tau^2) timed beside the
     same run without it, with the same kernel settings: atom-steps/s of both."""
     opts = choice_options(md, ch)
-    targets = np.asarray(system.temperature, np.float64)
-    n = np.diff(system.atom_offset)
-    n_mobile = np.array([int((system.rigid[a:b] == 0).sum()) for a, b in zip(system.atom_offset[:-1],
-                                                                            system.atom_offset[1:])])
-    dof = np.where(n_mobile < n, 3 * n_mobile, np.maximum(3 * n_mobile - 3, 1))
-    from paper_1107_2619_amd.inputs import KB_EV
-
-    q = dof * KB_EV * np.maximum(targets, 1.0) * tau_fs**2
+    targets, q = nh_masses(system, tau_fs)
     sim, ms_nve, _, _, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts)
     del sim
     sim, ms_nvt, _, _, _ = run_precision(md, system, precision, steps, warmup, timing=False, tune=opts,
@@ -191,6 +184,63 @@ def batched_vs_one_by_one(md, system, name, steps, warmup, precision="mixed"):
     }
 
 
+def nh_masses(system, tau_fs):
+    """Thermostat mass per replica, Q = g k_B T tau^2 (g as in the temperature)."""
+    from paper_1107_2619_amd.inputs import KB_EV
+
+    targets = np.asarray(system.temperature, np.float64)
+    n = np.diff(system.atom_offset)
+    n_mobile = np.array([int((system.rigid[a:b] == 0).sum()) for a, b in zip(system.atom_offset[:-1],
+                                                                            system.atom_offset[1:])])
+    dof = np.where(n_mobile < n, 3 * n_mobile, np.maximum(3 * n_mobile - 3, 1))
+    return targets, dof * KB_EV * np.maximum(targets, 1.0) * tau_fs**2
+
+
+def diffusion_leg(md, system, name, steps, warmup, sample_every, precision="mixed", tau_fs=100.0):
+    """The self-diffusion workload ("Self-diffusion in iron"): every replica
+    thermostatted at its own temperature, the mean square displacement
+    sampled every `sample_every` steps inside the timed region (each sample
+    synchronises), then the md_msd call on its own."""
+    import torch
+
+    log(f"{name}: {system.n_replicas} replicas, {system.n_atoms} atoms, {precision}, NVT, "
+        f"MSD every {sample_every} steps")
+    opts, ch = tune_options(md, system, precision)
+    targets, q = nh_masses(system, tau_fs)
+    sim = md.Simulation(system, precision=precision, want_e_atom=False, nh_temperature=targets, nh_mass=q)
+    for opt, val in opts.items():
+        sim.set_option(opt, val)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    for _ in range(2):
+        sim.step(max(warmup, 4 * system.rebuild_every + 2))
+    sim.msd_origin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    samples = []
+    for _ in range(steps // sample_every):
+        sim.step(sample_every)
+        samples.append(sim.msd()[0][:, 0])
+    elapsed = time.perf_counter() - t0
+    n_steps = sample_every * (steps // sample_every)
+    t1 = time.perf_counter()
+    for _ in range(50):
+        sim.msd()
+    msd_call_us = (time.perf_counter() - t1) / 50 * 1e6
+    en = sim.energy()
+    last = samples[-1]
+    by_t = {}
+    for t in np.unique(targets):
+        sel = targets == t
+        by_t[f"{t:.0f}"] = {"msd_A2": float(last[sel].mean()), "temperature_K": float(en.temperature[sel].mean())}
+    value = system.n_atoms * n_steps / elapsed
+    log(f"{name}: {value:.3e} atom-steps/s with MSD sampling, md_msd call {msd_call_us:.1f} us")
+    del sim
+    return {"workload": name, "n_replicas": system.n_replicas, "n_atoms": system.n_atoms, "precision": precision,
+            "steps": n_steps, "sample_every": sample_every, "tau_fs": tau_fs, "value": value,
+            "ms_per_step": elapsed * 1e3 / n_steps, "msd_call_us": msd_call_us, "autotuned": ch,
+            "by_temperature_after_run": by_t}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +256,8 @@ def main():
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
     ap.add_argument("--nvt-steps", type=int, default=100,
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
+    ap.add_argument("--diffusion-steps", type=int, default=1000,
+                    help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -224,6 +276,7 @@ def main():
         batched_sys[w] = inputs.workload(w, **kw)
         log(f"built {w} in {time.perf_counter() - t:.1f} s")
     piston = inputs.workload("fcc_piston") if args.piston_steps > 0 else None
+    vacancy = inputs.workload("vacancy192") if args.diffusion_steps > 0 else None
 
     import torch
 
@@ -279,6 +332,10 @@ def main():
     if "liquid4096" in batched_sys:  # cfg5 also compares FP64 with mixed
         batched.append(batched_vs_one_by_one(md, batched_sys["liquid4096"], "liquid4096", args.batched_steps,
                                              args.warmup, precision="fp64"))
+
+    diffusion = None
+    if vacancy is not None:
+        diffusion = diffusion_leg(md, vacancy, "vacancy192", args.diffusion_steps, args.warmup, 100)
 
     # the free-surface piston slab (2.88 M atoms, mixed)
     piston_rec = None
@@ -389,6 +446,7 @@ def main():
         "half_list_atomics": half,
         "batched_vs_one_by_one": batched,
         "nvt_batched": nvt_rec,
+        "diffusion": diffusion,
         "piston_slab": piston_rec,
         "roofline": roofline,
         "cpu_baseline": cpu,

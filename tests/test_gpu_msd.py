@@ -128,3 +128,23 @@ def test_msd_batched_equals_one_by_one(md):
         one.step(20)
         m1, _ = one.msd()
         assert np.array_equal(m1[0], m[r])
+
+
+def test_msd_vacancy_workload_nvt(md, orc):
+    """The self-diffusion workload at its replica shape (1999-atom bcc Fe with
+    a vacancy) under the thermostat at 900 and 2000 K: per-replica MSD after
+    100 FP64 steps against the oracle's NVT trajectory."""
+    s = inputs.vacancy_replicas(temperatures=(900, 2000), per_temperature=1)
+    kb = 8.617333262e-5
+    q = np.array([(3 * 1999 - 3) * kb * t * 100.0**2 for t in s.temperature])
+    announce("msd vacancy workload nvt")
+    sim = md.Simulation(s, nh_temperature=s.temperature, nh_mass=q)
+    sim.step(100)
+    m, _ = sim.msd()
+    for r in range(s.n_replicas):
+        sub = s.replica(r)
+        ref = orc.run_nh(sub.pos, sub.vel, sub.species, sub.box[0], sub.periodic[0], orc.Potential(sub.potential),
+                         sub.dt_fs, 100, float(s.temperature[r]), float(q[r]))
+        m_ref, _ = orc.msd(ref.pos, sub.pos, sub.species, sub.atom_offset, 1)
+        np.testing.assert_allclose(m[r], m_ref[0], rtol=1e-7, atol=1e-12)
+    assert m[1, 0] > m[0, 0]

@@ -81,3 +81,17 @@ def test_fec_carbons_kept_apart():
         if len(c) > 1:
             d, _ = cKDTree(c, boxsize=s.box[r]).query(c, k=2)
             assert d[:, 1].min() >= 2.87 - 1e-9
+
+
+def test_vacancy_replicas_one_vacancy_each():
+    s = inputs.vacancy_replicas(temperatures=(900, 1500), per_temperature=3, cells=6, seed0=6100)
+    assert s.n_replicas == 6
+    assert np.all(np.diff(s.atom_offset) == 2 * 6**3 - 1)
+    assert s.temperature.tolist() == [900.0] * 3 + [1500.0] * 3
+    # each replica misses a different (seeded) lattice site
+    firsts = {tuple(np.round(s.pos[a:b].sum(0), 6)) for a, b in zip(s.atom_offset[:-1], s.atom_offset[1:])}
+    assert len(firsts) > 1
+    s2 = inputs.vacancy_replicas(temperatures=(900, 1500), per_temperature=3, cells=6, seed0=6100)
+    assert np.array_equal(s.pos, s2.pos) and np.array_equal(s.vel, s2.vel)
+    full = inputs.workload("vacancy192")
+    assert full.n_replicas == 192 and full.n_atoms == 192 * 1999
