@@ -256,6 +256,8 @@ def main():
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
     ap.add_argument("--nvt-steps", type=int, default=100,
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
+    ap.add_argument("--evaluator-steps", type=int, default=100,
+                    help="steps of the table versus explicit evaluation comparison (0 = skip)")
     ap.add_argument("--diffusion-steps", type=int, default=1000,
                     help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -322,6 +324,23 @@ def main():
             half[prec] = {"value": n * args.half_steps / (ms_h * 1e-3), "ms_per_step": ms_h / args.half_steps}
             log(f"half list {prec}: {ms_h / args.half_steps * 1e3:.1f} us/step")
             del sim_h
+
+    # the paper's lookup-table versus explicit-evaluation comparison ("Parallel
+    # benchmarks"): the exact local-polynomial tables against the term-by-term
+    # knot sums, each precision with its autotuned kernel settings
+    evaluator = {}
+    if args.evaluator_steps > 0:
+        for prec in ("fp64", "mixed"):
+            opts = choice_options(md, tuned[prec])
+            rates = {}
+            for ev, label in ((0, "table"), (1, "explicit")):
+                sim_e, ms_e, _, _, _ = run_precision(md, system, prec, args.evaluator_steps, args.warmup,
+                                                     timing=False, tune={**opts, md.MD_OPT_EVALUATOR: ev})
+                rates[label] = n * args.evaluator_steps / (ms_e * 1e-3)
+                del sim_e
+            rates["table_speedup"] = rates["table"] / rates["explicit"]
+            evaluator[prec] = rates
+            log(f"evaluator {prec}: table {rates['table']:.3e}, explicit {rates['explicit']:.3e} atom-steps/s")
 
     batched = [batched_vs_one_by_one(md, system_b, w, args.batched_steps, args.warmup)
                for w, system_b in batched_sys.items()]
@@ -444,6 +463,7 @@ def main():
         "fp64": rec["fp64"],
         "mixed": rec["mixed"],
         "half_list_atomics": half,
+        "table_vs_explicit": evaluator,
         "batched_vs_one_by_one": batched,
         "nvt_batched": nvt_rec,
         "diffusion": diffusion,
