@@ -85,6 +85,8 @@ def _load():
     lib.or_kinetic.argtypes = [i64, vp, vp, vp, vp, vp, P]
     lib.or_run_verlet.restype = i32
     lib.or_run_verlet.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
+    lib.or_run_gear.restype = i32
+    lib.or_run_gear.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
     lib.or_run_nh.restype = i32
     lib.or_run_nh.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, d, d, d, vp, vp, vp, vp, vp]
     _lib = lib
@@ -290,6 +292,33 @@ def run_verlet(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps,
     ke = np.zeros(nsteps + 1)
     wk = np.zeros(nsteps + 1)
     rc = _load().or_run_verlet(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data,
+        vz.ctypes.data, sp.ctypes.data, _ptr(rg), box.ctypes.data, per.ctypes.data, pot.ref,
+        float(dt_fs), _ptr(vp), int(nsteps), f.ctypes.data, pe.ctypes.data, ke.ctypes.data,
+        wk.ctypes.data,
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return RunResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, wk)
+
+
+def run_gear(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps, rigid=None,
+             rigid_velocity=None) -> RunResult:
+    """Third-order Gear predictor-corrector (paper, "Time integration") with
+    brute-force forces; pe[s] at the predicted positions of step s, ke[s] of
+    the corrected velocities, work[s] by the trapezoid rule over the
+    evaluations."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    vp = None if rigid_velocity is None else _f64(rigid_velocity)
+    box = _f64(box)
+    per = _u8(periodic)
+    f = np.zeros((n, 3))
+    pe, ke, wk = np.zeros(nsteps + 1), np.zeros(nsteps + 1), np.zeros(nsteps + 1)
+    rc = _load().or_run_gear(
         n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data,
         vz.ctypes.data, sp.ctypes.data, _ptr(rg), box.ctypes.data, per.ctypes.data, pot.ref,
         float(dt_fs), _ptr(vp), int(nsteps), f.ctypes.data, pe.ctypes.data, ke.ctypes.data,

@@ -590,6 +590,106 @@ done:
     return rc;
 }
 
+/*
+ * Third-order Gear predictor-corrector (paper, "Time integration": the
+ * alternative to velocity Verlet).  Gear's method for a second-order equation
+ * carries four values per coordinate, the position r0 and the scaled time
+ * derivatives r1 = h v, r2 = h^2 a / 2, r3 = h^3 b / 6.  Each step:
+ *   predict  the Taylor series: r0 += r1 + r2 + r3, r1 += 2 r2 + 3 r3,
+ *            r2 += 3 r3 (binomial coefficients);
+ *   evaluate the forces at the predicted positions;
+ *   correct  with e = h^2 f / (2 m) - r2: r_k += c_k e, c = {1/6, 5/6, 1, 1/3}.
+ * Start: a = f(x0) / m, b = 0.  pe_out[s] is the potential energy of the force
+ * evaluation of step s (at the predicted positions; s = 0: at x0), ke_out[s]
+ * the kinetic energy of the corrected velocities.  Rigid atoms move on
+ * x0 + vp t; work_out[s] integrates their power -f . vp over the evaluations
+ * of steps 0..s by the trapezoid rule.
+ */
+int or_run_gear(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                const uint8_t *species, const uint8_t *rigid, const double *box, const uint8_t *periodic,
+                const or_potential *p, double dt_fs, const double *vp_fs, int64_t nsteps, double *f,
+                double *pe_out, double *ke_out, double *work_out)
+{
+    static const double c[4] = {1.0 / 6.0, 5.0 / 6.0, 1.0, 1.0 / 3.0};
+    const double t0 = or_time_unit_fs();
+    const double h = dt_fs / t0;
+    double vp[3] = {0.0, 0.0, 0.0};
+    if (vp_fs)
+        for (int a = 0; a < 3; ++a) vp[a] = vp_fs[a] * t0;
+    double *v[3] = {vx, vy, vz};
+    double *r0[3] = {x, y, z};
+    const size_t m3 = 3 * (size_t)(n > 0 ? n : 1);
+    double *r1 = (double *)malloc(sizeof(double) * m3);
+    double *r2 = (double *)malloc(sizeof(double) * m3);
+    double *r3 = (double *)malloc(sizeof(double) * m3);
+    double *rigid0 = (double *)malloc(sizeof(double) * m3);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            v[a][i] *= t0;
+            rigid0[3 * i + a] = r0[a][i];
+        }
+    double pe, work = 0.0, power_prev = 0.0;
+    int rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+    if (rc) goto done;
+    power_prev = -rigid_power(n, f, rigid, vp);
+    for (int64_t i = 0; i < n; ++i) {
+        const double m = p->mass[species[i]];
+        for (int a = 0; a < 3; ++a) {
+            r1[3 * i + a] = h * v[a][i];
+            r2[3 * i + a] = 0.5 * h * h * f[3 * i + a] / m;
+            r3[3 * i + a] = 0.0;
+        }
+    }
+    for (int64_t s = 0;; ++s) {
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) ke_out[s] = mobile_ke(n, v, species, rigid, p);
+        if (work_out) work_out[s] = work;
+        if (s == nsteps) break;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) {
+                const double t = (double)(s + 1) * h;
+                for (int a = 0; a < 3; ++a) r0[a][i] = rigid0[3 * i + a] + vp[a] * t;
+                continue;
+            }
+            for (int a = 0; a < 3; ++a) {
+                const size_t k = 3 * (size_t)i + a;
+                r0[a][i] += r1[k] + r2[k] + r3[k];
+                r1[k] += 2.0 * r2[k] + 3.0 * r3[k];
+                r2[k] += 3.0 * r3[k];
+            }
+        }
+        rc = or_forces(n, x, y, z, species, rigid, box, periodic, p, f, NULL, NULL, NULL, &pe);
+        if (rc) goto done;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rigid && rigid[i]) continue;
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) {
+                const size_t k = 3 * (size_t)i + a;
+                const double e = 0.5 * h * h * f[k] / m - r2[k];
+                r0[a][i] += c[0] * e;
+                r1[k] += c[1] * e;
+                r2[k] += c[2] * e;
+                r3[k] += c[3] * e;
+                v[a][i] = r1[k] / h;
+            }
+        }
+        const double power = -rigid_power(n, f, rigid, vp);
+        work += 0.5 * h * (power_prev + power);
+        power_prev = power;
+    }
+done:
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+        if (rigid && rigid[i])
+            for (int a = 0; a < 3; ++a) v[a][i] = vp_fs ? vp_fs[a] : 0.0;
+    }
+    free(r1);
+    free(r2);
+    free(r3);
+    free(rigid0);
+    return rc;
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP
