@@ -56,6 +56,7 @@ enum {
 
 enum { MD_FP64 = 0, MD_MIXED = 1 };              /* md_config.precision */
 enum { MD_NBR_FULL = 0, MD_NBR_HALF_ATOMIC = 1 }; /* md_config.nbr_mode  */
+enum { MD_VERLET = 0, MD_GEAR3 = 1 };             /* md_config.integrator */
 
 #define MD_MAX_SPECIES 4
 #define MD_MAX_KNOTS 8
@@ -112,6 +113,16 @@ typedef struct {
      * NVE; both set = every replica thermostatted. */
     const double *nh_temperature; /* [R] target temperature, K, >= 0 */
     const double *nh_mass;        /* [R] thermostat mass Q, eV fs^2, > 0 */
+    /* Time integration ("Time integration"): MD_VERLET (velocity Verlet) or
+     * MD_GEAR3, the third-order Gear predictor-corrector, which carries the
+     * acceleration and its time derivative beside x and v.  Those two live in
+     * the workspace: the first md_step after md_bind starts them (a = f/m,
+     * da/dt = 0) and later calls continue from them, so x and v should change
+     * between md_step calls only through md_step (or md_bind again).  Forces
+     * and potential energy are those at the predicted positions of the last
+     * step; rigid atoms' work uses the trapezoid rule over the evaluations.
+     * MD_GEAR3 runs NVE only (no thermostat). */
+    int32_t integrator;
 } md_config;
 
 /*

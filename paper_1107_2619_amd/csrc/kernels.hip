@@ -254,6 +254,13 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
         b.type[qn][u] = b.type[q][t];
         b.cell_sorted[u] = b.cell_of[t];
         b.pwork[qn][u] = b.pwork[q][t];
+        if (b.acc[q][0]) {  // Gear integrator state travels with its atom
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b.acc[qn][a][u] = b.acc[q][a][t];
+                b.jrk[qn][a][u] = b.jrk[q][a][t];
+            }
+        }
     } else {
         const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
         b.pos[pn][u] = z;
@@ -267,6 +274,13 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
         b.type[qn][u] = kEmptySlot;
         b.pwork[qn][u] = 0.0;
         b.cell_sorted[u] = -1;
+        if (b.acc[q][0]) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b.acc[qn][a][u] = 0.0;
+                b.jrk[qn][a][u] = 0.0;
+            }
+        }
     }
 }
 
@@ -918,6 +932,134 @@ __global__ void k_nh_scale(Buffers b, int q, int64_t n_slots, md_state st, int e
 }
 
 // ---------------------------------------------------------------------------
+// Third-order Gear predictor-corrector (paper, "Time integration").  Per
+// coordinate the state is x, v, the acceleration a and its time derivative b.
+// The predictor is the Taylor series to third order; after the force pass at
+// the predicted positions the mismatch d = f/m - a_pred corrects the four
+// values with Gear's weights for second-order equations.  In unscaled form
+// (step h): x += h^2 d / 12, v += 5 h d / 12, a = f/m, b += d / h.  The force
+// pass keeps f (fhalf); the corrector runs as its own pass because every atom
+// must see its neighbours' predicted positions first.
+
+// a = f/m of the starting positions, b = 0.
+__global__ void k_gear_start(Buffers b, int q, int64_t n_slots, PotArgs P)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const uint8_t ty = b.type[q][t];
+    const double acc = (ty & kRigidBit) ? 0.0 : (P.ns == 1 ? P.accel : G.accel[ty & 0x3F]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b.acc[q][a][t] = acc * b.fhalf[a][t];
+        b.jrk[q][a][t] = 0.0;
+    }
+}
+
+// Predicted positions pos[p^1] (and their compact records).  Rigid atoms take
+// their next position on x0 + vp t and the first half of the step's work
+// from the force of the previous evaluation.
+__global__ void k_gear_predict(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, int compact)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const uint8_t ty = b.type[q][t];
+    const double3 x = load_xyz(b.pos[p], t);
+    double xn[3] = {x.x, x.y, x.z};
+    if (ty & kRigidBit) {
+        const double f[3] = {b.fhalf[0][t], b.fhalf[1][t], b.fhalf[2][t]};
+        b.pwork[q][t] += -(f[0] * R.vp[0] + f[1] * R.vp[1] + f[2] * R.vp[2]) * 0.5 * h;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xn[a] += h * R.vp[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double inc = b.vel[q][a][t] + h * (0.5 * b.acc[q][a][t] + (h / 6.0) * b.jrk[q][a][t]);
+            xn[a] = fma(h, inc, xn[a]);
+        }
+    }
+    double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
+    *reinterpret_cast<double2*>(dst) = make_double2(xn[0], xn[1]);
+    dst[2] = xn[2];
+    if (compact) {
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        int4 rq;
+        if (!compact_coords(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
+}
+
+// Corrector from pos[p] (predicted) into pos[p^1].  The last step of a call
+// takes f from the caller's arrays (its force pass wrote them), keeps it for
+// the next call, fixes the kinetic and work terms of the energy record and
+// writes the caller's x and v.
+__global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, md_state st, int last)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const uint8_t ty = b.type[q][t];
+    const int32_t id = b.id[q][t];
+    const double3 xp = load_xyz(b.pos[p], t);
+    double xc[3] = {xp.x, xp.y, xp.z};
+    double f[3];
+    if (last) {
+        f[0] = st.fx[id];
+        f[1] = st.fy[id];
+        f[2] = st.fz[id];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b.fhalf[a][t] = f[a];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f[a] = b.fhalf[a][t];
+    }
+    double v[3];
+    double ke = 0.0;
+    if (ty & kRigidBit) {
+        b.pwork[q][t] += -(f[0] * R.vp[0] + f[1] * R.vp[1] + f[2] * R.vp[2]) * 0.5 * h;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[a] = R.vp[a];
+    } else {
+        const int si = ty & 0x3F;
+        const double acc = P.ns == 1 ? P.accel : G.accel[si];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double a0 = b.acc[q][a][t], j0 = b.jrk[q][a][t];
+            const double an = acc * f[a];
+            const double d = an - fma(h, j0, a0);
+            v[a] = b.vel[q][a][t] + h * (a0 + 0.5 * h * j0) + (5.0 / 12.0) * h * d;
+            xc[a] += (h * h / 12.0) * d;
+            b.vel[q][a][t] = v[a];
+            b.acc[q][a][t] = an;
+            b.jrk[q][a][t] = j0 + d / h;
+        }
+        ke = (P.ns == 1 ? P.half_m : G.half_m[si]) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
+    double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
+    *reinterpret_cast<double2*>(dst) = make_double2(xc[0], xc[1]);
+    dst[2] = xc[2];
+    if (last) {
+        b.eslot[(int64_t)E_KE * n_slots + t] = ke;
+        b.eslot[(int64_t)E_PW * n_slots + t] = (ty & kRigidBit) ? b.pwork[q][t] : 0.0;
+        st.x[id] = xc[0] + b.img[q][0][t] * R.box[0];
+        st.y[id] = xc[1] + b.img[q][1][t] * R.box[1];
+        st.z[id] = xc[2] + b.img[q][2][t] * R.box[2];
+        st.vx[id] = v[0];
+        st.vy[id] = v[1];
+        st.vz[id] = v[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Half-list variant (MD_NBR_HALF_ATOMIC): the comparison form in which every
 // unordered pair is evaluated once, by its lower slot, and the partner's share
 // goes to memory with FP64 atomics; the paper's own OpenMP code resolves the
@@ -1287,6 +1429,25 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 {
     hipLaunchKernelGGL(k_nh_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
                        k.compact);
+}
+
+void launch_gear_start(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gear_start, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+}
+
+void launch_gear_predict(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gear_predict, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P,
+                       dt_fs, k.compact);
+}
+
+void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                         const md_state& st, int last, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gear_correct, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P,
+                       dt_fs, st, last);
 }
 
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s)

@@ -160,6 +160,8 @@ struct Buffers {
     double* nh_state;     // [R][4] pi (1/fs), xi, velocity scale of the last update, KE after it (eV)
     double* nh_partial;   // [n_chunks] kinetic energy per reduction chunk
     double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
+    double* acc[2][3];    // [Np] Gear integrator: acceleration, A/fs^2 (null with Verlet)
+    double* jrk[2][3];    // [Np] Gear integrator: its time derivative, A/fs^3
     double* x0[3];        // [N] origin positions of the mean square displacement, caller order
     uint8_t* ctype;       // [N] species | rigid bit, caller order
     double* msd_partial;  // [n_chunks][2 * MD_MAX_SPECIES] sums of d^2 and atom counts
@@ -216,6 +218,12 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
                     hipStream_t s);
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s);
 // Brick path (kernels_brick.hip).
+void launch_gear_start(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, hipStream_t s);
+void launch_gear_predict(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                         hipStream_t s);
+void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                         const md_state& st, int last, hipStream_t s);
+
 // Launchers (kernels_analysis.hip).
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);
 

@@ -19,6 +19,8 @@ struct md_ctx {
     bool compact_ok = false;
     bool compact_on = true;  // MD_OPT_COMPACT
     bool nvt = false;        // Nose-Hoover thermostat per replica
+    bool gear = false;       // third-order Gear predictor-corrector instead of Verlet
+    bool gear_ready = false; // Gear derivatives started since md_bind
     std::vector<double> nh_T, nh_Q;
     std::vector<double> nh_gkt;  // host copy of nh_param
     std::vector<int64_t> atom_off;
@@ -321,6 +323,8 @@ void plan_workspace(md_ctx* c)
     size_t max_bricks = 0;
     for (int r = 0; r < c->R; ++r)
         max_bricks += (size_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
+    const bool keep_f = c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt || c->gear;
+    const size_t gear = c->gear ? Np * 8 : 0;
     std::vector<size_t> sizes = {
         Np * 32, Np * 32,                                    // pos[2]
         Np * 8, Np * 8, Np * 8, Np * 8, Np * 8, Np * 8,      // vel[2][3]
@@ -343,9 +347,9 @@ void plan_workspace(md_ctx* c)
         (size_t)c->R * kEnergySlots * 8,                     // energies
         c->chunk_rep.size() * 4, c->chunk_off.size() * 4,     // reduction chunks
         c->chunk_rep.size() * kEnergySlots * 8,
-        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,  // fhalf[3] (also the thermostat's forces)
-        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,
-        (c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt) ? Np * 8 : 0,
+        keep_f ? Np * 8 : 0,  // fhalf[3] (also the forces kept by the thermostat and the Gear steps)
+        keep_f ? Np * 8 : 0,
+        keep_f ? Np * 8 : 0,
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // rhalf
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // ehalf
         (size_t)c->R * 16, (size_t)c->R * 32,                // nh_param, nh_state
@@ -368,6 +372,8 @@ void plan_workspace(md_ctx* c)
         (size_t)c->N,                                        // ctype
         std::max<size_t>(c->chunk_rep.size(), 1) * 2 * MD_MAX_SPECIES * 8,  // msd_partial
         (size_t)c->R * 2 * MD_MAX_SPECIES * 8,               // msd_out
+        gear, gear, gear, gear, gear, gear,                  // acc[2][3]
+        gear, gear, gear, gear, gear, gear,                  // jrk[2][3]
     };
     c->off.clear();
     size_t o = 0;
@@ -444,6 +450,13 @@ void bind_buffers(md_ctx* c)
     at(b.ctype);
     at(b.msd_partial);
     at(b.msd_out);
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 3; ++a) at(b.acc[k][a]);
+    for (int k = 0; k < 2; ++k)
+        for (int a = 0; a < 3; ++a) at(b.jrk[k][a]);
+    if (!c->gear)  // the sort moves Gear state only where it exists
+        for (int k = 0; k < 2; ++k)
+            for (int a = 0; a < 3; ++a) b.acc[k][a] = b.jrk[k][a] = nullptr;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -577,11 +590,38 @@ void nh_boundary(md_ctx* c, int halves, hipStream_t s)
 
 bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
 
+// One Gear step ("Time integration"): predictor, the list rebuild on schedule
+// (at the predicted positions, where the forces are taken), force pass,
+// corrector.  The last step of a call also produces the energies and writes
+// the caller's state.
+void gear_step(md_ctx* c, bool last, hipStream_t s)
+{
+    {
+        Timed tm(c, MD_KT_FORCE, s);
+        launch_gear_predict(c->buf, c->p, c->q, shape(c), c->args, c->dt_fs, s);
+    }
+    c->p ^= 1;
+    ++c->step;
+    if (due(c)) rebuild(c, s, true);
+    forces(c, last ? ForceFlags{1, 0, 0, 1} : ForceFlags{0, 0, 0, 0}, s, false);
+    const KernelShape k = shape(c);
+    {
+        Timed tm(c, MD_KT_FORCE, s);
+        launch_gear_correct(c->buf, c->p, c->q, k, c->args, c->dt_fs, c->st, last ? 1 : 0, s);
+    }
+    c->p ^= 1;
+    if (last) reduce_energies(c, k, s);
+}
+
 // The middle steps of md_step (closing kick, list rebuild on schedule, force
 // pass, opening kick and drift), `n` of them.
 void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
 {
     for (int64_t k = 0; k < n; ++k) {
+        if (c->gear) {
+            gear_step(c, false, s);
+            continue;
+        }
         ++c->step;
         if (due(c)) rebuild(c, s, true);
         if (c->nvt) {
@@ -674,6 +714,9 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     if ((cfg->nh_temperature == nullptr) != (cfg->nh_mass == nullptr))
         return reject(MD_ERR_ARG, "nh_temperature and nh_mass go together (both NULL for NVE)");
     c->nvt = cfg->nh_temperature != nullptr;
+    if (cfg->integrator != MD_VERLET && cfg->integrator != MD_GEAR3) return reject(MD_ERR_ARG, "integrator must be MD_VERLET or MD_GEAR3");
+    c->gear = cfg->integrator == MD_GEAR3;
+    if (c->gear && c->nvt) return reject(MD_ERR_ARG, "the Gear integrator runs NVE only (no thermostat)");
     if (c->nvt) {
         c->nh_T.assign(cfg->nh_temperature, cfg->nh_temperature + c->R);
         c->nh_Q.assign(cfg->nh_mass, cfg->nh_mass + c->R);
@@ -927,6 +970,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
             return MD_ERR_DEVICE;
     }
     c->bound = true;
+    c->gear_ready = false;
     c->drop_graphs();
     if (!build_cell_table(c)) return MD_ERR_DEVICE;
     c->have_slots = c->have_list = c->have_energy = false;
@@ -969,7 +1013,13 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     const bool build = !c->have_list || due(c);
     load_state(c, s, build);
     if (build) rebuild(c, s, true);
-    if (c->nvt) {
+    if (c->gear) {
+        if (!c->gear_ready) {
+            forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0): a = f/m, da/dt = 0
+            launch_gear_start(c->buf, c->q, shape(c), c->args, s);
+            c->gear_ready = true;
+        }
+    } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
         nh_boundary(c, 1, s);                  // thermostat half step, opening kick, drift
     } else {
@@ -987,6 +1037,10 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         const int64_t n = c->use_graph ? std::min(left, P - c->step % P) : left;
         middle_steps(c, n, s);
         left -= n;
+    }
+    if (c->gear) {
+        gear_step(c, true, s);
+        return check_launch(c);
     }
     ++c->step;
     if (due(c)) rebuild(c, s, true);

@@ -32,6 +32,7 @@ ERROR_NAMES = {
 }
 MD_FP64, MD_MIXED = 0, 1
 MD_NBR_FULL, MD_NBR_HALF_ATOMIC = 0, 1
+MD_VERLET, MD_GEAR3 = 0, 1
 MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_OPT_TIMING = 1, 2, 3, 4, 5
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
@@ -69,7 +70,7 @@ class _Config(ctypes.Structure):
         ("atom_offset", ctypes.c_void_p), ("box", ctypes.c_void_p), ("origin", ctypes.c_void_p),
         ("periodic", ctypes.c_void_p), ("rigid_velocity", ctypes.c_void_p),
         ("skin", ctypes.c_double), ("dt_fs", ctypes.c_double),
-        ("nh_temperature", ctypes.c_void_p), ("nh_mass", ctypes.c_void_p),
+        ("nh_temperature", ctypes.c_void_p), ("nh_mass", ctypes.c_void_p), ("integrator", ctypes.c_int32),
     ]
 
 
@@ -143,7 +144,7 @@ class Context:
 
     def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
                  skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
-                 nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None):
+                 nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None, integrator="verlet"):
         self.lib = library()
         pa = _c(potential["pair_a"], np.float64)
         ns = pa.shape[0]
@@ -172,6 +173,7 @@ class Context:
             None if k["origin"] is None else k["origin"].ctypes.data, k["periodic"].ctypes.data,
             None if k["vp"] is None else k["vp"].ctypes.data, float(skin), float(dt_fs),
             None if k["nh_t"] is None else k["nh_t"].ctypes.data, None if k["nh_q"] is None else k["nh_q"].ctypes.data,
+            {"verlet": MD_VERLET, "gear3": MD_GEAR3}[integrator] if isinstance(integrator, str) else int(integrator),
         )
         h = ctypes.c_void_p()
         rc = self.lib.md_create(ctypes.byref(cfg), ctypes.byref(pot), ctypes.byref(h))
@@ -231,7 +233,7 @@ class Simulation:
 
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
                  device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
-                 nh_mass=None):
+                 nh_mass=None, integrator="verlet"):
         import torch
 
         self.torch = torch
@@ -244,7 +246,7 @@ class Simulation:
             dt_fs=system.dt_fs, rebuild_every=system.rebuild_every if rebuild_every is None else rebuild_every,
             max_neighbours=self.cap,
             precision=precision, nbr_mode=nbr_mode, lanes_per_atom=lanes_per_atom,
-            nh_temperature=nh_temperature, nh_mass=nh_mass,
+            nh_temperature=nh_temperature, nh_mass=nh_mass, integrator=integrator,
         )
         d = self.device
         f64 = dict(dtype=torch.float64, device=d)

@@ -147,3 +147,16 @@ def test_msd_needs_a_bound_state(md):
     assert c.lib.md_msd_origin(c.handle, None) == md.MD_ERR_STATE
     assert c.lib.md_msd(c.handle, None, None, None) == md.MD_ERR_ARG
     assert c.lib.md_msd(None, out.ctypes.data, None, None) == md.MD_ERR_ARG
+
+
+def test_integrator_validation(md):
+    """MD_GEAR3 is accepted alone; an unknown integrator, and Gear with the
+    thermostat, are refused on the host."""
+    _ctx(md, integrator="gear3")
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, integrator=5)
+    assert e.value.code == md.MD_ERR_ARG
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, integrator="gear3", nh_temperature=[300.0], nh_mass=[50.0])
+    assert e.value.code == md.MD_ERR_ARG
+    assert _ctx(md, integrator="gear3").workspace_bytes() > _ctx(md).workspace_bytes()
