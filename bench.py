@@ -87,11 +87,13 @@ def timed_steps(sim, steps):
     return t0.elapsed_time(t1), time.perf_counter() - wall0
 
 
-def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None, nvt=None):
+def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None, nvt=None,
+                  integrator="verlet"):
     """A warmed-up timed run.  tune: options to apply (e.g. an autotuner's
     choice); graph replay is used unless per-kernel timing is requested.
     nvt: (targets [R] K, thermostat masses [R] eV fs^2) for a Nose-Hoover run."""
     kw = {} if nvt is None else {"nh_temperature": nvt[0], "nh_mass": nvt[1]}
+    kw["integrator"] = integrator
     sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode, **kw)
     for opt, val in (tune or {}).items():
         sim.set_option(opt, val)
@@ -118,7 +120,8 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
 def choice_options(md, ch):
     """The md_set_option settings of an autotuner choice."""
     return {md.MD_OPT_KERNEL: ch["kernel"], md.MD_OPT_BRICK_DIMS: ch["brick_dims"] if ch["kernel"] == 0 else 0,
-            md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"]}
+            md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"],
+            md.MD_OPT_EVALUATOR: ch["evaluator"]}
 
 
 def tune_options(md, system, precision):
@@ -256,6 +259,8 @@ def main():
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
     ap.add_argument("--nvt-steps", type=int, default=100,
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
+    ap.add_argument("--gear-steps", type=int, default=100,
+                    help="steps of the Gear predictor-corrector on the main workload (0 = skip)")
     ap.add_argument("--evaluator-steps", type=int, default=100,
                     help="steps of the table versus explicit evaluation comparison (0 = skip)")
     ap.add_argument("--diffusion-steps", type=int, default=1000,
@@ -315,6 +320,8 @@ def main():
         results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt, "warmup_run": sim.warmup_steps}
         del sim_t
 
+    rec_ms = {prec: results[prec]["ms"] / args.steps for prec in ("fp64", "mixed")}
+
     # the half-list + FP64-atomics variant on the same workload (comparison)
     half = {}
     if args.half_steps > 0:
@@ -341,6 +348,18 @@ def main():
             rates["table_speedup"] = rates["table"] / rates["explicit"]
             evaluator[prec] = rates
             log(f"evaluator {prec}: table {rates['table']:.3e}, explicit {rates['explicit']:.3e} atom-steps/s")
+
+    # the third-order Gear predictor-corrector on the same workload ("Time
+    # integration"), each precision with its autotuned kernel settings
+    gear = {}
+    if args.gear_steps > 0:
+        for prec in ("fp64", "mixed"):
+            sim_g, ms_g, _, _, _ = run_precision(md, system, prec, args.gear_steps, args.warmup, timing=False,
+                                                 tune=choice_options(md, tuned[prec]), integrator="gear3")
+            gear[prec] = {"value": n * args.gear_steps / (ms_g * 1e-3), "ms_per_step": ms_g / args.gear_steps,
+                          "vs_verlet": (ms_g / args.gear_steps) / rec_ms[prec]}
+            log(f"gear {prec}: {ms_g / args.gear_steps * 1e3:.1f} us/step")
+            del sim_g
 
     batched = [batched_vs_one_by_one(md, system_b, w, args.batched_steps, args.warmup)
                for w, system_b in batched_sys.items()]
@@ -464,6 +483,7 @@ def main():
         "mixed": rec["mixed"],
         "half_list_atomics": half,
         "table_vs_explicit": evaluator,
+        "gear_predictor_corrector": gear,
         "batched_vs_one_by_one": batched,
         "nvt_batched": nvt_rec,
         "diffusion": diffusion,

@@ -259,7 +259,8 @@ int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);
  * the best settings machine dependent; section "Parallel benchmarks").  Times,
  * on the current positions, the global-gather kernels and (full list only)
  * LDS-brick shapes {automatic, 4x4x4, 2x2x2} x lanes per atom {1, 2} x
- * workgroup sizes {512, 1024}: one list build plus `trials` density + force
+ * workgroup sizes {512, 1024}, in FP64 each with either evaluator (tables or
+ * knot sums, MD_OPT_EVALUATOR): one list build plus `trials` density + force
  * passes each (forces are written to the caller's arrays; positions and
  * velocities are untouched), and keeps the configuration with the lowest
  * force-pass time plus build time / rebuild_every, readable through

@@ -995,11 +995,16 @@ __global__ void k_gear_predict(Buffers b, int p, int q, int64_t n_slots, PotArgs
     }
 }
 
-// Corrector from pos[p] (predicted) into pos[p^1].  The last step of a call
-// takes f from the caller's arrays (its force pass wrote them), keeps it for
-// the next call, fixes the kinetic and work terms of the energy record and
-// writes the caller's x and v.
-__global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, md_state st, int last)
+// Corrector from pos[p] (predicted) into pos[p^1].  Within a call the same
+// pass predicts the next step from the corrected values (all of them local to
+// the atom), so pos[p^1] receives the next predicted position and its compact
+// record, and rigid atoms account both halves of the work at this evaluation.
+// The last step of a call stores the corrected position instead, takes f from
+// the caller's arrays (its force pass wrote them), keeps it for the next call,
+// fixes the kinetic and work terms of the energy record and writes the
+// caller's x and v.
+__global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, md_state st, int last,
+                               int compact)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -1025,9 +1030,12 @@ __global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs
     double v[3];
     double ke = 0.0;
     if (ty & kRigidBit) {
-        b.pwork[q][t] += -(f[0] * R.vp[0] + f[1] * R.vp[1] + f[2] * R.vp[2]) * 0.5 * h;
+        b.pwork[q][t] += -(f[0] * R.vp[0] + f[1] * R.vp[1] + f[2] * R.vp[2]) * (last ? 0.5 * h : h);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[a] = R.vp[a];
+        for (int a = 0; a < 3; ++a) {
+            v[a] = R.vp[a];
+            if (!last) xc[a] += h * R.vp[a];
+        }
     } else {
         const int si = ty & 0x3F;
         const double acc = P.ns == 1 ? P.accel : G.accel[si];
@@ -1036,17 +1044,26 @@ __global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs
             const double a0 = b.acc[q][a][t], j0 = b.jrk[q][a][t];
             const double an = acc * f[a];
             const double d = an - fma(h, j0, a0);
+            const double jn = j0 + d / h;
             v[a] = b.vel[q][a][t] + h * (a0 + 0.5 * h * j0) + (5.0 / 12.0) * h * d;
             xc[a] += (h * h / 12.0) * d;
+            if (!last) xc[a] = fma(h, v[a] + h * (0.5 * an + (h / 6.0) * jn), xc[a]);  // next prediction
             b.vel[q][a][t] = v[a];
             b.acc[q][a][t] = an;
-            b.jrk[q][a][t] = j0 + d / h;
+            b.jrk[q][a][t] = jn;
         }
         ke = (P.ns == 1 ? P.half_m : G.half_m[si]) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     }
     double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
     *reinterpret_cast<double2*>(dst) = make_double2(xc[0], xc[1]);
     dst[2] = xc[2];
+    if (compact && !last) {
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        int4 rq;
+        if (!compact_coords(R, c, xc[0], xc[1], xc[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
     if (last) {
         b.eslot[(int64_t)E_KE * n_slots + t] = ke;
         b.eslot[(int64_t)E_PW * n_slots + t] = (ty & kRigidBit) ? b.pwork[q][t] : 0.0;
@@ -1447,7 +1464,7 @@ void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, c
                          const md_state& st, int last, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gear_correct, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P,
-                       dt_fs, st, last);
+                       dt_fs, st, last, k.compact);
 }
 
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s)

@@ -590,17 +590,13 @@ void nh_boundary(md_ctx* c, int halves, hipStream_t s)
 
 bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
 
-// One Gear step ("Time integration"): predictor, the list rebuild on schedule
-// (at the predicted positions, where the forces are taken), force pass,
-// corrector.  The last step of a call also produces the energies and writes
-// the caller's state.
+// One Gear step ("Time integration") from predicted positions in pos[p]: the
+// list rebuild on schedule (at the predicted positions, where the forces are
+// taken), the force pass, then the corrector, which within a call also
+// predicts the next step.  The last step of a call also produces the energies
+// and writes the caller's state.
 void gear_step(md_ctx* c, bool last, hipStream_t s)
 {
-    {
-        Timed tm(c, MD_KT_FORCE, s);
-        launch_gear_predict(c->buf, c->p, c->q, shape(c), c->args, c->dt_fs, s);
-    }
-    c->p ^= 1;
     ++c->step;
     if (due(c)) rebuild(c, s, true);
     forces(c, last ? ForceFlags{1, 0, 0, 1} : ForceFlags{0, 0, 0, 0}, s, false);
@@ -1019,6 +1015,11 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
             launch_gear_start(c->buf, c->q, shape(c), c->args, s);
             c->gear_ready = true;
         }
+        {
+            Timed tm(c, MD_KT_FORCE, s);  // first prediction of the call
+            launch_gear_predict(c->buf, c->p, c->q, shape(c), c->args, c->dt_fs, s);
+        }
+        c->p ^= 1;
     } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
         nh_boundary(c, 1, s);                  // thermostat half step, opening kick, drift
@@ -1249,13 +1250,20 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     if (c->timing) return fail(c, MD_ERR_STATE, "md_autotune: turn MD_OPT_TIMING off first");
     hipStream_t s = as_stream(stream);
     struct Cand {
-        int32_t kernel, dims, lanes, block;
+        int32_t kernel, dims, lanes, block, evaluator;
     };
-    std::vector<Cand> cands = {{1, 0, 0, 512}};
-    if (c->nbr_mode == MD_NBR_FULL)
-        for (int32_t dims : {0, 444, 222})
-            for (int32_t lanes : {1, 2})
-                for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block});
+    // FP64 may take either evaluator (both meet its tolerance); mixed keeps the
+    // current one, since its explicit FP32 knot sums do not
+    std::vector<int32_t> evals = {(c->table_ok && c->evaluator == 0) ? 0 : 1};
+    if (c->precision == MD_FP64 && c->table_ok) evals = {0, 1};
+    std::vector<Cand> cands;
+    for (int32_t e : evals) {
+        cands.push_back({1, 0, 0, 512, e});
+        if (c->nbr_mode == MD_NBR_FULL)
+            for (int32_t dims : {0, 444, 222})
+                for (int32_t lanes : {1, 2})
+                    for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block, e});
+    }
     hipEvent_t ev[3];
     for (auto& e : ev)
         if (!hip_ok(c, hipEventCreate(&e), "md_autotune events")) return MD_ERR_DEVICE;
@@ -1265,7 +1273,8 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     for (const Cand& cd : cands) {
         if ((rc = md_set_option(c, MD_OPT_KERNEL, cd.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, cd.dims)) != MD_OK ||
             (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, cd.lanes)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK)
+            (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK ||
+            (rc = md_set_option(c, MD_OPT_EVALUATOR, cd.evaluator)) != MD_OK)
             break;
         ensure_slots(c, s);
         launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
@@ -1292,7 +1301,8 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     if (rc != MD_OK) return rc;
     if ((rc = md_set_option(c, MD_OPT_KERNEL, choice.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, choice.dims)) != MD_OK ||
         (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, choice.lanes)) != MD_OK ||
-        (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, choice.block)) != MD_OK)
+        (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, choice.block)) != MD_OK ||
+        (rc = md_set_option(c, MD_OPT_EVALUATOR, choice.evaluator)) != MD_OK)
         return rc;
     c->tuned_us = best * 1e3;
     c->have_list = false;  // the next call builds the list of the chosen configuration

@@ -357,7 +357,7 @@ class Simulation:
         self.ctx._check(self.ctx.lib.md_autotune(self.ctx.handle, int(trials), self.stream))
         opts = {name: self.get_option(opt) for name, opt in (
             ("kernel", MD_OPT_KERNEL), ("brick_dims", MD_OPT_BRICK_DIMS), ("lanes", MD_OPT_LANES_PER_ATOM),
-            ("block", MD_OPT_BRICK_BLOCK))}
+            ("block", MD_OPT_BRICK_BLOCK), ("evaluator", MD_OPT_EVALUATOR))}
         opts["step_us"] = self.get_option(MD_OPT_TUNED_NS) / 1e3
         return opts
 
