@@ -816,41 +816,47 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double vi
 // pi again with the scaled K.  Between two steps the two half steps meet, so
 // one kinetic-energy reduction per step serves both.
 
-// Kinetic energy of the mobile atoms of each reduction chunk (fixed order).
-__global__ __launch_bounds__(kBlock) void k_nh_ke_chunks(Buffers b, int q, int64_t n_slots, PotArgs P)
+// Kinetic energy of the mobile atoms of each wavefront (a wavefront never
+// straddles two replicas): one partial per wave, summed by shuffles in a fixed
+// order.  The whole slot range runs in parallel.
+__global__ __launch_bounds__(kBlock) void k_nh_ke_waves(Buffers b, int q, int64_t n_slots, PotArgs P)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;  // n_slots is a multiple of the wave size: whole waves leave
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    const DevPotential& G = *b.pot;
+    double ke = 0.0;
+    if (t - R.slot_off < R.n_atoms) {
+        const uint8_t ty = b.type[q][t];
+        if (!(ty & kRigidBit)) {
+            const double vx = b.vel[q][0][t], vy = b.vel[q][1][t], vz = b.vel[q][2][t];
+            ke = (P.ns == 1 ? P.half_m : G.half_m[ty & 0x3F]) * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) ke += __shfl_down(ke, off, kWave);
+    if ((t & (kWave - 1)) == 0) b.nh_partial[t / kWave] = ke;
+}
+
+// One workgroup per replica: the kinetic energy from the replica's wave
+// partials (a fixed tree), then on one lane `halves` thermostat half steps of
+// length dt/2; nh_state = {pi, xi, total velocity scale, kinetic energy after}.
+__global__ __launch_bounds__(kBlock) void k_nh_update(Buffers b, int halves, double dt)
 {
     __shared__ double sh[kBlock];
-    const int c = blockIdx.x;
-    const int r = b.chunk_rep[c];
+    const int r = blockIdx.x;
     const DevReplica& R = b.reps[r];
-    const DevPotential& G = *b.pot;
-    const int64_t s0 = R.slot_off + (int64_t)(c - b.chunk_off[r]) * kReduceChunk;
-    const int64_t s1 = min(s0 + (int64_t)kReduceChunk, (int64_t)R.slot_off + R.n_atoms);
-    double ke = 0.0;
-    for (int64_t t = s0 + threadIdx.x; t < s1; t += kBlock) {
-        const uint8_t ty = b.type[q][t];
-        if (ty & kRigidBit) continue;
-        const double vx = b.vel[q][0][t], vy = b.vel[q][1][t], vz = b.vel[q][2][t];
-        const double hm = P.ns == 1 ? P.half_m : G.half_m[ty & 0x3F];
-        ke += hm * (vx * vx + vy * vy + vz * vz);
-    }
-    sh[threadIdx.x] = ke;
+    const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
+    double part = 0.0;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) part += b.nh_partial[w];
+    sh[threadIdx.x] = part;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) b.nh_partial[c] = sh[0];
-}
-
-// Per replica: the kinetic energy, then `halves` thermostat half steps of
-// length dt/2; nh_state = {pi, xi, total velocity scale, kinetic energy after}.
-__global__ void k_nh_update(Buffers b, int n_replicas, int halves, double dt)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_replicas) return;
-    double K = 0.0;
-    for (int c = b.chunk_off[r]; c < b.chunk_off[r + 1]; ++c) K += b.nh_partial[c];
+    if (threadIdx.x != 0) return;
+    double K = sh[0];
     double* st = b.nh_state + 4 * (int64_t)r;
     const double Q = b.nh_param[2 * r], gkt = b.nh_param[2 * r + 1];
     double pi = st[0], xi = st[1], S = 1.0;
@@ -1436,9 +1442,9 @@ void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const Po
 void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int halves, double dt_fs,
                       hipStream_t s)
 {
-    if (k.n_chunks > 0) hipLaunchKernelGGL(k_nh_ke_chunks, dim3(k.n_chunks), dim3(kBlock), 0, s, b, q, k.n_slots, P);
-    hipLaunchKernelGGL(k_nh_update, dim3((k.n_replicas + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b, k.n_replicas,
-                       halves, dt_fs);
+    hipLaunchKernelGGL(k_nh_ke_waves, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+    if (k.n_replicas > 0)
+        hipLaunchKernelGGL(k_nh_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, halves, dt_fs);
 }
 
 void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,

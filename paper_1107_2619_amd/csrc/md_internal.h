@@ -158,7 +158,7 @@ struct Buffers {
     double* rhalf;        // [Np] half-list density accumulator
     double* nh_param;     // [R][2] thermostat mass Q (eV fs^2), g k_B T (eV)
     double* nh_state;     // [R][4] pi (1/fs), xi, velocity scale of the last update, KE after it (eV)
-    double* nh_partial;   // [n_chunks] kinetic energy per reduction chunk
+    double* nh_partial;   // [Np / 64] kinetic energy per wavefront
     double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
     double* acc[2][3];    // [Np] Gear integrator: acceleration, A/fs^2 (null with Verlet)
     double* jrk[2][3];    // [Np] Gear integrator: its time derivative, A/fs^3

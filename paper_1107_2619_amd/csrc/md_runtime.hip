@@ -353,7 +353,7 @@ void plan_workspace(md_ctx* c)
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // rhalf
         c->nbr_mode == MD_NBR_HALF_ATOMIC ? Np * 8 : 0,     // ehalf
         (size_t)c->R * 16, (size_t)c->R * 32,                // nh_param, nh_state
-        std::max<size_t>(c->chunk_rep.size(), 1) * 8,        // nh_partial
+        Np / kWave * 8,                                      // nh_partial
         F_COUNT * 4,                                         // flags
         c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
         c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
