@@ -37,8 +37,15 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {"fetch_kib": 113234.8, "write_kib": 71280.1, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256_16": "0fa8ea7e34f62ffb", "workload": "bcc1m", "precision": "mixed"}
+FORCE_TRAFFIC = {"fetch_kib": 113237.6, "write_kib": 71280.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256_16": "24a05e2bf0316653", "workload": "bcc1m", "precision": "mixed"}
+# VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
+# SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
+# so this is also the lane-operations per atom of one launch.
+FORCE_VALU_PER_WAVE = 1602.0
+# Lane-operation issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz (FP64 and unpacked FP32 issue at the same rate; packed FP32 is off).
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 FORCE_SOURCES = ["paper_1107_2619_amd/csrc/kernels.hip", "paper_1107_2619_amd/csrc/md_device.h",
                  "paper_1107_2619_amd/csrc/md_internal.h"]
 
@@ -259,12 +266,16 @@ def main():
     ap.add_argument("--half-steps", type=int, default=100, help="steps of the half-list + atomics comparison")
     ap.add_argument("--nvt-steps", type=int, default=100,
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of the main workload for a median (reported beside value)")
     ap.add_argument("--gear-steps", type=int, default=100,
                     help="steps of the Gear predictor-corrector on the main workload (0 = skip)")
     ap.add_argument("--evaluator-steps", type=int, default=100,
                     help="steps of the table versus explicit evaluation comparison (0 = skip)")
     ap.add_argument("--diffusion-steps", type=int, default=1000,
                     help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
+    ap.add_argument("--copy-gbs-mib", type=int, default=1024,
+                    help="size of the device copy whose bandwidth is reported beside the roofline (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -303,6 +314,22 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {nbytes} bytes")
         del src, dst
+    # a plain device-to-device copy: the HBM bandwidth this GPU reaches
+    copy_gbs = None
+    if args.copy_gbs_mib > 0:
+        nbytes = args.copy_gbs_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+        del src, dst
     log(f"building workload {args.workload}")
     system = inputs.workload(args.workload)
     n = system.n_atoms
@@ -315,9 +342,11 @@ def main():
         log(f"{prec}: warmup 2 x {args.warmup}, timed {args.steps} steps")
         sim, ms, wall, en, _ = run_precision(md, system, prec, args.steps, args.warmup, timing=False, tune=opts)
         log(f"{prec}: {ms / args.steps * 1e3:.1f} us/step  (wall {wall:.3f} s)")
+        repeats = [timed_steps(sim, args.steps)[0] for _ in range(args.repeats)]
         # a second timed pass with per-kernel HIP events for the roofline
         sim_t, ms_t, _, _, kt = run_precision(md, system, prec, args.steps, args.warmup, timing=True, tune=opts)
-        results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt, "warmup_run": sim.warmup_steps}
+        results[prec] = {"sim": sim, "ms": ms, "ms_timed": ms_t, "en": en, "kt": kt, "warmup_run": sim.warmup_steps,
+                         "repeats": repeats}
         del sim_t
 
     rec_ms = {prec: results[prec]["ms"] / args.steps for prec in ("fp64", "mixed")}
@@ -425,6 +454,8 @@ def main():
             "autotuned": tuned[prec],
             "graph_replay": True,
             "warmup_steps_run": r["warmup_run"],
+            "repeat_ms_per_step": [x / args.steps for x in r["repeats"]],
+            "median_value": (n * args.steps / (float(np.median(r["repeats"])) * 1e-3)) if r["repeats"] else None,
         }
     gate_ok = mix_err <= 1e-5
     head = rec["mixed"] if gate_ok else rec["fp64"]
@@ -438,6 +469,12 @@ def main():
             and head.get("autotuned", {}).get("kernel") == 1):
         traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
         traffic = traffic_bytes / (force_us * 1e-6) / 1e9
+    alu = None
+    if (gate_ok and args.workload == t["workload"] and force_sources_hash() == t["sources_sha256_16"]
+            and head.get("autotuned", {}).get("kernel") == 1):
+        lane_ops = FORCE_VALU_PER_WAVE * n / (force_us * 1e-6)
+        alu = {"achieved": lane_ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+               "frac": lane_ops / VALU_PEAK_LANE_OPS, "valu_instr_per_wave": FORCE_VALU_PER_WAVE}
     roofline = {
         "bound": "hbm",
         "kernel": "k_force (force pass + velocity Verlet)",
@@ -451,6 +488,8 @@ def main():
         "bytes_per_atom": force_kernel_bytes_per_atom(nbar),
         "step_bytes_per_atom": step_bytes_per_atom(nbar, system.rebuild_every),
         "step_frac": step_bytes_per_atom(nbar, system.rebuild_every) * head["value"] / 1e9 / HBM_PEAK_GBS,
+        "measured_copy_GBs": copy_gbs,
+        "alu": alu,
     }
 
     cpu = None
@@ -515,6 +554,15 @@ def cpu_baseline(system, sim, pos, f_gpu, seconds):
     dt = time.perf_counter() - t
     fr = f_gpu[sample]
     err = float(np.max(np.linalg.norm(fr - ref.f, axis=1)) / np.sqrt(np.mean(np.sum(ref.f**2, 1))))
+    # the whole 2000-atom crystal for 100 velocity-Verlet steps, as the oracle runs it
+    from paper_1107_2619_amd import inputs
+
+    small = inputs.workload("bcc2000")
+    t = time.perf_counter()
+    oracle.run_verlet(small.pos, small.vel, small.species, small.box[0], small.periodic[0],
+                      oracle.Potential(small.potential), small.dt_fs, 100)
+    small_rate = small.n_atoms * 100 / (time.perf_counter() - t)
+    log(f"cpu baseline: bcc2000 x 100 steps at {small_rate:.3e} atom-steps/s")
     return {
         "value": s / dt,
         "unit": "atom-steps/s",
@@ -523,6 +571,8 @@ def cpu_baseline(system, sim, pos, f_gpu, seconds):
         "sample": f"forces of {s} random atoms of the same {system.n_atoms}-atom state, brute force O(N) each "
                   f"(O(N^2) algorithm), FP64, OpenMP; {dt:.1f} s",
         "gpu_fp64_force_err_on_sample": err,
+        "bcc2000_100_steps": {"value": small_rate, "unit": "atom-steps/s",
+                              "note": "2000-atom bcc Fe, 100 velocity-Verlet steps, whole run, O(N^2) per step"},
     }
 
 
