@@ -268,6 +268,8 @@ def main():
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed runs of the main workload for a median (reported beside value)")
+    ap.add_argument("--large-steps", type=int, default=200,
+                    help="steps of the 4.15 M-atom crystal (beyond the last-level cache; 0 = skip)")
     ap.add_argument("--gear-steps", type=int, default=100,
                     help="steps of the Gear predictor-corrector on the main workload (0 = skip)")
     ap.add_argument("--evaluator-steps", type=int, default=100,
@@ -350,6 +352,22 @@ def main():
         del sim_t
 
     rec_ms = {prec: results[prec]["ms"] / args.steps for prec in ("fp64", "mixed")}
+
+    # the same crystal four times larger, beyond the 256 MB last-level cache
+    size_sweep = []
+    if args.large_steps > 0:
+        big = inputs.workload("bcc4m")
+        for prec in ("fp64", "mixed"):
+            opts_b, ch_b = tune_options(md, big, prec)
+            sim_b, ms_b, _, _, _ = run_precision(md, big, prec, args.large_steps, args.warmup, timing=False,
+                                                 tune=opts_b)
+            size_sweep.append({"workload": "bcc4m: bcc Fe 128^3 cells, 1% vacancies, 600 K, rebuild every 10",
+                               "n_atoms": big.n_atoms, "precision": prec, "steps": args.large_steps,
+                               "value": big.n_atoms * args.large_steps / (ms_b * 1e-3),
+                               "ms_per_step": ms_b / args.large_steps, "autotuned": ch_b})
+            log(f"bcc4m {prec}: {ms_b / args.large_steps * 1e3:.1f} us/step")
+            del sim_b
+        del big
 
     # the half-list + FP64-atomics variant on the same workload (comparison)
     half = {}
@@ -520,6 +538,7 @@ def main():
         "mixed_force_err_vs_fp64": mix_err,
         "fp64": rec["fp64"],
         "mixed": rec["mixed"],
+        "larger_system": size_sweep,
         "half_list_atomics": half,
         "table_vs_explicit": evaluator,
         "gear_predictor_corrector": gear,

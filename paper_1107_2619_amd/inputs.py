@@ -457,6 +457,9 @@ def workload(name: str, **kw) -> System:
         # handful of atoms per interval, 0.4 A (6.7 sigma) is not.
         kw.setdefault("skin", 0.4)
         return bcc_fe(80, temperature=600.0, vacancy_frac=0.01, seed=2, steps=1000, name=name, **kw)
+    if name == "bcc4m":  # 128^3 cells, 1% vacancies -> 4,152,361 atoms, 600 K (beyond the 256 MB cache)
+        kw.setdefault("skin", 0.4)
+        return bcc_fe(128, temperature=600.0, vacancy_frac=0.01, seed=7, steps=200, name=name, **kw)
     if name == "fcc_piston":
         return fcc_piston(**kw)
     if name == "fec256":
