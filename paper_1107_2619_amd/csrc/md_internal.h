@@ -26,7 +26,7 @@ constexpr int kNumXcd = 8;      // MI355X: 8 accelerator dies, one L2 each
 
 enum EnergyIndex { E_PE = 0, E_KE = 1, E_W0 = 2, E_PW = 8, E_NONFINITE = 9 };
 constexpr int kEnergyTerms = 10;       // per-atom terms written on energy steps
-constexpr int kReduceChunk = 16384;    // slots per first-stage reduction chunk
+constexpr int kReduceChunk = 2048;     // slots per first-stage reduction chunk (one workgroup each)
 constexpr int kHaloMax = 216;          // halo cells of a brick: (4 + 2)^3 at most
 constexpr int kBrickMaxDim = 4;
 
