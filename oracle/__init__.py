@@ -85,6 +85,9 @@ def _load():
     lib.or_kinetic.argtypes = [i64, vp, vp, vp, vp, vp, P]
     lib.or_run_verlet.restype = i32
     lib.or_run_verlet.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
+    lib.or_run_pr.restype = i32
+    lib.or_run_pr.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, vp, vp, vp, vp, vp, vp,
+                              vp]
     lib.or_run_gear.restype = i32
     lib.or_run_gear.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
     lib.or_run_nh.restype = i32
@@ -327,6 +330,46 @@ def run_gear(pos, vel, species, box, periodic, pot: Potential, dt_fs, nsteps, ri
     if rc:
         raise ValueError("oracle: periodic box length must exceed twice the cutoff")
     return RunResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, wk)
+
+
+@dataclass
+class PRResult:
+    pos: np.ndarray
+    vel: np.ndarray
+    f: np.ndarray
+    pe: np.ndarray
+    ke: np.ndarray
+    box: np.ndarray    # [nsteps+1, 3] A
+    ldot: np.ndarray   # [nsteps+1, 3] A/fs
+    baro: np.ndarray   # [nsteps+1] P Omega + W |dL/dt|^2 / 2, eV
+    pressure: np.ndarray  # [nsteps+1] (2 KE + tr W) / (3 Omega), GPa
+
+
+def run_pr(pos, vel, species, box, pot: Potential, dt_fs, nsteps, p_gpa, w_ev_fs2_a2, origin=None,
+           ldot0=None) -> PRResult:
+    """Parrinello-Rahman NPH run (paper, "Barostat NPTp") with an orthorhombic
+    box and hydrostatic external pressure, brute-force forces; every axis
+    periodic.  W in eV fs^2 / A^2, P in GPa."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    L = _f64(box).copy()
+    o = np.zeros(3) if origin is None else _f64(origin)
+    l0 = None if ldot0 is None else _f64(ldot0)
+    f = np.zeros((n, 3))
+    pe, ke, bx, ld, ba, pr = (np.zeros(nsteps + 1), np.zeros(nsteps + 1), np.zeros(3 * (nsteps + 1)),
+                              np.zeros(3 * (nsteps + 1)), np.zeros(nsteps + 1), np.zeros(nsteps + 1))
+    rc = _load().or_run_pr(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
+        sp.ctypes.data, L.ctypes.data, o.ctypes.data, _ptr(l0), pot.ref, float(dt_fs), int(nsteps), float(p_gpa),
+        float(w_ev_fs2_a2), f.ctypes.data, pe.ctypes.data, ke.ctypes.data, bx.ctypes.data, ld.ctypes.data,
+        ba.ctypes.data, pr.ctypes.data,
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return PRResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, bx.reshape(-1, 3),
+                    ld.reshape(-1, 3), ba, pr)
 
 
 @dataclass

@@ -690,6 +690,111 @@ done:
     return rc;
 }
 
+/*
+ * Parrinello-Rahman barostat (paper, "Barostat NPTp"), restricted to an
+ * orthorhombic box: the box matrix h = diag(L) and a hydrostatic external
+ * stress S = P.  The particle equations in the velocities v = h ds/dt read
+ * dv/dt = f/m - (dL/dt / L) v per axis and dx/dt = (dL/dt / L)(x - o) + v;
+ * the box obeys W d2L_a/dt2 = sigma_aa (pi_aa - P), sigma = Omega h^-T (the
+ * reciprocal box, Omega / L_a on the diagonal) and pi = (sum_i m v v + W_vir)
+ * / Omega the internal stress.  PE + KE + P Omega + W |dL/dt|^2 / 2 is
+ * conserved.  A step composes exact sub-flows symmetrically: box half kick,
+ * friction half step v *= exp(-(h/2) dL/dt / L), velocity half kick, drift of
+ * positions and box with dL/dt held (s = (x - o)/L moves by v h log1p(u)/(u L),
+ * u = h dL/dt / L), forces, then the mirror image.  All axes must be
+ * periodic.  Outputs per step s: pe, ke, box[3], ldot[3] (A/fs), the
+ * barostat energy P Omega + W |dL/dt|^2 / 2 and the pressure (2 KE + tr W) /
+ * (3 Omega) in GPa.  W in eV fs^2 / A^2, P in GPa; ldot0 (A/fs) may be NULL.
+ */
+static void pr_box_kick(int64_t n, double *const v[3], const uint8_t *species, const or_potential *p,
+                        const double vir[6], const double L[3], double tau, double w, double pext,
+                        double ldot[3])
+{
+    double k2[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        const double m = p->mass[species[i]];
+        for (int a = 0; a < 3; ++a) k2[a] += m * v[a][i] * v[a][i];
+    }
+    const double omega = L[0] * L[1] * L[2];
+    for (int a = 0; a < 3; ++a) {
+        const double pi_aa = (k2[a] + vir[a]) / omega;
+        const double sigma_aa = omega / L[a];
+        ldot[a] += tau * sigma_aa * (pi_aa - pext) / w;
+    }
+}
+
+static void pr_friction(int64_t n, double *const v[3], const double L[3], const double ldot[3], double tau)
+{
+    for (int a = 0; a < 3; ++a) {
+        const double s = exp(-tau * ldot[a] / L[a]);
+        for (int64_t i = 0; i < n; ++i) v[a][i] *= s;
+    }
+}
+
+int or_run_pr(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+              const uint8_t *species, double *box, const double *origin, const double *ldot0_fs,
+              const or_potential *p, double dt_fs, int64_t nsteps, double p_gpa, double w_ev_fs2_a2, double *f,
+              double *pe_out, double *ke_out, double *box_out, double *ldot_out, double *baro_out,
+              double *press_out)
+{
+    const uint8_t periodic[3] = {1, 1, 1};
+    const double t0 = or_time_unit_fs();
+    const double h = dt_fs / t0;
+    const double w = w_ev_fs2_a2 / (t0 * t0);
+    const double pext = p_gpa / or_pressure_unit_gpa();
+    double *v[3] = {vx, vy, vz};
+    double *r[3] = {x, y, z};
+    double L[3] = {box[0], box[1], box[2]}, ldot[3] = {0.0, 0.0, 0.0}, vir[6], pe;
+    if (ldot0_fs)
+        for (int a = 0; a < 3; ++a) ldot[a] = ldot0_fs[a] * t0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] *= t0;
+    int rc = or_forces(n, x, y, z, species, NULL, L, periodic, p, f, NULL, NULL, vir, &pe);
+    if (rc) goto done;
+    for (int64_t s = 0;; ++s) {
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) ke_out[s] = mobile_ke(n, v, species, NULL, p);
+        const double omega = L[0] * L[1] * L[2];
+        if (box_out)
+            for (int a = 0; a < 3; ++a) box_out[3 * s + a] = L[a];
+        if (ldot_out)
+            for (int a = 0; a < 3; ++a) ldot_out[3 * s + a] = ldot[a] / t0;
+        if (baro_out)
+            baro_out[s] = pext * omega + 0.5 * w * (ldot[0] * ldot[0] + ldot[1] * ldot[1] + ldot[2] * ldot[2]);
+        if (press_out)
+            press_out[s] = (2.0 * mobile_ke(n, v, species, NULL, p) + vir[0] + vir[1] + vir[2]) / (3.0 * omega) *
+                           or_pressure_unit_gpa();
+        if (s == nsteps) break;
+        pr_box_kick(n, v, species, p, vir, L, 0.5 * h, w, pext, ldot);
+        pr_friction(n, v, L, ldot, 0.5 * h);
+        for (int64_t i = 0; i < n; ++i) {
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * h * f[3 * i + a] / m;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double u = h * ldot[a] / L[a];
+            const double phi = u == 0.0 ? 1.0 : log1p(u) / u;
+            const double Ln = L[a] + h * ldot[a];
+            for (int64_t i = 0; i < n; ++i)
+                r[a][i] = origin[a] + (r[a][i] - origin[a] + v[a][i] * h * phi) * (Ln / L[a]);
+            L[a] = Ln;
+        }
+        rc = or_forces(n, x, y, z, species, NULL, L, periodic, p, f, NULL, NULL, vir, &pe);
+        if (rc) goto done;
+        for (int64_t i = 0; i < n; ++i) {
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * h * f[3 * i + a] / m;
+        }
+        pr_friction(n, v, L, ldot, 0.5 * h);
+        pr_box_kick(n, v, species, p, vir, L, 0.5 * h, w, pext, ldot);
+    }
+done:
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+    for (int a = 0; a < 3; ++a) box[a] = L[a];
+    return rc;
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -635,3 +635,90 @@ def test_gear_energy_drifts_linearly(orc):
     sv = np.polyfit(t, ev, 1)[0]
     assert abs(s1 - s2) < 0.2 * abs(s1)
     assert abs(s1) > 5.0 * abs(sv)
+
+
+# --- Parrinello-Rahman barostat, orthorhombic box ("Barostat NPTp") ----------
+
+def _pr_system():
+    from paper_1107_2619_amd import inputs
+
+    return inputs.bcc_fe(4, a=2.90, temperature=600.0, seed=7, displace=0.02)
+
+
+def test_pr_infinite_box_mass_is_nve(orc):
+    """W -> infinity freezes the box: the NVE trajectory."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    v = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 200)
+    r = orc.run_pr(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 200, 0.0, 1e30)
+    assert np.max(np.abs(v.pos - r.pos)) < 1e-10
+    assert np.all(r.box == s.box[0])
+
+
+def test_pr_cold_lattice_box_against_independent_integrator(orc):
+    """A perfect lattice at rest stays a scaled lattice, so the box alone obeys
+    W d2L/dt2 = (Omega / L)(pi(L) - P) with pi from the (pinned) virial: scipy's
+    DOP853 integrates that equation independently.  The barostat run follows it
+    with second-order error in the step, and all three edges stay equal."""
+    from scipy.integrate import solve_ivp
+
+    from paper_1107_2619_amd import inputs
+
+    lat = inputs.bcc_fe(4, a=2.90, temperature=0.0, seed=7)
+    pot = orc.Potential(lat.potential)
+    L0, w = lat.box[0][0], 1e4
+    conv = orc.pressure_unit_gpa()
+    p_ext = 1.5  # GPa
+
+    def rhs(_t, y):
+        vir = orc.forces(lat.pos * (y[0] / L0), lat.species, [y[0]] * 3, [1, 1, 1], pot).virial
+        return [y[1], y[0] ** 2 * (vir[0] / y[0] ** 3 - p_ext / conv) / w]
+
+    times = [100.0, 200.0, 300.0, 400.0]
+    ref = solve_ivp(rhs, (0.0, 400.0), [L0, 0.0], method="DOP853", rtol=1e-12, atol=1e-13, t_eval=times).y[0]
+    assert np.ptp(ref) > 0.2  # the box really moves
+    errs = []
+    for dt in (1.0, 0.5):
+        e = 0.0
+        for t, rr in zip(times, ref):
+            r = orc.run_pr(lat.pos, np.zeros_like(lat.pos), lat.species, lat.box[0], pot, dt, int(t / dt), p_ext, w)
+            assert np.ptp(r.box[-1]) < 1e-9
+            e = max(e, abs(r.box[-1, 0] - rr))
+        errs.append(e)
+    assert errs[0] < 1e-3 and 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_pr_conserved_quantity(orc):
+    """PE + KE + P Omega + W |dL/dt|^2 / 2 stays within a band a thousand times
+    narrower than the swing of PE + KE, and the band shrinks as dt^2."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    bands = []
+    for dt in (1.0, 0.5):
+        r = orc.run_pr(s.pos, s.vel, s.species, s.box[0], pot, dt, int(2000 / dt), 0.0, 1e4)
+        h = r.pe + r.ke + r.baro
+        bands.append(np.ptp(h))
+        assert np.ptp(h) < 2e-3 * np.ptp(r.pe + r.ke)
+    assert bands[1] < 0.35 * bands[0]
+
+
+def test_pr_mean_pressure_is_the_target(orc):
+    """The box settles where the time-averaged internal pressure equals the
+    external one (a sign error in the box force would run away instead)."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    for p_ext in (0.0, 5.0):
+        r = orc.run_pr(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 6000, p_ext, 1e4)
+        assert abs(r.pressure[2000:].mean() - p_ext) < 0.15
+
+
+def test_pr_time_reversible(orc):
+    """Reversing the velocities and the box velocity retraces the path."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    a = orc.run_pr(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 200, 0.0, 1e4)
+    assert np.max(np.abs(a.ldot[-1])) > 1e-5
+    b = orc.run_pr(a.pos, -a.vel, s.species, a.box[-1], pot, 1.0, 200, 0.0, 1e4, ldot0=-a.ldot[-1])
+    assert np.max(np.abs(b.pos - s.pos)) < 1e-10
+    assert np.max(np.abs(b.box[-1] - s.box[0])) < 1e-11
+    assert np.max(np.abs(b.ldot[-1])) < 1e-13
