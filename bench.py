@@ -268,6 +268,8 @@ def main():
                     help="steps of the batched Nose-Hoover run beside its NVE twin (0 = skip)")
     ap.add_argument("--repeats", type=int, default=5,
                     help="further timed runs of the main workload for a median (reported beside value)")
+    ap.add_argument("--pr-steps", type=int, default=200,
+                    help="steps of the main crystal under the barostat beside a fixed box (0 = skip)")
     ap.add_argument("--large-steps", type=int, default=200,
                     help="steps of the 4.15 M-atom crystal (beyond the last-level cache; 0 = skip)")
     ap.add_argument("--gear-steps", type=int, default=100,
@@ -352,6 +354,33 @@ def main():
         del sim_t
 
     rec_ms = {prec: results[prec]["ms"] / args.steps for prec in ("fp64", "mixed")}
+
+    # the Parrinello-Rahman barostat on the same crystal (zero pressure, box
+    # period ~1 ps), beside the same run with a fixed box; both with a 0.5 A skin,
+    # which leaves the barostat's displacement and strain guards room at 600 K
+    barostat = None
+    if args.pr_steps > 0:
+        opts_pr = choice_options(md, tuned["mixed"])
+        opts_pr[md.MD_OPT_KERNEL] = 1
+        rates = {}
+        for label, kw in (("fixed_box", {}), ("barostat", {"pr_pressure_gpa": [0.0], "pr_mass": [2.0e7]})):
+            sim_b = md.Simulation(system, precision="mixed", want_e_atom=False, skin=0.5, **kw)
+            for opt, val in opts_pr.items():
+                sim_b.set_option(opt, val)
+            sim_b.set_option(md.MD_OPT_USE_GRAPH, 1)
+            for _ in range(2):
+                sim_b.step(max(args.warmup, 4 * system.rebuild_every + 2))
+                sim_b.energy()
+            ms_b, _ = timed_steps(sim_b, args.pr_steps)
+            e_b = sim_b.energy()
+            rates[label] = {"value": n * args.pr_steps / (ms_b * 1e-3), "ms_per_step": ms_b / args.pr_steps,
+                            "box_A": [float(x) for x in e_b.box[0]], "pressure_gpa": float(e_b.pressure_gpa[0])}
+            del sim_b
+        barostat = {"workload": f"{args.workload} with a 0.5 A skin", "precision": "mixed", "steps": args.pr_steps,
+                    "pressure_gpa": 0.0, "box_mass_eV_fs2_per_A2": 2.0e7, **rates,
+                    "overhead": rates["barostat"]["ms_per_step"] / rates["fixed_box"]["ms_per_step"] - 1.0}
+        log(f"barostat: {rates['barostat']['value']:.3e} atom-steps/s, fixed box {rates['fixed_box']['value']:.3e} "
+            f"({barostat['overhead']:+.1%})")
 
     # the same crystal four times larger, beyond the 256 MB last-level cache
     size_sweep = []
@@ -539,6 +568,7 @@ def main():
         "fp64": rec["fp64"],
         "mixed": rec["mixed"],
         "larger_system": size_sweep,
+        "barostat": barostat,
         "half_list_atomics": half,
         "table_vs_explicit": evaluator,
         "gear_predictor_corrector": gear,

@@ -123,6 +123,18 @@ typedef struct {
      * step; rigid atoms' work uses the trapezoid rule over the evaluations.
      * MD_GEAR3 runs NVE only (no thermostat). */
     int32_t integrator;
+    /* Parrinello-Rahman barostat per replica ("Barostat NPTp") on an
+     * orthorhombic box: h = diag(L) and a hydrostatic external stress.  The
+     * box edges obey W d2L_a/dt2 = (Omega / L_a)(pi_aa - P), pi the internal
+     * stress tensor, and the particles feel the matching friction
+     * -(dL_a/dt / L_a) v_a (NPH; PE + KE + P Omega + W |dL/dt|^2 / 2 is
+     * conserved).  Both NULL = fixed box; both set = every replica under its
+     * own pressure.  Needs periodic axes, MD_VERLET, no thermostat, the full
+     * list and no rigid atoms; the link-cell grid leaves 5% room for
+     * compression (more gives MD_ERR_BOX).  The LDS-brick kernels are not
+     * used. */
+    const double *pr_pressure_gpa; /* [R] external pressure, GPa, finite */
+    const double *pr_mass;         /* [R] box mass W, eV fs^2 / Angstrom^2, > 0 */
 } md_config;
 
 /*
@@ -162,6 +174,10 @@ typedef struct {
     double nh_energy;    /* thermostat energy Q pi_s^2 / 2 + g k_B T xi, eV, with
                             xi the time integral of pi_s: pe + ke + nh_energy is
                             conserved by the NVT dynamics */
+    double box[3];       /* edge lengths of this state, Angstrom (they move under
+                            the barostat) */
+    double pr_energy;    /* barostat energy P Omega + W |dL/dt|^2 / 2, eV (0 without
+                            barostat): pe + ke + pr_energy is conserved */
 } md_energies;
 
 /* Validates the configuration and potential on the host (no device work)

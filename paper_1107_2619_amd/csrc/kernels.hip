@@ -117,8 +117,12 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
     wave_run_add(b.cell_count, cell);
     if (!valid) return;
     if (check_skin) {
+        // displacement since the build, after mapping the build position into
+        // the current box (the two boxes differ only under the barostat)
         const double3 x0 = load_xyz(b.xbuild, t);
-        const double dx = x.x - x0.x, dy = x.y - x0.y, dz = x.z - x0.z;
+        const double dx = (x.x - bx.o[0]) - (x0.x - bx.o[0]) * (R.box[0] / R.lbuild[0]);
+        const double dy = (x.y - bx.o[1]) - (x0.y - bx.o[1]) * (R.box[1] / R.lbuild[1]);
+        const double dz = (x.z - bx.o[2]) - (x0.z - bx.o[2]) * (R.box[2] / R.lbuild[2]);
         if (dx * dx + dy * dy + dz * dz > half_skin2) atomicAdd(&b.flags[F_SKIN], 1);
     }
     // atoms beyond the grid extent of a free axis (clamped into edge cells)
@@ -938,6 +942,174 @@ __global__ void k_nh_scale(Buffers b, int q, int64_t n_slots, md_state st, int e
 }
 
 // ---------------------------------------------------------------------------
+// Parrinello-Rahman barostat on an orthorhombic box (paper, "Barostat NPTp";
+// h = diag(L), hydrostatic external stress).  The step composes exact
+// sub-flows symmetrically: box half kick W dL/dt += (h/2)(Omega/L)(pi - P),
+// friction half step v *= exp(-(h/2) dL/dt / L), velocity half kick, drift of
+// positions and box with dL/dt held, forces, and the mirror image.  Between two
+// steps the closing and opening halves meet: the force pass closes the kick,
+// k_pr_update takes both box half kicks from one stress tensor and drifts the
+// box, k_pr_open applies both friction halves, the opening kick and the drift.
+
+// Per wave: sums of m v_a^2 and of the per-atom virial diagonal (eslot).
+__global__ __launch_bounds__(kBlock) void k_pr_tensor_waves(Buffers b, int q, int64_t n_slots, PotArgs P)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;  // whole waves
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    const DevPotential& G = *b.pot;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (t - R.slot_off < R.n_atoms) {
+        const uint8_t ty = b.type[q][t];
+        const double m2 = 2.0 * (P.ns == 1 ? P.half_m : G.half_m[ty & 0x3F]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double va = b.vel[q][a][t];
+            v[a] = m2 * va * va;
+            v[3 + a] = b.eslot[(int64_t)(E_W0 + a) * n_slots + t];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
+        if ((t & (kWave - 1)) == 0) b.pr_partial[(t / kWave) * 6 + k] = x;
+    }
+}
+
+// One workgroup per replica: the stress tensor from the wave partials (fixed
+// tree), then on one lane the closing and/or opening box half kicks and, with
+// `open`, the box drift and the factors of the open pass.
+__global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int open, double h, double rlist,
+                                                      double strain_tol)
+{
+    __shared__ double sh[6][kBlock];
+    const int r = blockIdx.x;
+    DevReplica& R = b.reps[r];
+    const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
+    double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) part[k] += b.pr_partial[w * 6 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = part[k];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double* st = b.pr_state + (int64_t)kPrState * r;
+    const double W = b.pr_param[2 * r], pext = b.pr_param[2 * r + 1];
+    double L[3], Ld[3], lam_c[3];
+    for (int a = 0; a < 3; ++a) {
+        L[a] = st[a];
+        Ld[a] = st[3 + a];
+        lam_c[a] = close ? Ld[a] / L[a] : 0.0;
+    }
+    const double omega = L[0] * L[1] * L[2];
+    for (int a = 0; a < 3; ++a) {
+        // m v_a^2 after the closing friction half step, and the full-list virial
+        // (every pair seen from both atoms)
+        const double mv2 = sh[a][0] * exp(-h * lam_c[a]);
+        const double pi_aa = (mv2 - 0.5 * sh[3 + a][0]) / omega;
+        Ld[a] += (close + open) * 0.5 * h * (omega / L[a]) * (pi_aa - pext) / W;
+        st[15 + a] = exp(-0.5 * h * lam_c[a]);
+        st[3 + a] = Ld[a];
+    }
+    if (!open) return;
+    for (int a = 0; a < 3; ++a) {
+        const double lam_o = Ld[a] / L[a];
+        const double u = h * lam_o;
+        const double phi = u == 0.0 ? 1.0 : log1p(u) / u;
+        const double Ln = L[a] + h * Ld[a];
+        st[6 + a] = exp(-0.5 * h * (lam_c[a] + lam_o));
+        st[9 + a] = Ln / L[a];
+        st[12 + a] = h * phi * (Ln / L[a]);
+        st[a] = Ln;
+        R.box[a] = Ln;
+        R.inv_box[a] = 1.0 / Ln;
+        R.cell[a] = Ln / (double)R.nc[a];
+        R.qs[a] = ldexp(R.cell[a], -kCompactBits);
+        R.iqs[a] = ldexp(1.0 / R.cell[a], kCompactBits);
+        if (R.cell[a] < rlist) atomicAdd(&b.flags[F_PR_BOX], 1);
+        if (fabs(Ln / R.lbuild[a] - 1.0) * rlist > strain_tol) atomicAdd(&b.flags[F_SKIN], 1);
+    }
+}
+
+// Both friction halves, the opening kick and the drift of positions (scaled
+// about the box origin) into pos[p^1], with the compact record in the new box.
+__global__ void k_pr_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, int compact)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const double* st = b.pr_state + (int64_t)kPrState * r;
+    const uint8_t ty = b.type[q][t];
+    const double acc = P.ns == 1 ? P.accel : G.accel[ty & 0x3F];
+    const double3 x = load_xyz(b.pos[p], t);
+    const double xo[3] = {x.x - R.origin[0], x.y - R.origin[1], x.z - R.origin[2]};
+    double xn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = fma(0.5 * h * acc, b.fhalf[a][t], st[6 + a] * b.vel[q][a][t]);
+        b.vel[q][a][t] = v;
+        xn[a] = R.origin[a] + fma(st[12 + a], v, xo[a] * st[9 + a]);
+    }
+    double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
+    *reinterpret_cast<double2*>(dst) = make_double2(xn[0], xn[1]);
+    dst[2] = xn[2];
+    if (compact) {
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        int4 rq;
+        if (!compact_coords(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
+}
+
+// Closing friction half step of the last step of a call: the internal and the
+// caller's velocities and the kinetic terms of the energy record.
+__global__ void k_pr_close_scale(Buffers b, int q, int64_t n_slots, PotArgs P, md_state st)
+{
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const int r = uniform(b.rep_of_wave[t / kWave]);
+    const DevReplica& R = b.reps[r];
+    if (t - R.slot_off >= R.n_atoms) return;
+    const DevPotential& G = *b.pot;
+    const double* ps = b.pr_state + (int64_t)kPrState * r;
+    const uint8_t ty = b.type[q][t];
+    const int32_t id = b.id[q][t];
+    double v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v[a] = b.vel[q][a][t] * ps[15 + a];
+        b.vel[q][a][t] = v[a];
+    }
+    st.vx[id] = v[0];
+    st.vy[id] = v[1];
+    st.vz[id] = v[2];
+    b.eslot[(int64_t)E_KE * n_slots + t] = (P.ns == 1 ? P.half_m : G.half_m[ty & 0x3F]) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+// After a list build: the build box of every replica is the current one.
+__global__ void k_pr_mark_build(Buffers b, int n_replicas)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_replicas) return;
+    DevReplica& R = b.reps[r];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.lbuild[a] = R.box[a];
+}
+
+// ---------------------------------------------------------------------------
 // Third-order Gear predictor-corrector (paper, "Time integration").  Per
 // coordinate the state is x, v, the acceleration a and its time derivative b.
 // The predictor is the Taylor series to third order; after the force pass at
@@ -1362,13 +1534,17 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
                           double dt_fs, const md_state& st, hipStream_t s)
 {
     if (!fl.close && !fl.open) {
-        if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
+            force_launch<R, S, NP, ND, EV, true, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else force_launch<R, S, NP, ND, EV, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.writeback && fl.energy) {  // barostat: closing kick with the stress, forces kept
+        force_launch<R, S, NP, ND, EV, true, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {
         force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else {
@@ -1452,6 +1628,35 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 {
     hipLaunchKernelGGL(k_nh_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
                        k.compact);
+}
+
+void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
+                      double dt_fs, double rlist, double strain_tol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pr_tensor_waves, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+    if (k.n_replicas > 0)
+        hipLaunchKernelGGL(k_pr_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, close, open, dt_fs, rlist,
+                           strain_tol);
+}
+
+void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pr_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
+                       k.compact);
+}
+
+void launch_pr_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pr_close_scale, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P, st);
+}
+
+void launch_pr_mark_build(const Buffers& b, const KernelShape& k, hipStream_t s)
+{
+    if (k.n_replicas > 0)
+        hipLaunchKernelGGL(k_pr_mark_build, dim3((k.n_replicas + kBlock - 1) / kBlock), dim3(kBlock), 0, s, b,
+                           k.n_replicas);
 }
 
 void launch_gear_start(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, hipStream_t s)

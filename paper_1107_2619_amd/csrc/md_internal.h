@@ -69,6 +69,7 @@ struct DevReplica {
     double cell[3];  // link-cell edge per axis, box / nc
     double qs[3];    // compact coordinate unit per axis, cell * 2^-kCompactBits
     double iqs[3];   // its inverse
+    double lbuild[3];  // edges at the last list build (differ from box only under the barostat)
 };
 
 __host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)
@@ -111,10 +112,11 @@ struct PotArgs {
 // F_MAX_COUNT: largest list length found by any build (overflow when > cap);
 // F_SKIN: atoms whose net displacement between builds exceeded skin/2;
 // F_OUTSIDE: atoms beyond the grid extent of a free axis (clamped; legal).
+// F_PR_BOX: the barostat shrank a link-cell edge below the list radius;
 // F_HALO: brick passes whose halo did not fit the LDS staging area (those
 // read their neighbours from global memory instead).  F_COMPACT: atoms too far
 // outside their link cell for the compact mixed-mode record.
-enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_COUNT = 8 };
+enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_PR_BOX = 5, F_COUNT = 8 };
 
 // Pointers into the workspace.
 struct Buffers {
@@ -162,6 +164,9 @@ struct Buffers {
     double* ehalf;        // [Np] half-list pair-energy accumulator (half of sum phi)
     double* acc[2][3];    // [Np] Gear integrator: acceleration, A/fs^2 (null with Verlet)
     double* jrk[2][3];    // [Np] Gear integrator: its time derivative, A/fs^3
+    double* pr_param;     // [R][2] barostat mass W (eV fs^2/A^2), external pressure (eV/A^3)
+    double* pr_state;     // [R][kPrState] box, box velocity and the factors of the open pass
+    double* pr_partial;   // [Np / 64][6] per-wave sums of m v_a^2 and of the virial diagonal
     double* x0[3];        // [N] origin positions of the mean square displacement, caller order
     uint8_t* ctype;       // [N] species | rigid bit, caller order
     double* msd_partial;  // [n_chunks][2 * MD_MAX_SPECIES] sums of d^2 and atom counts
@@ -223,6 +228,18 @@ void launch_gear_predict(const Buffers& b, int p, int q, const KernelShape& k, c
                          hipStream_t s);
 void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                          const md_state& st, int last, hipStream_t s);
+
+// Barostat (orthorhombic Parrinello-Rahman).  pr_state per replica:
+// [0,3) L, [3,6) dL/dt, [6,9) velocity scale of the open pass, [9,12) L'/L of
+// its drift, [12,15) h phi(u) L'/L of its drift, [15,18) closing velocity scale.
+constexpr int kPrState = 20;
+void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
+                      double dt_fs, double rlist, double strain_tol, hipStream_t s);
+void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                    hipStream_t s);
+void launch_pr_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,
+                           hipStream_t s);
+void launch_pr_mark_build(const Buffers& b, const KernelShape& k, hipStream_t s);
 
 // Launchers (kernels_analysis.hip).
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);

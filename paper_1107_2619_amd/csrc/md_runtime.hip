@@ -21,6 +21,8 @@ struct md_ctx {
     bool nvt = false;        // Nose-Hoover thermostat per replica
     bool gear = false;       // third-order Gear predictor-corrector instead of Verlet
     bool gear_ready = false; // Gear derivatives started since md_bind
+    bool pr = false;         // Parrinello-Rahman barostat per replica (orthorhombic box)
+    std::vector<double> pr_P, pr_W;  // GPa, eV fs^2 / A^2
     std::vector<double> nh_T, nh_Q;
     std::vector<double> nh_gkt;  // host copy of nh_param
     std::vector<int64_t> atom_off;
@@ -124,7 +126,7 @@ KernelShape shape(const md_ctx* c)
     k.table = c->table_ok && c->evaluator == 0;
     k.n_chunks = (int32_t)c->chunk_rep.size();
     k.n_bricks = (int32_t)c->brick_rep.size();
-    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL;
+    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL && !c->pr;  // the barostat moves the bricks' box
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
@@ -230,10 +232,31 @@ bool build_cell_table(md_ctx* c)
     return hip_ok(c, hipGetLastError(), "cell table") && hip_ok(c, hipStreamSynchronize(nullptr), "cell table");
 }
 
+// Edge-dependent fields of a replica descriptor for edges L.
+void set_edges(DevReplica& D, const double L[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        D.box[a] = L[a];
+        D.inv_box[a] = 1.0 / L[a];
+        D.cell[a] = L[a] / (double)D.nc[a];
+        D.qs[a] = std::ldexp(D.cell[a], -kCompactBits);
+        D.iqs[a] = std::ldexp(1.0 / D.cell[a], kCompactBits);
+    }
+}
+
 bool upload_geometry(md_ctx* c)
 {
     if (!c->bound) return true;
     c->have_list = false;
+    if (c->pr) {  // the device holds the barostat's current box: keep it
+        std::vector<DevReplica> cur(c->reps.size());
+        if (!hip_ok(c, hipMemcpy(cur.data(), c->buf.reps, cur.size() * sizeof(DevReplica), hipMemcpyDeviceToHost), "upload"))
+            return false;
+        for (size_t r = 0; r < cur.size(); ++r) {
+            set_edges(c->reps[r], cur[r].box);
+            for (int a = 0; a < 3; ++a) c->reps[r].lbuild[a] = cur[r].lbuild[a];
+        }
+    }
     return hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "upload") &&
            hip_ok(c, hipMemcpy(c->buf.cell_shift, c->cell_shift.data(), c->cell_shift.size() * 4, hipMemcpyHostToDevice), "upload") &&
            hip_ok(c, hipMemcpy(c->buf.cell_rep, c->cell_rep.data(), c->cell_rep.size() * 4, hipMemcpyHostToDevice), "upload") &&
@@ -323,7 +346,7 @@ void plan_workspace(md_ctx* c)
     size_t max_bricks = 0;
     for (int r = 0; r < c->R; ++r)
         max_bricks += (size_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
-    const bool keep_f = c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt || c->gear;
+    const bool keep_f = c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt || c->gear || c->pr;
     const size_t gear = c->gear ? Np * 8 : 0;
     std::vector<size_t> sizes = {
         Np * 32, Np * 32,                                    // pos[2]
@@ -374,6 +397,9 @@ void plan_workspace(md_ctx* c)
         (size_t)c->R * 2 * MD_MAX_SPECIES * 8,               // msd_out
         gear, gear, gear, gear, gear, gear,                  // acc[2][3]
         gear, gear, gear, gear, gear, gear,                  // jrk[2][3]
+        c->pr ? (size_t)c->R * 16 : 0,                       // pr_param
+        c->pr ? (size_t)c->R * kPrState * 8 : 0,             // pr_state
+        c->pr ? Np / kWave * 6 * 8 : 0,                      // pr_partial
     };
     c->off.clear();
     size_t o = 0;
@@ -457,6 +483,9 @@ void bind_buffers(md_ctx* c)
     if (!c->gear)  // the sort moves Gear state only where it exists
         for (int k = 0; k < 2; ++k)
             for (int a = 0; a < 3; ++a) b.acc[k][a] = b.jrk[k][a] = nullptr;
+    at(b.pr_param);
+    at(b.pr_state);
+    at(b.pr_partial);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -526,13 +555,16 @@ void ensure_slots(md_ctx* c, hipStream_t s)
 void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
 {
     const KernelShape k = shape(c);
-    const double half_skin2 = (c->have_list && check_skin) ? 0.25 * c->skin * c->skin : -1.0;
+    // under the barostat the skin is shared: 0.4 skin per atom and 0.2 skin for the strain
+    const double guard = c->pr ? 0.4 * c->skin : 0.5 * c->skin;
+    const double half_skin2 = (c->have_list && check_skin) ? guard * guard : -1.0;
     Timed tm(c, MD_KT_BUILD, s);
     launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
     c->p ^= 1;
     c->q ^= 1;
     if (k.brick) launch_brick_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, s);
     else launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    if (c->pr) launch_pr_mark_build(c->buf, k, s);
     c->have_list = true;
     c->built_at = c->step;
     ++c->n_builds;
@@ -590,6 +622,20 @@ void nh_boundary(md_ctx* c, int halves, hipStream_t s)
 
 bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
 
+// Barostat step boundary: the stress tensor, the box half kicks (closing,
+// opening or both), and with `open` the box drift and the particles' opening
+// friction, kick and drift (into pos[p^1]).
+void pr_boundary(md_ctx* c, int close, int open, hipStream_t s)
+{
+    const KernelShape k = shape(c);
+    Timed tm(c, MD_KT_FORCE, s);
+    launch_pr_update(c->buf, c->q, k, c->args, close, open, c->dt_fs, c->rlist, 0.2 * c->skin, s);
+    if (open) {
+        launch_pr_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
+        c->p ^= 1;
+    }
+}
+
 // One Gear step ("Time integration") from predicted positions in pos[p]: the
 // list rebuild on schedule (at the predicted positions, where the forces are
 // taken), the force pass, then the corrector, which within a call also
@@ -620,7 +666,10 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
         }
         ++c->step;
         if (due(c)) rebuild(c, s, true);
-        if (c->nvt) {
+        if (c->pr) {
+            forces(c, ForceFlags{1, 1, 0, 0}, s, false);  // closing kick and the stress, forces kept
+            pr_boundary(c, 1, 1, s);
+        } else if (c->nvt) {
             forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
             nh_boundary(c, 2, s);
         } else {
@@ -713,6 +762,19 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     if (cfg->integrator != MD_VERLET && cfg->integrator != MD_GEAR3) return reject(MD_ERR_ARG, "integrator must be MD_VERLET or MD_GEAR3");
     c->gear = cfg->integrator == MD_GEAR3;
     if (c->gear && c->nvt) return reject(MD_ERR_ARG, "the Gear integrator runs NVE only (no thermostat)");
+    if ((cfg->pr_pressure_gpa == nullptr) != (cfg->pr_mass == nullptr))
+        return reject(MD_ERR_ARG, "pr_pressure_gpa and pr_mass go together (both NULL for a fixed box)");
+    c->pr = cfg->pr_pressure_gpa != nullptr;
+    if (c->pr) {
+        if (c->nvt || c->gear) return reject(MD_ERR_ARG, "the barostat runs with velocity Verlet and no thermostat");
+        if (cfg->nbr_mode != MD_NBR_FULL) return reject(MD_ERR_ARG, "the barostat needs the full neighbour list");
+        c->pr_P.assign(cfg->pr_pressure_gpa, cfg->pr_pressure_gpa + c->R);
+        c->pr_W.assign(cfg->pr_mass, cfg->pr_mass + c->R);
+        for (int r = 0; r < c->R; ++r) {
+            if (!std::isfinite(c->pr_P[r])) return reject(MD_ERR_ARG, "pr_pressure_gpa must be finite");
+            if (!(c->pr_W[r] > 0.0) || !std::isfinite(c->pr_W[r])) return reject(MD_ERR_ARG, "pr_mass must be finite and > 0");
+        }
+    }
     if (c->nvt) {
         c->nh_T.assign(cfg->nh_temperature, cfg->nh_temperature + c->R);
         c->nh_Q.assign(cfg->nh_mass, cfg->nh_mass + c->R);
@@ -838,12 +900,19 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             D.inv_box[a] = 1.0 / L;
             D.origin[a] = c->origin[3 * r + a];
             D.vp[a] = c->vp[3 * r + a];
-            int64_t nc = (int64_t)std::floor(L / c->rlist);
+            // under the barostat the grid leaves 5% room for compression
+            int64_t nc = (int64_t)std::floor(L / (c->pr ? 1.05 * c->rlist : c->rlist));
             nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1023));
+            if (c->pr && (!per || nc < 3)) {
+                char msg[160];
+                std::snprintf(msg, sizeof msg, "replica %d axis %d: the barostat needs a periodic axis of at least three link cells", r, a);
+                return reject(c->pr && !per ? MD_ERR_ARG : MD_ERR_BOX, msg);
+            }
             D.nc[a] = (int32_t)nc;
             D.cell[a] = L / (double)nc;
             D.qs[a] = std::ldexp(D.cell[a], -kCompactBits);
             D.iqs[a] = std::ldexp(1.0 / D.cell[a], kCompactBits);
+            D.lbuild[a] = L;
             cell_min = std::min(cell_min, D.cell[a]);
             if (per) D.periodic_mask |= 1 << a;
             worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
@@ -907,6 +976,11 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     c->st = *st;
     c->ws = workspace;
     bind_buffers(c);
+    if (c->pr)  // the barostat restarts from the configured box
+        for (int r = 0; r < c->R; ++r) {
+            set_edges(c->reps[r], &c->box[3 * (size_t)r]);
+            for (int a = 0; a < 3; ++a) c->reps[r].lbuild[a] = c->box[3 * (size_t)r + a];
+        }
     if (!hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.pot, &c->pot, sizeof(DevPotential), hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.rep_of_wave, c->rep_of_wave.data(), c->rep_of_wave.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
@@ -952,6 +1026,25 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
             !hip_ok(c, hipMemcpy(c->buf.nh_state, state.data(), state.size() * 8, hipMemcpyHostToDevice), "md_bind thermostat"))
             return MD_ERR_DEVICE;
         c->nh_gkt.assign(param.begin(), param.end());
+    }
+    if (c->pr) {
+        // barostat: W and P per replica; the box starts at the configured edges at rest
+        for (int r = 0; r < c->R; ++r)
+            if (c->n_mobile[r] < c->reps[r].n_atoms) return fail(c, MD_ERR_ARG, "md_bind: the barostat takes no rigid atoms");
+        std::vector<double> param(2 * (size_t)c->R), state((size_t)kPrState * c->R, 0.0);
+        for (int r = 0; r < c->R; ++r) {
+            param[2 * r] = c->pr_W[r];
+            param[2 * r + 1] = c->pr_P[r] / kEvPerA3InGpa;
+            for (int a = 0; a < 3; ++a) {
+                state[(size_t)kPrState * r + a] = c->box[3 * r + a];
+                state[(size_t)kPrState * r + 6 + a] = 1.0;
+                state[(size_t)kPrState * r + 9 + a] = 1.0;
+                state[(size_t)kPrState * r + 15 + a] = 1.0;
+            }
+        }
+        if (!hip_ok(c, hipMemcpy(c->buf.pr_param, param.data(), param.size() * 8, hipMemcpyHostToDevice), "md_bind barostat") ||
+            !hip_ok(c, hipMemcpy(c->buf.pr_state, state.data(), state.size() * 8, hipMemcpyHostToDevice), "md_bind barostat"))
+            return MD_ERR_DEVICE;
     }
     if (c->N > 0) {
         // mean square displacement: species and rigid flag in caller order, and
@@ -1020,6 +1113,9 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
             launch_gear_predict(c->buf, c->p, c->q, shape(c), c->args, c->dt_fs, s);
         }
         c->p ^= 1;
+    } else if (c->pr) {
+        forces(c, ForceFlags{1, 0, 0, 0}, s, false);  // f(x0) and the stress
+        pr_boundary(c, 0, 1, s);                      // box half kick and drift, opening kick and drift
     } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
         nh_boundary(c, 1, s);                  // thermostat half step, opening kick, drift
@@ -1045,7 +1141,16 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     }
     ++c->step;
     if (due(c)) rebuild(c, s, true);
-    if (c->nvt) {
+    if (c->pr) {
+        forces(c, ForceFlags{1, 1, 0, 1}, s, false);  // closing kick, energies, write back
+        const KernelShape k = shape(c);
+        {
+            Timed tm(c, MD_KT_FORCE, s);
+            launch_pr_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, s);  // closing box half kick
+            launch_pr_close_scale(c->buf, c->q, k, c->args, c->st, s);
+        }
+        reduce_energies(c, k, s);
+    } else if (c->nvt) {
         forces(c, ForceFlags{1, 1, 0, 1}, s, false);  // closing kick, energies, write back
         const KernelShape k = shape(c);
         {
@@ -1076,6 +1181,9 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     std::vector<double> nh((size_t)c->R * 4, 0.0);
     if (c->nvt && !hip_ok(c, hipMemcpy(nh.data(), c->buf.nh_state, nh.size() * 8, hipMemcpyDeviceToHost), "md_energy thermostat"))
         return MD_ERR_DEVICE;
+    std::vector<double> pr((size_t)c->R * kPrState, 0.0);
+    if (c->pr && !hip_ok(c, hipMemcpy(pr.data(), c->buf.pr_state, pr.size() * 8, hipMemcpyDeviceToHost), "md_energy barostat"))
+        return MD_ERR_DEVICE;
     for (int r = 0; r < c->R; ++r) {
         const double* v = e.data() + (size_t)r * kEnergySlots;
         md_energies& o = out[r];
@@ -1086,7 +1194,12 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         o.pe = v[E_PE];
         o.ke = v[E_KE];
         o.temperature = dof > 0 ? 2.0 * o.ke / ((double)dof * kBoltzmannEv) : 0.0;
-        o.volume = D.box[0] * D.box[1] * D.box[2];
+        for (int a = 0; a < 3; ++a) o.box[a] = c->pr ? pr[(size_t)kPrState * r + a] : D.box[a];
+        o.volume = o.box[0] * o.box[1] * o.box[2];
+        if (c->pr) {
+            const double* ld = &pr[(size_t)kPrState * r + 3];
+            o.pr_energy = c->pr_P[r] / kEvPerA3InGpa * o.volume + 0.5 * c->pr_W[r] * (ld[0] * ld[0] + ld[1] * ld[1] + ld[2] * ld[2]);
+        }
         for (int k = 0; k < 6; ++k) o.virial[k] = v[E_W0 + k];
         o.pressure_gpa = (2.0 * o.ke + o.virial[0] + o.virial[1] + o.virial[2]) / (3.0 * o.volume) * kEvPerA3InGpa;
         o.piston_work = v[E_PW];
@@ -1112,10 +1225,12 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         return fail(c, MD_ERR_NBR_OVERFLOW, msg);
     }
     c->halo_overflows = flags[F_HALO];
+    if (flags[F_PR_BOX] > 0)
+        return fail(c, MD_ERR_BOX, "barostat: a box edge shrank below its link cells' list radius (more than the 5% the grid allows)");
     if (flags[F_SKIN] > 0) {
         char msg[200];
-        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved more than skin/2 = %.4g A between list builds", flags[F_SKIN],
-                      0.5 * c->skin);
+        std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved more than %.4g A between list builds%s", flags[F_SKIN],
+                      (c->pr ? 0.4 : 0.5) * c->skin, c->pr ? " (or the box strained more than 0.2 skin / list radius)" : "");
         return fail(c, MD_ERR_SKIN, msg);
     }
     if (flags[F_COMPACT] > 0) {

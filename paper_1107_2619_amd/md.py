@@ -71,6 +71,7 @@ class _Config(ctypes.Structure):
         ("periodic", ctypes.c_void_p), ("rigid_velocity", ctypes.c_void_p),
         ("skin", ctypes.c_double), ("dt_fs", ctypes.c_double),
         ("nh_temperature", ctypes.c_void_p), ("nh_mass", ctypes.c_void_p), ("integrator", ctypes.c_int32),
+        ("pr_pressure_gpa", ctypes.c_void_p), ("pr_mass", ctypes.c_void_p),
     ]
 
 
@@ -85,7 +86,8 @@ class _Energies(ctypes.Structure):
         ("pressure_gpa", ctypes.c_double), ("volume", ctypes.c_double),
         ("piston_work", ctypes.c_double), ("virial", ctypes.c_double * 6),
         ("step", ctypes.c_int64), ("n_atoms", ctypes.c_int64), ("n_mobile", ctypes.c_int64),
-        ("nh_pi", ctypes.c_double), ("nh_energy", ctypes.c_double),
+        ("nh_pi", ctypes.c_double), ("nh_energy", ctypes.c_double), ("box", ctypes.c_double * 3),
+        ("pr_energy", ctypes.c_double),
     ]
 
 
@@ -144,7 +146,8 @@ class Context:
 
     def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
                  skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
-                 nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None, integrator="verlet"):
+                 nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None, integrator="verlet",
+                 pr_pressure_gpa=None, pr_mass=None):
         self.lib = library()
         pa = _c(potential["pair_a"], np.float64)
         ns = pa.shape[0]
@@ -162,6 +165,9 @@ class Context:
         k["nh_t"] = None if nh_temperature is None else np.broadcast_to(
             np.asarray(nh_temperature, np.float64), (n_rep,)).copy()
         k["nh_q"] = None if nh_mass is None else np.broadcast_to(np.asarray(nh_mass, np.float64), (n_rep,)).copy()
+        k["pr_p"] = None if pr_pressure_gpa is None else np.broadcast_to(
+            np.asarray(pr_pressure_gpa, np.float64), (n_rep,)).copy()
+        k["pr_w"] = None if pr_mass is None else np.broadcast_to(np.asarray(pr_mass, np.float64), (n_rep,)).copy()
         pot = _Potential(ns, pa.shape[2], k["dens_A"].shape[2], 0, pa.ctypes.data, k["pair_r"].ctypes.data,
                          k["dens_A"].ctypes.data, k["dens_R"].ctypes.data, k["emb_c"].ctypes.data,
                          k["mass"].ctypes.data)
@@ -174,6 +180,7 @@ class Context:
             None if k["vp"] is None else k["vp"].ctypes.data, float(skin), float(dt_fs),
             None if k["nh_t"] is None else k["nh_t"].ctypes.data, None if k["nh_q"] is None else k["nh_q"].ctypes.data,
             {"verlet": MD_VERLET, "gear3": MD_GEAR3}[integrator] if isinstance(integrator, str) else int(integrator),
+            None if k["pr_p"] is None else k["pr_p"].ctypes.data, None if k["pr_w"] is None else k["pr_w"].ctypes.data,
         )
         h = ctypes.c_void_p()
         rc = self.lib.md_create(ctypes.byref(cfg), ctypes.byref(pot), ctypes.byref(h))
@@ -226,6 +233,8 @@ class Energies:
     n_mobile: np.ndarray
     nh_pi: np.ndarray      # thermostat momentum per replica, 1/fs (0 without a thermostat)
     nh_energy: np.ndarray  # thermostat energy 0.5 Q pi^2 + g k T xi, eV
+    box: np.ndarray        # [R, 3] edge lengths, A
+    pr_energy: np.ndarray  # barostat energy P Omega + W |dL/dt|^2 / 2, eV
 
 
 class Simulation:
@@ -233,7 +242,7 @@ class Simulation:
 
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
                  device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
-                 nh_mass=None, integrator="verlet"):
+                 nh_mass=None, integrator="verlet", pr_pressure_gpa=None, pr_mass=None):
         import torch
 
         self.torch = torch
@@ -247,6 +256,7 @@ class Simulation:
             max_neighbours=self.cap,
             precision=precision, nbr_mode=nbr_mode, lanes_per_atom=lanes_per_atom,
             nh_temperature=nh_temperature, nh_mass=nh_mass, integrator=integrator,
+            pr_pressure_gpa=pr_pressure_gpa, pr_mass=pr_mass,
         )
         d = self.device
         f64 = dict(dtype=torch.float64, device=d)
@@ -312,7 +322,7 @@ class Simulation:
         g = lambda name: np.array([getattr(o, name) for o in out])  # noqa: E731
         return Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"), g("piston_work"),
                         np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"),
-                        g("nh_pi"), g("nh_energy"))
+                        g("nh_pi"), g("nh_energy"), np.array([list(o.box) for o in out]), g("pr_energy"))
 
     def msd(self):
         """(msd [R, n_species] A^2, count [R, n_species]): mean square displacement

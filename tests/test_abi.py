@@ -160,3 +160,29 @@ def test_integrator_validation(md):
         _ctx(md, integrator="gear3", nh_temperature=[300.0], nh_mass=[50.0])
     assert e.value.code == md.MD_ERR_ARG
     assert _ctx(md, integrator="gear3").workspace_bytes() > _ctx(md).workspace_bytes()
+
+
+def test_barostat_validation(md):
+    """The barostat's arguments and preconditions are checked on the host."""
+    s = inputs.bcc_fe(6, a=2.90)
+    base = dict(skin=0.3, max_neighbours=48)
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4], **base)
+    bad = [
+        dict(pr_pressure_gpa=[1.0]), dict(pr_mass=[1e4]),
+        dict(pr_pressure_gpa=[np.nan], pr_mass=[1e4]), dict(pr_pressure_gpa=[1.0], pr_mass=[0.0]),
+        dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], nh_temperature=[300.0], nh_mass=[50.0]),
+        dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], integrator="gear3"),
+        dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], nbr_mode="half"),
+    ]
+    for kw in bad:
+        with pytest.raises(md.MDError) as e:
+            md.Context(s.potential, s.atom_offset, s.box, s.periodic, **base, **kw)
+        assert e.value.code == md.MD_ERR_ARG, kw
+    # a free axis, and a box of fewer than three link cells with the 5% margin
+    with pytest.raises(md.MDError):
+        md.Context(s.potential, s.atom_offset, s.box, [[1, 1, 0]], pr_pressure_gpa=[1.0], pr_mass=[1e4], **base)
+    small = inputs.bcc_fe(4, a=2.90)
+    with pytest.raises(md.MDError) as e:
+        md.Context(small.potential, small.atom_offset, small.box, small.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4],
+                   **base)
+    assert e.value.code == md.MD_ERR_BOX
