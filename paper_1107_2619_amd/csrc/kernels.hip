@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
 }
 
 // Force pass + velocity Verlet (global gathers).
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
           bool CMP>
 __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
                                                    double dt, md_state st)
@@ -679,7 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
     if (EV == EV_TABLE && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
         lds_fill(s, tf, P.nbt * kForceStride);
-        if (ENERGY) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        if (ENERGY == 1) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
         __syncthreads();
         tf = s;
         te = s + P.nbt * kForceStride;
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
             if (!(r2 < P.rc2)) continue;
             const double ri = inv_dist<R>(r2);
             const double r = r2 * ri;
-            const uint8_t tj = (!SINGLE || ENERGY) ? b.type[q][e[u] & kIndexMask] : 0;
+            const uint8_t tj = (!SINGLE || ENERGY == 1) ? b.type[q][e[u] & kIndexMask] : 0;
             R g, phi;
             pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, fpj, g, phi);
             accumulate<ENERGY>(A, (double)g * ri, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
@@ -1334,7 +1334,7 @@ __global__ __launch_bounds__(kBlock) void k_force_half(Buffers b, int p, int q, 
     if (EV == EV_TABLE && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
         lds_fill(s, tf, P.nbt * kForceStride);
-        if (ENERGY) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        if (ENERGY == 1) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
         __syncthreads();
         tf = s;
         te = s + P.nbt * kForceStride;
@@ -1515,11 +1515,11 @@ void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const 
     }
 }
 
-template <typename R, bool S, int NP, int ND, int EV, bool E, bool C, bool O, bool W>
+template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W>
 static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                          const md_state& st, hipStream_t s)
 {
-    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (E ? 4 : 0)) * sizeof(R) : 0;
+    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (E == 1 ? 4 : 0)) * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
     if (k.compact)
         hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
@@ -1535,7 +1535,7 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
 {
     if (!fl.close && !fl.open) {
         if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
-            force_launch<R, S, NP, ND, EV, true, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+            force_launch<R, S, NP, ND, EV, 2, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else force_launch<R, S, NP, ND, EV, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
@@ -1544,7 +1544,7 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
     } else if (fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy) {  // barostat: closing kick with the stress, forces kept
-        force_launch<R, S, NP, ND, EV, true, true, false, false>(b, p, q, k, P, dt_fs, st, s);
+        force_launch<R, S, NP, ND, EV, 2, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {
         force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else {

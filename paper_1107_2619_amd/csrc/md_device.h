@@ -317,7 +317,7 @@ __device__ __forceinline__ R density_term(const PotArgs& P, const DevPotential& 
 // g_ij = phi'_{ij}(r) + F'_i rho'_{ij}(r) + F'_j rho'_{ji}(r) and, on energy
 // steps, phi_{ij}(r).  Tables: tf = [ns*ns][nbt][kForceStride] derivative quadratics,
 // te = [ns*ns][nbt][4] value cubics.
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool ENERGY>
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY>
 __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential& G, const R* tf, const R* te,
                                            int si, int sj, double r, R fpi, R fpj, R& g, R& phi)
 {
@@ -328,18 +328,18 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
         if (SINGLE) {
             const R* c = tf + bin * kForceStride;
             g = quadratic(c, u) + (fpi + fpj) * quadratic(c + 3, u);
-            if (ENERGY) phi = cubic(te + bin * 4, u);
+            if (ENERGY == 1) phi = cubic(te + bin * 4, u);
         } else {
             const int64_t ab = si * G.ns + sj, ba = sj * G.ns + si;
             const R* c = tf + (ab * P.nbt + bin) * kForceStride;
             const R* c2 = tf + (ba * P.nbt + bin) * kForceStride;
             g = quadratic(c, u) + fpi * quadratic(c + 3, u) + fpj * quadratic(c2 + 3, u);
-            if (ENERGY) phi = cubic(te + (ab * P.nbt + bin) * 4, u);
+            if (ENERGY == 1) phi = cubic(te + (ab * P.nbt + bin) * 4, u);
         }
     } else if (SINGLE) {
         const Coef<R> C1 = single_coef<R>(P);
         R dphi;
-        if (ENERGY) knot_both<R, NPK>(C1.pa, C1.pd, C1.pr, r, phi, dphi);
+        if (ENERGY == 1) knot_both<R, NPK>(C1.pa, C1.pd, C1.pr, r, phi, dphi);
         else dphi = knot_deriv<R, NPK>(C1.pd, C1.pr, r);
         g = dphi + (fpi + fpj) * knot_deriv<R, NDK>(C1.dd, C1.dr, r);
     } else {
@@ -347,7 +347,7 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
         KnotSet<R, NPK> kp;
         load_knots<R, NPK>(G.pair_a[ab], G.pair_d[ab], G.pair_r[ab], kp);
         R dphi;
-        if (ENERGY) knot_both<R, NPK>(kp.a, kp.d, kp.r, r, phi, dphi);
+        if (ENERGY == 1) knot_both<R, NPK>(kp.a, kp.d, kp.r, r, phi, dphi);
         else dphi = knot_deriv<R, NPK>(kp.d, kp.r, r);
         KnotSet<R, NDK> kab, kba;
         load_knots<R, NDK>(G.dens_a[ab], G.dens_d[ab], G.dens_r[ab], kab);
@@ -356,22 +356,23 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
     }
 }
 
-// Pair accumulation into the site atom: force, and on energy steps the pair
-// energy and the virial tensor (pairs of two rigid atoms excluded).
+// Pair accumulation into the site atom: force, and on energy steps
+// (ENERGY = 1) the pair energy and the virial tensor (pairs of two rigid atoms
+// excluded); ENERGY = 2 (barostat steps) keeps only the virial diagonal.
 struct PairAcc {
     double f[3] = {0.0, 0.0, 0.0};
     double epair = 0.0;
     double w[6] = {0, 0, 0, 0, 0, 0};
 };
 
-template <bool ENERGY>
+template <int ENERGY>
 __device__ __forceinline__ void accumulate(PairAcc& A, double s, double dx, double dy, double dz, double phi,
                                            bool both_rigid)
 {
     A.f[0] = fma(s, dx, A.f[0]);
     A.f[1] = fma(s, dy, A.f[1]);
     A.f[2] = fma(s, dz, A.f[2]);
-    if (ENERGY) {
+    if (ENERGY == 1) {
         A.epair += phi;
         if (!both_rigid) {
             A.w[0] = fma(s * dx, dx, A.w[0]);
@@ -381,6 +382,10 @@ __device__ __forceinline__ void accumulate(PairAcc& A, double s, double dx, doub
             A.w[4] = fma(s * dx, dz, A.w[4]);
             A.w[5] = fma(s * dy, dz, A.w[5]);
         }
+    } else if (ENERGY == 2) {  // the barostat takes no rigid atoms
+        A.w[0] = fma(s * dx, dx, A.w[0]);
+        A.w[1] = fma(s * dy, dy, A.w[1]);
+        A.w[2] = fma(s * dz, dz, A.w[2]);
     }
 }
 
@@ -391,7 +396,7 @@ __device__ __forceinline__ void accumulate(PairAcc& A, double s, double dx, doub
 // accumulate the work -f.v_p dt/2 per half step (trapezoid rule).  On energy
 // steps the atom's energy terms go to its slot of `eslot`; with WRITEBACK the
 // final state returns to the caller's arrays (caller order, unwrapped).
-template <bool SINGLE, bool ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK>
+template <bool SINGLE, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK>
 __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, int64_t t, int64_t n_slots,
                                               const DevReplica& Rp, const PotArgs& P, const DevPotential& G,
                                               double dt, const md_state& st, const double4& pi, uint8_t ti,
@@ -422,7 +427,7 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
 #pragma unroll
             for (int a = 0; a < 3; ++a) v[a] = fma(0.5 * dt * acc, f[a], v[a]);
         }
-        if (ENERGY) ke = (SINGLE ? P.half_m : G.half_m[si]) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (ENERGY == 1) ke = (SINGLE ? P.half_m : G.half_m[si]) * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         if (OPEN) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -441,12 +446,15 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         dst[2] = xn[2];
     }
     double pe = 0.0;
-    if (ENERGY) {
+    if (ENERGY == 1) {
         pe = 0.5 * A.epair + b.femb[t];
         const int nonfinite = (!isfinite(pe) || !isfinite(ke) || !isfinite(f[0] + f[1] + f[2])) ? 1 : 0;
         const double vals[kEnergyTerms] = {pe, ke, A.w[0], A.w[1], A.w[2], A.w[3], A.w[4], A.w[5], pw, (double)nonfinite};
 #pragma unroll
         for (int k = 0; k < kEnergyTerms; ++k) b.eslot[(int64_t)k * n_slots + t] = vals[k];
+    } else if (ENERGY == 2) {  // barostat steps: the virial diagonal only
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
     }
     if (!OPEN && !WRITEBACK) {
         // thermostatted steps: the opening kick runs after the kinetic-energy
@@ -467,7 +475,7 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
             st.vy[a] = v[1];
             st.vz[a] = v[2];
         }
-        if (ENERGY && st.e_atom) st.e_atom[a] = pe;
+        if (ENERGY == 1 && st.e_atom) st.e_atom[a] = pe;
     }
 }
 

@@ -208,6 +208,7 @@ void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipSt
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
+// energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat)
 struct ForceFlags {
     int energy, close, open, writeback;
 };

@@ -597,8 +597,9 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
     {
         Timed tm(c, MD_KT_DENSITY, s);
-        if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fl.energy, s);
-        else launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fl.energy, s);
+        const int fe = fl.energy == 1;  // barostat steps (energy 2) need no embedding energies
+        if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
+        else launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fe, s);
     }
     {
         Timed tm(c, MD_KT_FORCE, s);
@@ -606,7 +607,7 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
         else launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
     }
     if (fl.open) c->p ^= 1;
-    if (fl.energy && reduce) reduce_energies(c, k, s);
+    if (fl.energy == 1 && reduce) reduce_energies(c, k, s);
 }
 
 // Thermostatted step boundary: kinetic energy, `halves` thermostat half steps,
@@ -667,7 +668,7 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
         ++c->step;
         if (due(c)) rebuild(c, s, true);
         if (c->pr) {
-            forces(c, ForceFlags{1, 1, 0, 0}, s, false);  // closing kick and the stress, forces kept
+            forces(c, ForceFlags{2, 1, 0, 0}, s, false);  // closing kick and the virial, forces kept
             pr_boundary(c, 1, 1, s);
         } else if (c->nvt) {
             forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
@@ -1114,7 +1115,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         }
         c->p ^= 1;
     } else if (c->pr) {
-        forces(c, ForceFlags{1, 0, 0, 0}, s, false);  // f(x0) and the stress
+        forces(c, ForceFlags{2, 0, 0, 0}, s, false);  // f(x0) and the virial
         pr_boundary(c, 0, 1, s);                      // box half kick and drift, opening kick and drift
     } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
