@@ -88,6 +88,9 @@ def _load():
     lib.or_run_pr.restype = i32
     lib.or_run_pr.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, vp, vp, vp, vp, vp, vp,
                               vp]
+    lib.or_run_npt.restype = i32
+    lib.or_run_npt.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, d, d, vp, vp, vp, vp, vp,
+                               vp, vp]
     lib.or_run_gear.restype = i32
     lib.or_run_gear.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
     lib.or_run_nh.restype = i32
@@ -370,6 +373,47 @@ def run_pr(pos, vel, species, box, pot: Potential, dt_fs, nsteps, p_gpa, w_ev_fs
         raise ValueError("oracle: periodic box length must exceed twice the cutoff")
     return PRResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, bx.reshape(-1, 3),
                     ld.reshape(-1, 3), ba, pr)
+
+
+@dataclass
+class NPTResult:
+    pos: np.ndarray
+    vel: np.ndarray
+    f: np.ndarray
+    pe: np.ndarray
+    ke: np.ndarray
+    box: np.ndarray       # [nsteps+1, 3] A
+    baro: np.ndarray      # P Omega + W |dL/dt|^2 / 2, eV
+    pressure: np.ndarray  # GPa
+    pi: np.ndarray        # thermostat momentum, 1/fs
+    nh_energy: np.ndarray  # Q pi^2 / 2 + g k_B T xi, eV
+
+
+def run_npt(pos, vel, species, box, pot: Potential, dt_fs, nsteps, p_gpa, w_ev_fs2_a2, t_target, q_ev_fs2,
+            origin=None) -> NPTResult:
+    """Parrinello-Rahman barostat with the Nose-Hoover thermostat (paper,
+    "Barostat NPTp"), orthorhombic box, hydrostatic pressure; every axis
+    periodic, no rigid atoms."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    L = _f64(box).copy()
+    o = np.zeros(3) if origin is None else _f64(origin)
+    f = np.zeros((n, 3))
+    m1 = nsteps + 1
+    pe, ke, bx, ba, pr, nh = (np.zeros(m1), np.zeros(m1), np.zeros(3 * m1), np.zeros(m1), np.zeros(m1),
+                              np.zeros(2 * m1))
+    rc = _load().or_run_npt(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
+        sp.ctypes.data, L.ctypes.data, o.ctypes.data, pot.ref, float(dt_fs), int(nsteps), float(p_gpa),
+        float(w_ev_fs2_a2), float(t_target), float(q_ev_fs2), f.ctypes.data, pe.ctypes.data, ke.ctypes.data,
+        bx.ctypes.data, ba.ctypes.data, pr.ctypes.data, nh.ctypes.data,
+    )
+    if rc:
+        raise ValueError("oracle: periodic box length must exceed twice the cutoff")
+    return NPTResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, bx.reshape(-1, 3), ba, pr,
+                     nh[0::2].copy(), nh[1::2].copy())
 
 
 @dataclass

@@ -795,6 +795,83 @@ done:
     return rc;
 }
 
+/*
+ * Parrinello-Rahman barostat with the Nose-Hoover thermostat (paper, "Barostat
+ * NPTp": "NPEp (or with Nose, NPTp)"), orthorhombic box.  The particle
+ * velocities feel both frictions, -(dL/dt / L) v and -pi_s v; the box and the
+ * thermostat follow their own equations as in or_run_pr and or_run_nh.  A step
+ * composes the exact sub-flows symmetrically: box half kick, thermostat half
+ * step, box friction half step, velocity half kick, drift, forces, and the
+ * mirror image.  PE + KE + P Omega + W |dL/dt|^2 / 2 + Q pi_s^2 / 2 + g k_B T xi
+ * is conserved.  Outputs as or_run_pr, plus nh_out[2s] = pi_s (1/fs) and
+ * nh_out[2s+1] = Q pi_s^2 / 2 + g k_B T xi.
+ */
+int or_run_npt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+               const uint8_t *species, double *box, const double *origin, const or_potential *p, double dt_fs,
+               int64_t nsteps, double p_gpa, double w_ev_fs2_a2, double t_target, double q_ev_fs2, double *f,
+               double *pe_out, double *ke_out, double *box_out, double *baro_out, double *press_out, double *nh_out)
+{
+    const uint8_t periodic[3] = {1, 1, 1};
+    const double t0 = or_time_unit_fs();
+    const double h = dt_fs / t0;
+    const double w = w_ev_fs2_a2 / (t0 * t0);
+    const double q = q_ev_fs2 / (t0 * t0);
+    const double pext = p_gpa / or_pressure_unit_gpa();
+    const double gkt = (3.0 * (double)n - 3.0) * OR_KB_EV_PER_K * t_target;
+    double *v[3] = {vx, vy, vz};
+    double *r[3] = {x, y, z};
+    double L[3] = {box[0], box[1], box[2]}, ldot[3] = {0.0, 0.0, 0.0}, vir[6], pe, pi = 0.0, xi = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] *= t0;
+    int rc = or_forces(n, x, y, z, species, NULL, L, periodic, p, f, NULL, NULL, vir, &pe);
+    if (rc) goto done;
+    for (int64_t s = 0;; ++s) {
+        const double omega = L[0] * L[1] * L[2];
+        const double ke = mobile_ke(n, v, species, NULL, p);
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) ke_out[s] = ke;
+        if (box_out)
+            for (int a = 0; a < 3; ++a) box_out[3 * s + a] = L[a];
+        if (baro_out)
+            baro_out[s] = pext * omega + 0.5 * w * (ldot[0] * ldot[0] + ldot[1] * ldot[1] + ldot[2] * ldot[2]);
+        if (press_out) press_out[s] = (2.0 * ke + vir[0] + vir[1] + vir[2]) / (3.0 * omega) * or_pressure_unit_gpa();
+        if (nh_out) {
+            nh_out[2 * s] = pi / t0;
+            nh_out[2 * s + 1] = 0.5 * q * pi * pi + gkt * xi;
+        }
+        if (s == nsteps) break;
+        pr_box_kick(n, v, species, p, vir, L, 0.5 * h, w, pext, ldot);
+        nh_half_step(n, v, species, NULL, p, 0.5 * h, q, gkt, &pi, &xi);
+        pr_friction(n, v, L, ldot, 0.5 * h);
+        for (int64_t i = 0; i < n; ++i) {
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * h * f[3 * i + a] / m;
+        }
+        for (int a = 0; a < 3; ++a) {
+            const double u = h * ldot[a] / L[a];
+            const double phi = u == 0.0 ? 1.0 : log1p(u) / u;
+            const double Ln = L[a] + h * ldot[a];
+            for (int64_t i = 0; i < n; ++i)
+                r[a][i] = origin[a] + (r[a][i] - origin[a] + v[a][i] * h * phi) * (Ln / L[a]);
+            L[a] = Ln;
+        }
+        rc = or_forces(n, x, y, z, species, NULL, L, periodic, p, f, NULL, NULL, vir, &pe);
+        if (rc) goto done;
+        for (int64_t i = 0; i < n; ++i) {
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * h * f[3 * i + a] / m;
+        }
+        pr_friction(n, v, L, ldot, 0.5 * h);
+        nh_half_step(n, v, species, NULL, p, 0.5 * h, q, gkt, &pi, &xi);
+        pr_box_kick(n, v, species, p, vir, L, 0.5 * h, w, pext, ldot);
+    }
+done:
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+    for (int a = 0; a < 3; ++a) box[a] = L[a];
+    return rc;
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -722,3 +722,36 @@ def test_pr_time_reversible(orc):
     assert np.max(np.abs(b.pos - s.pos)) < 1e-10
     assert np.max(np.abs(b.box[-1] - s.box[0])) < 1e-11
     assert np.max(np.abs(b.ldot[-1])) < 1e-13
+
+
+# --- Barostat with thermostat (NPT, "Barostat NPTp") --------------------------
+
+def test_npt_limits_are_nph_and_nvt(orc):
+    """Q -> infinity gives the barostat alone, W -> infinity the thermostat
+    alone, trajectory for trajectory."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    g = 3 * s.n_atoms - 3
+    q = g * orc.boltzmann_ev() * 500.0 * 50.0**2
+    a = orc.run_npt(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 200, 1.0, 1e4, 500.0, 1e30)
+    b = orc.run_pr(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 200, 1.0, 1e4)
+    assert np.max(np.abs(a.pos - b.pos)) < 1e-10 and np.max(np.abs(a.box - b.box)) < 1e-12
+    c = orc.run_npt(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 200, 1.0, 1e30, 500.0, q)
+    d = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 200, 500.0, q)
+    assert np.max(np.abs(c.pos - d.pos)) < 1e-10 and abs(c.pi[-1] - d.pi[-1]) < 1e-14
+
+
+def test_npt_conserved_quantity_and_averages(orc):
+    """PE + KE + barostat and thermostat energies stay within a band a
+    thousand times narrower than the swing of PE + KE; the time-averaged
+    pressure and temperature settle at their targets."""
+    s = _pr_system()
+    pot = orc.Potential(s.potential)
+    g = 3 * s.n_atoms - 3
+    q = g * orc.boltzmann_ev() * 500.0 * 50.0**2
+    r = orc.run_npt(s.pos, s.vel, s.species, s.box[0], pot, 1.0, 6000, 2.0, 1e4, 500.0, q)
+    h = r.pe + r.ke + r.baro + r.nh_energy
+    assert np.ptp(h) < 2e-3 * np.ptp(r.pe + r.ke)
+    assert abs(r.pressure[2000:].mean() - 2.0) < 0.15
+    t = 2.0 * r.ke[2000:] / (g * orc.boltzmann_ev())
+    assert abs(t.mean() - 500.0) < 15.0
