@@ -129,10 +129,11 @@ typedef struct {
      * stress tensor, and the particles feel the matching friction
      * -(dL_a/dt / L_a) v_a (NPH; PE + KE + P Omega + W |dL/dt|^2 / 2 is
      * conserved).  Both NULL = fixed box; both set = every replica under its
-     * own pressure.  Needs periodic axes, MD_VERLET, no thermostat, the full
-     * list and no rigid atoms; the link-cell grid leaves 5% room for
-     * compression (more gives MD_ERR_BOX).  The LDS-brick kernels are not
-     * used. */
+     * own pressure.  With the thermostat set too, the particles feel both
+     * frictions (NPT; pe + ke + pr_energy + nh_energy is conserved).  Needs
+     * periodic axes, MD_VERLET, the full list and no rigid atoms; the
+     * link-cell grid leaves 5% room for compression (more gives MD_ERR_BOX).
+     * The LDS-brick kernels are not used. */
     const double *pr_pressure_gpa; /* [R] external pressure, GPa, finite */
     const double *pr_mass;         /* [R] box mass W, eV fs^2 / Angstrom^2, > 0 */
 } md_config;

@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_tensor_waves(Buffers b, int q, in
 // tree), then on one lane the closing and/or opening box half kicks and, with
 // `open`, the box drift and the factors of the open pass.
 __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int open, double h, double rlist,
-                                                      double strain_tol)
+                                                      double strain_tol, int nvt)
 {
     __shared__ double sh[6][kBlock];
     const int r = blockIdx.x;
@@ -1004,21 +1004,48 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int 
     if (threadIdx.x != 0) return;
     double* st = b.pr_state + (int64_t)kPrState * r;
     const double W = b.pr_param[2 * r], pext = b.pr_param[2 * r + 1];
-    double L[3], Ld[3], lam_c[3];
+    double L[3], Ld[3], lam_c[3], mv2[3];
     for (int a = 0; a < 3; ++a) {
         L[a] = st[a];
         Ld[a] = st[3 + a];
         lam_c[a] = close ? Ld[a] / L[a] : 0.0;
+        mv2[a] = sh[a][0] * exp(-h * lam_c[a]);  // m v_a^2 after the closing friction half step
+    }
+    // with the thermostat (NPT): its half steps sit between the box friction
+    // and the box kicks, and scale every velocity of the replica alike
+    double* nh = b.nh_state + 4 * (int64_t)r;
+    double pi_s = 0.0, xi = 0.0, s_close = 1.0, s_open = 1.0;
+    const double Q = nvt ? b.nh_param[2 * r] : 1.0, gkt = nvt ? b.nh_param[2 * r + 1] : 0.0;
+    auto thermostat_half = [&](double& scale) {
+        const double hh = 0.5 * h;
+        double K = 0.5 * (mv2[0] + mv2[1] + mv2[2]);
+        pi_s += 0.5 * hh * (2.0 * K - gkt) / Q;
+        const double sc = exp(-pi_s * hh);
+        scale = sc;
+        for (int a = 0; a < 3; ++a) mv2[a] *= sc * sc;
+        K *= sc * sc;
+        xi += pi_s * hh;
+        pi_s += 0.5 * hh * (2.0 * K - gkt) / Q;
+    };
+    if (nvt) {
+        pi_s = nh[0];
+        xi = nh[1];
+        if (close) thermostat_half(s_close);
     }
     const double omega = L[0] * L[1] * L[2];
     for (int a = 0; a < 3; ++a) {
-        // m v_a^2 after the closing friction half step, and the full-list virial
-        // (every pair seen from both atoms)
-        const double mv2 = sh[a][0] * exp(-h * lam_c[a]);
-        const double pi_aa = (mv2 - 0.5 * sh[3 + a][0]) / omega;
+        // the full-list virial sees every pair from both atoms
+        const double pi_aa = (mv2[a] - 0.5 * sh[3 + a][0]) / omega;
         Ld[a] += (close + open) * 0.5 * h * (omega / L[a]) * (pi_aa - pext) / W;
-        st[15 + a] = exp(-0.5 * h * lam_c[a]);
+        st[15 + a] = exp(-0.5 * h * lam_c[a]) * s_close;
         st[3 + a] = Ld[a];
+    }
+    if (nvt && open) thermostat_half(s_open);
+    if (nvt) {
+        nh[0] = pi_s;
+        nh[1] = xi;
+        nh[2] = s_close * s_open;
+        nh[3] = 0.5 * (mv2[0] + mv2[1] + mv2[2]);
     }
     if (!open) return;
     for (int a = 0; a < 3; ++a) {
@@ -1026,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int 
         const double u = h * lam_o;
         const double phi = u == 0.0 ? 1.0 : log1p(u) / u;
         const double Ln = L[a] + h * Ld[a];
-        st[6 + a] = exp(-0.5 * h * (lam_c[a] + lam_o));
+        st[6 + a] = exp(-0.5 * h * (lam_c[a] + lam_o)) * s_close * s_open;
         st[9 + a] = Ln / L[a];
         st[12 + a] = h * phi * (Ln / L[a]);
         st[a] = Ln;
@@ -1631,12 +1658,12 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 }
 
 void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
-                      double dt_fs, double rlist, double strain_tol, hipStream_t s)
+                      double dt_fs, double rlist, double strain_tol, int nvt, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pr_tensor_waves, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
     if (k.n_replicas > 0)
         hipLaunchKernelGGL(k_pr_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, close, open, dt_fs, rlist,
-                           strain_tol);
+                           strain_tol, nvt);
 }
 
 void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,

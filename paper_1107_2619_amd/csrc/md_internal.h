@@ -235,7 +235,7 @@ void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, c
 // its drift, [12,15) h phi(u) L'/L of its drift, [15,18) closing velocity scale.
 constexpr int kPrState = 20;
 void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
-                      double dt_fs, double rlist, double strain_tol, hipStream_t s);
+                      double dt_fs, double rlist, double strain_tol, int nvt, hipStream_t s);
 void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                     hipStream_t s);
 void launch_pr_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,

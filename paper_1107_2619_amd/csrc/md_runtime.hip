@@ -630,7 +630,7 @@ void pr_boundary(md_ctx* c, int close, int open, hipStream_t s)
 {
     const KernelShape k = shape(c);
     Timed tm(c, MD_KT_FORCE, s);
-    launch_pr_update(c->buf, c->q, k, c->args, close, open, c->dt_fs, c->rlist, 0.2 * c->skin, s);
+    launch_pr_update(c->buf, c->q, k, c->args, close, open, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);
     if (open) {
         launch_pr_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
         c->p ^= 1;
@@ -767,7 +767,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
         return reject(MD_ERR_ARG, "pr_pressure_gpa and pr_mass go together (both NULL for a fixed box)");
     c->pr = cfg->pr_pressure_gpa != nullptr;
     if (c->pr) {
-        if (c->nvt || c->gear) return reject(MD_ERR_ARG, "the barostat runs with velocity Verlet and no thermostat");
+        if (c->gear) return reject(MD_ERR_ARG, "the barostat runs with velocity Verlet");
         if (cfg->nbr_mode != MD_NBR_FULL) return reject(MD_ERR_ARG, "the barostat needs the full neighbour list");
         c->pr_P.assign(cfg->pr_pressure_gpa, cfg->pr_pressure_gpa + c->R);
         c->pr_W.assign(cfg->pr_mass, cfg->pr_mass + c->R);
@@ -1147,7 +1147,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         const KernelShape k = shape(c);
         {
             Timed tm(c, MD_KT_FORCE, s);
-            launch_pr_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, s);  // closing box half kick
+            launch_pr_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);  // closing halves
             launch_pr_close_scale(c->buf, c->q, k, c->args, c->st, s);
         }
         reduce_energies(c, k, s);

@@ -167,10 +167,11 @@ def test_barostat_validation(md):
     s = inputs.bcc_fe(6, a=2.90)
     base = dict(skin=0.3, max_neighbours=48)
     md.Context(s.potential, s.atom_offset, s.box, s.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4], **base)
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4],
+               nh_temperature=[300.0], nh_mass=[50.0], **base)  # NPT
     bad = [
         dict(pr_pressure_gpa=[1.0]), dict(pr_mass=[1e4]),
         dict(pr_pressure_gpa=[np.nan], pr_mass=[1e4]), dict(pr_pressure_gpa=[1.0], pr_mass=[0.0]),
-        dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], nh_temperature=[300.0], nh_mass=[50.0]),
         dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], integrator="gear3"),
         dict(pr_pressure_gpa=[1.0], pr_mass=[1e4], nbr_mode="half"),
     ]

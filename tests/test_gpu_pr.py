@@ -183,3 +183,53 @@ def test_pr_refuses_rigid_atoms(md):
     with pytest.raises(md.MDError) as e:
         md.Simulation(s, pr_pressure_gpa=[0.0], pr_mass=[W_BOX])
     assert e.value.code == md.MD_ERR_ARG
+
+
+def _npt_oracle(orc, s, r, nsteps, p_gpa, w, t, q):
+    sub = s.replica(r) if s.n_replicas > 1 else s
+    return orc.run_npt(sub.pos, sub.vel, sub.species, sub.box[0], orc.Potential(sub.potential), sub.dt_fs, nsteps,
+                       p_gpa, w, t, q, origin=sub.origin[0])
+
+
+def test_npt_trajectory_against_oracle(md, orc):
+    """Barostat and thermostat together (NPT): 100 FP64 steps of 432 atoms at
+    2 GPa and 900 K against the oracle's NPT integrator, including the
+    thermostat's momentum and energy."""
+    s = _crystal()
+    q = (3 * s.n_atoms - 3) * 8.617333262e-5 * 900.0 * 50.0**2
+    announce("npt trajectory")
+    sim = md.Simulation(s, pr_pressure_gpa=[2.0], pr_mass=[W_BOX], nh_temperature=[900.0], nh_mass=[q])
+    sim.step(100)
+    en = sim.energy()
+    ref = _npt_oracle(orc, s, 0, 100, 2.0, W_BOX, 900.0, q)
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert np.max(np.abs(en.box[0] - ref.box[-1])) < 1e-10 * ref.box[-1].max()
+    assert abs(en.pe[0] - ref.pe[-1]) <= 1e-10 * abs(ref.pe[-1])
+    assert abs(en.ke[0] - ref.ke[-1]) <= 1e-8 * abs(ref.ke[-1])
+    assert abs(en.nh_pi[0] - ref.pi[-1]) <= 1e-8 * abs(ref.pi[-1]) + 1e-14
+    assert abs(en.nh_energy[0] - ref.nh_energy[-1]) <= 1e-8 * abs(ref.nh_energy[-1]) + 1e-10
+    assert abs(en.pr_energy[0] - ref.baro[-1]) <= 1e-9 * abs(ref.baro[-1])
+    assert abs(ref.pi[-1]) > 1e-5 and np.max(np.abs(ref.box[-1] - s.box[0])) > 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_npt_graph_replay_and_split_calls(md, precision):
+    """NPT steps replayed from graphs equal the eager ones bitwise; split calls
+    agree with one call."""
+    s = _crystal(7)
+    q = (3 * s.n_atoms - 3) * 8.617333262e-5 * 700.0 * 50.0**2
+    kw = dict(precision=precision, pr_pressure_gpa=[1.0], pr_mass=[W_BOX], nh_temperature=[700.0], nh_mass=[q])
+    announce(f"npt graph replay {precision}")
+    out = []
+    for use_graph in (0, 1):
+        sim = md.Simulation(s, **kw)
+        sim.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+        sim.step(60)
+        e = sim.energy()
+        out.append((sim.positions(), e.box.copy(), e.nh_pi.copy()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    split = md.Simulation(s, **kw)
+    for n in (1, 22, 37):
+        split.step(n)
+    np.testing.assert_allclose(split.positions(), out[0][0], rtol=0, atol=1e-9 if precision == "fp64" else 1e-6)
