@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int 
             for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || R.n_atoms == 0) return;  // an empty replica's box stays put
     double* st = b.pr_state + (int64_t)kPrState * r;
     const double W = b.pr_param[2 * r], pext = b.pr_param[2 * r + 1];
     double L[3], Ld[3], lam_c[3], mv2[3];

@@ -233,3 +233,25 @@ def test_npt_graph_replay_and_split_calls(md, precision):
     for n in (1, 22, 37):
         split.step(n)
     np.testing.assert_allclose(split.positions(), out[0][0], rtol=0, atol=1e-9 if precision == "fp64" else 1e-6)
+
+
+def test_pr_empty_replica_keeps_its_box(md, orc):
+    """An empty replica beside a crystal: its box stays put (no internal
+    pressure resists the external one, and no atom needs the box to move),
+    while the crystal's replica follows the oracle."""
+    c = _crystal()
+    n = c.n_atoms
+    s = inputs.System(
+        name="pr_empty", pos=c.pos, vel=c.vel, species=c.species, rigid=c.rigid,
+        atom_offset=np.array([0, 0, n], np.int64), box=np.array([[20.0] * 3, c.box[0]]), origin=np.zeros((2, 3)),
+        periodic=np.ones((2, 3), np.uint8), rigid_velocity=np.zeros((2, 3)), potential=c.potential, dt_fs=1.0,
+        skin=0.6, rebuild_every=10, steps=0, temperature=np.array([0.0, 600.0]), max_neighbours=80,
+    )
+    announce("pr empty replica")
+    sim = md.Simulation(s, pr_pressure_gpa=[3.0, 0.0], pr_mass=[W_BOX, W_BOX])
+    sim.step(40)
+    en = sim.energy()
+    assert np.array_equal(en.box[0], [20.0, 20.0, 20.0])
+    ref = _oracle(orc, c, 0, 40, 0.0, W_BOX)
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert np.max(np.abs(en.box[1] - ref.box[-1])) < 1e-10 * ref.box[-1].max()
