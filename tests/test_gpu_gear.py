@@ -149,3 +149,15 @@ def test_gear_energy_drifts_linearly_on_gpu(md):
     announce(f"gear drift per 100 steps: {s1:.3e}, {s2:.3e} eV/atom")
     assert abs(s1 - s2) < 0.3 * max(abs(s1), abs(s2))
     assert abs(e[-1] - e[0]) < 1e-3
+
+
+def test_gear_autotune_between_calls(md, orc):
+    """md_autotune between Gear calls re-sorts the atoms; the Gear derivatives
+    travel with them and the trajectory still follows the oracle."""
+    s = inputs.workload("bcc2000")
+    announce("gear autotune between calls")
+    sim = md.Simulation(s, integrator="gear3")
+    sim.step(20)
+    sim.autotune(trials=1)
+    sim.step(30)
+    _check(sim.energy(), 0, _oracle(orc, s, 0, 50), sim.positions(), sim.forces(), "fp64")

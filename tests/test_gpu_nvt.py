@@ -265,3 +265,17 @@ def test_nvt_extended_energy_and_mean_temperature(md):
     assert np.all(np.ptp(h, 0) < 0.02 * np.ptp(u, 0))
     assert np.all(np.ptp(h, 0) / n < 1e-4)
     assert np.all(np.abs(temp.mean(0) - targets) < 0.04 * targets)
+
+
+def test_nvt_autotune_between_calls(md, orc):
+    """md_autotune between thermostatted calls leaves the thermostat state and
+    the trajectory alone."""
+    s = inputs.workload("bcc2000")
+    t, q = [500.0], _masses(s, [500.0])
+    announce("nvt autotune between calls")
+    sim = md.Simulation(s, nh_temperature=t, nh_mass=q)
+    sim.step(20)
+    sim.autotune(trials=1)
+    sim.step(30)
+    ref = _oracle(orc, s, 0, 50, t[0], q[0])
+    _check_replica(sim.energy(), 0, ref, sim.positions(), sim.forces(), "fp64", s.n_atoms)

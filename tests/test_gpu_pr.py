@@ -255,3 +255,25 @@ def test_pr_empty_replica_keeps_its_box(md, orc):
     ref = _oracle(orc, c, 0, 40, 0.0, W_BOX)
     assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
     assert np.max(np.abs(en.box[1] - ref.box[-1])) < 1e-10 * ref.box[-1].max()
+
+
+def test_pr_options_and_autotune_keep_the_box(md, orc):
+    """Changing a kernel option between calls re-uploads the replica
+    descriptors; under the barostat that upload keeps the box the device has
+    reached (not the configured one).  md_autotune in between changes nothing
+    of the state either: the split run still follows the oracle."""
+    s = _crystal()
+    announce("pr options and autotune between calls")
+    sim = md.Simulation(s, pr_pressure_gpa=[1.0], pr_mass=[W_BOX])
+    sim.step(30)
+    box_mid = sim.energy().box[0].copy()
+    assert np.max(np.abs(box_mid - s.box[0])) > 1e-3
+    sim.set_option(md.MD_OPT_COMPACT, 0)
+    sim.set_option(md.MD_OPT_BRICK_BLOCK, 512)
+    assert np.array_equal(sim.energy().box[0], box_mid)
+    sim.autotune(trials=1)
+    sim.step(30)
+    en = sim.energy()
+    ref = _oracle(orc, s, 0, 60, 1.0, W_BOX)
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert np.max(np.abs(en.box[0] - ref.box[-1])) < 1e-10 * ref.box[-1].max()
