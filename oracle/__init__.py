@@ -91,6 +91,11 @@ def _load():
     lib.or_run_npt.restype = i32
     lib.or_run_npt.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, d, d, vp, vp, vp, vp, vp,
                                vp, vp]
+    lib.or_forces_tri.restype = i32
+    lib.or_forces_tri.argtypes = [i64, vp, vp, vp, vp, vp, vp, P, vp, vp, vp, vp, vp]
+    lib.or_run_prt.restype = i32
+    lib.or_run_prt.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, d, d, vp, vp,
+                               vp, vp, vp, vp, vp, vp]
     lib.or_run_gear.restype = i32
     lib.or_run_gear.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
     lib.or_run_nh.restype = i32
@@ -414,6 +419,77 @@ def run_npt(pos, vel, species, box, pot: Potential, dt_fs, nsteps, p_gpa, w_ev_f
         raise ValueError("oracle: periodic box length must exceed twice the cutoff")
     return NPTResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, bx.reshape(-1, 3), ba, pr,
                      nh[0::2].copy(), nh[1::2].copy())
+
+
+def forces_tri(pos, species, h, pot: Potential, rigid=None) -> ForceResult:
+    """Brute-force forces, energies, densities and virial in a periodic cell
+    with box matrix ``h`` [3,3] (edge vectors as columns, r = h s)."""
+    x, y, z = _split(pos)
+    n = x.shape[0]
+    sp = _u8(species)
+    rg = None if rigid is None else _u8(rigid)
+    hm = _f64(np.asarray(h).reshape(9))
+    f = np.zeros((n, 3))
+    e = np.zeros(n)
+    rho = np.zeros(n)
+    w = np.zeros(6)
+    pe = ctypes.c_double()
+    rc = _load().or_forces_tri(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, sp.ctypes.data, _ptr(rg), hm.ctypes.data, pot.ref,
+        f.ctypes.data, e.ctypes.data, rho.ctypes.data, w.ctypes.data, ctypes.addressof(pe),
+    )
+    if rc:
+        raise ValueError("oracle: every width of the cell must exceed twice the cutoff")
+    return ForceResult(f, e, rho, w, pe.value)
+
+
+@dataclass
+class PRTResult:
+    pos: np.ndarray
+    vel: np.ndarray
+    f: np.ndarray
+    pe: np.ndarray
+    ke: np.ndarray
+    h: np.ndarray       # [nsteps+1, 3, 3] box matrix, A (edge vectors as columns)
+    hdot: np.ndarray    # [nsteps+1, 3, 3] A/fs
+    baro: np.ndarray    # P Omega + W tr(h'^T h') / 2 + Omega0 tr((S - P) eps), eV
+    stress: np.ndarray  # [nsteps+1, 6] internal stress (xx,yy,zz,xy,xz,yz), GPa
+    pi: np.ndarray      # thermostat momentum, 1/fs (zero without one)
+    nh_energy: np.ndarray  # Q pi^2 / 2 + g k_B T xi, eV
+
+
+def run_prt(pos, vel, species, h, pot: Potential, dt_fs, nsteps, p_gpa=0.0, w_ev_fs2_a2=0.0, stress_gpa=None,
+            origin=None, hdot0=None, t_target=0.0, q_ev_fs2=0.0, h_ref=None) -> PRTResult:
+    """Parrinello-Rahman dynamics of the full box matrix under pressure P and
+    external stress S (paper, "Barostat NPTp"), brute-force forces, every axis
+    periodic; with ``q_ev_fs2`` > 0 the Nose-Hoover thermostat too.  W = 0
+    keeps the sheared cell fixed (plain velocity Verlet).  ``h_ref`` is the
+    reference cell h0 of the strain (default: the starting cell)."""
+    x, y, z = (a.copy() for a in _split(pos))
+    vx, vy, vz = (a.copy() for a in _split(vel))
+    n = x.shape[0]
+    sp = _u8(species)
+    hm = _f64(np.asarray(h).reshape(9)).copy()
+    o = np.zeros(3) if origin is None else _f64(origin)
+    hd = None if hdot0 is None else _f64(np.asarray(hdot0).reshape(9))
+    sg = None if stress_gpa is None else _f64(np.asarray(stress_gpa).reshape(9))
+    hr = None if h_ref is None else _f64(np.asarray(h_ref).reshape(9))
+    f = np.zeros((n, 3))
+    m1 = nsteps + 1
+    pe, ke, ho, hdo, ba, so, nh = (np.zeros(m1), np.zeros(m1), np.zeros(9 * m1), np.zeros(9 * m1), np.zeros(m1),
+                                   np.zeros(6 * m1), np.zeros(2 * m1))
+    rc = _load().or_run_prt(
+        n, x.ctypes.data, y.ctypes.data, z.ctypes.data, vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
+        sp.ctypes.data, hm.ctypes.data, o.ctypes.data, _ptr(hd), _ptr(sg), _ptr(hr), pot.ref, float(dt_fs), int(nsteps),
+        float(p_gpa), float(w_ev_fs2_a2), float(t_target), float(q_ev_fs2), f.ctypes.data, pe.ctypes.data,
+        ke.ctypes.data, ho.ctypes.data, hdo.ctypes.data, ba.ctypes.data, so.ctypes.data, nh.ctypes.data,
+    )
+    if rc == -1:
+        raise ValueError("oracle: every width of the cell must exceed twice the cutoff")
+    if rc:
+        raise ValueError("oracle: the box moved more than half its size in one step")
+    return PRTResult(np.stack([x, y, z], 1), np.stack([vx, vy, vz], 1), f, pe, ke, ho.reshape(-1, 3, 3),
+                     hdo.reshape(-1, 3, 3), ba, so.reshape(-1, 6), nh[0::2].copy(), nh[1::2].copy())
 
 
 @dataclass

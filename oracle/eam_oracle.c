@@ -123,6 +123,32 @@ static void image_vector(const double *xi, const double *xj, const double *box,
     }
 }
 
+/* A periodic box given by its matrix h = [a, b, c] (paper, "Barostat NPTp":
+ * r = h x, the edge vectors as columns; matrices row-major, m[3 r + c]), or an
+ * orthorhombic box with per-axis periodic flags (box != NULL). */
+typedef struct {
+    const double *box;
+    const uint8_t *periodic;
+    double h[9], hi[9];
+} or_geom;
+
+/* Shortest image with a box matrix: k = rint(h^-1 d) lattice vectors are
+ * taken off d.  When every width of the cell (the distance between opposite
+ * faces, 1 / |row a of h^-1|) exceeds twice the cutoff, a separation shorter
+ * than the cutoff has fractional components below 1/2, so this finds it, and
+ * it is the only image in range. */
+static void geom_image(const or_geom *g, const double *xi, const double *xj, double d[3])
+{
+    if (g->box) {
+        image_vector(xi, xj, g->box, g->periodic, d);
+        return;
+    }
+    double v[3], k[3];
+    for (int a = 0; a < 3; ++a) v[a] = xj[a] - xi[a];
+    for (int a = 0; a < 3; ++a) k[a] = rint(g->hi[3 * a] * v[0] + g->hi[3 * a + 1] * v[1] + g->hi[3 * a + 2] * v[2]);
+    for (int a = 0; a < 3; ++a) d[a] = v[a] - (g->h[3 * a] * k[0] + g->h[3 * a + 1] * k[1] + g->h[3 * a + 2] * k[2]);
+}
+
 static void load_pos(const double *x, const double *y, const double *z, int64_t i, double out[3])
 {
     out[0] = x[i];
@@ -141,8 +167,8 @@ static int check_box(const double *box, const uint8_t *periodic, double rc)
 
 /* Host density rho_i of one atom by brute force over all atoms. */
 static double density_of(int64_t i, int64_t n, const double *x, const double *y,
-                         const double *z, const uint8_t *species, const double *box,
-                         const uint8_t *periodic, const or_potential *p, double rc)
+                         const double *z, const uint8_t *species, const or_geom *g,
+                         const or_potential *p, double rc)
 {
     double xi[3], xj[3], d[3];
     load_pos(x, y, z, i, xi);
@@ -150,7 +176,7 @@ static double density_of(int64_t i, int64_t n, const double *x, const double *y,
     for (int64_t j = 0; j < n; ++j) {
         if (j == i) continue;
         load_pos(x, y, z, j, xj);
-        image_vector(xi, xj, box, periodic, d);
+        geom_image(g, xi, xj, d);
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         if (r >= rc) continue;
         rho += or_density(p, species[i], species[j], r, NULL);
@@ -173,13 +199,11 @@ static double density_of(int64_t i, int64_t n, const double *x, const double *y,
  * rigid may be NULL (no fixed atoms).  Returns 0, or -1 if a periodic length
  * is not larger than twice the cutoff.
  */
-int or_forces(int64_t n, const double *x, const double *y, const double *z,
-              const uint8_t *species, const uint8_t *rigid, const double *box,
-              const uint8_t *periodic, const or_potential *p, double *f,
-              double *e_atom, double *rho_out, double *virial, double *pe)
+static void forces_geom(int64_t n, const double *x, const double *y, const double *z,
+                        const uint8_t *species, const uint8_t *rigid, const or_geom *g,
+                        const or_potential *p, double rc, double *f, double *e_atom,
+                        double *rho_out, double *virial, double *pe)
 {
-    const double rc = or_cutoff(p);
-    if (check_box(box, periodic, rc)) return -1;
 
     double *rho = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *dF = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -190,7 +214,7 @@ int or_forces(int64_t n, const double *x, const double *y, const double *z,
     /* Pass 1: densities and embedding. */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
-        rho[i] = density_of(i, n, x, y, z, species, box, periodic, p, rc);
+        rho[i] = density_of(i, n, x, y, z, species, g, p, rc);
         Fe[i] = or_embed(p, species[i], rho[i], &dF[i]);
     }
 
@@ -205,7 +229,7 @@ int or_forces(int64_t n, const double *x, const double *y, const double *z,
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             load_pos(x, y, z, j, xj);
-            image_vector(xi, xj, box, periodic, d);
+            geom_image(g, xi, xj, d);
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             if (r >= rc) continue;
             const int sj = species[j];
@@ -249,6 +273,17 @@ int or_forces(int64_t n, const double *x, const double *y, const double *z,
     free(Fe);
     free(eat);
     free(wrow);
+}
+
+int or_forces(int64_t n, const double *x, const double *y, const double *z,
+              const uint8_t *species, const uint8_t *rigid, const double *box,
+              const uint8_t *periodic, const or_potential *p, double *f,
+              double *e_atom, double *rho_out, double *virial, double *pe)
+{
+    const double rc = or_cutoff(p);
+    if (check_box(box, periodic, rc)) return -1;
+    const or_geom g = {box, periodic, {0}, {0}};
+    forces_geom(n, x, y, z, species, rigid, &g, p, rc, f, e_atom, rho_out, virial, pe);
     return 0;
 }
 
@@ -295,6 +330,7 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
 {
     const double rc = or_cutoff(p);
     if (check_box(box, periodic, rc)) return -1;
+    const or_geom g = {box, periodic, {0}, {0}};
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int64_t s = 0; s < m; ++s) {
@@ -329,7 +365,7 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
         for (int64_t q = 0; q < cnt; ++q) {
             const int64_t j = nb[q];
             const int sj = species[j];
-            double rho_j = density_of(j, n, x, y, z, species, box, periodic, p, rc);
+            double rho_j = density_of(j, n, x, y, z, species, &g, p, rc);
             double dFj;
             or_embed(p, sj, rho_j, &dFj);
             load_pos(x, y, z, j, xj);
@@ -870,6 +906,330 @@ done:
         for (int a = 0; a < 3; ++a) v[a][i] /= t0;
     for (int a = 0; a < 3; ++a) box[a] = L[a];
     return rc;
+}
+
+/* ---- Box matrices (paper, "Barostat NPTp") --------------------------------
+ * h = [a, b, c] with the edge vectors as columns, r = h x; row-major storage. */
+static void m3_mul(const double *a, const double *b, double *o)
+{
+    double t[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) t[3 * r + c] = a[3 * r] * b[c] + a[3 * r + 1] * b[3 + c] + a[3 * r + 2] * b[6 + c];
+    memcpy(o, t, sizeof t);
+}
+
+static void m3_transpose(const double *a, double *o)
+{
+    double t[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) t[3 * r + c] = a[3 * c + r];
+    memcpy(o, t, sizeof t);
+}
+
+static double m3_det(const double *a)
+{
+    return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) + a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+/* Inverse by cofactors over the determinant. */
+static void m3_inverse(const double *a, double *o)
+{
+    const double id = 1.0 / m3_det(a);
+    double t[9];
+    t[0] = (a[4] * a[8] - a[5] * a[7]) * id;
+    t[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+    t[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+    t[3] = (a[5] * a[6] - a[3] * a[8]) * id;
+    t[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+    t[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+    t[6] = (a[3] * a[7] - a[4] * a[6]) * id;
+    t[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+    t[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+    memcpy(o, t, sizeof t);
+}
+
+static void m3_apply(const double *m, const double *v, double *o)
+{
+    double t[3];
+    for (int r = 0; r < 3; ++r) t[r] = m[3 * r] * v[0] + m[3 * r + 1] * v[1] + m[3 * r + 2] * v[2];
+    memcpy(o, t, sizeof t);
+}
+
+static double m3_norm1(const double *a)
+{
+    double m = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double s = fabs(a[c]) + fabs(a[3 + c]) + fabs(a[6 + c]);
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+/* exp(a): the Taylor series, summed until its terms stop changing the sum,
+ * after halving a until its norm is below 1/2 and squaring back. */
+static void m3_exp(const double *a, double *o)
+{
+    int sq = 0;
+    double b[9];
+    memcpy(b, a, sizeof b);
+    while (m3_norm1(b) > 0.5) {
+        for (int k = 0; k < 9; ++k) b[k] *= 0.5;
+        ++sq;
+    }
+    double sum[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, term[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int k = 1; k < 40; ++k) {
+        m3_mul(term, b, term);
+        for (int e = 0; e < 9; ++e) term[e] /= (double)k;
+        for (int e = 0; e < 9; ++e) sum[e] += term[e];
+        if (m3_norm1(term) < 1e-18 * m3_norm1(sum)) break;
+    }
+    for (int k = 0; k < sq; ++k) m3_mul(sum, sum, sum);
+    memcpy(o, sum, sizeof sum);
+}
+
+/* phi(z) = sum_{k>=0} (-z)^k / (k + 1) = z^-1 log(1 + z) for |z| < 1: the
+ * integral over t in [0, 1] of (1 + t z)^-1.  Returns -1 if |z| >= 1/2. */
+static int m3_logphi(const double *z, double *o)
+{
+    if (m3_norm1(z) >= 0.5) return -1;
+    double sum[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, pw[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int k = 1; k < 80; ++k) {
+        m3_mul(pw, z, pw);
+        for (int e = 0; e < 9; ++e) pw[e] = -pw[e];
+        double term[9];
+        for (int e = 0; e < 9; ++e) term[e] = pw[e] / (double)(k + 1);
+        for (int e = 0; e < 9; ++e) sum[e] += term[e];
+        if (m3_norm1(term) < 1e-18) break;
+    }
+    memcpy(o, sum, sizeof sum);
+    return 0;
+}
+
+/* Returns 0 when every width of the cell h exceeds twice the cutoff. */
+static int tri_geom(const double *h, double rc, or_geom *g)
+{
+    g->box = NULL;
+    g->periodic = NULL;
+    memcpy(g->h, h, sizeof g->h);
+    if (!(fabs(m3_det(h)) > 0.0)) return -1;
+    m3_inverse(h, g->hi);
+    for (int a = 0; a < 3; ++a) {
+        const double w = 1.0 / sqrt(g->hi[3 * a] * g->hi[3 * a] + g->hi[3 * a + 1] * g->hi[3 * a + 1] +
+                                    g->hi[3 * a + 2] * g->hi[3 * a + 2]);
+        if (!(w > 2.0 * rc)) return -1;
+    }
+    return 0;
+}
+
+/* or_forces in a periodic cell with box matrix h[9] (paper, "Barostat NPTp"
+ * for h, "Boundary conditions" for the shortest image).  Same outputs.
+ * Returns -1 if a width of the cell is not larger than twice the cutoff. */
+int or_forces_tri(int64_t n, const double *x, const double *y, const double *z,
+                  const uint8_t *species, const uint8_t *rigid, const double *h,
+                  const or_potential *p, double *f, double *e_atom, double *rho_out,
+                  double *virial, double *pe)
+{
+    const double rc = or_cutoff(p);
+    or_geom g;
+    if (tri_geom(h, rc, &g)) return -1;
+    forces_geom(n, x, y, z, species, rigid, &g, p, rc, f, e_atom, rho_out, virial, pe);
+    return 0;
+}
+
+/*
+ * Parrinello-Rahman dynamics of the full box matrix (paper, "Barostat NPTp":
+ * the Lagrangian with nine box degrees of freedom, the external pressure P and
+ * the external stress S, and the box equation of motion
+ *   W h'' = (pi - P) sigma - h Sigma,
+ * sigma = Omega h^-T (columns b x c, c x a, a x b), pi = (sum m v v^T + Wvir) / Omega
+ * the internal stress, Sigma = Omega0 h0^-1 (S - P) h0^-T with h0 the starting
+ * box (the reading that makes the Lagrangian's elastic term the strain energy
+ * Omega0 tr((S - P) eps) of the printed strain eps = (h0^-T h^T h h0^-1 - 1) / 2).
+ * With v = h ds/dt the particles obey dv/dt = f/m - h^-T h'^T v and
+ * dr/dt = v + h' h^-1 (r - o).  The conserved quantity is
+ * PE + KE + P Omega + W tr(h'^T h') / 2 + Omega0 tr((S - P) eps).
+ * With a thermostat (q > 0) the velocities also feel -pi_s v and pi_s follows
+ * the Nose-Hoover equation of or_run_nh (NPTp); its energy adds Q pi_s^2 / 2 +
+ * g k_B T xi.
+ *
+ * A step composes exact sub-flows symmetrically: box half kick, thermostat half
+ * step, friction half step v <- exp(-(h/2) h^-T h'^T) v, velocity half kick,
+ * drift with h' held (r <- o + h_new h^-1 (r - o) + dt h_new phi(dt h^-1 h') h^-1 v,
+ * h_new = h + dt h', phi(z) = z^-1 log(1 + z)), forces, and the mirror image.
+ * w = 0 keeps the box fixed (plain velocity Verlet in a sheared cell).
+ *
+ * Inputs: h[9] (A, overwritten by the final box), origin[3], hdot0[9] (A/fs,
+ * may be NULL), stress[9] (GPa, symmetric; NULL means S = P), href[9] (the
+ * reference box h0 of the strain; NULL: the starting box), P in GPa, W in
+ * eV fs^2 / A^2, the thermostat target (K) and Q (eV fs^2; q <= 0: none).
+ * Outputs per step s = 0..nsteps (each may be NULL): pe, ke, h_out[9 s],
+ * hdot_out[9 s] (A/fs), baro_out[s] = P Omega + W tr(h'^T h')/2 + the strain
+ * energy, stress_out[6 s] = pi (xx, yy, zz, xy, xz, yz) in GPa, nh_out[2 s] =
+ * (pi_s in 1/fs, its energy).  Returns 0, -1 for a cell too thin for the
+ * cutoff, -2 if the box moves more than half its size in one step.
+ */
+int or_run_prt(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
+               const uint8_t *species, double *hbox, const double *origin, const double *hdot0_fs,
+               const double *stress_gpa, const double *href, const or_potential *p, double dt_fs, int64_t nsteps,
+               double p_gpa,
+               double w_ev_fs2_a2, double t_target, double q_ev_fs2, double *f, double *pe_out, double *ke_out,
+               double *h_out, double *hdot_out, double *baro_out, double *stress_out, double *nh_out)
+{
+    const double t0 = or_time_unit_fs();
+    const double dt = dt_fs / t0;
+    const double w = w_ev_fs2_a2 / (t0 * t0);
+    const double pext = p_gpa / or_pressure_unit_gpa();
+    const int nvt = q_ev_fs2 > 0.0;
+    const double q = nvt ? q_ev_fs2 / (t0 * t0) : 1.0;
+    const double gkt = (3.0 * (double)n - 3.0) * OR_KB_EV_PER_K * t_target;
+    const double rc = or_cutoff(p);
+    double *v[3] = {vx, vy, vz};
+    double *r[3] = {x, y, z};
+    double H[9], Hd[9] = {0}, h0i[9], Sig[9], sp[9], vir[6], pe, pi_s = 0.0, xi = 0.0;
+    memcpy(H, hbox, sizeof H);
+    if (hdot0_fs)
+        for (int k = 0; k < 9; ++k) Hd[k] = hdot0_fs[k] * t0;
+    const double *h0 = href ? href : hbox;
+    const double omega0 = fabs(m3_det(h0));
+    for (int k = 0; k < 9; ++k) sp[k] = (stress_gpa ? stress_gpa[k] / or_pressure_unit_gpa() : 0.0);
+    if (!stress_gpa)
+        for (int a = 0; a < 3; ++a) sp[4 * a] = pext;
+    for (int a = 0; a < 3; ++a) sp[4 * a] -= pext; /* S - P */
+    m3_inverse(h0, h0i);
+    {
+        double t[9], h0it[9];
+        m3_transpose(h0i, h0it);
+        m3_mul(h0i, sp, t);
+        m3_mul(t, h0it, Sig);
+        for (int k = 0; k < 9; ++k) Sig[k] *= omega0;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] *= t0;
+    or_geom g;
+    int rc_ = tri_geom(H, rc, &g);
+    if (rc_) goto done;
+    forces_geom(n, x, y, z, species, NULL, &g, p, rc, f, NULL, NULL, vir, &pe);
+
+    for (int64_t s = 0;; ++s) {
+        const double omega = fabs(m3_det(H));
+        double K[9] = {0};
+        for (int64_t i = 0; i < n; ++i) {
+            const double m = p->mass[species[i]];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) K[3 * a + b] += m * v[a][i] * v[b][i];
+        }
+        const double ke = 0.5 * (K[0] + K[4] + K[8]);
+        if (pe_out) pe_out[s] = pe;
+        if (ke_out) ke_out[s] = ke;
+        if (h_out) memcpy(h_out + 9 * s, H, sizeof H);
+        if (hdot_out)
+            for (int k = 0; k < 9; ++k) hdot_out[9 * s + k] = Hd[k] / t0;
+        if (baro_out) {
+            double kb = 0.0, eps[9], G[9], ht[9], t[9], h0it[9], el = 0.0;
+            for (int k = 0; k < 9; ++k) kb += Hd[k] * Hd[k];
+            m3_transpose(H, ht);
+            m3_mul(ht, H, G);
+            m3_transpose(h0i, h0it);
+            m3_mul(h0it, G, t);
+            m3_mul(t, h0i, eps);
+            for (int a = 0; a < 3; ++a) eps[4 * a] -= 1.0;
+            for (int k = 0; k < 9; ++k) eps[k] *= 0.5;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) el += sp[3 * a + b] * eps[3 * b + a];
+            baro_out[s] = pext * omega + 0.5 * w * kb + omega0 * el;
+        }
+        if (stress_out) {
+            const int ia[6] = {0, 4, 8, 1, 2, 5}, iv[6] = {0, 1, 2, 3, 4, 5};
+            for (int c = 0; c < 6; ++c)
+                stress_out[6 * s + c] = (K[ia[c]] + vir[iv[c]]) / omega * or_pressure_unit_gpa();
+        }
+        if (nh_out) {
+            nh_out[2 * s] = pi_s / t0;
+            nh_out[2 * s + 1] = 0.5 * q * pi_s * pi_s + gkt * xi;
+        }
+        if (s == nsteps) break;
+        for (int half = 0; half < 2; ++half) {
+            /* half == 0: box kick, thermostat, friction, kick (then drift);
+             * half == 1: kick, friction, thermostat, box kick (after forces) */
+            if (half == 1) {
+                for (int64_t i = 0; i < n; ++i) {
+                    const double m = p->mass[species[i]];
+                    for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+                }
+            }
+            for (int stage = 0; stage < 3; ++stage) {
+                const int op = half == 0 ? stage : 2 - stage; /* 0 box kick, 1 thermostat, 2 friction */
+                if (op == 0 && w > 0.0) {
+                    double Kt[9] = {0}, pi_t[9], sig[9], hi[9], t[9], hs[9];
+                    for (int64_t i = 0; i < n; ++i) {
+                        const double m = p->mass[species[i]];
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) Kt[3 * a + b] += m * v[a][i] * v[b][i];
+                    }
+                    const double om = fabs(m3_det(H));
+                    const double wv[9] = {vir[0], vir[3], vir[4], vir[3], vir[1], vir[5], vir[4], vir[5], vir[2]};
+                    for (int k = 0; k < 9; ++k) pi_t[k] = (Kt[k] + wv[k]) / om;
+                    for (int a = 0; a < 3; ++a) pi_t[4 * a] -= pext;
+                    m3_inverse(H, hi);
+                    m3_transpose(hi, sig);
+                    for (int k = 0; k < 9; ++k) sig[k] *= om;
+                    m3_mul(pi_t, sig, t);
+                    m3_mul(H, Sig, hs);
+                    for (int k = 0; k < 9; ++k) Hd[k] += 0.5 * dt * (t[k] - hs[k]) / w;
+                } else if (op == 1 && nvt) {
+                    nh_half_step(n, v, species, NULL, p, 0.5 * dt, q, gkt, &pi_s, &xi);
+                } else if (op == 2 && w > 0.0) {
+                    double hi[9], hit[9], hdt[9], A[9], E[9];
+                    m3_inverse(H, hi);
+                    m3_transpose(hi, hit);
+                    m3_transpose(Hd, hdt);
+                    m3_mul(hit, hdt, A);
+                    for (int k = 0; k < 9; ++k) A[k] *= -0.5 * dt;
+                    m3_exp(A, E);
+                    for (int64_t i = 0; i < n; ++i) {
+                        double vi[3] = {v[0][i], v[1][i], v[2][i]};
+                        m3_apply(E, vi, vi);
+                        for (int a = 0; a < 3; ++a) v[a][i] = vi[a];
+                    }
+                }
+            }
+            if (half == 1) break;
+            for (int64_t i = 0; i < n; ++i) {
+                const double m = p->mass[species[i]];
+                for (int a = 0; a < 3; ++a) v[a][i] += 0.5 * dt * f[3 * i + a] / m;
+            }
+            /* drift with h' held */
+            double hi[9], B[9], Phi[9], Hn[9], M[9], D[9], t[9];
+            m3_inverse(H, hi);
+            m3_mul(hi, Hd, B);
+            for (int k = 0; k < 9; ++k) B[k] *= dt;
+            if (m3_logphi(B, Phi)) {
+                rc_ = -2;
+                goto done;
+            }
+            for (int k = 0; k < 9; ++k) Hn[k] = H[k] + dt * Hd[k];
+            m3_mul(Hn, hi, M);
+            m3_mul(Hn, Phi, t);
+            m3_mul(t, hi, D);
+            for (int k = 0; k < 9; ++k) D[k] *= dt;
+            for (int64_t i = 0; i < n; ++i) {
+                double xo[3], vi[3] = {v[0][i], v[1][i], v[2][i]}, a1[3], a2[3];
+                for (int a = 0; a < 3; ++a) xo[a] = r[a][i] - origin[a];
+                m3_apply(M, xo, a1);
+                m3_apply(D, vi, a2);
+                for (int a = 0; a < 3; ++a) r[a][i] = origin[a] + a1[a] + a2[a];
+            }
+            memcpy(H, Hn, sizeof H);
+            rc_ = tri_geom(H, rc, &g);
+            if (rc_) goto done;
+            forces_geom(n, x, y, z, species, NULL, &g, p, rc, f, NULL, NULL, vir, &pe);
+        }
+    }
+done:
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) v[a][i] /= t0;
+    memcpy(hbox, H, sizeof H);
+    return rc_;
 }
 
 int or_num_threads(void)

@@ -755,3 +755,239 @@ def test_npt_conserved_quantity_and_averages(orc):
     assert abs(r.pressure[2000:].mean() - 2.0) < 0.15
     t = 2.0 * r.ke[2000:] / (g * orc.boltzmann_ev())
     assert abs(t.mean() - 500.0) < 15.0
+
+
+# --- Box matrix: sheared cells and Parrinello-Rahman with nine box degrees of
+# freedom ("Barostat NPTp") ----------------------------------------------------
+
+_UNIMODULAR = np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])  # c' = c + a
+
+
+def _skewed_crystal(n=7, temperature=300.0, displace=0.02):
+    """A bcc crystal of n^3 cells described by the cell [a, b, c + a]: the same
+    periodic system as the cube, in a cell whose edges are not orthogonal."""
+    s = inputs.bcc_fe(n, a=2.87, temperature=temperature, seed=7, displace=displace)
+    return s, np.diag(s.box[0]) @ _UNIMODULAR
+
+
+def test_sheared_cell_equals_cube(orc, fec_pot, rng):
+    """A cell spanning the same lattice of images gives the cube's forces,
+    energies and virial."""
+    s = inputs.bcc_fe(6, a=2.87, temperature=0.0, seed=7, displace=0.08)
+    sp = (rng.random(s.n_atoms) < 0.2).astype(np.uint8)
+    ref = orc.forces(s.pos, sp, s.box[0], [1, 1, 1], fec_pot)
+    for u in (_UNIMODULAR, _UNIMODULAR.T):
+        t = orc.forces_tri(s.pos, sp, np.diag(s.box[0]) @ u, fec_pot)
+        assert np.max(np.abs(t.f - ref.f)) < 1e-12
+        assert np.max(np.abs(t.e_atom - ref.e_atom)) < 1e-12
+        assert np.max(np.abs(t.virial - ref.virial)) < 1e-10
+
+
+def test_sheared_cell_rotation_covariance(orc, fe_pot, rng):
+    """Rotating atoms and cell together rotates the forces and the virial
+    tensor and leaves every per-atom energy unchanged."""
+    s, h = _skewed_crystal(6, 0.0, 0.08)
+    ref = orc.forces_tri(s.pos, s.species, h, fe_pot)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    t = orc.forces_tri(s.pos @ q.T, s.species, q @ h, fe_pot)
+    scale = np.abs(ref.f).max()
+    assert np.max(np.abs(t.f - ref.f @ q.T)) < 1e-12 * scale * 100
+    assert np.max(np.abs(t.e_atom - ref.e_atom)) < 1e-12
+    w = lambda v: np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])  # noqa: E731
+    assert np.max(np.abs(w(t.virial) - q @ w(ref.virial) @ q.T)) < 1e-9
+
+
+def test_sheared_cell_shortest_image_by_enumeration(orc, fec_pot):
+    """Against a plain enumeration of the periodic images (-2..2 lattice
+    vectors per edge) in a strongly sheared cell: every pair in range, the
+    densities, energies and forces."""
+    h = np.array([[9.2, 3.1, 2.4], [0.4, 9.6, -2.7], [-0.6, 0.9, 10.1]])
+    gen = np.random.default_rng(5)
+    frac = gen.random((24, 3))
+    pos = frac @ h.T + gen.normal(scale=0.3, size=(24, 3))
+    sp = (gen.random(24) < 0.3).astype(np.uint8)
+    res = orc.forces_tri(pos, sp, h, fec_pot)
+    rc = orc.cutoff(fec_pot)
+    shifts = np.array([[i, j, k] for i in range(-2, 3) for j in range(-2, 3) for k in range(-2, 3)]) @ h.T
+    n = len(pos)
+    pairs = []
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            d = pos[j] + shifts - pos[i]
+            r = np.sqrt((d * d).sum(1))
+            hit = np.nonzero(r < rc)[0]
+            assert len(hit) <= 1
+            for k in hit:
+                pairs.append((i, j, d[k], r[k]))
+    rho = np.zeros(n)
+    for i, j, d, r in pairs:
+        rho[i] += orc.density(fec_pot, sp[i], sp[j], r)[0]
+    dF = np.array([orc.embed(fec_pot, sp[i], rho[i])[1] for i in range(n)])
+    e = np.array([orc.embed(fec_pot, sp[i], rho[i])[0] for i in range(n)])
+    f = np.zeros((n, 3))
+    for i, j, d, r in pairs:
+        phi, dphi = orc.pair(fec_pot, sp[i], sp[j], r)
+        g = dphi + dF[i] * orc.density(fec_pot, sp[i], sp[j], r)[1] + dF[j] * orc.density(fec_pot, sp[j], sp[i], r)[1]
+        f[i] += g * d / r
+        e[i] += 0.5 * phi
+    assert len(pairs) > 100
+    assert np.allclose(res.rho, rho, rtol=1e-13, atol=1e-14)
+    assert np.allclose(res.e_atom, e, rtol=1e-12, atol=1e-13)
+    assert np.max(np.abs(res.f - f)) < 1e-12
+
+
+def test_virial_tensor_is_box_derivative(orc, fec_pot, rng):
+    """-dU/dh at fixed fractional coordinates equals W h^-T (the virial tensor
+    times the inverse transposed cell), all nine components of a sheared
+    cell: the driving term of the box equation."""
+    s = inputs.bcc_fe(4, a=2.87, temperature=0.0, seed=7, displace=0.1)
+    h = np.diag(s.box[0]) @ np.array([[1.0, 0.05, 0.03], [0.0, 1.0, 0.04], [0.0, 0.0, 1.0]])
+    pos = s.pos @ (h @ np.diag(1.0 / s.box[0])).T
+    sp = (rng.random(s.n_atoms) < 0.25).astype(np.uint8)
+    res = orc.forces_tri(pos, sp, h, fec_pot)
+    v = res.virial
+    w = np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+    want = w @ np.linalg.inv(h).T
+    frac = pos @ np.linalg.inv(h).T
+
+    def u(dh):
+        hh = h + dh
+        return orc.forces_tri(frac @ hh.T, sp, hh, fec_pot).pe
+
+    step = 1e-4
+    got = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = 1.0
+            d1 = (u(step * e) - u(-step * e)) / (2 * step)
+            d2 = (u(0.5 * step * e) - u(-0.5 * step * e)) / step
+            got[a, b] = -(4 * d2 - d1) / 3
+    assert np.abs(want).max() > 1.0 and abs(want[0, 1]) > 0.1
+    assert np.max(np.abs(got - want)) < 1e-6 * np.abs(want).max()
+
+
+def test_sheared_fixed_cell_is_the_cube_run(orc):
+    """With the box held (W = 0) the run in the sheared cell is the velocity
+    Verlet run of the cube, step for step."""
+    s, h = _skewed_crystal(6)
+    pot = orc.Potential(s.potential)
+    a = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 60)
+    b = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 60)
+    assert np.max(np.abs(a.pos - b.pos)) < 1e-12
+    assert np.max(np.abs(a.pe - b.pe)) < 1e-9
+    assert np.all(b.h == h)
+
+
+def test_prt_cold_lattice_box_against_independent_integrator(orc):
+    """A strained perfect lattice at rest stays a lattice, so the box alone
+    obeys W h'' = (pi(h) - P) Omega h^-T - h Sigma with pi from the (pinned)
+    virial tensor: scipy's DOP853 integrates those nine equations
+    independently, under pressure and a deviatoric stress.  The run follows it
+    with second-order error in the step."""
+    from scipy.integrate import solve_ivp
+
+    lat = inputs.bcc_fe(4, a=2.90, temperature=0.0, seed=7)
+    pot = orc.Potential(lat.potential)
+    h0 = np.diag(lat.box[0]) @ np.array([[1.0, 0.05, 0.03], [0.0, 1.0, 0.04], [0.0, 0.0, 1.0]])
+    frac = lat.pos @ np.diag(1.0 / lat.box[0])
+    w, conv, p_ext = 1e4, orc.pressure_unit_gpa(), 1.0
+    stress = p_ext * np.eye(3) + np.array([[0.3, 0.8, 0.0], [0.8, -0.2, -0.5], [0.0, -0.5, 0.0]])
+    om0 = abs(np.linalg.det(h0))
+    sig = om0 * np.linalg.inv(h0) @ ((stress - p_ext * np.eye(3)) / conv) @ np.linalg.inv(h0).T
+
+    def rhs(_t, y):
+        h, hd = y[:9].reshape(3, 3), y[9:]
+        v = orc.forces_tri(frac @ h.T, lat.species, h, pot).virial
+        om = abs(np.linalg.det(h))
+        pi = np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]]) / om
+        acc = ((pi - p_ext / conv * np.eye(3)) @ (om * np.linalg.inv(h).T) - h @ sig) / w
+        return np.concatenate([hd, acc.reshape(9)])
+
+    times = [100.0, 200.0, 300.0]
+    ref = solve_ivp(rhs, (0.0, 300.0), np.concatenate([h0.reshape(9), np.zeros(9)]), method="DOP853",
+                    rtol=1e-11, atol=1e-12, t_eval=times).y[:9].T.reshape(-1, 3, 3)
+    assert np.ptp(ref[:, 0, 1]) > 0.05  # the shear really moves
+    errs = []
+    for dt in (1.0, 0.5):
+        e = 0.0
+        for t, rr in zip(times, ref):
+            r = orc.run_prt(lat.pos @ (h0 @ np.diag(1.0 / lat.box[0])).T, np.zeros_like(lat.pos), lat.species, h0,
+                            pot, dt, int(t / dt), p_ext, w, stress_gpa=stress)
+            e = max(e, np.abs(r.h[-1] - rr).max())
+        errs.append(e)
+    assert errs[0] < 1e-2 and 3.0 < errs[0] / errs[1] < 5.0
+
+
+def _prt_stress():
+    s = 1.0 * np.eye(3)
+    s[0, 1] = s[1, 0] = 0.5
+    s[1, 2] = s[2, 1] = -0.3
+    return s
+
+
+def test_prt_conserved_quantity(orc):
+    """PE + KE + P Omega + W tr(h'^T h')/2 + Omega0 tr((S - P) eps) stays in a
+    band a thousand times narrower than the swing of PE + KE in a sheared cell
+    under shear stress, and the band shrinks as dt^2."""
+    s, h = _skewed_crystal()
+    pot = orc.Potential(s.potential)
+    bands = []
+    for dt in (1.0, 0.5):
+        r = orc.run_prt(s.pos, s.vel, s.species, h, pot, dt, int(1000 / dt), 1.0, 3e4, stress_gpa=_prt_stress())
+        tot = r.pe + r.ke + r.baro
+        bands.append(np.ptp(tot))
+        assert np.ptp(tot) < 2e-3 * np.ptp(r.pe + r.ke)
+        assert np.abs(r.h[-1] - h).max() > 0.1  # the cell really deforms
+    assert bands[1] < 0.35 * bands[0]
+
+
+def test_prt_mean_stress_balances_the_load(orc):
+    """The cell settles where the time-averaged internal stress equals the
+    load carried to the current cell, P + (Omega0 / Omega) F (S - P) F^T with
+    F = h h0^-1 (the box equation at rest); a sign or transposition error in
+    the stress term would not settle there."""
+    s, h0 = _skewed_crystal()
+    pot = orc.Potential(s.potential)
+    stress = _prt_stress()
+    r = orc.run_prt(s.pos, s.vel, s.species, h0, pot, 1.0, 3000, 1.0, 3e4, stress_gpa=stress)
+    st = r.stress[1000:].mean(0)
+    pi = np.array([[st[0], st[3], st[4]], [st[3], st[1], st[5]], [st[4], st[5], st[2]]])
+    hm = r.h[1000:].mean(0)
+    f = hm @ np.linalg.inv(h0)
+    load = np.eye(3) + abs(np.linalg.det(h0)) / abs(np.linalg.det(hm)) * f @ (stress - np.eye(3)) @ f.T
+    assert np.max(np.abs(pi - load)) < 0.05
+    assert abs(pi[0, 1] - 0.5) < 0.1 and abs(pi[1, 2] + 0.3) < 0.1
+
+
+def test_prt_time_reversible(orc):
+    """Reversing the velocities and the box velocity (same reference cell for
+    the strain) retraces the path."""
+    s, h = _skewed_crystal(6)
+    pot = orc.Potential(s.potential)
+    a = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 150, 1.0, 1e4, stress_gpa=_prt_stress())
+    assert np.max(np.abs(a.hdot[-1])) > 1e-4
+    b = orc.run_prt(a.pos, -a.vel, s.species, a.h[-1], pot, 1.0, 150, 1.0, 1e4, stress_gpa=_prt_stress(),
+                    hdot0=-a.hdot[-1], h_ref=h)
+    assert np.max(np.abs(b.pos - s.pos)) < 1e-9
+    assert np.max(np.abs(b.h[-1] - h)) < 1e-11
+    assert np.max(np.abs(b.hdot[-1])) < 1e-13
+    assert abs(b.baro[-1] - a.baro[0]) < 1e-9
+
+
+def test_prt_with_thermostat_limits(orc):
+    """Q -> infinity gives the barostat alone; W -> infinity the thermostat
+    alone in the fixed sheared cell, which is the cube's thermostat run."""
+    s, h = _skewed_crystal(6)
+    pot = orc.Potential(s.potential)
+    g = 3 * s.n_atoms - 3
+    q = g * orc.boltzmann_ev() * 500.0 * 50.0**2
+    a = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 100, 1.0, 1e4, stress_gpa=_prt_stress(), t_target=500.0,
+                    q_ev_fs2=1e30)
+    b = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 100, 1.0, 1e4, stress_gpa=_prt_stress())
+    assert np.max(np.abs(a.pos - b.pos)) < 1e-10 and np.max(np.abs(a.h - b.h)) < 1e-12
+    c = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 100, 0.0, 0.0, t_target=500.0, q_ev_fs2=q)
+    d = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100, 500.0, q)
+    assert np.max(np.abs(c.pos - d.pos)) < 1e-10 and abs(c.pi[-1] - d.pi[-1]) < 1e-14
