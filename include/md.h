@@ -87,7 +87,8 @@ typedef struct {
 /*
  * Run configuration: R >= 1 independent replicas ("statistics must be gathered
  * over a number of equivalent runs", Introduction), each an orthorhombic box
- * with per-axis periodic or free boundaries ("Boundary conditions").  Replica
+ * with per-axis periodic or free boundaries ("Boundary conditions"), or a
+ * periodic cell given by its box matrix.  Replica
  * r owns atoms [atom_offset[r], atom_offset[r+1]) of the state arrays.
  * All pointers are host pointers, copied by md_create.
  */
@@ -123,8 +124,9 @@ typedef struct {
      * step; rigid atoms' work uses the trapezoid rule over the evaluations.
      * MD_GEAR3 runs NVE only (no thermostat). */
     int32_t integrator;
-    /* Parrinello-Rahman barostat per replica ("Barostat NPTp") on an
-     * orthorhombic box: h = diag(L) and a hydrostatic external stress.  The
+    /* Parrinello-Rahman barostat per replica ("Barostat NPTp").  On an
+     * orthorhombic box (no box_matrix, no pr_stress_gpa below): h = diag(L)
+     * and a hydrostatic external stress.  The
      * box edges obey W d2L_a/dt2 = (Omega / L_a)(pi_aa - P), pi the internal
      * stress tensor, and the particles feel the matching friction
      * -(dL_a/dt / L_a) v_a (NPH; PE + KE + P Omega + W |dL/dt|^2 / 2 is
@@ -136,6 +138,22 @@ typedef struct {
      * The LDS-brick kernels are not used. */
     const double *pr_pressure_gpa; /* [R] external pressure, GPa, finite */
     const double *pr_mass;         /* [R] box mass W, eV fs^2 / Angstrom^2, > 0 */
+    /* Box matrices ("Barostat NPTp": r = o + h s with h = [a, b, c], the edge
+     * vectors as columns, s the fractional coordinates).  box_matrix [R][9]
+     * row-major (h[3 i + j] = component i of edge j), determinant > 0; NULL =
+     * the orthorhombic boxes of `box` (which may then be NULL).  A box matrix
+     * needs every axis periodic and at least three link cells between each
+     * pair of opposite faces (width >= 3 (r_c + skin), 3.15 (r_c + skin) under
+     * the barostat); the separation of a pair is its shortest image.  The
+     * LDS-brick kernels and the compact mixed-mode records are not used.
+     * With the barostat set, a box matrix (or pr_stress_gpa) makes all nine
+     * entries of h dynamic: W d2h/dt2 = (pi - P) sigma - h Sigma with
+     * sigma = Omega h^-T, Sigma = Omega0 h0^-1 (S - P) h0^-T and h0 the box at
+     * md_bind, and the particles feel -h^-T (dh/dt)^T v (the conserved
+     * quantity is pe + ke + pr_energy, + nh_energy with the thermostat). */
+    const double *box_matrix;      /* [R][9] Angstrom, or NULL */
+    const double *pr_stress_gpa;   /* [R][9] external stress S, GPa, symmetric; NULL = P on
+                                      the diagonal.  Needs the barostat. */
 } md_config;
 
 /*
@@ -178,7 +196,12 @@ typedef struct {
     double box[3];       /* edge lengths of this state, Angstrom (they move under
                             the barostat) */
     double pr_energy;    /* barostat energy P Omega + W |dL/dt|^2 / 2, eV (0 without
-                            barostat): pe + ke + pr_energy is conserved */
+                            barostat): pe + ke + pr_energy is conserved.  With a
+                            box matrix: P Omega + W tr(dh/dt^T dh/dt) / 2 +
+                            Omega0 tr((S - P) eps), eps = (h0^-T h^T h h0^-1 - 1) / 2 */
+    double h[9];         /* box matrix of this state, row-major, edge vectors as
+                            columns (diag(box) for an orthorhombic box); box[]
+                            then holds the edge lengths */
 } md_energies;
 
 /* Validates the configuration and potential on the host (no device work)

@@ -55,7 +55,8 @@ __global__ void k_init_slots(Buffers b, int q, const uint8_t* __restrict__ speci
 }
 
 // Caller state (caller order, unwrapped) -> slots.  Inside the library a
-// position is kept as x - n L along periodic axes, with the integer image
+// position is kept as x - n L along periodic axes (x - h n in a sheared cell),
+// with the integer image
 // count n of the slot fixed at the last list build, so that list entries can
 // carry their periodic shift and the force loop needs no minimum image.
 __global__ void k_load_state(Buffers b, int p, int q, md_state st, int64_t n_slots)
@@ -65,8 +66,9 @@ __global__ void k_load_state(Buffers b, int p, int q, md_state st, int64_t n_slo
     const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
     const int32_t a = b.id[q][t];
     if (a >= 0) {
-        b.pos[p][t] = make_double4(st.x[a] - b.img[q][0][t] * R.box[0], st.y[a] - b.img[q][1][t] * R.box[1],
-                                   st.z[a] - b.img[q][2][t] * R.box[2], 0.0);
+        double sh[3];
+        lattice_shift(R, b.img[q][0][t], b.img[q][1][t], b.img[q][2][t], sh);
+        b.pos[p][t] = make_double4(st.x[a] - sh[0], st.y[a] - sh[1], st.z[a] - sh[2], 0.0);
         b.vel[q][0][t] = st.vx[a];
         b.vel[q][1][t] = st.vy[a];
         b.vel[q][2][t] = st.vz[a];
@@ -120,9 +122,17 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
         // displacement since the build, after mapping the build position into
         // the current box (the two boxes differ only under the barostat)
         const double3 x0 = load_xyz(b.xbuild, t);
-        const double dx = (x.x - bx.o[0]) - (x0.x - bx.o[0]) * (R.box[0] / R.lbuild[0]);
-        const double dy = (x.y - bx.o[1]) - (x0.y - bx.o[1]) * (R.box[1] / R.lbuild[1]);
-        const double dz = (x.z - bx.o[2]) - (x0.z - bx.o[2]) * (R.box[2] / R.lbuild[2]);
+        double dx, dy, dz;
+        if (bx.tri) {  // strained by the homogeneous map mb since the build
+            const double u[3] = {x0.x - bx.o[0], x0.y - bx.o[1], x0.z - bx.o[2]};
+            dx = (x.x - bx.o[0]) - (R.mb[0] * u[0] + R.mb[1] * u[1] + R.mb[2] * u[2]);
+            dy = (x.y - bx.o[1]) - (R.mb[3] * u[0] + R.mb[4] * u[1] + R.mb[5] * u[2]);
+            dz = (x.z - bx.o[2]) - (R.mb[6] * u[0] + R.mb[7] * u[1] + R.mb[8] * u[2]);
+        } else {
+            dx = (x.x - bx.o[0]) - (x0.x - bx.o[0]) * (R.box[0] / R.lbuild[0]);
+            dy = (x.y - bx.o[1]) - (x0.y - bx.o[1]) * (R.box[1] / R.lbuild[1]);
+            dz = (x.z - bx.o[2]) - (x0.z - bx.o[2]) * (R.box[2] / R.lbuild[2]);
+        }
         if (dx * dx + dy * dy + dz * dz > half_skin2) atomicAdd(&b.flags[F_SKIN], 1);
     }
     // atoms beyond the grid extent of a free axis (clamped into edge cells)
@@ -237,17 +247,32 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
         const double3 x = load_xyz(b.pos[p], t);
         double xw[3] = {x.x, x.y, x.z};
         // re-wrap atoms that left the primary box on a periodic axis
+        if (R.tri) {  // sheared cell: whole edge vectors, from the fractional coordinates
+            double f[3];
+            frac_coords(R.hinv, R.origin, xw[0], xw[1], xw[2], f);
+            double k[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int32_t n = b.img[q][a][t];
-            if (R.periodic_mask & (1 << a)) {
-                const double s = floor((xw[a] - R.origin[a]) * R.inv_box[a]);
-                if (s != 0.0) {
-                    xw[a] -= s * R.box[a];
-                    n += (int32_t)s;
-                }
+            for (int a = 0; a < 3; ++a) {
+                k[a] = floor(f[a]);
+                b.img[qn][a][u] = b.img[q][a][t] + (int32_t)k[a];
             }
-            b.img[qn][a][u] = n;
+            double sh[3];
+            lattice_shift(R, k[0], k[1], k[2], sh);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xw[a] -= sh[a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int32_t n = b.img[q][a][t];
+                if (R.periodic_mask & (1 << a)) {
+                    const double s = floor((xw[a] - R.origin[a]) * R.inv_box[a]);
+                    if (s != 0.0) {
+                        xw[a] -= s * R.box[a];
+                        n += (int32_t)s;
+                    }
+                }
+                b.img[qn][a][u] = n;
+            }
         }
         const double4 x4 = make_double4(xw[0], xw[1], xw[2], 0.0);
         b.pos[pn][u] = x4;
@@ -502,9 +527,17 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                 const int j = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
                 const int w = __shfl(nb_wrap, k, kWave);
                 const double3 xj = load_xyz(pos, j);
-                cx[u] = xj.x + select_shift(w & 3, bx.L[0]);
-                cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
-                cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
+                if (bx.tri) {  // the image cell's edge-vector shift
+                    double dsh[3] = {0.0, 0.0, 0.0};
+                    apply_shift(bx, w & 63, dsh[0], dsh[1], dsh[2]);
+                    cx[u] = xj.x + dsh[0];
+                    cy[u] = xj.y + dsh[1];
+                    cz[u] = xj.z + dsh[2];
+                } else {
+                    cx[u] = xj.x + select_shift(w & 3, bx.L[0]);
+                    cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
+                    cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
+                }
                 ce[u] = j | (__shfl(nb_code, k, kWave) << kIndexBits);
                 cj[u] = j;
                 live[u] = m0 < total;
@@ -1134,6 +1167,12 @@ __global__ void k_pr_mark_build(Buffers b, int n_replicas)
     DevReplica& R = b.reps[r];
 #pragma unroll
     for (int a = 0; a < 3; ++a) R.lbuild[a] = R.box[a];
+    if (R.tri)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            R.hbinv[e] = R.hinv[e];
+            R.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -1272,9 +1311,11 @@ __global__ void k_gear_correct(Buffers b, int p, int q, int64_t n_slots, PotArgs
     if (last) {
         b.eslot[(int64_t)E_KE * n_slots + t] = ke;
         b.eslot[(int64_t)E_PW * n_slots + t] = (ty & kRigidBit) ? b.pwork[q][t] : 0.0;
-        st.x[id] = xc[0] + b.img[q][0][t] * R.box[0];
-        st.y[id] = xc[1] + b.img[q][1][t] * R.box[1];
-        st.z[id] = xc[2] + b.img[q][2][t] * R.box[2];
+        double sh[3];
+        lattice_shift(R, b.img[q][0][t], b.img[q][1][t], b.img[q][2][t], sh);
+        st.x[id] = xc[0] + sh[0];
+        st.y[id] = xc[1] + sh[1];
+        st.z[id] = xc[2] + sh[2];
         st.vx[id] = v[0];
         st.vy[id] = v[1];
         st.vz[id] = v[2];
@@ -1561,7 +1602,9 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
                           double dt_fs, const md_state& st, hipStream_t s)
 {
     if (!fl.close && !fl.open) {
-        if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
+        if (!fl.writeback && fl.energy == 1)  // full-matrix barostat: the whole stress tensor, forces kept
+            force_launch<R, S, NP, ND, EV, 1, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
             force_launch<R, S, NP, ND, EV, 2, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
@@ -1570,6 +1613,8 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.writeback && fl.energy == 1) {  // full-matrix barostat: closing kick, stress tensor
+        force_launch<R, S, NP, ND, EV, 1, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy) {  // barostat: closing kick with the stress, forces kept
         force_launch<R, S, NP, ND, EV, 2, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {

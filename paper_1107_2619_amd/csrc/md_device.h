@@ -36,6 +36,9 @@ struct Box {
     int pmask;
     int nc[3];
     int cell_off;
+    int tri;             // sheared cell: images and cells along the edge vectors
+    const double* h;     // its box matrix (edge vectors as columns, row-major)
+    const double* hinv;
 };
 
 __device__ __forceinline__ Box load_box(const DevReplica& R)
@@ -50,7 +53,33 @@ __device__ __forceinline__ Box load_box(const DevReplica& R)
     }
     b.pmask = R.periodic_mask;
     b.cell_off = R.cell_off;
+    b.tri = R.tri;
+    b.h = R.h;
+    b.hinv = R.hinv;
     return b;
+}
+
+// Lattice translation by the integer image counts n: n_a L_a along each axis of
+// an orthorhombic box, h n in a sheared cell.
+__device__ __forceinline__ void lattice_shift(const DevReplica& R, double n0, double n1, double n2, double out[3])
+{
+    if (R.tri) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = R.h[3 * a] * n0 + R.h[3 * a + 1] * n1 + R.h[3 * a + 2] * n2;
+    } else {
+        out[0] = n0 * R.box[0];
+        out[1] = n1 * R.box[1];
+        out[2] = n2 * R.box[2];
+    }
+}
+
+// Fractional coordinates s = h^-1 (x - o) of a point in a sheared cell.
+__device__ __forceinline__ void frac_coords(const double* hinv, const double o[3], double x, double y, double z,
+                                            double s[3])
+{
+    const double d[3] = {x - o[0], y - o[1], z - o[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s[a] = hinv[3 * a] * d[0] + hinv[3 * a + 1] * d[1] + hinv[3 * a + 2] * d[2];
 }
 
 // Minimum image of d at list-build time: applies the shortest periodic image
@@ -72,9 +101,19 @@ __device__ __forceinline__ int image_code(const Box& b, double& dx, double& dy, 
     return code;
 }
 
-// Reapply a stored periodic shift (rare: only pairs across a box face).
+// Reapply a stored periodic shift (rare: only pairs across a box face).  In a
+// sheared cell the shift is the sum of the edge vectors the code names.
 __device__ __forceinline__ void apply_shift(const Box& b, int code, double& dx, double& dy, double& dz)
 {
+    if (b.tri) {
+        const double k0 = (code & 3) ? ((code & 1) ? 1.0 : -1.0) : 0.0;
+        const double k1 = (code & 12) ? ((code & 4) ? 1.0 : -1.0) : 0.0;
+        const double k2 = (code & 48) ? ((code & 16) ? 1.0 : -1.0) : 0.0;
+        dx += b.h[0] * k0 + b.h[1] * k1 + b.h[2] * k2;
+        dy += b.h[3] * k0 + b.h[4] * k1 + b.h[5] * k2;
+        dz += b.h[6] * k0 + b.h[7] * k1 + b.h[8] * k2;
+        return;
+    }
     if (code & 3) dx += (code & 1) ? b.L[0] : -b.L[0];
     if (code & 12) dy += (code & 4) ? b.L[1] : -b.L[1];
     if (code & 48) dz += (code & 16) ? b.L[2] : -b.L[2];
@@ -83,6 +122,13 @@ __device__ __forceinline__ void apply_shift(const Box& b, int code, double& dx, 
 // Link cell along one axis: periodic axes wrap the fractional coordinate into
 // [0, 1); free axes clamp (monotone, so atoms closer than one cell edge still
 // land in the same or adjacent cells).
+__device__ __forceinline__ int cell_of_frac(double f, int nc, bool periodic)
+{
+    if (periodic) f -= floor(f);
+    int c = (int)floor(f * nc);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
 __device__ __forceinline__ int cell_axis(double x, double o, double iL, int nc, bool periodic)
 {
     double f = (x - o) * iL;
@@ -93,6 +139,13 @@ __device__ __forceinline__ int cell_axis(double x, double o, double iL, int nc, 
 
 __device__ __forceinline__ void cell_coords(const Box& b, double x, double y, double z, int c[3])
 {
+    if (b.tri) {  // cells along the edge vectors: fractional coordinates, all axes periodic
+        double f[3];
+        frac_coords(b.hinv, b.o, x, y, z, f);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] = cell_of_frac(f[a], b.nc[a], true);
+        return;
+    }
     c[0] = cell_axis(x, b.o[0], b.iL[0], b.nc[0], b.pmask & 1);
     c[1] = cell_axis(y, b.o[1], b.iL[1], b.nc[1], b.pmask & 2);
     c[2] = cell_axis(z, b.o[2], b.iL[2], b.nc[2], b.pmask & 4);
@@ -468,9 +521,11 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         st.fy[a] = f[1];
         st.fz[a] = f[2];
         if (CLOSE) {
-            st.x[a] = xn[0] + b.img[q][0][t] * Rp.box[0];
-            st.y[a] = xn[1] + b.img[q][1][t] * Rp.box[1];
-            st.z[a] = xn[2] + b.img[q][2][t] * Rp.box[2];
+            double sh[3];
+            lattice_shift(Rp, b.img[q][0][t], b.img[q][1][t], b.img[q][2][t], sh);
+            st.x[a] = xn[0] + sh[0];
+            st.y[a] = xn[1] + sh[1];
+            st.z[a] = xn[2] + sh[2];
             st.vx[a] = v[0];
             st.vy[a] = v[1];
             st.vz[a] = v[2];

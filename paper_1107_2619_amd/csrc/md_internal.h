@@ -70,6 +70,14 @@ struct DevReplica {
     double qs[3];    // compact coordinate unit per axis, cell * 2^-kCompactBits
     double iqs[3];   // its inverse
     double lbuild[3];  // edges at the last list build (differ from box only under the barostat)
+    // Sheared cell (tri = 1): the box matrix h with the edge vectors as
+    // columns (row-major), r = o + h s with s the fractional coordinates; every
+    // axis periodic, link cells and image counts along the edge vectors.  box
+    // then holds the widths of the cell (distances between opposite faces).
+    int32_t tri, pad_tri;
+    double h[9], hinv[9];
+    double hbinv[9];  // inverse of h at the last list build
+    double mb[9];     // h times hbinv: the homogeneous strain since that build
 };
 
 __host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)
@@ -167,6 +175,7 @@ struct Buffers {
     double* pr_param;     // [R][2] barostat mass W (eV fs^2/A^2), external pressure (eV/A^3)
     double* pr_state;     // [R][kPrState] box, box velocity and the factors of the open pass
     double* pr_partial;   // [Np / 64][6] per-wave sums of m v_a^2 and of the virial diagonal
+                          // ([Np / 64][12]: m v_a v_b and the six virial terms, full box matrix)
     double* x0[3];        // [N] origin positions of the mean square displacement, caller order
     uint8_t* ctype;       // [N] species | rigid bit, caller order
     double* msd_partial;  // [n_chunks][2 * MD_MAX_SPECIES] sums of d^2 and atom counts
@@ -208,7 +217,8 @@ void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipSt
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
-// energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat)
+// energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat);
+// with close or open and no writeback the force is kept for a separate pass
 struct ForceFlags {
     int energy, close, open, writeback;
 };
@@ -241,6 +251,18 @@ void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 void launch_pr_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,
                            hipStream_t s);
 void launch_pr_mark_build(const Buffers& b, const KernelShape& k, hipStream_t s);
+
+// Barostat on the full box matrix.  pr_state per replica (matrices row-major):
+// [0,9) h, [9,18) dh/dt (A per time unit), [18,27) Sigma = Omega0 h0^-1 (S - P) h0^-T
+// (eV), [27,36) velocity map of the open pass, [36,45) h'h^-1 of its drift,
+// [45,54) the velocity term of its drift, [54,63) closing velocity map.
+constexpr int kPrtState = 64;
+void launch_prt_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
+                       double dt_fs, double rlist, double strain_tol, int nvt, hipStream_t s);
+void launch_prt_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                     hipStream_t s);
+void launch_prt_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,
+                            hipStream_t s);
 
 // Launchers (kernels_analysis.hip).
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);

@@ -21,8 +21,10 @@ struct md_ctx {
     bool nvt = false;        // Nose-Hoover thermostat per replica
     bool gear = false;       // third-order Gear predictor-corrector instead of Verlet
     bool gear_ready = false; // Gear derivatives started since md_bind
-    bool pr = false;         // Parrinello-Rahman barostat per replica (orthorhombic box)
+    bool pr = false;         // Parrinello-Rahman barostat per replica
     std::vector<double> pr_P, pr_W;  // GPa, eV fs^2 / A^2
+    bool tri = false;        // box matrices (sheared cells; the barostat then moves all nine entries)
+    std::vector<double> hmat, pr_S;  // [R][9] box matrices (A), external stress (GPa)
     std::vector<double> nh_T, nh_Q;
     std::vector<double> nh_gkt;  // host copy of nh_param
     std::vector<int64_t> atom_off;
@@ -113,6 +115,22 @@ bool hip_ok(md_ctx* c, hipError_t e, const char* what)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Inverse of a 3x3 matrix (row-major) by cofactors.
+void invert3(const double* m, double* o)
+{
+    const double id =
+        1.0 / (m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) + m[2] * (m[3] * m[7] - m[4] * m[6]));
+    o[0] = (m[4] * m[8] - m[5] * m[7]) * id;
+    o[1] = (m[2] * m[7] - m[1] * m[8]) * id;
+    o[2] = (m[1] * m[5] - m[2] * m[4]) * id;
+    o[3] = (m[5] * m[6] - m[3] * m[8]) * id;
+    o[4] = (m[0] * m[8] - m[2] * m[6]) * id;
+    o[5] = (m[2] * m[3] - m[0] * m[5]) * id;
+    o[6] = (m[3] * m[7] - m[4] * m[6]) * id;
+    o[7] = (m[1] * m[6] - m[0] * m[7]) * id;
+    o[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+}
+
 KernelShape shape(const md_ctx* c)
 {
     KernelShape k;
@@ -126,11 +144,13 @@ KernelShape shape(const md_ctx* c)
     k.table = c->table_ok && c->evaluator == 0;
     k.n_chunks = (int32_t)c->chunk_rep.size();
     k.n_bricks = (int32_t)c->brick_rep.size();
-    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL && !c->pr;  // the barostat moves the bricks' box
+    // the barostat moves the bricks' box; the brick kernels take orthorhombic boxes only
+    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri;
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
-    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL;
+    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL &&
+                !c->tri;  // compact records are per-axis cell offsets of an orthorhombic grid
     return k;
 }
 
@@ -253,6 +273,18 @@ bool upload_geometry(md_ctx* c)
         if (!hip_ok(c, hipMemcpy(cur.data(), c->buf.reps, cur.size() * sizeof(DevReplica), hipMemcpyDeviceToHost), "upload"))
             return false;
         for (size_t r = 0; r < cur.size(); ++r) {
+            if (c->tri) {
+                DevReplica& D = c->reps[r];
+                std::memcpy(D.h, cur[r].h, sizeof D.h);
+                std::memcpy(D.hinv, cur[r].hinv, sizeof D.hinv);
+                std::memcpy(D.hbinv, cur[r].hbinv, sizeof D.hbinv);
+                std::memcpy(D.mb, cur[r].mb, sizeof D.mb);
+                for (int a = 0; a < 3; ++a) {
+                    D.box[a] = cur[r].box[a];
+                    D.inv_box[a] = cur[r].inv_box[a];
+                }
+                continue;
+            }
             set_edges(c->reps[r], cur[r].box);
             for (int a = 0; a < 3; ++a) c->reps[r].lbuild[a] = cur[r].lbuild[a];
         }
@@ -398,8 +430,8 @@ void plan_workspace(md_ctx* c)
         gear, gear, gear, gear, gear, gear,                  // acc[2][3]
         gear, gear, gear, gear, gear, gear,                  // jrk[2][3]
         c->pr ? (size_t)c->R * 16 : 0,                       // pr_param
-        c->pr ? (size_t)c->R * kPrState * 8 : 0,             // pr_state
-        c->pr ? Np / kWave * 6 * 8 : 0,                      // pr_partial
+        c->pr ? (size_t)c->R * (c->tri ? kPrtState : kPrState) * 8 : 0,  // pr_state
+        c->pr ? Np / kWave * (c->tri ? 12 : 6) * 8 : 0,      // pr_partial
     };
     c->off.clear();
     size_t o = 0;
@@ -630,6 +662,14 @@ void pr_boundary(md_ctx* c, int close, int open, hipStream_t s)
 {
     const KernelShape k = shape(c);
     Timed tm(c, MD_KT_FORCE, s);
+    if (c->tri) {
+        launch_prt_update(c->buf, c->q, k, c->args, close, open, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);
+        if (open) {
+            launch_prt_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
+            c->p ^= 1;
+        }
+        return;
+    }
     launch_pr_update(c->buf, c->q, k, c->args, close, open, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);
     if (open) {
         launch_pr_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
@@ -668,7 +708,8 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
         ++c->step;
         if (due(c)) rebuild(c, s, true);
         if (c->pr) {
-            forces(c, ForceFlags{2, 1, 0, 0}, s, false);  // closing kick and the virial, forces kept
+            // closing kick and the virial (the whole tensor for a box matrix), forces kept
+            forces(c, ForceFlags{c->tri ? 1 : 2, 1, 0, 0}, s, false);
             pr_boundary(c, 1, 1, s);
         } else if (c->nvt) {
             forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
@@ -740,7 +781,8 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     };
     // ---- configuration
     if (cfg->n_replicas < 1) return reject(MD_ERR_ARG, "n_replicas must be >= 1");
-    if (!cfg->atom_offset || !cfg->box || !cfg->periodic) return reject(MD_ERR_ARG, "atom_offset, box and periodic are required");
+    if (!cfg->atom_offset || !(cfg->box || cfg->box_matrix) || !cfg->periodic)
+        return reject(MD_ERR_ARG, "atom_offset, box (or box_matrix) and periodic are required");
     if (cfg->max_neighbours < 1) return reject(MD_ERR_ARG, "max_neighbours must be >= 1");
     if (cfg->rebuild_every < 1) return reject(MD_ERR_ARG, "rebuild_every must be >= 1");
     if (cfg->precision != MD_FP64 && cfg->precision != MD_MIXED) return reject(MD_ERR_ARG, "precision must be MD_FP64 or MD_MIXED");
@@ -789,8 +831,54 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     for (int r = 0; r < c->R; ++r)
         if (c->atom_off[r + 1] < c->atom_off[r]) return reject(MD_ERR_ARG, "atom_offset must be non-decreasing");
     c->N = c->atom_off[c->R];
-    c->box.assign(cfg->box, cfg->box + 3 * c->R);
     c->periodic.assign(cfg->periodic, cfg->periodic + 3 * c->R);
+    // box matrices: a sheared cell per replica, or the full-matrix barostat
+    // (an external stress) starting from orthorhombic boxes
+    if (cfg->pr_stress_gpa && !c->pr) return reject(MD_ERR_ARG, "pr_stress_gpa needs the barostat (pr_pressure_gpa and pr_mass)");
+    c->tri = cfg->box_matrix != nullptr || cfg->pr_stress_gpa != nullptr;
+    if (c->tri) {
+        c->hmat.assign(9 * (size_t)c->R, 0.0);
+        c->box.assign(3 * (size_t)c->R, 0.0);
+        for (int r = 0; r < c->R; ++r) {
+            double* h = &c->hmat[9 * (size_t)r];
+            if (cfg->box_matrix) std::memcpy(h, cfg->box_matrix + 9 * (size_t)r, 9 * sizeof(double));
+            else
+                for (int a = 0; a < 3; ++a) h[4 * a] = cfg->box[3 * (size_t)r + a];
+            for (int e = 0; e < 9; ++e)
+                if (!std::isfinite(h[e])) return reject(MD_ERR_BOX, "box_matrix entries must be finite");
+            const double det = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) + h[2] * (h[3] * h[7] - h[4] * h[6]);
+            if (!(det > 0.0)) return reject(MD_ERR_BOX, "box_matrix must have a positive determinant (right-handed edge vectors)");
+            for (int a = 0; a < 3; ++a) {
+                if (cfg->periodic[3 * (size_t)r + a] != 1) return reject(MD_ERR_ARG, "a box matrix needs every axis periodic");
+                // width between the faces spanned by the other two edges: volume / |their cross product|
+                const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+                const double cx = h[3 + b1] * h[6 + b2] - h[6 + b1] * h[3 + b2];
+                const double cy = h[6 + b1] * h[b2] - h[b1] * h[6 + b2];
+                const double cz = h[b1] * h[3 + b2] - h[3 + b1] * h[b2];
+                c->box[3 * (size_t)r + a] = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+            }
+        }
+        if (c->pr) {
+            c->pr_S.assign(9 * (size_t)c->R, 0.0);
+            for (int r = 0; r < c->R; ++r) {
+                double* S = &c->pr_S[9 * (size_t)r];
+                if (cfg->pr_stress_gpa) std::memcpy(S, cfg->pr_stress_gpa + 9 * (size_t)r, 9 * sizeof(double));
+                else
+                    for (int a = 0; a < 3; ++a) S[4 * a] = c->pr_P[r];
+                double scale = 0.0;
+                for (int e = 0; e < 9; ++e) {
+                    if (!std::isfinite(S[e])) return reject(MD_ERR_ARG, "pr_stress_gpa entries must be finite");
+                    scale = std::max(scale, std::fabs(S[e]));
+                }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a + 1; b < 3; ++b)
+                        if (std::fabs(S[3 * a + b] - S[3 * b + a]) > 1e-12 * scale)
+                            return reject(MD_ERR_ARG, "pr_stress_gpa must be symmetric");
+            }
+        }
+    } else {
+        c->box.assign(cfg->box, cfg->box + 3 * c->R);
+    }
     c->origin.assign(3 * c->R, 0.0);
     if (cfg->origin) c->origin.assign(cfg->origin, cfg->origin + 3 * c->R);
     c->vp.assign(3 * c->R, 0.0);
@@ -904,6 +992,13 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             // under the barostat the grid leaves 5% room for compression
             int64_t nc = (int64_t)std::floor(L / (c->pr ? 1.05 * c->rlist : c->rlist));
             nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1023));
+            if (c->tri && nc < 3) {  // L is the width between opposite faces here
+                char msg[200];
+                std::snprintf(msg, sizeof msg,
+                              "replica %d: a box matrix needs at least three link cells between each pair of faces "
+                              "(width %.6g, list radius %.6g)", r, L, c->rlist);
+                return reject(MD_ERR_BOX, msg);
+            }
             if (c->pr && (!per || nc < 3)) {
                 char msg[160];
                 std::snprintf(msg, sizeof msg, "replica %d axis %d: the barostat needs a periodic axis of at least three link cells", r, a);
@@ -917,6 +1012,14 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             cell_min = std::min(cell_min, D.cell[a]);
             if (per) D.periodic_mask |= 1 << a;
             worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
+        }
+        D.tri = c->tri ? 1 : 0;
+        if (c->tri) {
+            const double* h = &c->hmat[9 * (size_t)r];
+            std::memcpy(D.h, h, sizeof D.h);
+            invert3(h, D.hinv);
+            std::memcpy(D.hbinv, D.hinv, sizeof D.hbinv);
+            for (int e = 0; e < 9; ++e) D.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
         }
         slot += (n + kWave - 1) / kWave * kWave;
         cells_alloc += worst;
@@ -979,8 +1082,20 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     bind_buffers(c);
     if (c->pr)  // the barostat restarts from the configured box
         for (int r = 0; r < c->R; ++r) {
-            set_edges(c->reps[r], &c->box[3 * (size_t)r]);
-            for (int a = 0; a < 3; ++a) c->reps[r].lbuild[a] = c->box[3 * (size_t)r + a];
+            DevReplica& D = c->reps[r];
+            if (c->tri) {
+                std::memcpy(D.h, &c->hmat[9 * (size_t)r], sizeof D.h);
+                invert3(D.h, D.hinv);
+                std::memcpy(D.hbinv, D.hinv, sizeof D.hbinv);
+                for (int e = 0; e < 9; ++e) D.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    D.box[a] = c->box[3 * (size_t)r + a];
+                    D.inv_box[a] = 1.0 / D.box[a];
+                }
+                continue;
+            }
+            set_edges(D, &c->box[3 * (size_t)r]);
+            for (int a = 0; a < 3; ++a) D.lbuild[a] = c->box[3 * (size_t)r + a];
         }
     if (!hip_ok(c, hipMemcpy(c->buf.reps, c->reps.data(), c->reps.size() * sizeof(DevReplica), hipMemcpyHostToDevice), "md_bind upload") ||
         !hip_ok(c, hipMemcpy(c->buf.pot, &c->pot, sizeof(DevPotential), hipMemcpyHostToDevice), "md_bind upload") ||
@@ -1032,10 +1147,31 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         // barostat: W and P per replica; the box starts at the configured edges at rest
         for (int r = 0; r < c->R; ++r)
             if (c->n_mobile[r] < c->reps[r].n_atoms) return fail(c, MD_ERR_ARG, "md_bind: the barostat takes no rigid atoms");
-        std::vector<double> param(2 * (size_t)c->R), state((size_t)kPrState * c->R, 0.0);
+        const int ns = c->tri ? kPrtState : kPrState;
+        std::vector<double> param(2 * (size_t)c->R), state((size_t)ns * c->R, 0.0);
         for (int r = 0; r < c->R; ++r) {
             param[2 * r] = c->pr_W[r];
             param[2 * r + 1] = c->pr_P[r] / kEvPerA3InGpa;
+            if (c->tri) {
+                // h, dh/dt = 0, Sigma = Omega0 h0^-1 (S - P) h0^-T (eV), identity maps
+                double* st = &state[(size_t)ns * r];
+                const double* h0 = &c->hmat[9 * (size_t)r];
+                double hi[9], sp[9];
+                invert3(h0, hi);
+                const double om0 = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                                   h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
+                for (int e = 0; e < 9; ++e) sp[e] = (c->pr_S[9 * (size_t)r + e] - (e % 4 == 0 ? c->pr_P[r] : 0.0)) / kEvPerA3InGpa;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double v = 0.0;
+                        for (int k = 0; k < 3; ++k)
+                            for (int l = 0; l < 3; ++l) v += hi[3 * i + k] * sp[3 * k + l] * hi[3 * j + l];
+                        st[18 + 3 * i + j] = om0 * v;
+                    }
+                std::memcpy(st, h0, 9 * sizeof(double));
+                for (int e = 0; e < 9; e += 4) st[27 + e] = st[36 + e] = st[54 + e] = 1.0;
+                continue;
+            }
             for (int a = 0; a < 3; ++a) {
                 state[(size_t)kPrState * r + a] = c->box[3 * r + a];
                 state[(size_t)kPrState * r + 6 + a] = 1.0;
@@ -1115,7 +1251,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         }
         c->p ^= 1;
     } else if (c->pr) {
-        forces(c, ForceFlags{2, 0, 0, 0}, s, false);  // f(x0) and the virial
+        forces(c, ForceFlags{c->tri ? 1 : 2, 0, 0, 0}, s, false);  // f(x0) and the virial
         pr_boundary(c, 0, 1, s);                      // box half kick and drift, opening kick and drift
     } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
@@ -1147,8 +1283,13 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         const KernelShape k = shape(c);
         {
             Timed tm(c, MD_KT_FORCE, s);
-            launch_pr_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);  // closing halves
-            launch_pr_close_scale(c->buf, c->q, k, c->args, c->st, s);
+            if (c->tri) {
+                launch_prt_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);
+                launch_prt_close_scale(c->buf, c->q, k, c->args, c->st, s);
+            } else {
+                launch_pr_update(c->buf, c->q, k, c->args, 1, 0, c->dt_fs, c->rlist, 0.2 * c->skin, c->nvt, s);  // closing halves
+                launch_pr_close_scale(c->buf, c->q, k, c->args, c->st, s);
+            }
         }
         reduce_energies(c, k, s);
     } else if (c->nvt) {
@@ -1182,7 +1323,8 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     std::vector<double> nh((size_t)c->R * 4, 0.0);
     if (c->nvt && !hip_ok(c, hipMemcpy(nh.data(), c->buf.nh_state, nh.size() * 8, hipMemcpyDeviceToHost), "md_energy thermostat"))
         return MD_ERR_DEVICE;
-    std::vector<double> pr((size_t)c->R * kPrState, 0.0);
+    const int nps = c->tri ? kPrtState : kPrState;
+    std::vector<double> pr((size_t)c->R * nps, 0.0);
     if (c->pr && !hip_ok(c, hipMemcpy(pr.data(), c->buf.pr_state, pr.size() * 8, hipMemcpyDeviceToHost), "md_energy barostat"))
         return MD_ERR_DEVICE;
     for (int r = 0; r < c->R; ++r) {
@@ -1195,11 +1337,42 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         o.pe = v[E_PE];
         o.ke = v[E_KE];
         o.temperature = dof > 0 ? 2.0 * o.ke / ((double)dof * kBoltzmannEv) : 0.0;
-        for (int a = 0; a < 3; ++a) o.box[a] = c->pr ? pr[(size_t)kPrState * r + a] : D.box[a];
-        o.volume = o.box[0] * o.box[1] * o.box[2];
-        if (c->pr) {
-            const double* ld = &pr[(size_t)kPrState * r + 3];
-            o.pr_energy = c->pr_P[r] / kEvPerA3InGpa * o.volume + 0.5 * c->pr_W[r] * (ld[0] * ld[0] + ld[1] * ld[1] + ld[2] * ld[2]);
+        if (c->tri) {
+            // the box matrix, its edge lengths and volume; with the barostat the
+            // energy P Omega + W tr(dh/dt^T dh/dt) / 2 + Omega0 tr((S - P) eps),
+            // eps = (h0^-T h^T h h0^-1 - 1) / 2 the strain from the bound box h0
+            const double* h = c->pr ? &pr[(size_t)nps * r] : &c->hmat[9 * (size_t)r];
+            std::memcpy(o.h, h, sizeof o.h);
+            for (int a = 0; a < 3; ++a) o.box[a] = std::sqrt(h[a] * h[a] + h[3 + a] * h[3 + a] + h[6 + a] * h[6 + a]);
+            o.volume = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) + h[2] * (h[3] * h[7] - h[4] * h[6]);
+            if (c->pr) {
+                const double* hd = &pr[(size_t)nps * r + 9];
+                const double* h0 = &c->hmat[9 * (size_t)r];
+                double kb = 0.0;
+                for (int e = 0; e < 9; ++e) kb += hd[e] * hd[e];
+                double h0i[9], f[9], eps[9];
+                invert3(h0, h0i);
+                for (int i = 0; i < 3; ++i)  // f = h h0^-1
+                    for (int j = 0; j < 3; ++j) f[3 * i + j] = h[3 * i] * h0i[j] + h[3 * i + 1] * h0i[3 + j] + h[3 * i + 2] * h0i[6 + j];
+                for (int i = 0; i < 3; ++i)  // eps = (f^T f - 1) / 2
+                    for (int j = 0; j < 3; ++j)
+                        eps[3 * i + j] = 0.5 * (f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j] - (i == j ? 1.0 : 0.0));
+                const double om0 = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                                   h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
+                double el = 0.0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        el += (c->pr_S[9 * (size_t)r + 3 * i + j] - (i == j ? c->pr_P[r] : 0.0)) * eps[3 * j + i];
+                o.pr_energy = (c->pr_P[r] * o.volume + om0 * el) / kEvPerA3InGpa + 0.5 * c->pr_W[r] * kb;
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) o.box[a] = c->pr ? pr[(size_t)kPrState * r + a] : D.box[a];
+            for (int a = 0; a < 3; ++a) o.h[4 * a] = o.box[a];
+            o.volume = o.box[0] * o.box[1] * o.box[2];
+            if (c->pr) {
+                const double* ld = &pr[(size_t)kPrState * r + 3];
+                o.pr_energy = c->pr_P[r] / kEvPerA3InGpa * o.volume + 0.5 * c->pr_W[r] * (ld[0] * ld[0] + ld[1] * ld[1] + ld[2] * ld[2]);
+            }
         }
         for (int k = 0; k < 6; ++k) o.virial[k] = v[E_W0 + k];
         o.pressure_gpa = (2.0 * o.ke + o.virial[0] + o.virial[1] + o.virial[2]) / (3.0 * o.volume) * kEvPerA3InGpa;
@@ -1227,7 +1400,9 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     }
     c->halo_overflows = flags[F_HALO];
     if (flags[F_PR_BOX] > 0)
-        return fail(c, MD_ERR_BOX, "barostat: a box edge shrank below its link cells' list radius (more than the 5% the grid allows)");
+        return fail(c, MD_ERR_BOX, c->tri ? "barostat: the cell narrowed below its link cells' list radius between a pair of faces "
+                                            "(more than the 5% the grid allows), or the box velocity is too large for the step"
+                                          : "barostat: a box edge shrank below its link cells' list radius (more than the 5% the grid allows)");
     if (flags[F_SKIN] > 0) {
         char msg[200];
         std::snprintf(msg, sizeof msg, "skin violation: %d atom(s) moved more than %.4g A between list builds%s", flags[F_SKIN],
@@ -1375,7 +1550,7 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     std::vector<Cand> cands;
     for (int32_t e : evals) {
         cands.push_back({1, 0, 0, 512, e});
-        if (c->nbr_mode == MD_NBR_FULL)
+        if (c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri)  // the brick kernels take fixed orthorhombic boxes
             for (int32_t dims : {0, 444, 222})
                 for (int32_t lanes : {1, 2})
                     for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block, e});

@@ -72,6 +72,7 @@ class _Config(ctypes.Structure):
         ("skin", ctypes.c_double), ("dt_fs", ctypes.c_double),
         ("nh_temperature", ctypes.c_void_p), ("nh_mass", ctypes.c_void_p), ("integrator", ctypes.c_int32),
         ("pr_pressure_gpa", ctypes.c_void_p), ("pr_mass", ctypes.c_void_p),
+        ("box_matrix", ctypes.c_void_p), ("pr_stress_gpa", ctypes.c_void_p),
     ]
 
 
@@ -87,7 +88,7 @@ class _Energies(ctypes.Structure):
         ("piston_work", ctypes.c_double), ("virial", ctypes.c_double * 6),
         ("step", ctypes.c_int64), ("n_atoms", ctypes.c_int64), ("n_mobile", ctypes.c_int64),
         ("nh_pi", ctypes.c_double), ("nh_energy", ctypes.c_double), ("box", ctypes.c_double * 3),
-        ("pr_energy", ctypes.c_double),
+        ("pr_energy", ctypes.c_double), ("h", ctypes.c_double * 9),
     ]
 
 
@@ -147,7 +148,7 @@ class Context:
     def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
                  skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
                  nbr_mode="full", lanes_per_atom=0, nh_temperature=None, nh_mass=None, integrator="verlet",
-                 pr_pressure_gpa=None, pr_mass=None):
+                 pr_pressure_gpa=None, pr_mass=None, box_matrix=None, pr_stress_gpa=None):
         self.lib = library()
         pa = _c(potential["pair_a"], np.float64)
         ns = pa.shape[0]
@@ -168,6 +169,11 @@ class Context:
         k["pr_p"] = None if pr_pressure_gpa is None else np.broadcast_to(
             np.asarray(pr_pressure_gpa, np.float64), (n_rep,)).copy()
         k["pr_w"] = None if pr_mass is None else np.broadcast_to(np.asarray(pr_mass, np.float64), (n_rep,)).copy()
+        # box matrices [R, 3, 3] (edge vectors as columns) and external stresses [R, 3, 3]
+        k["hmat"] = None if box_matrix is None else np.broadcast_to(
+            np.asarray(box_matrix, np.float64), (n_rep, 3, 3)).copy()
+        k["pr_s"] = None if pr_stress_gpa is None else np.broadcast_to(
+            np.asarray(pr_stress_gpa, np.float64), (n_rep, 3, 3)).copy()
         pot = _Potential(ns, pa.shape[2], k["dens_A"].shape[2], 0, pa.ctypes.data, k["pair_r"].ctypes.data,
                          k["dens_A"].ctypes.data, k["dens_R"].ctypes.data, k["emb_c"].ctypes.data,
                          k["mass"].ctypes.data)
@@ -181,6 +187,7 @@ class Context:
             None if k["nh_t"] is None else k["nh_t"].ctypes.data, None if k["nh_q"] is None else k["nh_q"].ctypes.data,
             {"verlet": MD_VERLET, "gear3": MD_GEAR3}[integrator] if isinstance(integrator, str) else int(integrator),
             None if k["pr_p"] is None else k["pr_p"].ctypes.data, None if k["pr_w"] is None else k["pr_w"].ctypes.data,
+            None if k["hmat"] is None else k["hmat"].ctypes.data, None if k["pr_s"] is None else k["pr_s"].ctypes.data,
         )
         h = ctypes.c_void_p()
         rc = self.lib.md_create(ctypes.byref(cfg), ctypes.byref(pot), ctypes.byref(h))
@@ -234,7 +241,8 @@ class Energies:
     nh_pi: np.ndarray      # thermostat momentum per replica, 1/fs (0 without a thermostat)
     nh_energy: np.ndarray  # thermostat energy 0.5 Q pi^2 + g k T xi, eV
     box: np.ndarray        # [R, 3] edge lengths, A
-    pr_energy: np.ndarray  # barostat energy P Omega + W |dL/dt|^2 / 2, eV
+    pr_energy: np.ndarray  # barostat energy P Omega + W |dL/dt|^2 / 2 (+ the strain energy), eV
+    h: np.ndarray          # [R, 3, 3] box matrices (edge vectors as columns), A
 
 
 class Simulation:
@@ -242,7 +250,8 @@ class Simulation:
 
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
                  device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
-                 nh_mass=None, integrator="verlet", pr_pressure_gpa=None, pr_mass=None):
+                 nh_mass=None, integrator="verlet", pr_pressure_gpa=None, pr_mass=None, box_matrix=None,
+                 pr_stress_gpa=None):
         import torch
 
         self.torch = torch
@@ -256,7 +265,7 @@ class Simulation:
             max_neighbours=self.cap,
             precision=precision, nbr_mode=nbr_mode, lanes_per_atom=lanes_per_atom,
             nh_temperature=nh_temperature, nh_mass=nh_mass, integrator=integrator,
-            pr_pressure_gpa=pr_pressure_gpa, pr_mass=pr_mass,
+            pr_pressure_gpa=pr_pressure_gpa, pr_mass=pr_mass, box_matrix=box_matrix, pr_stress_gpa=pr_stress_gpa,
         )
         d = self.device
         f64 = dict(dtype=torch.float64, device=d)
@@ -322,7 +331,8 @@ class Simulation:
         g = lambda name: np.array([getattr(o, name) for o in out])  # noqa: E731
         return Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"), g("piston_work"),
                         np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"),
-                        g("nh_pi"), g("nh_energy"), np.array([list(o.box) for o in out]), g("pr_energy"))
+                        g("nh_pi"), g("nh_energy"), np.array([list(o.box) for o in out]), g("pr_energy"),
+                        np.array([list(o.h) for o in out]).reshape(R, 3, 3))
 
     def msd(self):
         """(msd [R, n_species] A^2, count [R, n_species]): mean square displacement

@@ -187,3 +187,38 @@ def test_barostat_validation(md):
         md.Context(small.potential, small.atom_offset, small.box, small.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4],
                    **base)
     assert e.value.code == md.MD_ERR_BOX
+
+
+def test_box_matrix_validation(md):
+    """Box matrices and the external stress are checked on the host: every axis
+    periodic, a positive determinant, three link cells between each pair of
+    faces, a symmetric stress that comes with the barostat."""
+    s = inputs.bcc_fe(7, a=2.87)
+    L = s.box[0][0]
+    skew = np.diag([L] * 3) @ np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])  # widths L/sqrt2, L, L
+    base = dict(skin=0.3, max_neighbours=48)
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, box_matrix=skew, **base)
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, box_matrix=skew, nbr_mode="half", **base)
+    stress = np.eye(3)
+    stress[0, 1] = stress[1, 0] = 0.5
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, box_matrix=skew, pr_pressure_gpa=[1.0],
+               pr_mass=[1e4], pr_stress_gpa=stress, **base)
+    md.Context(s.potential, s.atom_offset, s.box, s.periodic, pr_pressure_gpa=[1.0], pr_mass=[1e4],
+               pr_stress_gpa=stress, **base)  # full-matrix barostat from the cube
+    lopsided = stress.copy()
+    lopsided[0, 1] = 0.7
+    cases = [
+        (dict(box_matrix=skew, pr_stress_gpa=stress), md.MD_ERR_ARG),  # stress without barostat
+        (dict(box_matrix=skew, pr_pressure_gpa=[1.0], pr_mass=[1e4], pr_stress_gpa=lopsided), md.MD_ERR_ARG),
+        (dict(box_matrix=skew, pr_pressure_gpa=[1.0], pr_mass=[1e4], nbr_mode="half"), md.MD_ERR_ARG),
+        (dict(box_matrix=skew * np.array([1.0, 1.0, -1.0])), md.MD_ERR_BOX),  # left-handed
+        (dict(box_matrix=np.diag([L] * 3) @ np.array([[1.0, 2.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])),
+         md.MD_ERR_BOX),  # width L/sqrt5 = 8.99 A: two link cells
+    ]
+    for kw, code in cases:
+        with pytest.raises(md.MDError) as e:
+            md.Context(s.potential, s.atom_offset, s.box, s.periodic, **base, **kw)
+        assert e.value.code == code, kw
+    with pytest.raises(md.MDError) as e:
+        md.Context(s.potential, s.atom_offset, s.box, [[1, 1, 0]], box_matrix=skew, **base)
+    assert e.value.code == md.MD_ERR_ARG
