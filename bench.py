@@ -33,12 +33,12 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes of one launch of the mixed-mode force kernel on bcc1m, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of
-# 199 dispatches), each scaled by the reading for a plain 1 GiB device copy
+# 444 dispatches), each scaled by the reading for a plain 1 GiB device copy
 # (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {"fetch_kib": 115002.6, "write_kib": 71280.2, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256_16": "d6d3933ae3536da5", "workload": "bcc1m", "precision": "mixed"}
+FORCE_TRAFFIC = {"fetch_kib": 115014.0, "write_kib": 71280.2, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256_16": "e38ab41cf4796703", "workload": "bcc1m", "precision": "mixed"}
 # VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
 # so this is also the lane-operations per atom of one launch.
@@ -363,7 +363,17 @@ def main():
         opts_pr = choice_options(md, tuned["mixed"])
         opts_pr[md.MD_OPT_KERNEL] = 1
         rates = {}
-        for label, kw in (("fixed_box", {}), ("barostat", {"pr_pressure_gpa": [0.0], "pr_mass": [2.0e7]})):
+        # the same crystal in the cell [a, b, c + a] (the cube's periodic
+        # system with non-orthogonal edges): held fixed, and under the
+        # full-matrix barostat with a 0.2 GPa xy shear stress
+        h_skew = np.diag(system.box[0]) @ np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+        shear = np.zeros((3, 3))
+        shear[0, 1] = shear[1, 0] = 0.2
+        legs = (("fixed_box", {}), ("barostat", {"pr_pressure_gpa": [0.0], "pr_mass": [2.0e7]}),
+                ("sheared_cell_fixed", {"box_matrix": h_skew}),
+                ("barostat_box_matrix", {"box_matrix": h_skew, "pr_pressure_gpa": [0.0], "pr_mass": [2.0e7],
+                                         "pr_stress_gpa": shear}))
+        for label, kw in legs:
             sim_b = md.Simulation(system, precision="mixed", want_e_atom=False, skin=0.5, **kw)
             for opt, val in opts_pr.items():
                 sim_b.set_option(opt, val)
@@ -375,12 +385,19 @@ def main():
             e_b = sim_b.energy()
             rates[label] = {"value": n * args.pr_steps / (ms_b * 1e-3), "ms_per_step": ms_b / args.pr_steps,
                             "box_A": [float(x) for x in e_b.box[0]], "pressure_gpa": float(e_b.pressure_gpa[0])}
+            if "box_matrix" in kw:
+                rates[label]["h_A"] = e_b.h[0].tolist()
             del sim_b
+        fixed_ms = rates["fixed_box"]["ms_per_step"]
         barostat = {"workload": f"{args.workload} with a 0.5 A skin", "precision": "mixed", "steps": args.pr_steps,
-                    "pressure_gpa": 0.0, "box_mass_eV_fs2_per_A2": 2.0e7, **rates,
-                    "overhead": rates["barostat"]["ms_per_step"] / rates["fixed_box"]["ms_per_step"] - 1.0}
+                    "pressure_gpa": 0.0, "box_mass_eV_fs2_per_A2": 2.0e7, "shear_stress_xy_gpa": 0.2, **rates,
+                    "overhead": rates["barostat"]["ms_per_step"] / fixed_ms - 1.0,
+                    "overhead_sheared_cell": rates["sheared_cell_fixed"]["ms_per_step"] / fixed_ms - 1.0,
+                    "overhead_box_matrix": rates["barostat_box_matrix"]["ms_per_step"] / fixed_ms - 1.0}
         log(f"barostat: {rates['barostat']['value']:.3e} atom-steps/s, fixed box {rates['fixed_box']['value']:.3e} "
-            f"({barostat['overhead']:+.1%})")
+            f"({barostat['overhead']:+.1%}); sheared cell {rates['sheared_cell_fixed']['value']:.3e} "
+            f"({barostat['overhead_sheared_cell']:+.1%}), full-matrix barostat "
+            f"{rates['barostat_box_matrix']['value']:.3e} ({barostat['overhead_box_matrix']:+.1%})")
 
     # the same crystal four times larger, beyond the 256 MB last-level cache
     size_sweep = []

@@ -464,6 +464,9 @@ __device__ __forceinline__ void test_candidates(int32_t* __restrict__ nbr, int64
     }
 }
 
+// TRI: sheared cells (candidate shifts are edge-vector sums), a separate
+// instantiation so the orthorhombic build keeps its short candidate loop.
+template <bool TRI>
 __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t n_slots, int32_t n_cells,
                                                       int32_t cap, double rlist2, int half_list, int compact)
 {
@@ -527,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                 const int j = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
                 const int w = __shfl(nb_wrap, k, kWave);
                 const double3 xj = load_xyz(pos, j);
-                if (bx.tri) {  // the image cell's edge-vector shift
+                if (TRI) {  // the image cell's edge-vector shift
                     double dsh[3] = {0.0, 0.0, 0.0};
                     apply_shift(bx, w & 63, dsh[0], dsh[1], dsh[2]);
                     cx[u] = xj.x + dsh[0];
@@ -1518,8 +1521,12 @@ void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, dou
 {
     (void)q;
     const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
-    hipLaunchKernelGGL(k_cell_list, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap, rlist2,
-                       half_list, k.compact);
+    if (k.tri)
+        hipLaunchKernelGGL(k_cell_list<true>, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap,
+                           rlist2, half_list, k.compact);
+    else
+        hipLaunchKernelGGL(k_cell_list<false>, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap,
+                           rlist2, half_list, k.compact);
 }
 
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)
@@ -1602,8 +1609,8 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
                           double dt_fs, const md_state& st, hipStream_t s)
 {
     if (!fl.close && !fl.open) {
-        if (!fl.writeback && fl.energy == 1)  // full-matrix barostat: the whole stress tensor, forces kept
-            force_launch<R, S, NP, ND, EV, 1, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        if (!fl.writeback && fl.energy == 3)  // full-matrix barostat: the whole virial tensor, forces kept
+            force_launch<R, S, NP, ND, EV, 3, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
             force_launch<R, S, NP, ND, EV, 2, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
@@ -1613,8 +1620,8 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
-    } else if (!fl.writeback && fl.energy == 1) {  // full-matrix barostat: closing kick, stress tensor
-        force_launch<R, S, NP, ND, EV, 1, true, false, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (!fl.writeback && fl.energy == 3) {  // full-matrix barostat: closing kick, virial tensor
+        force_launch<R, S, NP, ND, EV, 3, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy) {  // barostat: closing kick with the stress, forces kept
         force_launch<R, S, NP, ND, EV, 2, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {

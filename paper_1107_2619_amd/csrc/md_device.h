@@ -411,7 +411,8 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
 
 // Pair accumulation into the site atom: force, and on energy steps
 // (ENERGY = 1) the pair energy and the virial tensor (pairs of two rigid atoms
-// excluded); ENERGY = 2 (barostat steps) keeps only the virial diagonal.
+// excluded); ENERGY = 2 (barostat steps) keeps only the virial diagonal and
+// ENERGY = 3 (steps of the full-matrix barostat) the whole virial tensor.
 struct PairAcc {
     double f[3] = {0.0, 0.0, 0.0};
     double epair = 0.0;
@@ -435,10 +436,15 @@ __device__ __forceinline__ void accumulate(PairAcc& A, double s, double dx, doub
             A.w[4] = fma(s * dx, dz, A.w[4]);
             A.w[5] = fma(s * dy, dz, A.w[5]);
         }
-    } else if (ENERGY == 2) {  // the barostat takes no rigid atoms
+    } else if (ENERGY == 2 || ENERGY == 3) {  // the barostat takes no rigid atoms
         A.w[0] = fma(s * dx, dx, A.w[0]);
         A.w[1] = fma(s * dy, dy, A.w[1]);
         A.w[2] = fma(s * dz, dz, A.w[2]);
+        if (ENERGY == 3) {
+            A.w[3] = fma(s * dx, dy, A.w[3]);
+            A.w[4] = fma(s * dx, dz, A.w[4]);
+            A.w[5] = fma(s * dy, dz, A.w[5]);
+        }
     }
 }
 
@@ -505,9 +511,9 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         const double vals[kEnergyTerms] = {pe, ke, A.w[0], A.w[1], A.w[2], A.w[3], A.w[4], A.w[5], pw, (double)nonfinite};
 #pragma unroll
         for (int k = 0; k < kEnergyTerms; ++k) b.eslot[(int64_t)k * n_slots + t] = vals[k];
-    } else if (ENERGY == 2) {  // barostat steps: the virial diagonal only
+    } else if (ENERGY == 2 || ENERGY == 3) {  // barostat steps: the virial diagonal, or the whole tensor
 #pragma unroll
-        for (int k = 0; k < 3; ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
+        for (int k = 0; k < (ENERGY == 3 ? 6 : 3); ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
     }
     if (!OPEN && !WRITEBACK) {
         // thermostatted steps: the opening kick runs after the kinetic-energy

@@ -202,6 +202,7 @@ struct KernelShape {
     int32_t lanes;    // lanes sharing one atom's neighbour list (brick path)
     int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
     int32_t compact;  // 1 = mixed mode with compact records (global path)
+    int32_t tri;      // 1 = box matrices (sheared cells)
 };
 
 // Launchers (kernels.hip).  All enqueue on `s`.
@@ -217,8 +218,8 @@ void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipSt
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
-// energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat);
-// with close or open and no writeback the force is kept for a separate pass
+// energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat),
+// 3 the whole virial tensor only (full-matrix barostat)
 struct ForceFlags {
     int energy, close, open, writeback;
 };

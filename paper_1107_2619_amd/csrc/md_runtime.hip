@@ -151,6 +151,7 @@ KernelShape shape(const md_ctx* c)
     k.rowlen = (c->cap + 7) / 8 * 8;
     k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL &&
                 !c->tri;  // compact records are per-axis cell offsets of an orthorhombic grid
+    k.tri = c->tri ? 1 : 0;
     return k;
 }
 
@@ -709,7 +710,7 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
         if (due(c)) rebuild(c, s, true);
         if (c->pr) {
             // closing kick and the virial (the whole tensor for a box matrix), forces kept
-            forces(c, ForceFlags{c->tri ? 1 : 2, 1, 0, 0}, s, false);
+            forces(c, ForceFlags{c->tri ? 3 : 2, 1, 0, 0}, s, false);
             pr_boundary(c, 1, 1, s);
         } else if (c->nvt) {
             forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
@@ -1251,7 +1252,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         }
         c->p ^= 1;
     } else if (c->pr) {
-        forces(c, ForceFlags{c->tri ? 1 : 2, 0, 0, 0}, s, false);  // f(x0) and the virial
+        forces(c, ForceFlags{c->tri ? 3 : 2, 0, 0, 0}, s, false);  // f(x0) and the virial
         pr_boundary(c, 0, 1, s);                      // box half kick and drift, opening kick and drift
     } else if (c->nvt) {
         forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0) kept for the kick
