@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {"fetch_kib": 115014.0, "write_kib": 71280.2, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256_16": "e38ab41cf4796703", "workload": "bcc1m", "precision": "mixed"}
+FORCE_TRAFFIC = {"fetch_kib": 115005.4, "write_kib": 71280.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256_16": "5a1e7dc1a9147682", "workload": "bcc1m", "precision": "mixed"}
 # VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
 # so this is also the lane-operations per atom of one launch.
@@ -280,6 +280,8 @@ def main():
                     help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
     ap.add_argument("--copy-gbs-mib", type=int, default=1024,
                     help="size of the device copy whose bandwidth is reported beside the roofline (0 = skip)")
+    ap.add_argument("--kernel", choices=["auto", "global"], default="auto",
+                    help="main workload: autotuned configuration, or the global-gather kernels with tables")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -341,7 +343,12 @@ def main():
     results = {}
     tuned = {}
     for prec in ("fp64", "mixed"):
-        opts, ch = tune_options(md, system, prec)
+        if args.kernel == "global":  # fixed configuration (counter passes compare the same kernels)
+            ch = {"kernel": 1, "brick_dims": 0, "lanes": 1, "block": 512, "evaluator": 0, "step_us": None}
+            opts = choice_options(md, ch)
+            log(f"{prec}: global kernels, tables (no autotune)")
+        else:
+            opts, ch = tune_options(md, system, prec)
         tuned[prec] = ch
         log(f"{prec}: warmup 2 x {args.warmup}, timed {args.steps} steps")
         sim, ms, wall, en, _ = run_precision(md, system, prec, args.steps, args.warmup, timing=False, tune=opts)

@@ -313,25 +313,6 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
     }
 }
 
-// Compact record of a slot: cell-local coordinates in units of h_a 2^-28 (the
-// mixed mode's gather image of the FP64 positions).  Returns false if a
-// coordinate lies too far outside its link cell to encode.
-__device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[3], double x, double y, double z,
-                                               int4& out)
-{
-    const double xs[3] = {x, y, z};
-    int q[3];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double u = (xs[a] - (R.origin[a] + c[a] * R.cell[a])) * R.iqs[a];
-        ok = ok && fabs(u) < kCompactCells * (double)(1 << kCompactBits);
-        q[a] = ok ? (int)rint(u) : 0;
-    }
-    out = make_int4(q[0], q[1], q[2], 0);
-    return ok;
-}
-
 // Verlet list from the link cells (paper, "The Neighbourlist calculation":
 // a loop over link cells and their adjacent cells).  One wavefront per link
 // cell.  The up to 27 adjacent cells (fewer on free faces; on a periodic axis
@@ -559,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
             b.cellxyz[i] = make_int4(c[0], c[1], c[2], 0);
             if (compact) {
                 int4 rq;
-                if (!compact_coords(R, c, xl.x, xl.y, xl.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+                if (!compact_coords<TRI ? 2 : 1>(R, c, xl.x, xl.y, xl.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
                 b.rec[0][i] = rq;
             }
         }
@@ -593,9 +574,22 @@ __device__ __forceinline__ double compact_axis(int code_field, int qj, int qi1, 
     return (double)(int32_t)dq * qs;
 }
 
+// CMP = 1: orthorhombic cells.  CMP = 2: a sheared cell, whose records hold
+// fractional in-cell coordinates: the integer differences along the three edge
+// vectors map through qg = h diag(2^-28 / n_a) into the Cartesian separation.
+template <int CMP>
 __device__ __forceinline__ void compact_delta(const DevReplica& R, const int4& qi1, const int4& qj, int code,
                                               double& dx, double& dy, double& dz)
 {
+    if (CMP == 2) {
+        const double d0 = compact_axis(code & 3, qj.x, qi1.x, 1.0);
+        const double d1 = compact_axis((code >> 2) & 3, qj.y, qi1.y, 1.0);
+        const double d2 = compact_axis((code >> 4) & 3, qj.z, qi1.z, 1.0);
+        dx = fma(R.qg[0], d0, fma(R.qg[1], d1, R.qg[2] * d2));
+        dy = fma(R.qg[3], d0, fma(R.qg[4], d1, R.qg[5] * d2));
+        dz = fma(R.qg[6], d0, fma(R.qg[7], d1, R.qg[8] * d2));
+        return;
+    }
     dx = compact_axis(code & 3, qj.x, qi1.x, R.qs[0]);
     dy = compact_axis((code >> 2) & 3, qj.y, qi1.y, R.qs[1]);
     dz = compact_axis((code >> 4) & 3, qj.z, qi1.z, R.qs[2]);
@@ -633,7 +627,7 @@ __device__ __forceinline__ int4 record_load(__amdgpu_buffer_rsrc_t rs, int j)
 //
 // Density pass (Eq. Ucoh, the argument of F): rho_i = sum_j rho_{s_i s_j}(r_ij),
 // then F_i and F'_i.  The sum is accumulated in FP64 in both precision modes.
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, bool CMP>
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int CMP>
 __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
                                                      int energy)
 {
@@ -681,7 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
             const int code = (unsigned)e[u] >> kIndexBits;
             double dx, dy, dz;
             if (CMP) {
-                compact_delta(Rp, qb, qs[u], code, dx, dy, dz);
+                compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
             } else {
                 dx = xs[u].x - xi.x;
                 dy = xs[u].y - xi.y;
@@ -704,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
 
 // Force pass + velocity Verlet (global gathers).
 template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
-          bool CMP>
+          int CMP>
 __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
                                                    double dt, md_state st)
 {
@@ -760,7 +754,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
             double dx, dy, dz;
             R fpj;
             if (CMP) {
-                compact_delta(Rp, qb, qs[u], code, dx, dy, dz);
+                compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
                 fpj = (R)__int_as_float(qs[u].w);
             } else {
                 dx = ps[u].x - pi.x;
@@ -786,7 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
         const int c[3] = {c4.x, c4.y, c4.z};
         const double3 xn = load_xyz(b.pos[p ^ 1], t);
         int4 rq;
-        if (!compact_coords(Rp, c, xn.x, xn.y, xn.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        if (!compact_coords<CMP>(Rp, c, xn.x, xn.y, xn.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
         b.rec[0][t] = rq;
     }
 }
@@ -1132,7 +1126,7 @@ __global__ void k_pr_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, d
         const int4 c4 = b.cellxyz[t];
         const int c[3] = {c4.x, c4.y, c4.z};
         int4 rq;
-        if (!compact_coords(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        if (!compact_coords<1>(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
         b.rec[0][t] = rq;
     }
 }
@@ -1545,10 +1539,12 @@ static void density_variant(const Buffers& b, int p, int q, const KernelShape& k
 {
     const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * 4 * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
-    if (k.compact)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
+    if (k.compact == 2)
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
+    else if (k.compact)
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
     else
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, false>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 0>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>
@@ -1596,11 +1592,14 @@ static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, c
 {
     const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (E == 1 ? 4 : 0)) * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
-    if (k.compact)
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
+    if (k.compact == 2)
+        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
+                           P, dt_fs, st);
+    else if (k.compact)
+        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
                            P, dt_fs, st);
     else
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, false>), grid, dim3(kBlock), lds, s, b, p, q,
+        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 0>), grid, dim3(kBlock), lds, s, b, p, q,
                            k.n_slots, P, dt_fs, st);
 }
 

@@ -293,6 +293,8 @@ __global__ __launch_bounds__(kBlock) void k_prt_update(Buffers b, int close, int
     m3_store(Hni, R.hinv);
     const M3 mb = m3_mul(Hn, m3_load(R.hbinv));
     m3_store(mb, R.mb);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) R.qg[e] = ldexp(Hn.e[e] / (double)R.nc[e % 3], -kCompactBits);
     double strain2 = 0.0;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
@@ -306,12 +308,14 @@ __global__ __launch_bounds__(kBlock) void k_prt_update(Buffers b, int close, int
                                     Hni.e[3 * a + 2] * Hni.e[3 * a + 2]);
         R.box[a] = w;
         R.inv_box[a] = 1.0 / w;
+        R.cell[a] = w / (double)R.nc[a];
         if (!(w / (double)R.nc[a] >= rlist)) atomicAdd(&b.flags[F_PR_BOX], 1);
     }
 }
 
-// Opening velocity map and kick, then the drift into pos[p^1].
-__global__ void k_prt_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h)
+// Opening velocity map and kick, then the drift into pos[p^1], with the
+// compact record in the new cell (mixed mode).
+__global__ void k_prt_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double h, int compact)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -341,6 +345,13 @@ __global__ void k_prt_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, 
     double* dst = reinterpret_cast<double*>(b.pos[p ^ 1] + t);
     *reinterpret_cast<double2*>(dst) = make_double2(xn[0], xn[1]);
     dst[2] = xn[2];
+    if (compact) {
+        const int4 c4 = b.cellxyz[t];
+        const int c[3] = {c4.x, c4.y, c4.z};
+        int4 rq;
+        if (!compact_coords<2>(R, c, xn[0], xn[1], xn[2], rq)) atomicAdd(&b.flags[F_COMPACT], 1);
+        b.rec[0][t] = rq;
+    }
 }
 
 // Closing velocity map of the last step of a call: the internal and the
@@ -384,7 +395,8 @@ void launch_prt_update(const Buffers& b, int q, const KernelShape& k, const PotA
 void launch_prt_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prt_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs);
+    hipLaunchKernelGGL(k_prt_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
+                       k.compact);
 }
 
 void launch_prt_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,

@@ -151,6 +151,38 @@ __device__ __forceinline__ void cell_coords(const Box& b, double x, double y, do
     c[2] = cell_axis(z, b.o[2], b.iL[2], b.nc[2], b.pmask & 4);
 }
 
+// Compact record of a slot: cell-local coordinates in units of h_a 2^-28 (the
+// mixed mode's gather image of the FP64 positions).  In a sheared cell the
+// coordinates are fractional, along the edge vectors: (s_a n_a - c_a) 2^28 with
+// s = h^-1 (x - o).  Returns false if a coordinate lies too far outside its
+// link cell to encode.  KIND: 0 reads the cell type from the descriptor, 1
+// orthorhombic, 2 sheared (for kernels specialised on it).
+template <int KIND = 0>
+__device__ __forceinline__ bool compact_coords(const DevReplica& R, const int c[3], double x, double y, double z,
+                                               int4& out)
+{
+    double u[3];
+    if (KIND == 0 ? R.tri != 0 : KIND == 2) {
+        double f[3];
+        frac_coords(R.hinv, R.origin, x, y, z, f);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = ldexp(fma(f[a], (double)R.nc[a], -(double)c[a]), kCompactBits);
+    } else {
+        const double xs[3] = {x, y, z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = (xs[a] - (R.origin[a] + c[a] * R.cell[a])) * R.iqs[a];
+    }
+    int q[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && fabs(u[a]) < kCompactCells * (double)(1 << kCompactBits);
+        q[a] = ok ? (int)rint(u[a]) : 0;
+    }
+    out = make_int4(q[0], q[1], q[2], 0);
+    return ok;
+}
+
 __device__ __forceinline__ double3 load_xyz(const double4* p, int64_t i)
 {
     // 16 + 8 byte loads: never touches .w, which the density pass writes.

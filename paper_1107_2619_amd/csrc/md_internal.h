@@ -78,6 +78,7 @@ struct DevReplica {
     double h[9], hinv[9];
     double hbinv[9];  // inverse of h at the last list build
     double mb[9];     // h times hbinv: the homogeneous strain since that build
+    double qg[9];     // h diag(2^-kCompactBits / nc): compact-record units to Cartesian
 };
 
 __host__ __device__ inline int32_t cell_index(const DevReplica& R, int cx, int cy, int cz)
@@ -201,7 +202,7 @@ struct KernelShape {
     int32_t block;    // threads per brick workgroup
     int32_t lanes;    // lanes sharing one atom's neighbour list (brick path)
     int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
-    int32_t compact;  // 1 = mixed mode with compact records (global path)
+    int32_t compact;  // mixed mode with compact records (global path): 1 orthorhombic, 2 sheared cells
     int32_t tri;      // 1 = box matrices (sheared cells)
 };
 

@@ -131,6 +131,28 @@ void invert3(const double* m, double* o)
     o[8] = (m[0] * m[4] - m[1] * m[3]) * id;
 }
 
+// Descriptor fields of a sheared cell with box matrix h (the link-cell counts
+// nc already set): inverse, build inverse, strain map, compact-record units,
+// and the widths between opposite faces in place of edge lengths.
+void set_cell_matrix(DevReplica& D, const double* h)
+{
+    std::memcpy(D.h, h, sizeof D.h);
+    invert3(h, D.hinv);
+    std::memcpy(D.hbinv, D.hinv, sizeof D.hbinv);
+    for (int e = 0; e < 9; ++e) {
+        D.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
+        D.qg[e] = std::ldexp(h[e] / (double)D.nc[e % 3], -kCompactBits);
+    }
+    for (int a = 0; a < 3; ++a) {
+        const double* r = D.hinv + 3 * a;
+        const double w = 1.0 / std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        D.box[a] = w;
+        D.inv_box[a] = 1.0 / w;
+        D.cell[a] = w / (double)D.nc[a];
+        D.lbuild[a] = w;
+    }
+}
+
 KernelShape shape(const md_ctx* c)
 {
     KernelShape k;
@@ -149,8 +171,8 @@ KernelShape shape(const md_ctx* c)
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
-    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL &&
-                !c->tri;  // compact records are per-axis cell offsets of an orthorhombic grid
+    k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL;
+    if (k.compact && c->tri) k.compact = 2;  // fractional in-cell coordinates
     k.tri = c->tri ? 1 : 0;
     return k;
 }
@@ -280,6 +302,7 @@ bool upload_geometry(md_ctx* c)
                 std::memcpy(D.hinv, cur[r].hinv, sizeof D.hinv);
                 std::memcpy(D.hbinv, cur[r].hbinv, sizeof D.hbinv);
                 std::memcpy(D.mb, cur[r].mb, sizeof D.mb);
+                std::memcpy(D.qg, cur[r].qg, sizeof D.qg);
                 for (int a = 0; a < 3; ++a) {
                     D.box[a] = cur[r].box[a];
                     D.inv_box[a] = cur[r].inv_box[a];
@@ -1015,13 +1038,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             worst *= nc + kBrickMaxDim - 1;  // cells of the grid padded to whole bricks
         }
         D.tri = c->tri ? 1 : 0;
-        if (c->tri) {
-            const double* h = &c->hmat[9 * (size_t)r];
-            std::memcpy(D.h, h, sizeof D.h);
-            invert3(h, D.hinv);
-            std::memcpy(D.hbinv, D.hinv, sizeof D.hbinv);
-            for (int e = 0; e < 9; ++e) D.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
-        }
+        if (c->tri) set_cell_matrix(D, &c->hmat[9 * (size_t)r]);
         slot += (n + kWave - 1) / kWave * kWave;
         cells_alloc += worst;
         if (slot > (int64_t)kIndexMask || cells_alloc > (int64_t)INT32_MAX / 2)
@@ -1085,14 +1102,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         for (int r = 0; r < c->R; ++r) {
             DevReplica& D = c->reps[r];
             if (c->tri) {
-                std::memcpy(D.h, &c->hmat[9 * (size_t)r], sizeof D.h);
-                invert3(D.h, D.hinv);
-                std::memcpy(D.hbinv, D.hinv, sizeof D.hbinv);
-                for (int e = 0; e < 9; ++e) D.mb[e] = (e % 4 == 0) ? 1.0 : 0.0;
-                for (int a = 0; a < 3; ++a) {
-                    D.box[a] = c->box[3 * (size_t)r + a];
-                    D.inv_box[a] = 1.0 / D.box[a];
-                }
+                set_cell_matrix(D, &c->hmat[9 * (size_t)r]);
                 continue;
             }
             set_edges(D, &c->box[3 * (size_t)r]);
