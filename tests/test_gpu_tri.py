@@ -316,3 +316,30 @@ def test_prt_conserved_quantity_and_mean_stress(md):
     load = np.eye(3) + abs(np.linalg.det(h0)) / abs(np.linalg.det(hm)) * f @ (stress - np.eye(3)) @ f.T
     announce(f"mean stress {np.round(pi, 3).tolist()} load {np.round(load, 3).tolist()}")
     assert np.max(np.abs(pi - load)) < 0.1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_prt_options_and_autotune_keep_the_cell(md, orc, precision):
+    """Option changes between calls re-upload the replica descriptors; under
+    the full-matrix barostat that upload keeps the cell the device has reached
+    (box matrix, inverse, strain map, record units).  md_autotune in between
+    changes nothing of the state: the split run still follows the oracle."""
+    s, h = _moving()
+    announce(f"full-matrix barostat options and autotune between calls {precision}")
+    kw = dict(box_matrix=h, pr_pressure_gpa=[1.0], pr_mass=[W_BOX], pr_stress_gpa=_stress())
+    sim = md.Simulation(s, precision=precision, **kw)
+    sim.step(30)
+    h_mid = sim.energy().h[0].copy()
+    assert np.max(np.abs(h_mid - h)) > 1e-4
+    sim.set_option(md.MD_OPT_BRICK_BLOCK, 512)
+    assert np.array_equal(sim.energy().h[0], h_mid)
+    sim.autotune(trials=1)
+    sim.step(30)
+    en = sim.energy()
+    ref = _prt(orc, s, h, 60, 1.0, W_BOX, _stress())
+    if precision == "fp64":
+        assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+        assert np.max(np.abs(en.h[0] - ref.h[-1])) < 1e-10 * np.abs(ref.h[-1]).max()
+    else:
+        assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-4
+        assert np.max(np.abs(en.h[0] - ref.h[-1])) < 1e-5
