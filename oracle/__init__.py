@@ -93,6 +93,8 @@ def _load():
                                vp, vp]
     lib.or_forces_tri.restype = i32
     lib.or_forces_tri.argtypes = [i64, vp, vp, vp, vp, vp, vp, P, vp, vp, vp, vp, vp]
+    lib.or_forces_sampled_tri.restype = i32
+    lib.or_forces_sampled_tri.argtypes = [i64, vp, vp, vp, vp, vp, P, i64, vp, vp, vp, vp]
     lib.or_run_prt.restype = i32
     lib.or_run_prt.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, i64, d, d, d, d, vp, vp,
                                vp, vp, vp, vp, vp, vp]
@@ -441,6 +443,28 @@ def forces_tri(pos, species, h, pot: Potential, rigid=None) -> ForceResult:
     if rc:
         raise ValueError("oracle: every width of the cell must exceed twice the cutoff")
     return ForceResult(f, e, rho, w, pe.value)
+
+
+def forces_sampled_tri(pos, species, h, pot: Potential, sample):
+    """Forces, per-atom energies and densities of the atoms in ``sample`` only,
+    in a periodic cell with box matrix ``h`` [3,3]."""
+    x, y, z = _split(pos)
+    sp = _u8(species)
+    hm = _f64(np.asarray(h).reshape(9))
+    idx = np.ascontiguousarray(sample, dtype=np.int64)
+    m = idx.shape[0]
+    f = np.zeros((m, 3))
+    e = np.zeros(m)
+    rho = np.zeros(m)
+    rc = _load().or_forces_sampled_tri(
+        x.shape[0], x.ctypes.data, y.ctypes.data, z.ctypes.data, sp.ctypes.data, hm.ctypes.data, pot.ref, m,
+        idx.ctypes.data, f.ctypes.data, e.ctypes.data, rho.ctypes.data,
+    )
+    if rc == -1:
+        raise ValueError("oracle: every width of the cell must exceed twice the cutoff")
+    if rc:
+        raise ValueError(f"oracle: sampled evaluation failed ({rc})")
+    return ForceResult(f, e, rho, np.full(6, np.nan), float("nan"))
 
 
 @dataclass

@@ -323,14 +323,11 @@ double or_energy(int64_t n, const double *x, const double *y, const double *z,
  * tests per sampled atom.  Same definitions as or_forces.
  * Outputs: f[3m], e_atom[m], rho_out[m] (any of the last two may be NULL).
  */
-int or_forces_sampled(int64_t n, const double *x, const double *y, const double *z,
-                      const uint8_t *species, const double *box, const uint8_t *periodic,
-                      const or_potential *p, int64_t m, const int64_t *sample, double *f,
-                      double *e_atom, double *rho_out)
+static int sampled_geom(int64_t n, const double *x, const double *y, const double *z,
+                        const uint8_t *species, const or_geom *gp, const or_potential *p, double rc,
+                        int64_t m, const int64_t *sample, double *f, double *e_atom, double *rho_out)
 {
-    const double rc = or_cutoff(p);
-    if (check_box(box, periodic, rc)) return -1;
-    const or_geom g = {box, periodic, {0}, {0}};
+    const or_geom g = *gp;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int64_t s = 0; s < m; ++s) {
@@ -349,7 +346,7 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             load_pos(x, y, z, j, xj);
-            image_vector(xi, xj, box, periodic, d);
+            geom_image(&g, xi, xj, d);
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             if (r >= rc) continue;
             rho_i += or_density(p, si, species[j], r, NULL);
@@ -369,7 +366,7 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
             double dFj;
             or_embed(p, sj, rho_j, &dFj);
             load_pos(x, y, z, j, xj);
-            image_vector(xi, xj, box, periodic, d);
+            geom_image(&g, xi, xj, d);
             double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             double dphi, drho_ij, drho_ji;
             double phi = or_pair(p, si, sj, r, &dphi);
@@ -387,6 +384,17 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
         if (rho_out) rho_out[s] = rho_i;
     }
     return bad ? -2 : 0;
+}
+
+int or_forces_sampled(int64_t n, const double *x, const double *y, const double *z,
+                      const uint8_t *species, const double *box, const uint8_t *periodic,
+                      const or_potential *p, int64_t m, const int64_t *sample, double *f,
+                      double *e_atom, double *rho_out)
+{
+    const double rc = or_cutoff(p);
+    if (check_box(box, periodic, rc)) return -1;
+    const or_geom g = {box, periodic, {0}, {0}};
+    return sampled_geom(n, x, y, z, species, &g, p, rc, m, sample, f, e_atom, rho_out);
 }
 
 /* Kinetic energy (eV) of the mobile atoms, velocities in Angstrom/fs:
@@ -1034,6 +1042,17 @@ int or_forces_tri(int64_t n, const double *x, const double *y, const double *z,
     if (tri_geom(h, rc, &g)) return -1;
     forces_geom(n, x, y, z, species, rigid, &g, p, rc, f, e_atom, rho_out, virial, pe);
     return 0;
+}
+
+/* or_forces_sampled in a periodic cell with box matrix h[9]. */
+int or_forces_sampled_tri(int64_t n, const double *x, const double *y, const double *z,
+                          const uint8_t *species, const double *h, const or_potential *p, int64_t m,
+                          const int64_t *sample, double *f, double *e_atom, double *rho_out)
+{
+    const double rc = or_cutoff(p);
+    or_geom g;
+    if (tri_geom(h, rc, &g)) return -1;
+    return sampled_geom(n, x, y, z, species, &g, p, rc, m, sample, f, e_atom, rho_out);
 }
 
 /*

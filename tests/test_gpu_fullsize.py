@@ -59,6 +59,39 @@ def test_bcc1m_sampled_parity(md, orc, precision, config):
     _sampled_check(orc, sim, s, precision, 64, seed=1)
 
 
+@pytest.mark.parametrize("precision,barostat", [("mixed", False), ("fp64", False), ("mixed", True)])
+def test_bcc1m_sheared_cell_sampled_parity(md, orc, precision, barostat):
+    """The 1,013,760-atom crystal in the cell [a, b, c + a] in the benchmark's
+    configuration (0.5 A skin, graph replay): after 30 steps with the cell held,
+    or under the full-matrix barostat with a 0.2 GPa xy shear stress, the
+    sampled forces and energies against the oracle at the GPU's state and
+    cell."""
+    s = inputs.workload("bcc1m")
+    h = np.diag(s.box[0]) @ np.array([[1.0, 0.0, 1.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    kw = dict(box_matrix=h, skin=0.5)
+    if barostat:
+        shear = np.zeros((3, 3))
+        shear[0, 1] = shear[1, 0] = 0.2
+        kw.update(pr_pressure_gpa=[0.0], pr_mass=[2.0e7], pr_stress_gpa=shear)
+    announce(f"bcc1m sheared cell sampled {precision} barostat={barostat}")
+    sim = md.Simulation(s, precision=precision, **kw)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(30)
+    en = sim.energy()
+    hc = en.h[0]
+    if barostat:
+        assert np.max(np.abs(hc - h)) > 1e-6  # the cell moved
+    pos, f, e = sim.positions(), sim.forces(), sim.atom_energies()
+    sample = np.random.default_rng(5).choice(s.n_atoms, 64, replace=False)
+    ref = orc.forces_sampled_tri(pos, s.species, hc, orc.Potential(s.potential), sample)
+    rms = np.sqrt(np.mean(np.sum(ref.f**2, 1)))
+    err_f = np.max(np.linalg.norm(f[sample] - ref.f, axis=1)) / rms
+    err_e = np.max(np.abs(e[sample] - ref.e_atom) / np.abs(ref.e_atom))
+    announce(f"sheared bcc1m {precision}: sampled force err {err_f:.2e}, energy err {err_e:.2e}")
+    assert err_f <= TOL[precision]["force"]
+    assert err_e <= TOL[precision]["energy"]
+
+
 def test_fec256_sampled_parity(md, orc):
     """256 Fe-C replicas (2.1 M atoms), autotuned, graph replay, mixed."""
     s = inputs.workload("fec256")

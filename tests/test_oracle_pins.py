@@ -991,3 +991,19 @@ def test_prt_with_thermostat_limits(orc):
     c = orc.run_prt(s.pos, s.vel, s.species, h, pot, 1.0, 100, 0.0, 0.0, t_target=500.0, q_ev_fs2=q)
     d = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, 1.0, 100, 500.0, q)
     assert np.max(np.abs(c.pos - d.pos)) < 1e-10 and abs(c.pi[-1] - d.pi[-1]) < 1e-14
+
+
+def test_sheared_sampled_mode_matches_full(orc, fec_pot, rng):
+    """The sampled evaluation in a sheared cell gives the full evaluation's
+    rows for the sampled atoms (a strained crystal, two species)."""
+    s = inputs.bcc_fe(6, a=2.87, temperature=0.0, seed=7, displace=0.1)
+    f = np.array([[1.0, 0.04, -0.03], [0.02, 0.99, 0.05], [-0.04, 0.03, 1.01]])
+    h = f @ np.diag(s.box[0])
+    pos = s.pos @ f.T
+    sp = (rng.random(s.n_atoms) < 0.2).astype(np.uint8)
+    full = orc.forces_tri(pos, sp, h, fec_pot)
+    sample = rng.choice(s.n_atoms, 40, replace=False)
+    part = orc.forces_sampled_tri(pos, sp, h, fec_pot, sample)
+    assert np.max(np.abs(part.f - full.f[sample])) < 1e-12
+    assert np.max(np.abs(part.e_atom - full.e_atom[sample])) < 1e-12
+    assert np.max(np.abs(part.rho - full.rho[sample])) < 1e-13
