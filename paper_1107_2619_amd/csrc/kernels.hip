@@ -479,6 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
             nb_count = b.cell_count[adj.x];
         }
     }
+    // sheared cells: whether any adjacent cell lies across a face (interior
+    // cells, most of a large cell, skip the edge-vector shifts)
+    const bool any_wrap = TRI && __ballot(nb_wrap != 0) != 0;
     // exclusive prefix of the candidate counts over the 27 lanes
     int incl = nb_count;
 #pragma unroll
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                 const double3 xj = load_xyz(pos, j);
                 if (TRI) {  // the image cell's edge-vector shift
                     double dsh[3] = {0.0, 0.0, 0.0};
-                    apply_shift(bx, w & 63, dsh[0], dsh[1], dsh[2]);
+                    if (any_wrap) apply_shift(bx, w & 63, dsh[0], dsh[1], dsh[2]);
                     cx[u] = xj.x + dsh[0];
                     cy[u] = xj.y + dsh[1];
                     cz[u] = xj.z + dsh[2];

@@ -124,26 +124,33 @@ def test_sheared_cell_nve_trajectory(md, orc, precision, mode):
     _check(sim.energy(), 0, ref, sim.positions(), sim.forces(), precision, barostat=False)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("integrator", ["verlet", "gear3", "nvt"])
-def test_skewed_cell_is_the_cube(md, orc, integrator):
+def test_skewed_cell_is_the_cube(md, orc, integrator, precision):
     """The cell [a, b, c + a] holds the cube's periodic system, so every
     integrator in it follows the oracle's run of the cube (velocity Verlet,
-    Gear, Nose-Hoover)."""
+    Gear, Nose-Hoover); mixed precision carries sheared-cell compact records
+    through each integrator's passes."""
     s, h = _skewed()
     pot = orc.Potential(s.potential)
-    announce(f"skewed cell = cube, {integrator}")
+    announce(f"skewed cell = cube, {integrator} {precision}")
     if integrator == "nvt":
         q = (3 * s.n_atoms - 3) * orc.boltzmann_ev() * 500.0 * 50.0**2
-        sim = md.Simulation(s, box_matrix=h, nh_temperature=[500.0], nh_mass=[q])
+        sim = md.Simulation(s, precision=precision, box_matrix=h, nh_temperature=[500.0], nh_mass=[q])
         ref = orc.run_nh(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, s.dt_fs, 60, 500.0, q)
     elif integrator == "gear3":
-        sim = md.Simulation(s, box_matrix=h, integrator="gear3")
+        sim = md.Simulation(s, precision=precision, box_matrix=h, integrator="gear3")
         ref = orc.run_gear(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, s.dt_fs, 60)
     else:
-        sim = md.Simulation(s, box_matrix=h)
+        sim = md.Simulation(s, precision=precision, box_matrix=h)
         ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], pot, s.dt_fs, 60)
     sim.step(60)
     en = sim.energy()
+    if precision == "mixed":
+        assert sim.get_option(md.MD_OPT_COMPACT) == 1
+        assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-4
+        assert abs(en.pe[0] + en.ke[0] - ref.pe[-1] - ref.ke[-1]) < 1e-5 * s.n_atoms
+        return
     assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
     assert abs(en.pe[0] - ref.pe[-1]) <= 1e-10 * abs(ref.pe[-1])
     if integrator == "nvt":
