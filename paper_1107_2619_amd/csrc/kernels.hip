@@ -1011,7 +1011,29 @@ __global__ __launch_bounds__(kBlock) void k_pr_tensor_waves(Buffers b, int q, in
     }
 }
 
-// One workgroup per replica: the stress tensor from the wave partials (fixed
+// Barostat sums, first stage: one wavefront per reduction chunk (kReduceChunk
+// slots of one replica) adds the chunk's per-wave partials (N terms each) in a
+// fixed shuffle tree into chunk_partial[c][k].
+template <int N>
+__global__ __launch_bounds__(kWave) void k_pr_chunk_sums(Buffers b)
+{
+    const int c = blockIdx.x;
+    const int r = b.chunk_rep[c];
+    const DevReplica& R = b.reps[r];
+    const int64_t s0 = R.slot_off + (int64_t)(c - b.chunk_off[r]) * kReduceChunk;
+    const int64_t s1 = min(s0 + (int64_t)kReduceChunk, (int64_t)R.slot_off + R.n_atoms);
+    const int64_t w = s0 / kWave + threadIdx.x;
+    const bool live = w < (s1 + kWave - 1) / kWave;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        double x = live ? b.pr_partial[w * N + k] : 0.0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
+        if (threadIdx.x == 0) b.chunk_partial[(int64_t)c * kEnergySlots + k] = x;
+    }
+}
+
+// One workgroup per replica: the stress tensor from the chunk sums (fixed
 // tree), then on one lane the closing and/or opening box half kicks and, with
 // `open`, the box drift and the factors of the open pass.
 __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int open, double h, double rlist,
@@ -1020,11 +1042,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int 
     __shared__ double sh[6][kBlock];
     const int r = blockIdx.x;
     DevReplica& R = b.reps[r];
-    const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
     double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock)
+    for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) part[k] += b.pr_partial[w * 6 + k];
+        for (int k = 0; k < 6; ++k) part[k] += b.chunk_partial[(int64_t)c * kEnergySlots + k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = part[k];
     __syncthreads();
@@ -1711,10 +1732,18 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
                        k.compact);
 }
 
+void launch_pr_chunk_sums(const Buffers& b, const KernelShape& k, int n_terms, hipStream_t s)
+{
+    if (k.n_chunks == 0) return;
+    if (n_terms == 12) hipLaunchKernelGGL(k_pr_chunk_sums<12>, dim3(k.n_chunks), dim3(kWave), 0, s, b);
+    else hipLaunchKernelGGL(k_pr_chunk_sums<6>, dim3(k.n_chunks), dim3(kWave), 0, s, b);
+}
+
 void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
                       double dt_fs, double rlist, double strain_tol, int nvt, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pr_tensor_waves, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+    launch_pr_chunk_sums(b, k, 6, s);
     if (k.n_replicas > 0)
         hipLaunchKernelGGL(k_pr_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, close, open, dt_fs, rlist,
                            strain_tol, nvt);

@@ -253,6 +253,9 @@ void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 void launch_pr_close_scale(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, const md_state& st,
                            hipStream_t s);
 void launch_pr_mark_build(const Buffers& b, const KernelShape& k, hipStream_t s);
+// First stage of the barostat sums: per-wave partials (n_terms = 6 or 12) into
+// chunk_partial, one wavefront per reduction chunk.
+void launch_pr_chunk_sums(const Buffers& b, const KernelShape& k, int n_terms, hipStream_t s);
 
 // Barostat on the full box matrix.  pr_state per replica (matrices row-major):
 // [0,9) h, [9,18) dh/dt (A per time unit), [18,27) Sigma = Omega0 h0^-1 (S - P) h0^-T
