@@ -876,16 +876,22 @@ __global__ __launch_bounds__(kBlock) void k_nh_ke_waves(Buffers b, int q, int64_
 }
 
 // One workgroup per replica: the kinetic energy from the replica's wave
-// partials (a fixed tree), then on one lane `halves` thermostat half steps of
+// partials, or from its chunk sums when `chunked` (a fixed tree either way),
+// then on one lane `halves` thermostat half steps of
 // length dt/2; nh_state = {pi, xi, total velocity scale, kinetic energy after}.
-__global__ __launch_bounds__(kBlock) void k_nh_update(Buffers b, int halves, double dt)
+__global__ __launch_bounds__(kBlock) void k_nh_update(Buffers b, int halves, double dt, int chunked)
 {
     __shared__ double sh[kBlock];
     const int r = blockIdx.x;
-    const DevReplica& R = b.reps[r];
-    const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
     double part = 0.0;
-    for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) part += b.nh_partial[w];
+    if (chunked) {
+        for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
+            part += b.chunk_partial[(int64_t)c * kEnergySlots];
+    } else {
+        const DevReplica& R = b.reps[r];
+        const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock) part += b.nh_partial[w];
+    }
     sh[threadIdx.x] = part;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -1011,11 +1017,12 @@ __global__ __launch_bounds__(kBlock) void k_pr_tensor_waves(Buffers b, int q, in
     }
 }
 
-// Barostat sums, first stage: one wavefront per reduction chunk (kReduceChunk
-// slots of one replica) adds the chunk's per-wave partials (N terms each) in a
-// fixed shuffle tree into chunk_partial[c][k].
+// Thermostat and barostat sums, first stage: one wavefront per reduction chunk
+// (kReduceChunk slots of one replica) adds the chunk's per-wave partials (N
+// terms each) in a fixed shuffle tree into chunk_partial[c][k].  The update
+// kernels then read a replica's chunk sums instead of all its wave partials.
 template <int N>
-__global__ __launch_bounds__(kWave) void k_pr_chunk_sums(Buffers b)
+__global__ __launch_bounds__(kWave) void k_chunk_sums(Buffers b, const double* __restrict__ part)
 {
     const int c = blockIdx.x;
     const int r = b.chunk_rep[c];
@@ -1026,26 +1033,34 @@ __global__ __launch_bounds__(kWave) void k_pr_chunk_sums(Buffers b)
     const bool live = w < (s1 + kWave - 1) / kWave;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        double x = live ? b.pr_partial[w * N + k] : 0.0;
+        double x = live ? part[w * N + k] : 0.0;
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
         if (threadIdx.x == 0) b.chunk_partial[(int64_t)c * kEnergySlots + k] = x;
     }
 }
 
-// One workgroup per replica: the stress tensor from the chunk sums (fixed
-// tree), then on one lane the closing and/or opening box half kicks and, with
+// One workgroup per replica: the stress tensor from the wave partials or, when
+// `chunked`, the chunk sums (a fixed tree either way), then on one lane the
+// closing and/or opening box half kicks and, with
 // `open`, the box drift and the factors of the open pass.
 __global__ __launch_bounds__(kBlock) void k_pr_update(Buffers b, int close, int open, double h, double rlist,
-                                                      double strain_tol, int nvt)
+                                                      double strain_tol, int nvt, int chunked)
 {
     __shared__ double sh[6][kBlock];
     const int r = blockIdx.x;
     DevReplica& R = b.reps[r];
     double part[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
+    if (chunked) {
+        for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) part[k] += b.chunk_partial[(int64_t)c * kEnergySlots + k];
+            for (int k = 0; k < 6; ++k) part[k] += b.chunk_partial[(int64_t)c * kEnergySlots + k];
+    } else {
+        const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) part[k] += b.pr_partial[w * 6 + k];
+    }
 #pragma unroll
     for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = part[k];
     __syncthreads();
@@ -1721,8 +1736,10 @@ void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotAr
                       hipStream_t s)
 {
     hipLaunchKernelGGL(k_nh_ke_waves, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, P);
+    if (k.chunked && k.n_chunks > 0)
+        hipLaunchKernelGGL(k_chunk_sums<1>, dim3(k.n_chunks), dim3(kWave), 0, s, b, b.nh_partial);
     if (k.n_replicas > 0)
-        hipLaunchKernelGGL(k_nh_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, halves, dt_fs);
+        hipLaunchKernelGGL(k_nh_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, halves, dt_fs, k.chunked);
 }
 
 void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
@@ -1734,9 +1751,9 @@ void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const 
 
 void launch_pr_chunk_sums(const Buffers& b, const KernelShape& k, int n_terms, hipStream_t s)
 {
-    if (k.n_chunks == 0) return;
-    if (n_terms == 12) hipLaunchKernelGGL(k_pr_chunk_sums<12>, dim3(k.n_chunks), dim3(kWave), 0, s, b);
-    else hipLaunchKernelGGL(k_pr_chunk_sums<6>, dim3(k.n_chunks), dim3(kWave), 0, s, b);
+    if (!k.chunked || k.n_chunks == 0) return;
+    if (n_terms == 12) hipLaunchKernelGGL(k_chunk_sums<12>, dim3(k.n_chunks), dim3(kWave), 0, s, b, b.pr_partial);
+    else hipLaunchKernelGGL(k_chunk_sums<6>, dim3(k.n_chunks), dim3(kWave), 0, s, b, b.pr_partial);
 }
 
 void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int close, int open,
@@ -1746,7 +1763,7 @@ void launch_pr_update(const Buffers& b, int q, const KernelShape& k, const PotAr
     launch_pr_chunk_sums(b, k, 6, s);
     if (k.n_replicas > 0)
         hipLaunchKernelGGL(k_pr_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, close, open, dt_fs, rlist,
-                           strain_tol, nvt);
+                           strain_tol, nvt, k.chunked);
 }
 
 void launch_pr_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,

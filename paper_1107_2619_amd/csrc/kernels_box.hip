@@ -191,12 +191,13 @@ __device__ M3 m3_sym(const double* v)
     return m;
 }
 
-// One workgroup per replica: the stress tensor from the chunk sums (fixed
-// tree), then on one lane the closing friction and thermostat halves, the box
+// One workgroup per replica: the stress tensor from the wave partials or, when
+// `chunked`, the chunk sums (a fixed tree either way), then on one lane the
+// closing friction and thermostat halves, the box
 // half kicks and, with `open`, the opening halves, the box drift, the new
 // descriptor and the matrices of the open pass.
 __global__ __launch_bounds__(kBlock) void k_prt_update(Buffers b, int close, int open, double h, double rlist,
-                                                       double strain_tol, int nvt)
+                                                       double strain_tol, int nvt, int chunked)
 {
     __shared__ double sh[12][kBlock];
     const int r = blockIdx.x;
@@ -204,9 +205,16 @@ __global__ __launch_bounds__(kBlock) void k_prt_update(Buffers b, int close, int
     double part[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) part[k] = 0.0;
-    for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
+    if (chunked) {
+        for (int c = b.chunk_off[r] + threadIdx.x; c < b.chunk_off[r + 1]; c += kBlock)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) part[k] += b.chunk_partial[(int64_t)c * kEnergySlots + k];
+            for (int k = 0; k < 12; ++k) part[k] += b.chunk_partial[(int64_t)c * kEnergySlots + k];
+    } else {
+        const int64_t w0 = R.slot_off / kWave, w1 = (R.slot_off + (int64_t)R.n_atoms + kWave - 1) / kWave;
+        for (int64_t w = w0 + threadIdx.x; w < w1; w += kBlock)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) part[k] += b.pr_partial[w * 12 + k];
+    }
 #pragma unroll
     for (int k = 0; k < 12; ++k) sh[k][threadIdx.x] = part[k];
     __syncthreads();
@@ -389,7 +397,7 @@ void launch_prt_update(const Buffers& b, int q, const KernelShape& k, const PotA
     launch_pr_chunk_sums(b, k, 12, s);
     if (k.n_replicas > 0)
         hipLaunchKernelGGL(k_prt_update, dim3(k.n_replicas), dim3(kBlock), 0, s, b, close, open, dt_fs, rlist,
-                           strain_tol, nvt);
+                           strain_tol, nvt, k.chunked);
 }
 
 void launch_prt_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,

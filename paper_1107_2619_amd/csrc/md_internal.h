@@ -26,7 +26,8 @@ constexpr int kNumXcd = 8;      // MI355X: 8 accelerator dies, one L2 each
 
 enum EnergyIndex { E_PE = 0, E_KE = 1, E_W0 = 2, E_PW = 8, E_NONFINITE = 9 };
 constexpr int kEnergyTerms = 10;       // per-atom terms written on energy steps
-constexpr int kReduceChunk = 2048;     // slots per first-stage reduction chunk (one workgroup each)
+constexpr int kReduceChunk = 2048;
+constexpr int kChunkedSumWaves = 512;  // replicas above this many waves sum per chunk first     // slots per first-stage reduction chunk (one workgroup each)
 constexpr int kHaloMax = 216;          // halo cells of a brick: (4 + 2)^3 at most
 constexpr int kBrickMaxDim = 4;
 
@@ -204,6 +205,8 @@ struct KernelShape {
     int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
     int32_t compact;  // mixed mode with compact records (global path): 1 orthorhombic, 2 sheared cells
     int32_t tri;      // 1 = box matrices (sheared cells)
+    int32_t chunked;  // 1 = per-replica sums of the thermostat and barostat start with
+                      // per-chunk sums (some replica spans more than kChunkedSumWaves waves)
 };
 
 // Launchers (kernels.hip).  All enqueue on `s`.

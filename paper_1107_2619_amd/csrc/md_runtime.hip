@@ -25,6 +25,7 @@ struct md_ctx {
     std::vector<double> pr_P, pr_W;  // GPa, eV fs^2 / A^2
     bool tri = false;        // box matrices (sheared cells; the barostat then moves all nine entries)
     std::vector<double> hmat, pr_S;  // [R][9] box matrices (A), external stress (GPa)
+    bool chunked_sums = false;  // some replica spans more than kChunkedSumWaves wavefronts
     std::vector<double> nh_T, nh_Q;
     std::vector<double> nh_gkt;  // host copy of nh_param
     std::vector<int64_t> atom_off;
@@ -174,6 +175,7 @@ KernelShape shape(const md_ctx* c)
     k.compact = c->precision == MD_MIXED && !k.brick && c->compact_ok && c->compact_on && c->nbr_mode == MD_NBR_FULL;
     if (k.compact && c->tri) k.compact = 2;  // fractional in-cell coordinates
     k.tri = c->tri ? 1 : 0;
+    k.chunked = c->chunked_sums ? 1 : 0;
     return k;
 }
 
@@ -1045,6 +1047,8 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
             return reject(MD_ERR_ARG, "system too large: at most 2^26 atom slots and 2^30 link cells");
     }
     c->Np = std::max<int64_t>(slot, kWave);
+    for (const DevReplica& D : c->reps)
+        if ((D.n_atoms + kWave - 1) / kWave > kChunkedSumWaves) c->chunked_sums = true;
     // compact records hold coordinates up to kCompactCells cell edges from
     // their cell; cells under half the list radius (a free axis of a thin
     // slab) could see atoms beyond that between builds

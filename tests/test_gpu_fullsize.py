@@ -177,3 +177,41 @@ def test_liquid_per_replica_drift(md):
         announce(f"liquid16 {prec}: per-replica max |dE|/N over 1e3 steps: median {np.median(band):.2e}, "
                  f"max {band.max():.2e} eV")
         assert band.max() < 5e-3
+
+
+@pytest.mark.parametrize("ensemble", ["nvt", "nph", "nph_box_matrix"])
+def test_large_replica_chunked_sums_conserve(md, orc, ensemble):
+    """A replica of 43,904 atoms (686 wavefronts) takes the two-stage
+    thermostat and barostat sums (per-chunk sums first).  Over 400 FP64 steps
+    from a displaced 600 K lattice the extended energy stays in a band a
+    thousand times narrower than the swing of PE + KE; a chunk missed or
+    counted twice in the kinetic energy or the stress would drive the
+    thermostat or the box off that balance."""
+    s = inputs.bcc_fe(28, a=2.87, temperature=600.0, seed=11, displace=0.05, skin=0.6)
+    s.max_neighbours = 80
+    assert (s.n_atoms + 63) // 64 > 512
+    kw = {}
+    if ensemble == "nvt":
+        q = (3 * s.n_atoms - 3) * orc.boltzmann_ev() * 600.0 * 50.0**2
+        kw = dict(nh_temperature=[600.0], nh_mass=[q])
+    elif ensemble == "nph":
+        kw = dict(pr_pressure_gpa=[0.0], pr_mass=[2.0e7])
+    else:
+        shear = np.zeros((3, 3))
+        shear[0, 1] = shear[1, 0] = 0.3
+        kw = dict(pr_pressure_gpa=[0.0], pr_mass=[2.0e7], pr_stress_gpa=shear)
+    announce(f"large replica chunked sums {ensemble} N={s.n_atoms}")
+    sim = md.Simulation(s, **kw)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    tot, swing = [], []
+    for _ in range(20):
+        sim.step(20)
+        e = sim.energy()
+        extra = e.nh_energy[0] if ensemble == "nvt" else e.pr_energy[0]
+        tot.append(e.pe[0] + e.ke[0] + extra)
+        swing.append(e.pe[0] + e.ke[0])
+    announce(f"{ensemble}: band {np.ptp(tot):.3e} eV, swing {np.ptp(swing):.3e} eV")
+    if ensemble == "nph_box_matrix":
+        assert abs(e.h[0][0, 1]) + abs(e.h[0][1, 0]) > 1e-6  # the shear stress moved the cell
+    assert np.ptp(swing) > 1.0
+    assert np.ptp(tot) < 1e-3 * np.ptp(swing)
