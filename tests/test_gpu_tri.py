@@ -350,3 +350,23 @@ def test_prt_options_and_autotune_keep_the_cell(md, orc, precision):
     else:
         assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-4
         assert np.max(np.abs(en.h[0] - ref.h[-1])) < 1e-5
+
+
+def test_sheared_cell_unwrapped_images(md):
+    """Positions given several edge vectors away from the cell (unwrapped, as
+    the paper keeps them) give the same forces, and the caller's positions stay
+    unwrapped: after 30 steps each shifted atom sits at its unshifted twin plus
+    the same lattice vector."""
+    s, h = _strained()
+    rng = np.random.default_rng(3)
+    k = rng.integers(-3, 4, size=(s.n_atoms, 3)).astype(float)
+    shift = k @ h.T
+    announce("sheared cell unwrapped images")
+    a = md.Simulation(s, box_matrix=h)
+    a.step(30)
+    moved = inputs.System(**{**s.__dict__, "pos": s.pos + shift})
+    b = md.Simulation(moved, box_matrix=h)
+    b.step(30)
+    np.testing.assert_allclose(b.forces(), a.forces(), rtol=0, atol=1e-9)
+    np.testing.assert_allclose(b.positions() - shift, a.positions(), rtol=0, atol=1e-9)
+    assert b.energy().pe[0] == pytest.approx(a.energy().pe[0], rel=1e-12)
