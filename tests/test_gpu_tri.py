@@ -370,3 +370,22 @@ def test_sheared_cell_unwrapped_images(md):
     np.testing.assert_allclose(b.forces(), a.forces(), rtol=0, atol=1e-9)
     np.testing.assert_allclose(b.positions() - shift, a.positions(), rtol=0, atol=1e-9)
     assert b.energy().pe[0] == pytest.approx(a.energy().pe[0], rel=1e-12)
+
+
+def test_prt_compression_beyond_the_grid_is_reported(md):
+    """Under a pressure far above what the crystal holds the sheared cell
+    narrows past the room of its link-cell grid (three cells of 4.74 A across
+    its narrowest width for a 4.4 A list radius): MD_ERR_BOX, not a silently
+    incomplete list.  The list is rebuilt every step, so the strain between
+    builds stays under its own guard."""
+    s, h = _skewed()
+    announce("full-matrix barostat compression limit")
+    # W = 4e5: the oracle's cell reaches the limit near step 30 while the strain per step
+    # stays under the guard (with W = 4e4 the strain guard trips first, MD_ERR_SKIN)
+    sim = md.Simulation(s, box_matrix=h, rebuild_every=1, max_neighbours=160, pr_pressure_gpa=[200.0],
+                        pr_mass=[4.0e5])
+    with pytest.raises(md.MDError) as e:
+        for _ in range(50):
+            sim.step(2)
+            sim.energy()
+    assert e.value.code == md.MD_ERR_BOX
