@@ -636,6 +636,20 @@ def cpu_baseline(system, sim, pos, f_gpu, seconds):
                       oracle.Potential(small.potential), small.dt_fs, 100)
     small_rate = small.n_atoms * 100 / (time.perf_counter() - t)
     log(f"cpu baseline: bcc2000 x 100 steps at {small_rate:.3e} atom-steps/s")
+    # the same crystal on one thread (30 steps), and a 16,000-atom crystal (20^3 cells) for 3 steps
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    t = time.perf_counter()
+    oracle.run_verlet(small.pos, small.vel, small.species, small.box[0], small.periodic[0],
+                      oracle.Potential(small.potential), small.dt_fs, 30)
+    one_rate = small.n_atoms * 30 / (time.perf_counter() - t)
+    oracle.set_num_threads(threads)
+    big = inputs.bcc_fe(20, a=2.87, temperature=600.0, seed=2)
+    t = time.perf_counter()
+    oracle.run_verlet(big.pos, big.vel, big.species, big.box[0], big.periodic[0], oracle.Potential(big.potential),
+                      big.dt_fs, 3)
+    big_rate = big.n_atoms * 3 / (time.perf_counter() - t)
+    log(f"cpu baseline: bcc2000 on one thread {one_rate:.3e}, bcc16000 x 3 steps {big_rate:.3e} atom-steps/s")
     return {
         "value": s / dt,
         "unit": "atom-steps/s",
@@ -646,6 +660,9 @@ def cpu_baseline(system, sim, pos, f_gpu, seconds):
         "gpu_fp64_force_err_on_sample": err,
         "bcc2000_100_steps": {"value": small_rate, "unit": "atom-steps/s",
                               "note": "2000-atom bcc Fe, 100 velocity-Verlet steps, whole run, O(N^2) per step"},
+        "bcc2000_30_steps_one_thread": {"value": one_rate, "unit": "atom-steps/s", "cores": 1},
+        "bcc16000_3_steps": {"value": big_rate, "unit": "atom-steps/s",
+                             "note": "16,000-atom bcc Fe (20^3 cells), 3 velocity-Verlet steps, O(N^2) per step"},
     }
 
 

@@ -65,6 +65,8 @@ def _load():
     lib.or_boltzmann_ev.restype = d
     lib.or_pressure_unit_gpa.restype = d
     lib.or_num_threads.restype = i32
+    lib.or_set_num_threads.restype = None
+    lib.or_set_num_threads.argtypes = [i32]
     lib.or_knot_sum.restype = d
     lib.or_knot_sum.argtypes = [vp, vp, i32, d, vp]
     lib.or_pair.restype = d
@@ -164,6 +166,11 @@ def boltzmann_ev() -> float:
 
 def pressure_unit_gpa() -> float:
     return _load().or_pressure_unit_gpa()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later parallel loops."""
+    _load().or_set_num_threads(int(n))
 
 
 def num_threads() -> int:

@@ -1259,3 +1259,13 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the later parallel loops (timing at one thread and at all). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
