@@ -389,3 +389,27 @@ def test_prt_compression_beyond_the_grid_is_reported(md):
             sim.step(2)
             sim.energy()
     assert e.value.code == md.MD_ERR_BOX
+
+
+def test_prt_empty_replica_keeps_its_cell(md, orc):
+    """An empty sheared replica beside a crystal under the full-matrix
+    barostat: the empty cell stays put (nothing inside resists the load or
+    needs the cell to move) while the crystal follows the oracle."""
+    c, h = _moving()
+    n = c.n_atoms
+    h_empty = np.array([[24.0, 0.0, 6.0], [0.0, 24.0, 0.0], [0.0, 0.0, 24.0]])
+    s = inputs.System(
+        name="prt_empty", pos=c.pos, vel=c.vel, species=c.species, rigid=c.rigid,
+        atom_offset=np.array([0, 0, n], np.int64), box=np.array([[24.0] * 3, c.box[0]]), origin=np.zeros((2, 3)),
+        periodic=np.ones((2, 3), np.uint8), rigid_velocity=np.zeros((2, 3)), potential=c.potential, dt_fs=1.0,
+        skin=0.6, rebuild_every=10, steps=0, temperature=np.array([0.0, 300.0]), max_neighbours=80,
+    )
+    announce("full-matrix barostat empty replica")
+    sim = md.Simulation(s, box_matrix=np.array([h_empty, h]), pr_pressure_gpa=[3.0, 1.0], pr_mass=[W_BOX, W_BOX],
+                        pr_stress_gpa=np.array([_stress(3.0, 1.0, 0.0), _stress()]))
+    sim.step(40)
+    en = sim.energy()
+    assert np.array_equal(en.h[0], h_empty)
+    ref = _prt(orc, c, h, 40, 1.0, W_BOX, _stress())
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert np.max(np.abs(en.h[1] - ref.h[-1])) < 1e-10 * np.abs(ref.h[-1]).max()
