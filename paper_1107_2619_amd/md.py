@@ -143,7 +143,14 @@ def _c(a, dtype):
 
 
 class Context:
-    """Owns one ``md_ctx`` (host side only until ``bind``)."""
+    """Owns one ``md_ctx`` (host side only until ``bind``).
+
+    Per-replica options map onto ``md_config`` (include/md.h): the thermostat
+    (``nh_temperature``, ``nh_mass``), the integrator (``"verlet"`` or
+    ``"gear3"``), the barostat (``pr_pressure_gpa``, ``pr_mass``), sheared cells
+    (``box_matrix`` [R, 3, 3], edge vectors as columns; ``box`` is then ignored)
+    and the external stress of the full-matrix barostat (``pr_stress_gpa``
+    [R, 3, 3], GPa).  Scalars broadcast over the replicas."""
 
     def __init__(self, potential: dict, atom_offset, box, periodic, *, origin=None, rigid_velocity=None,
                  skin=0.3, dt_fs=1.0, rebuild_every=10, max_neighbours=64, precision="fp64",
@@ -246,7 +253,8 @@ class Energies:
 
 
 class Simulation:
-    """Device state (torch tensors) bound to a Context."""
+    """Device state (torch tensors) bound to a Context built from ``system``
+    (an ``inputs.System``); the keyword options are those of ``Context``."""
 
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
                  device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
