@@ -59,7 +59,7 @@ enum { MD_NBR_FULL = 0, MD_NBR_HALF_ATOMIC = 1 }; /* md_config.nbr_mode  */
 enum { MD_VERLET = 0, MD_GEAR3 = 1 };             /* md_config.integrator */
 
 #define MD_MAX_SPECIES 4
-#define MD_MAX_KNOTS 8
+#define MD_MAX_KNOTS 16
 
 /*
  * Cubic-knot potential (paper, "Available potentials": the generic ATVF form
@@ -72,6 +72,13 @@ enum { MD_VERLET = 0, MD_GEAR3 = 1 };             /* md_config.integrator */
  *   emb_c           [ns]  F_a(rho) = -emb_c[a] sqrt(rho); F = F' = 0 at rho = 0.
  *   mass_amu        [ns]  > 0.
  * All host pointers; md_create copies them.  The cutoff r_c is the largest knot.
+ * Evaluation (paper, "Parallel benchmarks": lookup table against direct
+ * evaluation, with a 15-spline iron potential): when every knot lies on a
+ * common grid the functions are tabulated exactly, one cubic per bin;
+ * otherwise the knot sums are evaluated term by term, which supports up to 8
+ * pair and 8 density knots, or, for one species, up to 16 pair and 4 density
+ * knots.  A potential that fits neither (off-grid knots beyond those counts)
+ * is rejected with MD_ERR_POTENTIAL.
  */
 typedef struct {
     int32_t n_species;    /* 1..MD_MAX_SPECIES */
@@ -273,7 +280,8 @@ enum {
     MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
     MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default when all
                                   knots lie on a common grid), 1 = term-by-term knot
-                                  sums (the paper's explicit evaluation)             */
+                                  sums (the paper's explicit evaluation; MD_ERR_ARG
+                                  for knot counts beyond those md_potential lists) */
     MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (full list only),
                                   1 = one thread per atom with global gathers
                                       (default)                                      */

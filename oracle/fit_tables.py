@@ -3,7 +3,7 @@
 The paper's own Fe and Cu coefficient files are not reproduced in it (only the
 form, "Available potentials", and a Ni/Al example file), so the workloads use
 synthetic tables of the same form.  This script fixes the knot positions and the
-density amplitudes and solves for the pair amplitudes a_1..a_6 by linear least
+density amplitudes and solves for the pair amplitudes a_k by linear least
 squares so that the ideal crystal has a chosen cohesive energy, zero pressure,
 bulk modulus, and the two cubic shear moduli as soft targets, plus a curvature penalty
 that keeps the amplitudes of order one.  Every observable is an energy computed by the oracle on a small
@@ -148,6 +148,27 @@ def main():
         "density": {"Fe<-Fe": {"R": fe_R, "A": fe_A}},
     }
 
+    # ---- Fe with 15 splines in all (the intermediate-complexity iron potential
+    # of the lookup-table benchmark, "Parallel benchmarks"): 13 pair knots on
+    # [2.3, 4.1] every 0.15 A and the two density knots above; the same targets.
+    fe15_knots = [round(float(v), 10) for v in np.linspace(2.3, 4.1, 13)]
+    fe15_amp, fe15_obs = fit_single(
+        "bcc", 2.87, fe15_knots, fe_A, fe_R, 55.845,
+        targets=[-4.28, 0.0, 170.0, 49.0, 116.0], soft_weight=0.05, smooth=0.2, r_lo=2.2,
+        core_r=1.8, core_val=5.0,
+    )
+    fe15 = {
+        "name": "fe15_fs",
+        "note": "synthetic bcc Fe Finnis-Sinclair table with 13 pair and 2 density knots (15 cubic "
+                "splines); fitted by oracle/fit_tables.py",
+        "fit": dict(zip(["E_atom_eV", "P_GPa", "B_GPa", "Cprime_GPa", "C44_GPa"], map(float, fe15_obs))),
+        "species": ["Fe"],
+        "mass": [55.845],
+        "emb_c": [1.0],
+        "pair": {"Fe-Fe": {"r": fe15_knots, "a": list(map(float, fe15_amp))}},
+        "density": {"Fe<-Fe": {"R": fe_R, "A": fe_A}},
+    }
+
     # ---- Cu, fcc: 6 pair knots on [2.0, 5.0], density knots {3.5, 4.3}.
     cu_knots = [round(float(v), 10) for v in np.linspace(2.0, 5.0, 6)]
     cu_A, cu_R = [0.3, 0.25], [3.5, 4.3]
@@ -192,7 +213,7 @@ def main():
             "C<-C": {"R": [2.5, 3.3], "A": [2.0, 0.6]},
         },
     }
-    for tab in (fe, cu, fec):
+    for tab in (fe, fe15, cu, fec):
         with open(os.path.join(OUT, tab["name"] + ".json"), "w") as fh:
             json.dump(tab, fh, indent=1)
         print(tab["name"], tab.get("fit"))

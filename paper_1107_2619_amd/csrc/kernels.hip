@@ -1604,12 +1604,12 @@ static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& 
     if (half_list) {
         if (k.table) density_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
         else if (k.npk == 6 && k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
-        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);  // reads only the density knots
         return;
     }
     if (k.table) density_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
     else if (k.npk == 6 && k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
-    else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+    else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);  // reads only the density knots
 }
 
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
@@ -1711,12 +1711,14 @@ static void force_dispatch(const Buffers& b, int p, int q, const KernelShape& k,
     if (half_list) {
         if (k.table) force_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
         else if (k.npk == 6 && k.ndk == 2) force_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-        else force_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if (k.npk <= 8 && k.ndk <= 8) force_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if constexpr (S) force_half_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
         return;
     }
     if (k.table) force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
     else if (k.npk == 6 && k.ndk == 2) force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-    else force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+    else if (k.npk <= 8 && k.ndk <= 8) force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+    else if constexpr (S) force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
 }
 
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

@@ -644,7 +644,8 @@ static void brick_force_dispatch(const Buffers& b, int p, int q, const KernelSha
 {
     if (k.table) brick_force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, precision, fl, dt_fs, st, s);
     else if (k.npk == 6 && k.ndk == 2) brick_force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
-    else brick_force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    else if (k.npk <= 8 && k.ndk <= 8) brick_force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    else if constexpr (S) brick_force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
 }
 
 void launch_brick_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

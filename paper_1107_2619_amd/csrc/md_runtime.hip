@@ -38,6 +38,7 @@ struct md_ctx {
     PotArgs args{};
     // local-polynomial tables (host copies, uploaded at md_bind)
     bool table_ok = false;
+    bool explicit_ok = false;  // a compiled knot-sum variant covers the knot counts
     int32_t evaluator = 0;  // 0 = tables when the knots share a grid, 1 = explicit knot sums
     std::vector<double> tf64, te64, td64;
     std::vector<float> tf32, te32, td32;
@@ -919,7 +920,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     // the run halts before it starts - the analogue of a non-zero ierror)
     const int ns = pot->n_species, npk = pot->n_pair_knots, ndk = pot->n_dens_knots;
     if (ns < 1 || ns > MD_MAX_SPECIES) return reject(MD_ERR_POTENTIAL, "n_species must be 1..4");
-    if (npk < 1 || npk > MD_MAX_KNOTS || ndk < 1 || ndk > MD_MAX_KNOTS) return reject(MD_ERR_POTENTIAL, "knot counts must be 1..8");
+    if (npk < 1 || npk > MD_MAX_KNOTS || ndk < 1 || ndk > MD_MAX_KNOTS) return reject(MD_ERR_POTENTIAL, "knot counts must be 1..16");
     if (pot->reserved != 0) return reject(MD_ERR_POTENTIAL, "reserved must be 0");
     if (!pot->pair_a || !pot->pair_r || !pot->dens_A || !pot->dens_R || !pot->emb_c || !pot->mass_amu)
         return reject(MD_ERR_POTENTIAL, "potential arrays are required");
@@ -970,6 +971,12 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     c->args.ns = ns;
     c->args.rc2 = P.rc2;
     c->table_ok = build_tables(c);
+    // term-by-term sums: <= 8 + 8 knots, or one species with <= 16 pair and <= 4
+    // density knots (a 13 + 2 iron potential of the paper's benchmark fits)
+    c->explicit_ok = (npk <= 8 && ndk <= 8) || (ns == 1 && npk <= 16 && ndk <= 4);
+    if (!c->table_ok && !c->explicit_ok)
+        return reject(MD_ERR_POTENTIAL, "more than 8 knots need the knots on a common tabulation grid "
+                                        "(or one species with at most 4 density knots)");
     if (c->single) {
         PotArgs& A = c->args;
         for (int k = 0; k < MD_MAX_KNOTS; ++k) {
@@ -1516,6 +1523,7 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
     case MD_OPT_EVALUATOR:
         if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "evaluator must be 0 (tables) or 1 (knot sums)");
         if (value == 0 && !c->table_ok) return fail(c, MD_ERR_ARG, "the knots share no tabulation grid");
+        if (value == 1 && !c->explicit_ok) return fail(c, MD_ERR_ARG, "no knot-sum variant for these knot counts");
         c->evaluator = (int32_t)value;
         return MD_OK;
     case MD_OPT_KERNEL:
@@ -1561,7 +1569,7 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     // FP64 may take either evaluator (both meet its tolerance); mixed keeps the
     // current one, since its explicit FP32 knot sums do not
     std::vector<int32_t> evals = {(c->table_ok && c->evaluator == 0) ? 0 : 1};
-    if (c->precision == MD_FP64 && c->table_ok) evals = {0, 1};
+    if (c->precision == MD_FP64 && c->table_ok && c->explicit_ok) evals = {0, 1};
     std::vector<Cand> cands;
     for (int32_t e : evals) {
         cands.push_back({1, 0, 0, 512, e});

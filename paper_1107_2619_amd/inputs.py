@@ -251,12 +251,13 @@ def _single(name, pos, vel, species, rigid, box, origin, periodic, vp, pot, dt, 
 def bcc_fe(n: int = 10, a: float = 2.87, temperature: float = 300.0, vacancy_frac: float = 0.0,
            seed: int = 1, pot_seed: int | None = None, dt_fs: float = 1.0, skin: float = 0.3,
            rebuild_every: int = 10, steps: int = 100, displace: float = 0.0,
-           name: str = "bcc_fe") -> System:
+           name: str = "bcc_fe", potential: str = "fe_fs") -> System:
     """bcc Fe cube of n^3 cells with optional random vacancies, Maxwell-Boltzmann
     velocities and an optional uniform random displacement of every atom
-    (the ``dsp`` input of the paper's parameter table)."""
+    (the ``dsp`` input of the paper's parameter table).  ``potential`` names the
+    base table (``fe_fs``: 6 + 2 knots, ``fe15_fs``: 13 + 2 knots)."""
     rng = np.random.default_rng(seed)
-    pot = perturbed_potential("fe_fs", seed if pot_seed is None else pot_seed)
+    pot = perturbed_potential(potential, seed if pot_seed is None else pot_seed)
     pos = bcc(n, n, n, a)
     if vacancy_frac > 0:
         nv = int(round(vacancy_frac * pos.shape[0]))
@@ -451,6 +452,12 @@ def workload(name: str, **kw) -> System:
     """Named workloads with the sizes the benchmark and the parity tests use."""
     if name == "bcc2000":  # 2000-atom bcc Fe, 300 K, 100 steps
         return bcc_fe(10, temperature=300.0, seed=1, steps=100, name=name, **kw)
+    if name == "bcc31250_fe15":  # 25^3 cells, 31,250 atoms, the 15-spline iron potential, 300 K
+        # this softer potential spreads a 10 fs displacement wider (sigma 0.023 A
+        # per axis at 300 K against ~0.015 A for fe_fs): a 0.4 A skin keeps the
+        # guard at 8.7 sigma
+        kw.setdefault("skin", 0.4)
+        return bcc_fe(25, temperature=300.0, seed=3, steps=100, name=name, potential="fe15_fs", **kw)
     if name == "bcc1m":  # 80^3 cells, 1% vacancies -> 1,013,760 atoms, 600 K
         # Over 10 fs at 600 K the per-axis displacement has sigma ~0.03 A; with
         # 10^6 atoms a 0.3 A skin (guard at 0.15 A = 5 sigma) is crossed by a

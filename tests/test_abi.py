@@ -90,6 +90,58 @@ def test_potential_validation(md):
         _ctx(md, potential=heavy)
 
 
+def _fe_knots(npk, ndk, step, ns=1):
+    """A one- or two-species table with npk pair and ndk density knots spaced
+    ``step`` apart below 4.1 A (amplitudes of no physical meaning)."""
+    pr = 4.1 - step * np.arange(npk)[::-1]
+    dr = 4.1 - step * np.arange(ndk)[::-1]
+    return {
+        "pair_a": np.tile(np.linspace(0.5, -0.1, npk), (ns, ns, 1)),
+        "pair_r": np.tile(pr, (ns, ns, 1)),
+        "dens_A": np.tile(np.linspace(1.0, 2.0, ndk), (ns, ns, 1)),
+        "dens_R": np.tile(dr, (ns, ns, 1)),
+        "emb_c": np.ones(ns),
+        "mass": np.full(ns, 55.845),
+    }
+
+
+def test_knot_limits_and_evaluators(md):
+    """Up to 16 knots per function (the paper's benchmark iron potential is a
+    sum of 15 cubic splines, "Parallel benchmarks"): tables need every knot on
+    a common grid; the term-by-term sums cover 8 + 8 knots, or 16 pair and 4
+    density knots for one species.  A potential neither covers is refused."""
+    fe15 = inputs.perturbed_potential("fe15_fs", 3)
+    assert fe15["pair_a"].shape[2] == 13 and fe15["dens_A"].shape[2] == 2
+    c = _ctx(md, potential=fe15)
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+    c.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 1
+    # 16 on-grid pair knots and 8 density knots: tables only
+    c = _ctx(md, potential=_fe_knots(16, 8, 0.1))
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+    with pytest.raises(md.MDError) as e:
+        c.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert e.value.code == md.MD_ERR_ARG
+    # off-grid knots (step 0.1234 A): 16 + 4 knot sums, no tables
+    c = _ctx(md, potential=_fe_knots(16, 4, 0.1234))
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 1
+    with pytest.raises(md.MDError) as e:
+        c.set_option(md.MD_OPT_EVALUATOR, 0)
+    assert e.value.code == md.MD_ERR_ARG
+    # off-grid with 5 density knots, or two species with 9 pair knots: refused
+    for pot in (_fe_knots(16, 5, 0.1234), _fe_knots(9, 2, 0.1234, ns=2)):
+        with pytest.raises(md.MDError) as e:
+            _ctx(md, potential=pot)
+        assert e.value.code == md.MD_ERR_POTENTIAL
+    # on the grid the two-species 9-knot table is accepted (tables)
+    c = _ctx(md, potential=_fe_knots(9, 2, 0.1, ns=2))
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+    # 17 knots exceed the limit
+    with pytest.raises(md.MDError) as e:
+        _ctx(md, potential=_fe_knots(17, 2, 0.1))
+    assert e.value.code == md.MD_ERR_POTENTIAL and "1..16" in str(e.value)
+
+
 def test_atom_offset_validation(md):
     with pytest.raises(md.MDError):
         _ctx(md, atom_offset=[1, 2000])

@@ -32,7 +32,11 @@ def _oracle_snapshot(orc, s, r=0):
                       rigid=sub.rigid if sub.rigid.any() else None)
 
 
-def _check_snapshot(md, orc, s, precision, options=None, check_energy=True, **kw):
+def _check_snapshot(md, orc, s, precision, options=None, check_energy=True, virial_rel=None, force_tol=None,
+                    **kw):
+    """virial_rel: bound on the virial error relative to its largest diagonal
+    term (default ten times the energy tolerance); force_tol: bound on the
+    force error (default the precision's tolerance)."""
     announce(f"snapshot {s.name} N={s.n_atoms} R={s.n_replicas} {precision} {kw} {options}")
     sim = md.Simulation(s, precision=precision, **kw)
     for opt, val in (options or {}).items():
@@ -48,13 +52,15 @@ def _check_snapshot(md, orc, s, precision, options=None, check_energy=True, **kw
             assert en.pe[r] == 0.0
             continue
         ref = _oracle_snapshot(orc, s, r)
-        assert force_error(f[a:b], ref.f) <= tol["force"], (r, force_error(f[a:b], ref.f))
+        ftol = tol["force"] if force_tol is None else force_tol
+        assert force_error(f[a:b], ref.f) <= ftol, (r, force_error(f[a:b], ref.f))
         if not check_energy:
             continue
         assert energy_error(e[a:b], ref.e_atom) <= tol["energy"], (r, energy_error(e[a:b], ref.e_atom))
         assert abs(en.pe[r] - ref.pe) <= tol["energy"] * abs(ref.pe)
         wscale = np.abs(ref.virial[:3]).max()
-        assert np.max(np.abs(en.virial[r] - ref.virial)) <= 10 * tol["energy"] * wscale + 1e-9 * (precision == "mixed")
+        vrel = 10 * tol["energy"] if virial_rel is None else virial_rel
+        assert np.max(np.abs(en.virial[r] - ref.virial)) <= vrel * wscale + 1e-9 * (precision == "mixed")
     return sim
 
 
