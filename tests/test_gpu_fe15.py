@@ -92,3 +92,21 @@ def test_fe15_autotune_then_parity(md, orc, precision):
     sim.eam_forces(want_energy=True)
     ref = _oracle_snapshot(orc, s)
     assert force_error(sim.forces(), ref.f) <= TOL[precision]["force"]
+
+
+@pytest.mark.parametrize("evaluator", [0, 1])
+def test_fe15_trajectory_100_steps(md, orc, evaluator):
+    """100 FP64 velocity-Verlet steps with list rebuilds every 10 steps, tables
+    and knot sums, against the oracle's brute-force trajectory (positions within
+    1e-8 A, as for the 6 + 2 knot potential)."""
+    s = inputs.bcc_fe(10, temperature=300.0, seed=35, potential="fe15_fs", pot_seed=3, skin=0.4,
+                      name="bcc_fe15_nve")
+    sim = md.Simulation(s, precision="fp64")
+    sim.set_option(md.MD_OPT_EVALUATOR, evaluator)
+    sim.step(100)
+    en = sim.energy()
+    ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), s.dt_fs, 100)
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert force_error(sim.forces(), ref.f) < 1e-8
+    assert abs(en.pe[0] - ref.pe[-1]) < 1e-10 * abs(ref.pe[-1])
+    assert en.step == 100
