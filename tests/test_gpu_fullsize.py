@@ -59,6 +59,31 @@ def test_bcc1m_sampled_parity(md, orc, precision, config):
     _sampled_check(orc, sim, s, precision, 64, seed=1)
 
 
+@pytest.mark.parametrize("precision,evaluator,kernel", [("fp64", 1, "brick444"), ("fp64", 0, "global"),
+                                                       ("mixed", 0, "global")])
+def test_bcc1m_fe15_sampled_parity(md, orc, precision, evaluator, kernel):
+    """The bcc1m crystal with the 15-spline iron potential, as the table
+    comparison of the benchmark runs it (0.5 A skin, capacity 64), after 30
+    graph-replayed steps: tables and the 16 + 4 knot sums."""
+    import copy
+
+    s = copy.copy(inputs.workload("bcc1m"))
+    s.potential = inputs.perturbed_potential("fe15_fs", 3)
+    s.skin, s.max_neighbours, s.name = 0.5, 64, "bcc1m_fe15"
+    announce(f"bcc1m_fe15 sampled {precision} evaluator {evaluator} {kernel}")
+    sim = md.Simulation(s, precision=precision)
+    sim.set_option(md.MD_OPT_EVALUATOR, evaluator)
+    if kernel == "global":
+        sim.set_option(md.MD_OPT_KERNEL, 1)
+    else:
+        for opt, val in ((md.MD_OPT_KERNEL, 0), (md.MD_OPT_BRICK_DIMS, 444), (md.MD_OPT_BRICK_BLOCK, 1024)):
+            sim.set_option(opt, val)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(30)
+    sim.energy()
+    _sampled_check(orc, sim, s, precision, 64, seed=5)
+
+
 @pytest.mark.parametrize("precision,barostat", [("mixed", False), ("fp64", False), ("mixed", True)])
 def test_bcc1m_sheared_cell_sampled_parity(md, orc, precision, barostat):
     """The 1,013,760-atom crystal in the cell [a, b, c + a] in the benchmark's
