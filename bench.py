@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {"fetch_kib": 115012.0, "write_kib": 71280.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256_16": "3748c06bc7349887", "workload": "bcc1m", "precision": "mixed"}
+FORCE_TRAFFIC = {"fetch_kib": 114999.0, "write_kib": 71280.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources_sha256_16": "acc9750b62671fb7", "workload": "bcc1m", "precision": "mixed"}
 # VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
 # so this is also the lane-operations per atom of one launch.

@@ -1603,13 +1603,13 @@ static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& 
 {
     if (half_list) {
         if (k.table) density_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
-        else if (k.npk == 6 && k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
-        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);  // reads only the density knots
+        else if (k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
+        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
         return;
     }
     if (k.table) density_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
-    else if (k.npk == 6 && k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);
-    else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);  // reads only the density knots
+    else if (k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
+    else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
 }
 
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
