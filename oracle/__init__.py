@@ -83,8 +83,6 @@ def _load():
     lib.or_energy.argtypes = [i64, vp, vp, vp, vp, vp, vp, P]
     lib.or_forces_sampled.restype = i32
     lib.or_forces_sampled.argtypes = [i64, vp, vp, vp, vp, vp, vp, P, i64, vp, vp, vp, vp]
-    lib.or_kinetic.restype = d
-    lib.or_kinetic.argtypes = [i64, vp, vp, vp, vp, vp, P]
     lib.or_run_verlet.restype = i32
     lib.or_run_verlet.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P, d, vp, i64, vp, vp, vp, vp]
     lib.or_run_pr.restype = i32
@@ -275,15 +273,6 @@ def forces_sampled(pos, species, box, periodic, pot: Potential, sample):
     if rc:
         raise ValueError(f"oracle: sampled evaluation failed ({rc})")
     return ForceResult(f, e, rho, np.full(6, np.nan), float("nan"))
-
-
-def kinetic(vel, species, pot: Potential, rigid=None) -> float:
-    """Kinetic energy (eV) of the mobile atoms; velocities in A/fs."""
-    vx, vy, vz = _split(vel)
-    sp = _u8(species)
-    rg = None if rigid is None else _u8(rigid)
-    return _load().or_kinetic(vx.shape[0], vx.ctypes.data, vy.ctypes.data, vz.ctypes.data,
-                              sp.ctypes.data, _ptr(rg), pot.ref)
 
 
 @dataclass

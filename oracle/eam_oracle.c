@@ -397,21 +397,6 @@ int or_forces_sampled(int64_t n, const double *x, const double *y, const double 
     return sampled_geom(n, x, y, z, species, &g, p, rc, m, sample, f, e_atom, rho_out);
 }
 
-/* Kinetic energy (eV) of the mobile atoms, velocities in Angstrom/fs:
- * KE = sum 1/2 m v^2 with v converted to Angstrom per time unit. */
-double or_kinetic(int64_t n, const double *vx, const double *vy, const double *vz,
-                  const uint8_t *species, const uint8_t *rigid, const or_potential *p)
-{
-    const double t0 = or_time_unit_fs();
-    double ke = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (rigid && rigid[i]) continue;
-        double v2 = (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) * t0 * t0;
-        ke += 0.5 * p->mass[species[i]] * v2;
-    }
-    return ke;
-}
-
 /* Sum of the forces on the rigid atoms dotted with their prescribed velocity
  * (Angstrom per time unit): the rate at which the system does work on the
  * moving rigid block, whose negative is the power the block delivers. */

@@ -65,7 +65,6 @@ int main(void)
     rc |= or_forces(N, x, y, z, sp, rigid, box, per, &pot, f, e, rho, vir, &pe);
     acc += pe + sum(f, 3 * N) + sum(vir, 6);
     acc += or_energy(N, x, y, z, sp, box, slab, &pot);
-    acc += or_kinetic(N, vx, vy, vz, sp, rigid, &pot);
     {
         const int64_t sample[3] = {0, 17, N - 1};
         double fs[9], es[3], rs[3];

@@ -101,6 +101,60 @@ def test_knot_sum_c2_at_knots_and_derivative(orc):
         assert orc.knot_sum(a, rk, r)[1] == pytest.approx(rich, rel=1e-9, abs=1e-12)
 
 
+def test_knot_sum_printed_ni_al_values(orc):
+    """The printed Ni/Al pair coefficients ("Available potentials") evaluated at
+    fixed radii, values worked out by hand from the printed numbers (stored in
+    the fixture with their derivation)."""
+    g = _golden_ni_al()
+    for r, (v_ref, d_ref) in g["values"].items():
+        v, d = orc.knot_sum(g["pair_a"], g["pair_r"], float(r))
+        assert v == pytest.approx(v_ref, abs=2e-12), r
+        assert d == pytest.approx(d_ref, abs=2e-12), r
+
+
+# ----------------------------------------------------------------------------- embedding
+def _with_emb_c(arr, c):
+    out = dict(arr)
+    out["emb_c"] = np.asarray(c, np.float64)
+    return out
+
+
+def test_embedding_constant_is_per_species(orc, fec_pot):
+    """F_a(rho) = -c_a sqrt(rho): the constant belongs to the site atom's species
+    ("Theoretical background", the Finnis-Sinclair square root)."""
+    c = [1.0, 0.7]
+    pot = orc.Potential(_with_emb_c(inputs.perturbed_potential("fec_eam", 1), c))
+    for a in (0, 1):
+        for rho in (0.25, 1.0, 3.7):
+            F, dF = orc.embed(pot, a, rho)
+            assert F == pytest.approx(-c[a] * math.sqrt(rho), rel=1e-15)
+            assert dF == pytest.approx(-c[a] / (2.0 * math.sqrt(rho)), rel=1e-15)
+
+
+def test_two_species_dimer_with_distinct_embedding(orc):
+    """A 0-1 dimer in open space: E = phi_01(r) - c_0 sqrt(rho_01(r)) - c_1 sqrt(rho_10(r)),
+    the embedding of each atom taken with its own constant; the bond force is the
+    derivative of that sum, which a centred difference of the closed form gives."""
+    c = [1.0, 0.7]
+    pot = orc.Potential(_with_emb_c(inputs.perturbed_potential("fec_eam", 1), c))
+    big = [100.0] * 3
+    for r in (1.9, 2.3, 2.8):
+        def closed(x):
+            return (orc.pair(pot, 0, 1, x)[0] - c[0] * math.sqrt(orc.density(pot, 0, 1, x)[0])
+                    - c[1] * math.sqrt(orc.density(pot, 1, 0, x)[0]))
+        pos = np.array([[10.0, 10.0, 10.0], [10.0 + r, 10.0, 10.0]])
+        res = orc.forces(pos, np.array([0, 1], np.uint8), big, [0, 0, 0], pot)
+        assert res.pe == pytest.approx(closed(r), rel=1e-14)
+        h = 1e-4
+        d1 = (closed(r + h) - closed(r - h)) / (2 * h)
+        d2 = (closed(r + h / 2) - closed(r - h / 2)) / h
+        g = (4 * d2 - d1) / 3  # dE/dr; the force on atom 1 is -g along +x
+        assert res.f[1, 0] == pytest.approx(-g, rel=1e-8)
+        assert res.f[0, 0] == pytest.approx(g, rel=1e-8)
+        assert res.e_atom[0] == pytest.approx(0.5 * orc.pair(pot, 0, 1, r)[0]
+                                              - c[0] * math.sqrt(orc.density(pot, 0, 1, r)[0]), rel=1e-14)
+
+
 # ----------------------------------------------------------------------------- lattices
 def _bcc_shells(a):
     return [(a * math.sqrt(3) / 2, 8), (a, 6), (a * math.sqrt(2), 12), (a * math.sqrt(11) / 2, 24),
@@ -140,11 +194,17 @@ def test_fcc_perfect_lattice_closed_form(orc):
     assert np.max(np.abs(res.f)) <= 1e-12
 
 
-def test_b2_two_species_closed_form(orc, fec_pot):
+@pytest.mark.parametrize("emb_c", [None, (1.0, 0.7)])
+def test_b2_two_species_closed_form(orc, fec_pot, emb_c):
     """Ordered CsCl-type crystal of species 0 at cube corners and species 1 at
     centres: the first shell of each atom is the other species, the next two
     its own.  Pins the [site, neighbour] index order of the density and the
-    per-species embedding (an asymmetric EAM density, "Theoretical background")."""
+    per-species embedding (an asymmetric EAM density, "Theoretical background"):
+    with distinct constants c_a the embedding term is written out as
+    -c_a sqrt(rho) from the potential's own numbers."""
+    if emb_c is not None:
+        fec_pot = orc.Potential(_with_emb_c(inputs.perturbed_potential("fec_eam", 1), emb_c))
+    c = fec_pot.emb_c
     a, n = 2.87, 4
     corners = inputs.bcc(n, n, n, a)[0::2]
     centres = inputs.bcc(n, n, n, a)[1::2]
@@ -156,7 +216,7 @@ def test_b2_two_species_closed_form(orc, fec_pot):
         rho = 8 * orc.density(fec_pot, s, o, d1)[0] + 6 * orc.density(fec_pot, s, s, d2)[0] + \
             12 * orc.density(fec_pot, s, s, d3)[0]
         e = 0.5 * (8 * orc.pair(fec_pot, s, o, d1)[0] + 6 * orc.pair(fec_pot, s, s, d2)[0] +
-                   12 * orc.pair(fec_pot, s, s, d3)[0]) + orc.embed(fec_pot, s, rho)[0]
+                   12 * orc.pair(fec_pot, s, s, d3)[0]) - c[s] * math.sqrt(rho)
         assert np.allclose(res.rho[sp == s], rho, rtol=1e-13)
         assert np.allclose(res.e_atom[sp == s], e, rtol=1e-13)
     # the two densities really differ, so a transposed index would be caught
