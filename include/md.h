@@ -73,12 +73,15 @@ enum { MD_VERLET = 0, MD_GEAR3 = 1 };             /* md_config.integrator */
  *   mass_amu        [ns]  > 0.
  * All host pointers; md_create copies them.  The cutoff r_c is the largest knot.
  * Evaluation (paper, "Parallel benchmarks": lookup table against direct
- * evaluation, with a 15-spline iron potential): when every knot lies on a
- * common grid the functions are tabulated exactly, one cubic per bin;
- * otherwise the knot sums are evaluated term by term, which supports up to 8
- * pair and 8 density knots, or, for one species, up to 16 pair and 4 density
- * knots.  A potential that fits neither (off-grid knots beyond those counts)
- * is rejected with MD_ERR_POTENTIAL.
+ * evaluation, with a 15-spline iron potential): by default the functions are
+ * tabulated exactly on uniform bins, one cubic per bin in the bin-local
+ * coordinate, plus, where a knot falls strictly inside a bin, that knot's own
+ * term (any knot placement; two knots of one function may not share a bin of
+ * the finest width r_c / 4096).  In FP64 the knot sums can also be evaluated
+ * term by term (MD_OPT_EVALUATOR = 1), for up to 8 pair and 8 density knots,
+ * or, for one species, up to 16 pair and 4 density knots.  MD_ERR_POTENTIAL
+ * for a potential that fits no evaluator of the chosen precision (mixed
+ * precision always evaluates through the tables).
  */
 typedef struct {
     int32_t n_species;    /* 1..MD_MAX_SPECIES */
@@ -92,8 +95,8 @@ typedef struct {
 } md_potential;
 
 /*
- * Run configuration: R >= 1 independent replicas ("statistics must be gathered
- * over a number of equivalent runs", Introduction), each an orthorhombic box
+ * Run configuration: R >= 1 independent replicas (the paper's Introduction
+ * averages results over many equivalent runs), each an orthorhombic box
  * with per-axis periodic or free boundaries ("Boundary conditions"), or a
  * periodic cell given by its box matrix.  Replica
  * r owns atoms [atom_offset[r], atom_offset[r+1]) of the state arrays.
@@ -278,10 +281,12 @@ enum {
     MD_OPT_MAX_COUNT = 3,      /* read only: largest list length seen (at md_energy)  */
     MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind                */
     MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
-    MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default when all
-                                  knots lie on a common grid), 1 = term-by-term knot
-                                  sums (the paper's explicit evaluation; MD_ERR_ARG
-                                  for knot counts beyond those md_potential lists) */
+    MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default), 1 =
+                                  term-by-term knot sums (the paper's explicit
+                                  evaluation; FP64 only: MD_ERR_ARG in mixed
+                                  precision, whose FP32 knot sums miss its energy
+                                  tolerance, and for knot counts beyond those
+                                  md_potential lists) */
     MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (full list only),
                                   1 = one thread per atom with global gathers
                                       (default)                                      */

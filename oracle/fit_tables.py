@@ -80,14 +80,16 @@ def observables(tab_arrays, kind, a, delta=0.004):
 
 
 def fit_single(kind, a, knots, dens_A, dens_R, mass, targets, soft_weight, smooth, r_lo,
-               core_r, core_val):
+               core_r, core_val, ridge=0.0):
     """Pair amplitudes of a one-species table.
 
     Cohesive energy, zero pressure, the bulk modulus and a short-range
     repulsion phi(core_r) = core_val are imposed exactly; the two shear moduli
     are soft targets (weight ``soft_weight``) and the curvature of phi on
     [r_lo, r_max] is penalised (weight ``smooth``), which keeps the amplitudes
-    of order one.  An equality-constrained least-squares problem, solved
+    of order one; ``ridge`` adds a penalty on the squared amplitudes, for knot
+    sets dense enough that the curvature penalty alone leaves large terms of
+    opposite sign.  An equality-constrained least-squares problem, solved
     through its KKT system.  The repulsive core matters for hot runs: without
     it the embedding term makes two atoms pushed closer than ~1.9 A attract.
     """
@@ -108,8 +110,8 @@ def fit_single(kind, a, knots, dens_A, dens_R, mass, targets, soft_weight, smoot
     rhs = np.asarray(targets) - base
     grid = np.linspace(r_lo, knots[-1], 80)
     curv = np.array([[6.0 * max(rk - r, 0.0) for rk in knots] for r in grid]) * np.sqrt(smooth)
-    Q = np.vstack([curv, M[3:] * soft_weight])
-    q = np.concatenate([np.zeros(len(grid)), rhs[3:] * soft_weight])
+    Q = np.vstack([curv, M[3:] * soft_weight, np.eye(npk) * np.sqrt(ridge)])
+    q = np.concatenate([np.zeros(len(grid)), rhs[3:] * soft_weight, np.zeros(npk)])
     core = np.array([[max(rk - core_r, 0.0) ** 3 for rk in knots]])
     E, e = np.vstack([M[:3], core]), np.concatenate([rhs[:3], [core_val]])
     kkt = np.block([[Q.T @ Q, E.T], [E, np.zeros((4, 4))]])
@@ -151,11 +153,15 @@ def main():
     # ---- Fe with 15 splines in all (the intermediate-complexity iron potential
     # of the lookup-table benchmark, "Parallel benchmarks"): 13 pair knots on
     # [2.3, 4.1] every 0.15 A and the two density knots above; the same targets.
+    # Thirteen knots 0.15 A apart admit large terms of opposite sign (amplitudes
+    # up to 45 with the curvature penalty alone, and a first-shell pair force
+    # 1/100 of its pair-potential part); the amplitude penalty keeps them below
+    # 7 at the same elastic constants.
     fe15_knots = [round(float(v), 10) for v in np.linspace(2.3, 4.1, 13)]
     fe15_amp, fe15_obs = fit_single(
         "bcc", 2.87, fe15_knots, fe_A, fe_R, 55.845,
         targets=[-4.28, 0.0, 170.0, 49.0, 116.0], soft_weight=0.05, smooth=0.2, r_lo=2.2,
-        core_r=1.8, core_val=5.0,
+        core_r=1.8, core_val=5.0, ridge=1.0,
     )
     fe15 = {
         "name": "fe15_fs",

@@ -314,7 +314,7 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
 }
 
 // Verlet list from the link cells (paper, "The Neighbourlist calculation":
-// a loop over link cells and their adjacent cells).  One wavefront per link
+// each cell's atoms are tested against the atoms of the 27 cells around it).  One wavefront per link
 // cell.  The up to 27 adjacent cells (fewer on free faces; on a periodic axis
 // with under three cells each distinct cell once) become one candidate
 // sequence: cell by cell (x fastest), atoms in slot order.  The wavefront
@@ -636,9 +636,9 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const R* tab = tables<R>(b).dens;
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tab, P.nbt * 4);
+        lds_fill(s, tab, P.nbt * value_stride(EV));
         __syncthreads();
         tab = s;
     }
@@ -709,13 +709,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
     const Tabs<R> T = tables<R>(b);
     const R* tf = T.force;
     const R* te = T.energy;
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tf, P.nbt * kForceStride);
-        if (ENERGY == 1) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        lds_fill(s, tf, P.nbt * force_stride(EV));
+        if (ENERGY == 1) lds_fill(s + P.nbt * force_stride(EV), te, P.nbt * value_stride(EV));
         __syncthreads();
         tf = s;
-        te = s + P.nbt * kForceStride;
+        te = s + P.nbt * force_stride(EV);
     }
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -1373,9 +1373,9 @@ __global__ __launch_bounds__(kBlock) void k_density_half(Buffers b, int p, int q
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const R* tab = tables<R>(b).dens;
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tab, P.nbt * 4);
+        lds_fill(s, tab, P.nbt * value_stride(EV));
         __syncthreads();
         tab = s;
     }
@@ -1435,13 +1435,13 @@ __global__ __launch_bounds__(kBlock) void k_force_half(Buffers b, int p, int q, 
     const Tabs<R> T = tables<R>(b);
     const R* tf = T.force;
     const R* te = T.energy;
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tf, P.nbt * kForceStride);
-        if (ENERGY == 1) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        lds_fill(s, tf, P.nbt * force_stride(EV));
+        if (ENERGY == 1) lds_fill(s + P.nbt * force_stride(EV), te, P.nbt * value_stride(EV));
         __syncthreads();
         tf = s;
-        te = s + P.nbt * kForceStride;
+        te = s + P.nbt * force_stride(EV);
     }
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -1576,7 +1576,7 @@ template <typename R, bool S, int NP, int ND, int EV>
 static void density_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                             hipStream_t s)
 {
-    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * 4 * sizeof(R) : 0;
+    const size_t lds = (EV != EV_KNOTS && S) ? (size_t)P.nbt * value_stride(EV) * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
     if (k.compact == 2)
         hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
@@ -1590,7 +1590,7 @@ template <typename R, bool S, int NP, int ND, int EV>
 static void density_half_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                                  hipStream_t s)
 {
-    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * 4 * sizeof(R) : 0;
+    const size_t lds = (EV != EV_KNOTS && S) ? (size_t)P.nbt * value_stride(EV) * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
     hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.rhalf, 0.0, k.n_slots);
     hipLaunchKernelGGL((k_density_half<R, S, NP, ND, EV>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
@@ -1601,15 +1601,23 @@ template <typename R, bool S>
 static void density_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int half_list,
                              int energy, hipStream_t s)
 {
+    // the term-by-term knot sums are FP64 only (the runtime refuses them in mixed precision)
+    constexpr bool knots = sizeof(R) == 8;
     if (half_list) {
-        if (k.table) density_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
-        else if (k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
-        else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+        if (k.table == 2) density_half_variant<R, S, 8, 8, EV_SPLIT>(b, p, q, k, P, energy, s);
+        else if (k.table || !knots) density_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
+        else if constexpr (knots) {
+            if (k.ndk == 2) density_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
+            else density_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+        }
         return;
     }
-    if (k.table) density_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
-    else if (k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
-    else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+    if (k.table == 2) density_variant<R, S, 8, 8, EV_SPLIT>(b, p, q, k, P, energy, s);
+    else if (k.table || !knots) density_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, energy, s);
+    else if constexpr (knots) {
+        if (k.ndk == 2) density_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, energy, s);  // density knots only
+        else density_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, energy, s);
+    }
 }
 
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
@@ -1629,7 +1637,8 @@ template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, boo
 static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                          const md_state& st, hipStream_t s)
 {
-    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (E == 1 ? 4 : 0)) * sizeof(R) : 0;
+    const size_t lds =
+        (EV != EV_KNOTS && S) ? (size_t)P.nbt * (force_stride(EV) + (E == 1 ? value_stride(EV) : 0)) * sizeof(R) : 0;
     const dim3 grid(blocks_for(k.n_slots));
     if (k.compact == 2)
         hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
@@ -1684,7 +1693,8 @@ static void force_half_variant(const Buffers& b, int p, int q, const KernelShape
     const dim3 grid(blocks_for(k.n_slots));
     for (int a = 0; a < 3; ++a) hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.fhalf[a], 0.0, k.n_slots);
     if (fl.energy) hipLaunchKernelGGL(k_fill_f64, grid, dim3(kBlock), 0, s, b.ehalf, 0.0, k.n_slots);
-    const size_t lds = (EV == EV_TABLE && S) ? (size_t)P.nbt * (kForceStride + (fl.energy ? 4 : 0)) * sizeof(R) : 0;
+    const size_t lds =
+        (EV != EV_KNOTS && S) ? (size_t)P.nbt * (force_stride(EV) + (fl.energy ? value_stride(EV) : 0)) * sizeof(R) : 0;
     if (fl.energy)
         hipLaunchKernelGGL((k_force_half<R, S, NP, ND, EV, true>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P);
     else
@@ -1708,17 +1718,24 @@ template <typename R, bool S>
 static void force_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int half_list,
                            ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s)
 {
+    constexpr bool knots = sizeof(R) == 8;  // knot sums: FP64 only
     if (half_list) {
-        if (k.table) force_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
-        else if (k.npk == 6 && k.ndk == 2) force_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-        else if (k.npk <= 8 && k.ndk <= 8) force_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-        else if constexpr (S) force_half_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        if (k.table == 2) force_half_variant<R, S, 8, 8, EV_SPLIT>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if (k.table || !knots) force_half_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if constexpr (knots) {
+            if (k.npk == 6 && k.ndk == 2) force_half_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+            else if (k.npk <= 8 && k.ndk <= 8) force_half_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+            else if constexpr (S) force_half_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        }
         return;
     }
-    if (k.table) force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
-    else if (k.npk == 6 && k.ndk == 2) force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-    else if (k.npk <= 8 && k.ndk <= 8) force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
-    else if constexpr (S) force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+    if (k.table == 2) force_variant<R, S, 8, 8, EV_SPLIT>(b, p, q, k, P, fl, dt_fs, st, s);
+    else if (k.table || !knots) force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, fl, dt_fs, st, s);
+    else if constexpr (knots) {
+        if (k.npk == 6 && k.ndk == 2) force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if (k.npk <= 8 && k.ndk <= 8) force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+        else if constexpr (S) force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, fl, dt_fs, st, s);
+    }
 }
 
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

@@ -217,8 +217,8 @@ __device__ __forceinline__ uint8_t halo_type(const Buffers& b, const Halo& M, in
 
 // ---------------------------------------------------------------------------
 // List build: every staged atom in the 27 halo cells around the atom's cell
-// with r < r_c + skin (paper, "The Neighbourlist calculation": a loop over the
-// link cell and its adjacent cells).  Entries are staging (LDS) indices,
+// with r < r_c + skin (paper, "The Neighbourlist calculation": the cell's
+// atoms against those of the cells around it).  Entries are staging (LDS) indices,
 // uint16, one row of `rowlen` (a multiple of 8) per atom, written 8 at a time.
 __global__ __launch_bounds__(1024) void k_brick_list(Buffers b, int p, int64_t n_slots, int32_t cap, double rlist2,
                                                      int halo_cap, int rowlen)
@@ -310,11 +310,11 @@ __global__ __launch_bounds__(1024) void k_brick_density(Buffers b, int p, int q,
     unsigned char* tail = smem + halo_bytes() + (size_t)halo_cap * sizeof(double4);
     const R* tab = tables<R>(b).dens;
     uint8_t* ltype = reinterpret_cast<uint8_t*>(tail);
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(tail);
-        lds_fill(s, tab, P.nbt * 4);
+        lds_fill(s, tab, P.nbt * value_stride(EV));
         tab = s;
-    } else if (EV == EV_TABLE) {
+    } else if (EV != EV_KNOTS) {
         ltype = reinterpret_cast<uint8_t*>(tail);
     }
     const int brick = brick_of_block();
@@ -398,13 +398,14 @@ __global__ __launch_bounds__(1024) void k_brick_force(Buffers b, int p, int q, i
     const R* tf = T.force;
     const R* te = T.energy;
     uint8_t* ltype = reinterpret_cast<uint8_t*>(tail);
-    if (EV == EV_TABLE && SINGLE) {
+    if (EV != EV_KNOTS && SINGLE) {
         R* s = reinterpret_cast<R*>(tail);
-        lds_fill(s, tf, P.nbt * kForceStride);
-        if (ENERGY) lds_fill(s + P.nbt * kForceStride, te, P.nbt * 4);
+        lds_fill(s, tf, P.nbt * force_stride(EV));
+        if (ENERGY) lds_fill(s + P.nbt * force_stride(EV), te, P.nbt * value_stride(EV));
         tf = s;
-        te = s + P.nbt * kForceStride;
-        ltype = reinterpret_cast<uint8_t*>(tail + (size_t)P.nbt * (kForceStride + (ENERGY ? 4 : 0)) * sizeof(R));
+        te = s + P.nbt * force_stride(EV);
+        ltype = reinterpret_cast<uint8_t*>(
+            tail + (size_t)P.nbt * (force_stride(EV) + (ENERGY ? value_stride(EV) : 0)) * sizeof(R));
     }
     const bool need_type = !SINGLE || ENERGY;
     const int brick = brick_of_block();
@@ -548,8 +549,9 @@ size_t brick_lds_bytes(const KernelShape& k, const PotArgs& P, int precision, in
     // type byte per atom after the tables
     const size_t rsz = precision == MD_MIXED ? 4 : 8;
     size_t bytes = halo_bytes() + (size_t)k.halo_cap * sizeof(double4);
-    if (pass == 1 && k.table && P.ns == 1) bytes += (size_t)P.nbt * 4 * rsz;
-    if (pass == 2 && k.table && P.ns == 1) bytes += (size_t)P.nbt * (kForceStride + (energy ? 4 : 0)) * rsz;
+    if (pass == 1 && k.table && P.ns == 1) bytes += (size_t)P.nbt * value_stride(k.table) * rsz;
+    if (pass == 2 && k.table && P.ns == 1)
+        bytes += (size_t)P.nbt * (force_stride(k.table) + (energy ? value_stride(k.table) : 0)) * rsz;
     if (pass > 0) bytes += (size_t)k.halo_cap;
     return bytes;
 }
@@ -584,9 +586,13 @@ template <typename R, bool S>
 static void brick_density_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P,
                                    int precision, int energy, hipStream_t s)
 {
-    if (k.table) brick_density_lanes<R, S, 8, EV_TABLE>(b, p, q, k, P, precision, energy, s);
-    else if (k.ndk == 2) brick_density_lanes<R, S, 2, EV_KNOTS>(b, p, q, k, P, precision, energy, s);
-    else brick_density_lanes<R, S, 8, EV_KNOTS>(b, p, q, k, P, precision, energy, s);
+    constexpr bool knots = sizeof(R) == 8;  // knot sums: FP64 only
+    if (k.table == 2) brick_density_lanes<R, S, 8, EV_SPLIT>(b, p, q, k, P, precision, energy, s);
+    else if (k.table || !knots) brick_density_lanes<R, S, 8, EV_TABLE>(b, p, q, k, P, precision, energy, s);
+    else if constexpr (knots) {
+        if (k.ndk == 2) brick_density_lanes<R, S, 2, EV_KNOTS>(b, p, q, k, P, precision, energy, s);
+        else brick_density_lanes<R, S, 8, EV_KNOTS>(b, p, q, k, P, precision, energy, s);
+    }
 }
 
 void launch_brick_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
@@ -642,10 +648,16 @@ template <typename R, bool S>
 static void brick_force_dispatch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P,
                                  int precision, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s)
 {
-    if (k.table) brick_force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, precision, fl, dt_fs, st, s);
-    else if (k.npk == 6 && k.ndk == 2) brick_force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
-    else if (k.npk <= 8 && k.ndk <= 8) brick_force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
-    else if constexpr (S) brick_force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    constexpr bool knots = sizeof(R) == 8;  // knot sums: FP64 only
+    if (k.table == 2) brick_force_variant<R, S, 8, 8, EV_SPLIT>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    else if (k.table || !knots) brick_force_variant<R, S, 8, 8, EV_TABLE>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    else if constexpr (knots) {
+        if (k.npk == 6 && k.ndk == 2)
+            brick_force_variant<R, S, 6, 2, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+        else if (k.npk <= 8 && k.ndk <= 8)
+            brick_force_variant<R, S, 8, 8, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+        else if constexpr (S) brick_force_variant<R, S, 16, 4, EV_KNOTS>(b, p, q, k, P, precision, fl, dt_fs, st, s);
+    }
 }
 
 void launch_brick_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

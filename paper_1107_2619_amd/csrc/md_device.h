@@ -327,15 +327,19 @@ __device__ __forceinline__ void wave_max_flag(int v, int32_t* flag)
 // whose edges include every knot, so no knot falls inside a bin and the
 // expansion reproduces the sum up to rounding.  With u < w small, the FP32
 // evaluation keeps full FP32 relative accuracy (no cancellation between knot
-// terms).  Coefficients live in LDS for one species, in the L1-cached global
-// table for several.  EV_KNOTS: the sums term by term (fallback when the knots
-// share no grid; also the explicit-evaluation comparison of the paper's
-// "Parallel benchmarks").
-enum { EV_KNOTS = 0, EV_TABLE = 1 };
+// terms).  EV_SPLIT: the same for knots that share no grid (any coefficient
+// file, "Available potentials"): a bin may hold one knot of each function,
+// whose term a (D - u)^3 H(D - u) (D the knot's offset from the bin start)
+// is added to the cubic of the knots switched on across the whole bin; still
+// exact up to rounding, and still free of cancellation since D - u < w.
+// Coefficients live in LDS for one species, in the L1-cached global table for
+// several.  EV_KNOTS: the sums term by term (the explicit-evaluation
+// comparison of the paper's "Parallel benchmarks"; FP64 only).
+enum { EV_KNOTS = 0, EV_TABLE = 1, EV_SPLIT = 2 };
 
 template <typename R>
 struct Tabs {
-    const R *force, *energy, *dens;  // [ns*ns][nbt][8], [..][4], [..][4]
+    const R *force, *energy, *dens;  // [ns*ns][nbt][force_stride], [..][value_stride] twice
 };
 template <typename R>
 __device__ __forceinline__ Tabs<R> tables(const Buffers& b);
@@ -379,15 +383,29 @@ __device__ __forceinline__ double lane_sum(double v)
 
 // One pair's contribution to the density of the site atom (species si) from
 // a neighbour of species sj at distance r: rho_{si sj}(r).
+// Knot term inside a bin: amp (D - u)^2 (P = 2, derivative records) or
+// amp (D - u)^3 (P = 3, value records), zero for u >= D.
+template <typename R, int PW>
+__device__ __forceinline__ R split_term(const R* c, R u)
+{
+    R t = c[0] - u;
+    t = t > R(0) ? t : R(0);
+    const R t2 = t * t;
+    return PW == 3 ? c[1] * t2 * t : c[1] * t2;
+}
+
 template <typename R, bool SINGLE, int NDK, int EV>
 __device__ __forceinline__ R density_term(const PotArgs& P, const DevPotential& G, const R* tab, int si, int sj,
                                           double r)
 {
-    if (EV == EV_TABLE) {
+    if (EV != EV_KNOTS) {
+        constexpr int VS = value_stride(EV);
         const int bin = (int)(r * P.inv_w);
         const R u = (R)fma(-(double)bin, P.w, r);
         const int ab = SINGLE ? 0 : si * G.ns + sj;
-        return cubic(tab + ((int64_t)ab * P.nbt + bin) * 4, u);
+        const R* c = tab + ((int64_t)ab * P.nbt + bin) * VS;
+        if (EV == EV_SPLIT) return cubic(c, u) + split_term<R, 3>(c + 4, u);
+        return cubic(c, u);
     } else if (SINGLE) {
         const Coef<R> C1 = single_coef<R>(P);
         return knot_value<R, NDK>(C1.da, C1.dr, r);
@@ -407,19 +425,39 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
                                            int si, int sj, double r, R fpi, R fpj, R& g, R& phi)
 {
     phi = R(0);
-    if (EV == EV_TABLE) {
+    if (EV != EV_KNOTS) {
+        constexpr int FS = force_stride(EV), VS = value_stride(EV);
         const int bin = (int)(r * P.inv_w);
         const R u = (R)fma(-(double)bin, P.w, r);
         if (SINGLE) {
-            const R* c = tf + bin * kForceStride;
-            g = quadratic(c, u) + (fpi + fpj) * quadratic(c + 3, u);
-            if (ENERGY == 1) phi = cubic(te + bin * 4, u);
+            const R* c = tf + bin * FS;
+            R dphi = quadratic(c, u), drho = quadratic(c + 3, u);
+            if (EV == EV_SPLIT) {
+                dphi += split_term<R, 2>(c + 6, u);
+                drho += split_term<R, 2>(c + 8, u);
+            }
+            g = dphi + (fpi + fpj) * drho;
+            if (ENERGY == 1) {
+                const R* e = te + bin * VS;
+                phi = cubic(e, u);
+                if (EV == EV_SPLIT) phi += split_term<R, 3>(e + 4, u);
+            }
         } else {
             const int64_t ab = si * G.ns + sj, ba = sj * G.ns + si;
-            const R* c = tf + (ab * P.nbt + bin) * kForceStride;
-            const R* c2 = tf + (ba * P.nbt + bin) * kForceStride;
-            g = quadratic(c, u) + fpi * quadratic(c + 3, u) + fpj * quadratic(c2 + 3, u);
-            if (ENERGY == 1) phi = cubic(te + (ab * P.nbt + bin) * 4, u);
+            const R* c = tf + (ab * P.nbt + bin) * FS;
+            const R* c2 = tf + (ba * P.nbt + bin) * FS;
+            R dphi = quadratic(c, u), dab = quadratic(c + 3, u), dba = quadratic(c2 + 3, u);
+            if (EV == EV_SPLIT) {
+                dphi += split_term<R, 2>(c + 6, u);
+                dab += split_term<R, 2>(c + 8, u);
+                dba += split_term<R, 2>(c2 + 8, u);
+            }
+            g = dphi + fpi * dab + fpj * dba;
+            if (ENERGY == 1) {
+                const R* e = te + (ab * P.nbt + bin) * VS;
+                phi = cubic(e, u);
+                if (EV == EV_SPLIT) phi += split_term<R, 3>(e + 4, u);
+            }
         }
     } else if (SINGLE) {
         const Coef<R> C1 = single_coef<R>(P);

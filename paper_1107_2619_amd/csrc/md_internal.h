@@ -37,6 +37,17 @@ constexpr int kIndexBits = 26;
 constexpr int kIndexMask = (1 << kIndexBits) - 1;
 constexpr int kChunk = 4;  // neighbours whose loads are issued together
 constexpr int kForceStride = 6;  // coefficients per bin of the force table (phi', rho' quadratics)
+// Tables whose bins may hold one knot of each function inside (knots on no
+// common grid): every function's record also carries that knot's offset D
+// from the bin start and its amplitude, for the term amp (D - u)^p H(D - u).
+// Force record: phi' quadratic, rho' quadratic, D_phi, -3 a_phi, D_rho, -3 a_rho;
+// value records (phi, rho): cubic, D, a.
+constexpr int kForceStrideSplit = 10;
+constexpr int kValueStride = 4;
+constexpr int kValueStrideSplit = 6;
+// table kind: 0 = term-by-term knot sums, 1 = knots on the bin grid, 2 = knots inside bins
+constexpr int force_stride(int kind) { return kind == 2 ? kForceStrideSplit : kForceStride; }
+constexpr int value_stride(int kind) { return kind == 2 ? kValueStrideSplit : kValueStride; }
 // Compact gather record of the mixed mode: cell-local coordinates as 32-bit
 // fixed point in units of h_a 2^-kCompactBits (h_a the link-cell edge of axis
 // a) and F' as FP32, 16 bytes.  A coordinate may lie up to kCompactCells cell
@@ -182,8 +193,8 @@ struct Buffers {
     uint8_t* ctype;       // [N] species | rigid bit, caller order
     double* msd_partial;  // [n_chunks][2 * MD_MAX_SPECIES] sums of d^2 and atom counts
     double* msd_out;      // [R][2 * MD_MAX_SPECIES] msd per species, then counts
-    // local-polynomial tables, [ns*ns][nbt][kForceStride] (phi' and rho' quadratics),
-    // [ns*ns][nbt][4] (phi cubic), [ns*ns][nbt][4] (rho cubic)
+    // local-polynomial tables, [ns*ns][nbt][force_stride] (phi' and rho' quadratics),
+    // [ns*ns][nbt][value_stride] (phi cubic), [ns*ns][nbt][value_stride] (rho cubic)
     double *tab_force64, *tab_energy64, *tab_dens64;
     float *tab_force32, *tab_energy32, *tab_dens32;
     int32_t* flags;       // [F_COUNT]
@@ -195,7 +206,8 @@ struct KernelShape {
     int32_t n_replicas;
     int32_t cap;
     int32_t npk, ndk; // knots per pair / density function
-    int32_t table;    // 1 = local-polynomial tables, 0 = explicit knot sums
+    int32_t table;    // 0 = explicit knot sums, 1 = local-polynomial tables (knots on the
+                      // bin grid), 2 = tables whose bins may hold a knot (split terms)
     int32_t n_chunks; // energy-reduction chunks over all replicas
     int32_t n_bricks; // bricks over all replicas
     int32_t brick;    // 1 = LDS brick kernels, 0 = global-gather kernels

@@ -38,8 +38,9 @@ struct md_ctx {
     PotArgs args{};
     // local-polynomial tables (host copies, uploaded at md_bind)
     bool table_ok = false;
+    int32_t table_kind = 0;    // 1 = knots on the bin grid, 2 = knots inside bins (split terms)
     bool explicit_ok = false;  // a compiled knot-sum variant covers the knot counts
-    int32_t evaluator = 0;  // 0 = tables when the knots share a grid, 1 = explicit knot sums
+    int32_t evaluator = 0;  // 0 = tables, 1 = explicit knot sums (FP64 only)
     std::vector<double> tf64, te64, td64;
     std::vector<float> tf32, te32, td32;
     // derived layout
@@ -165,7 +166,7 @@ KernelShape shape(const md_ctx* c)
     k.lanes = c->lanes > 0 ? std::min(c->lanes, 4) : 2;  // automatic: two lanes per atom
     k.npk = c->pot.npk;
     k.ndk = c->pot.ndk;
-    k.table = c->table_ok && c->evaluator == 0;
+    k.table = (c->table_ok && c->evaluator == 0) ? c->table_kind : 0;
     k.n_chunks = (int32_t)c->chunk_rep.size();
     k.n_bricks = (int32_t)c->brick_rep.size();
     // the barostat moves the bricks' box; the brick kernels take orthorhombic boxes only
@@ -205,7 +206,9 @@ constexpr double kHaloHeadroom = 1.25;
 void choose_bricks(md_ctx* c, int32_t dims)
 {
     const size_t rsz = c->precision == MD_MIXED ? 4 : 8;
-    const size_t tables = c->table_ok && c->pot.ns == 1 ? (size_t)c->args.nbt * (kForceStride + 4) * rsz : 0;
+    const size_t tables = c->table_ok && c->pot.ns == 1
+                              ? (size_t)c->args.nbt * (force_stride(c->table_kind) + value_stride(c->table_kind)) * rsz
+                              : 0;
     // an explicit shape may use all the LDS a workgroup can have
     const int64_t budget = dims > 0 ? (int64_t)c->lds_limit : std::min<int64_t>(kLdsBudget, c->lds_limit);
     const int64_t max_cap = std::max<int64_t>(64, std::min<int64_t>(65535, (budget - 4608 - (int64_t)tables) / 33));
@@ -324,71 +327,121 @@ bool upload_geometry(md_ctx* c)
            build_cell_table(c);
 }
 
-// Exact re-expansion of every cubic-knot sum on a grid of bins of width w
-// whose edges contain all knots: inside a bin the set of switched-on knots is
-// fixed, so f(b w + u) = sum_k a_k (D_k - u)^3 with D_k = r_k - b w is one
-// cubic c0 + c1 u + c2 u^2 + c3 u^3.  Returns false when no candidate width
-// puts every knot on the grid (the explicit knot sums are used then).
+// Exact re-expansion of every cubic-knot sum on a grid of bins of width w.
+// Inside a bin the set of knots switched on across the whole bin is fixed, so
+// their sum f(b w + u) = sum_k a_k (D_k - u)^3, D_k = r_k - b w, is one cubic
+// c0 + c1 u + c2 u^2 + c3 u^3.  Kind 1: every knot lies on the bin grid (a
+// bin edge), so that cubic is the whole function.  Kind 2 (knots on no common
+// grid, as in any coefficient file of "Available potentials"): a bin may hold
+// one knot of each function strictly inside; that knot's term a (D - u)^3
+// H(D - u) is stored beside the cubic as (D, a) and added in the kernels.
+// Returns false only when two knots of one function are closer than the
+// finest bin width allowed (4096 bins up to the cutoff).
 bool build_tables(md_ctx* c)
 {
     const DevPotential& P = c->pot;
     const int n2 = P.ns * P.ns;
-    auto knots_on_grid = [&](double w) {
-        auto on = [&](double rk) {
-            const double x = rk / w;
-            return std::fabs(x - std::nearbyint(x)) <= 1e-9 * std::max(1.0, x);
-        };
-        for (int ab = 0; ab < n2; ++ab) {
-            for (int k = 0; k < P.npk; ++k)
-                if (P.pair_a[ab][k] != 0.0 && !on(P.pair_r[ab][k])) return false;
-            for (int k = 0; k < P.ndk; ++k)
-                if (!on(P.dens_r[ab][k])) return false;
+    auto on_grid = [](double rk, double w) {
+        const double x = rk / w;
+        return std::fabs(x - std::nearbyint(x)) <= 1e-9 * std::max(1.0, x);
+    };
+    // every function's knots: (amplitudes, positions, count)
+    struct Fn {
+        const double *a, *r;
+        int n;
+    };
+    std::vector<Fn> fns;
+    for (int ab = 0; ab < n2; ++ab) {
+        fns.push_back({P.pair_a[ab], P.pair_r[ab], P.npk});
+        fns.push_back({P.dens_a[ab], P.dens_r[ab], P.ndk});
+    }
+    auto all_on_grid = [&](double w) {
+        for (const Fn& f : fns)
+            for (int k = 0; k < f.n; ++k)
+                if (f.a[k] != 0.0 && !on_grid(f.r[k], w)) return false;
+        return true;
+    };
+    // kind 2 needs at most one knot of each function strictly inside any bin
+    auto one_per_bin = [&](double w) {
+        for (const Fn& f : fns) {
+            std::vector<int64_t> inside;
+            for (int k = 0; k < f.n; ++k)
+                if (f.a[k] != 0.0 && !on_grid(f.r[k], w)) inside.push_back((int64_t)std::floor(f.r[k] / w));
+            std::sort(inside.begin(), inside.end());
+            if (std::adjacent_find(inside.begin(), inside.end()) != inside.end()) return false;
         }
         return true;
     };
     static const double cand[] = {0.02, 0.025, 0.01, 0.05, 0.04, 0.0125, 0.005, 0.002, 0.001};
     double w = 0.0;
+    int kind = 1;
     for (double wc : cand)
-        if (c->rc / wc <= 4096.0 && knots_on_grid(wc)) {
+        if (c->rc / wc <= 4096.0 && all_on_grid(wc)) {
             w = wc;
             break;
         }
+    if (w == 0.0) {
+        kind = 2;
+        for (double wc = 0.02; c->rc / wc <= 4096.0; wc *= 0.5)
+            if (one_per_bin(wc)) {
+                w = wc;
+                break;
+            }
+    }
     if (w == 0.0) return false;
     const int nb = (int)std::ceil(c->rc / w - 1e-9);
     const int nbt = nb + 2;  // two all-zero bins beyond the cutoff absorb rounding at r -> r_c
+    const int FS = force_stride(kind), VS = value_stride(kind);
+    c->table_kind = kind;
     c->args.w = w;
     c->args.inv_w = 1.0 / w;
     c->args.nbt = nbt;
-    c->tf64.assign((size_t)n2 * nbt * kForceStride, 0.0);
-    c->te64.assign((size_t)n2 * nbt * 4, 0.0);
-    c->td64.assign((size_t)n2 * nbt * 4, 0.0);
-    auto expand = [&](const double* amp, const double* rk, int nk, int b, double out[4]) {
-        out[0] = out[1] = out[2] = out[3] = 0.0;
+    c->tf64.assign((size_t)n2 * nbt * FS, 0.0);
+    c->te64.assign((size_t)n2 * nbt * VS, 0.0);
+    c->td64.assign((size_t)n2 * nbt * VS, 0.0);
+    // out[0..3]: cubic of the knots on across bin b; out[4], out[5]: offset and
+    // amplitude of the knot strictly inside bin b (0, 0 if none)
+    auto expand = [&](const double* amp, const double* rk, int nk, int b, double out[6]) {
+        for (int i = 0; i < 6; ++i) out[i] = 0.0;
         const double base = b * w;
         for (int k = 0; k < nk; ++k) {
-            if (amp[k] == 0.0 || std::llround(rk[k] / w) < b + 1) continue;
+            if (amp[k] == 0.0) continue;
+            const bool grid = on_grid(rk[k], w);
+            // bin of the knot: the bin it closes (grid) or the one it lies in
+            const int64_t kb = grid ? std::llround(rk[k] / w) - 1 : (int64_t)std::floor(rk[k] / w);
             const double D = rk[k] - base, a = amp[k];
-            out[0] += a * D * D * D;
-            out[1] += -3.0 * a * D * D;
-            out[2] += 3.0 * a * D;
-            out[3] += -a;
+            if (kb > b) {  // switched on across the whole bin
+                out[0] += a * D * D * D;
+                out[1] += -3.0 * a * D * D;
+                out[2] += 3.0 * a * D;
+                out[3] += -a;
+            } else if (kb == b && !grid) {
+                out[4] = D;
+                out[5] = a;
+            }
         }
     };
     for (int ab = 0; ab < n2; ++ab)
         for (int b = 0; b < nbt; ++b) {
-            double ph[4], rh[4];
+            double ph[6], rh[6];
             expand(P.pair_a[ab], P.pair_r[ab], P.npk, b, ph);
             expand(P.dens_a[ab], P.dens_r[ab], P.ndk, b, rh);
-            double* f = &c->tf64[((size_t)ab * nbt + b) * kForceStride];
+            double* f = &c->tf64[((size_t)ab * nbt + b) * FS];
             f[0] = ph[1];
             f[1] = 2.0 * ph[2];
             f[2] = 3.0 * ph[3];
             f[3] = rh[1];
             f[4] = 2.0 * rh[2];
             f[5] = 3.0 * rh[3];
-            for (int i = 0; i < 4; ++i) {
-                c->te64[((size_t)ab * nbt + b) * 4 + i] = ph[i];
-                c->td64[((size_t)ab * nbt + b) * 4 + i] = rh[i];
+            if (kind == 2) {
+                f[6] = ph[4];
+                f[7] = -3.0 * ph[5];
+                f[8] = rh[4];
+                f[9] = -3.0 * rh[5];
+            }
+            for (int i = 0; i < VS; ++i) {
+                c->te64[((size_t)ab * nbt + b) * VS + i] = ph[i];
+                c->td64[((size_t)ab * nbt + b) * VS + i] = rh[i];
             }
         }
     c->tf32.assign(c->tf64.begin(), c->tf64.end());
@@ -974,9 +1027,15 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     // term-by-term sums: <= 8 + 8 knots, or one species with <= 16 pair and <= 4
     // density knots (a 13 + 2 iron potential of the paper's benchmark fits)
     c->explicit_ok = (npk <= 8 && ndk <= 8) || (ns == 1 && npk <= 16 && ndk <= 4);
+    // mixed precision meets its tolerances only through the exact tables: its
+    // FP32 knot sums lose the per-atom energies to cancellation between terms
+    if (c->precision == MD_MIXED && !c->table_ok)
+        return reject(MD_ERR_POTENTIAL, "mixed precision needs the exact tables, and two knots of one function "
+                                        "lie closer than the finest table bin (r_c / 4096)");
     if (!c->table_ok && !c->explicit_ok)
-        return reject(MD_ERR_POTENTIAL, "more than 8 knots need the knots on a common tabulation grid "
-                                        "(or one species with at most 4 density knots)");
+        return reject(MD_ERR_POTENTIAL, "more than 8 knots need the tables, and two knots of one function lie "
+                                        "closer than the finest table bin (or one species with at most 4 "
+                                        "density knots)");
     if (c->single) {
         PotArgs& A = c->args;
         for (int k = 0; k < MD_MAX_KNOTS; ++k) {
@@ -1522,7 +1581,10 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
         return MD_OK;
     case MD_OPT_EVALUATOR:
         if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "evaluator must be 0 (tables) or 1 (knot sums)");
-        if (value == 0 && !c->table_ok) return fail(c, MD_ERR_ARG, "the knots share no tabulation grid");
+        if (value == 0 && !c->table_ok) return fail(c, MD_ERR_ARG, "two knots of one function share a table bin");
+        if (value == 1 && c->precision == MD_MIXED)
+            return fail(c, MD_ERR_ARG, "the knot sums are FP64 only: in FP32 they miss the mixed-precision "
+                                       "energy tolerance");
         if (value == 1 && !c->explicit_ok) return fail(c, MD_ERR_ARG, "no knot-sum variant for these knot counts");
         c->evaluator = (int32_t)value;
         return MD_OK;

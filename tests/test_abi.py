@@ -107,9 +107,10 @@ def _fe_knots(npk, ndk, step, ns=1):
 
 def test_knot_limits_and_evaluators(md):
     """Up to 16 knots per function (the paper's benchmark iron potential is a
-    sum of 15 cubic splines, "Parallel benchmarks"): tables need every knot on
-    a common grid; the term-by-term sums cover 8 + 8 knots, or 16 pair and 4
-    density knots for one species.  A potential neither covers is refused."""
+    sum of 15 cubic splines, "Parallel benchmarks").  The exact tables take any
+    knot placement (knots off the bin grid become split terms inside their
+    bin); the term-by-term sums, FP64 only, cover 8 + 8 knots, or 16 pair and
+    4 density knots for one species.  Mixed precision refuses the knot sums."""
     fe15 = inputs.perturbed_potential("fe15_fs", 3)
     assert fe15["pair_a"].shape[2] == 13 and fe15["dens_A"].shape[2] == 2
     c = _ctx(md, potential=fe15)
@@ -122,17 +123,38 @@ def test_knot_limits_and_evaluators(md):
     with pytest.raises(md.MDError) as e:
         c.set_option(md.MD_OPT_EVALUATOR, 1)
     assert e.value.code == md.MD_ERR_ARG
-    # off-grid knots (step 0.1234 A): 16 + 4 knot sums, no tables
+    # off-grid knots (step 0.1234 A): tables with split bins, and the 16 + 4 knot sums
     c = _ctx(md, potential=_fe_knots(16, 4, 0.1234))
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+    c.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 1
+    # off-grid with 5 density knots, or two species with 9 pair knots: tables only
+    for pot in (_fe_knots(16, 5, 0.1234), _fe_knots(9, 2, 0.1234, ns=2)):
+        c = _ctx(md, potential=pot)
+        assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+        with pytest.raises(md.MDError) as e:
+            c.set_option(md.MD_OPT_EVALUATOR, 1)
+        assert e.value.code == md.MD_ERR_ARG
+    # the printed Ni/Al pair knots (no common grid) in mixed precision: the tables
+    g = _golden_ni_al()
+    nial = _fe_knots(4, 2, 0.3)
+    nial["pair_a"] = np.array(g["pair_a"]).reshape(1, 1, 4)
+    nial["pair_r"] = np.array(g["pair_r"]).reshape(1, 1, 4)
+    c = _ctx(md, potential=nial, precision="mixed")
+    assert c.get_option(md.MD_OPT_EVALUATOR) == 0
+    with pytest.raises(md.MDError) as e:
+        c.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert e.value.code == md.MD_ERR_ARG and "FP64 only" in str(e.value)
+    # two knots of one function closer than the finest bin (4.1 / 4096 A): no
+    # tables, so FP64 takes the knot sums and mixed precision refuses the potential
+    close = _fe_knots(6, 2, 0.3)
+    close["pair_r"][0, 0, 0] = 2.6 + 1e-4 * np.sqrt(2.0)
+    close["pair_r"][0, 0, 1] = 2.6 + 2e-4 * np.sqrt(3.0)
+    c = _ctx(md, potential=close)
     assert c.get_option(md.MD_OPT_EVALUATOR) == 1
     with pytest.raises(md.MDError) as e:
-        c.set_option(md.MD_OPT_EVALUATOR, 0)
-    assert e.value.code == md.MD_ERR_ARG
-    # off-grid with 5 density knots, or two species with 9 pair knots: refused
-    for pot in (_fe_knots(16, 5, 0.1234), _fe_knots(9, 2, 0.1234, ns=2)):
-        with pytest.raises(md.MDError) as e:
-            _ctx(md, potential=pot)
-        assert e.value.code == md.MD_ERR_POTENTIAL
+        _ctx(md, potential=close, precision="mixed")
+    assert e.value.code == md.MD_ERR_POTENTIAL
     # on the grid the two-species 9-knot table is accepted (tables)
     c = _ctx(md, potential=_fe_knots(9, 2, 0.1, ns=2))
     assert c.get_option(md.MD_OPT_EVALUATOR) == 0
@@ -140,6 +162,13 @@ def test_knot_limits_and_evaluators(md):
     with pytest.raises(md.MDError) as e:
         _ctx(md, potential=_fe_knots(17, 2, 0.1))
     assert e.value.code == md.MD_ERR_POTENTIAL and "1..16" in str(e.value)
+
+
+def _golden_ni_al():
+    import json
+
+    with open(os.path.join(ROOT, "tests", "golden", "ni_al_atvf.json")) as fh:
+        return json.load(fh)
 
 
 def test_atom_offset_validation(md):

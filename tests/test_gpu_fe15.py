@@ -4,19 +4,10 @@ intermediate-complexity potential of the paper's lookup-table benchmark
 
 Every evaluator and kernel family that can run it is compared element by
 element on a displaced bcc crystal: the exact tables, the term-by-term knot
-sums (16 + 4 knot variant) in the global-gather and the LDS-brick kernels, the
-half list with atomics, and knots moved off every tabulation grid (knot sums
-only).  Tolerances as in the other parity tests, with two exceptions in mixed
-precision that follow from this potential's conditioning.  At the
-first-neighbour distance the pair term g is 1/1100 of the summed magnitudes of
-its knot terms (1/26 for the 6 + 2 knot iron table), so FP32 arithmetic on
-them carries ~1100 x 6e-8 = 6.6e-5 relative error:
-- FP32 knot sums term by term: force error bound 1e-4 (measured 2.4e-5), no
-  energy check, as for the other potentials;
-- tables (exact cubics with FP32 coefficients): forces and energies meet the
-  usual tolerances, but the virial, a sum of pair distance times g over every
-  pair with correlated rounding, reaches 1.7e-6 relative against the 1e-6 the
-  other parity tests ask, and is held to the force tolerance instead.
+sums (16 + 4 knot variant, FP64 only) in the global-gather and the LDS-brick
+kernels, the half list with atomics, and knots moved off every tabulation
+grid (tables with split bins, and the knot sums).  Tolerances as in the other
+parity tests, for both precisions.
 """
 import numpy as np
 import pytest
@@ -27,8 +18,6 @@ from tests.test_gpu_parity import _check_snapshot, _oracle_snapshot
 
 pytestmark = pytest.mark.gpu
 
-VREL = {"fp64": 10 * TOL["fp64"]["energy"], "mixed": TOL["mixed"]["force"]}
-KNOT_FORCE = {"fp64": TOL["fp64"]["force"], "mixed": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -51,35 +40,37 @@ def _fe15(displace=0.07, seed=31, n=10):
 def test_fe15_tables(md, orc, precision):
     s = _fe15()
     for kernel in (1, 0):
-        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel}, virial_rel=VREL[precision])
+        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel})
         assert sim.get_option(md.MD_OPT_EVALUATOR) == 0
-    _check_snapshot(md, orc, s, precision, nbr_mode="half", virial_rel=VREL[precision])
+    _check_snapshot(md, orc, s, precision, nbr_mode="half")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fe15_knot_sums(md, orc, precision):
+def test_fe15_knot_sums(md, orc):
+    """The term-by-term sums, FP64 only; mixed precision refuses them."""
     s = _fe15(seed=32)
-    full = precision == "fp64"
     for kernel in (1, 0):
-        _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel, md.MD_OPT_EVALUATOR: 1},
-                        check_energy=full, virial_rel=VREL[precision], force_tol=KNOT_FORCE[precision])
-    _check_snapshot(md, orc, s, precision, options={md.MD_OPT_EVALUATOR: 1}, nbr_mode="half",
-                    check_energy=full, virial_rel=VREL[precision], force_tol=KNOT_FORCE[precision])
+        _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_KERNEL: kernel, md.MD_OPT_EVALUATOR: 1})
+    _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_EVALUATOR: 1}, nbr_mode="half")
+    sim = md.Simulation(s, precision="mixed")
+    with pytest.raises(md.MDError) as e:
+        sim.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert e.value.code == md.MD_ERR_ARG
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fe15_off_grid_knots(md, orc, precision):
     """Pair knots moved by irrational fractions of a bin: no common grid, so
-    the knot sums are the only evaluator."""
+    the tables keep each knot that falls inside a bin as its own term."""
     s = _fe15(seed=33)
     pot = dict(s.potential)
     pot["pair_r"] = pot["pair_r"] + 1e-3 * np.sqrt(2.0) * np.arange(13)
     s.potential = pot
     for kernel in (1, 0):
-        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel},
-                              check_energy=precision == "fp64", virial_rel=VREL[precision],
-                              force_tol=KNOT_FORCE[precision])
-        assert sim.get_option(md.MD_OPT_EVALUATOR) == 1
+        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel})
+        assert sim.get_option(md.MD_OPT_EVALUATOR) == 0
+    _check_snapshot(md, orc, s, precision, nbr_mode="half")
+    if precision == "fp64":
+        _check_snapshot(md, orc, s, precision, options={md.MD_OPT_EVALUATOR: 1})
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])

@@ -94,15 +94,55 @@ def test_small_liquid_boxes_snapshot(md, orc, precision):
 @pytest.mark.parametrize("workload", ["bcc", "fec"])
 def test_explicit_knot_evaluator(md, orc, workload):
     """The term-by-term knot sums (the paper's explicit evaluation) agree with
-    the oracle in FP64; in mixed mode their FP32 knot terms cancel against each
-    other, so only the force tolerance is met (energies use the tables)."""
+    the oracle in FP64.  They are FP64 only: in FP32 their knot terms cancel
+    against each other and miss the mixed energy tolerance, so mixed precision
+    refuses them."""
     if workload == "bcc":
         s = inputs.bcc_fe(8, temperature=300.0, seed=6, displace=0.06)
     else:
         s = inputs.fec_replicas(2, nmin=300, nmax=800, seed0=4300)
         s.pos = s.pos + 0.04 * (2 * np.random.default_rng(5).random(s.pos.shape) - 1)
     _check_snapshot(md, orc, s, "fp64", options={md.MD_OPT_EVALUATOR: 1})
-    _check_snapshot(md, orc, s, "mixed", options={md.MD_OPT_EVALUATOR: 1}, check_energy=False)
+    sim = md.Simulation(s, precision="mixed")
+    with pytest.raises(md.MDError) as e:
+        sim.set_option(md.MD_OPT_EVALUATOR, 1)
+    assert e.value.code == md.MD_ERR_ARG
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_printed_ni_al_pair_knots(md, orc, precision):
+    """The pair coefficients the paper prints ("Available potentials", Ni/Al),
+    knots 2.96061 .. 4.35174 A on no common grid, with the iron density
+    functions, on a displaced bcc crystal: the tables with split bins meet the
+    contract in both precisions (global, brick and half-list kernels)."""
+    import json
+    import os
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ni_al_atvf.json")))
+    s = inputs.bcc_fe(7, temperature=300.0, seed=61, displace=0.06, name="bcc_ni_al_pair")
+    pot = dict(s.potential)
+    pot["pair_a"] = np.array(g["pair_a"]).reshape(1, 1, 4)
+    pot["pair_r"] = np.array(g["pair_r"]).reshape(1, 1, 4)
+    s.potential = pot
+    for kernel in (1, 0):
+        sim = _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel})
+        assert sim.get_option(md.MD_OPT_EVALUATOR) == 0
+    _check_snapshot(md, orc, s, precision, nbr_mode="half")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_species_distinct_embedding(md, orc, precision):
+    """Fe-C replicas with F_a = -c_a sqrt(rho) and c = (1.0, 0.7) ("Theoretical
+    background": the embedding belongs to the site atom's species), on the
+    global, brick and half-list kernels."""
+    s = inputs.fec_replicas(3, nmin=300, nmax=1500, seed0=4700)
+    s.pos = s.pos + 0.04 * (2 * np.random.default_rng(47).random(s.pos.shape) - 1)
+    pot = dict(s.potential)
+    pot["emb_c"] = np.array([1.0, 0.7])
+    s.potential = pot
+    for kernel in (1, 0):
+        _check_snapshot(md, orc, s, precision, options={md.MD_OPT_KERNEL: kernel})
+    _check_snapshot(md, orc, s, precision, nbr_mode="half")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
