@@ -4,14 +4,16 @@ Default workload: bcc Fe, 80^3 cells with 1% random vacancies (N = 1,013,760),
 600 K, neighbour list rebuilt every 10 steps.  A step is one pass of the whole
 hot path: (scheduled) cell sort + list build, density pass with embedding,
 force pass with velocity-Verlet update, and - on the last step of each
-md_step call - the energy/virial reductions.
+md_step call - the energy/virial reductions; the `energy_every_step` leg
+reduces energies and the virial on every step.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload bcc1m]
 
-`value` is the mixed-precision rate (FP32 pair terms, FP64 accumulation and
-integration) gated on its force error against the FP64 path; the FP64 rate is
-reported beside it.  Inputs are seeded and synthetic and already resident in
-HBM when the timed region starts.
+`value` is the FP64 rate (the paper's precision).  The mixed-precision rate
+(FP32 pair terms, FP64 accumulation and integration), gated on its force
+error against the FP64 path, is reported beside it with its own roofline.
+Inputs are seeded and synthetic and already resident in HBM when the timed
+region starts.
 """
 from __future__ import annotations
 
@@ -38,17 +40,31 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {"fetch_kib": 114999.0, "write_kib": 71280.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources_sha256_16": "acc9750b62671fb7", "workload": "bcc1m", "precision": "mixed"}
+FORCE_TRAFFIC = {}  # precision -> {"fetch_kib", "write_kib", "fetch_scale", "write_scale",
+                   #                 "sources_sha256_16", "workload", "kernel"}
 # VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
 # so this is also the lane-operations per atom of one launch.
-FORCE_VALU_PER_WAVE = 1655.0
+FORCE_VALU_PER_WAVE = {}  # precision -> VALU instructions per wave (64 atoms), same validity rule
 # Lane-operation issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz (FP64 and unpacked FP32 issue at the same rate; packed FP32 is off).
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-FORCE_SOURCES = ["paper_1107_2619_amd/csrc/kernels.hip", "paper_1107_2619_amd/csrc/md_device.h",
-                 "paper_1107_2619_amd/csrc/md_internal.h"]
+FORCE_SOURCES = ["paper_1107_2619_amd/csrc/kernels.hip", "paper_1107_2619_amd/csrc/kernels_brick.hip",
+                 "paper_1107_2619_amd/csrc/md_device.h", "paper_1107_2619_amd/csrc/md_internal.h"]
+# The paper's own timings (section "Parallel benchmarks"), quoted as context
+# only: they are FP64 runs of a Fortran 95 / OpenMP code on other hardware and
+# are never used as a ratio.
+PAPER_CONTEXT = {
+    "hardware": "4 x quad-core Intel Xeon E7310, 1.6 GHz, 16 GB shared memory, up to 16 OpenMP threads",
+    "precision": "FP64 (full 64-bit precision)",
+    "code": "MOLDY, Fortran 95 + OpenMP (2011)",
+    "workload": "bcc Fe, 15-spline iron potential, 300 K, Parrinello-Rahman at 0.1 GPa, dt 1 fs, 1000 steps, "
+                "no neighbour-list update during the run",
+    "runtime_per_atom": "about 0.013 at 16 threads for the smallest systems, levelling off near 0.092 from "
+                        "32k atoms up (the unit is not recoverable from the text; no rate is derived from it)",
+    "weak_scaling": "16 threads with ~18.4k atoms each take 1.4x the one-thread time of 18,432 atoms",
+    "neighbour_list": "a full list update costs about twice a force evaluation (serial list routine)",
+}
 
 
 def force_sources_hash() -> str:
@@ -78,6 +94,58 @@ def step_bytes_per_atom(nbar: float, k: int) -> float:
     return 136.0 + 4.0 * nbar + (56.0 + 2.0 * nbar) / k
 
 
+def roofline_for(r, prec, nbar, n, k, workload, copy_gbs):
+    """HBM roofline of the force kernel of one precision's timed run: the
+    algorithmic bytes per launch (force_kernel_bytes_per_atom x N) over the
+    kernel's mean duration (HIP events on its launch stream), against the
+    MI355X peak; traffic from committed FETCH/WRITE counters when they were
+    taken on these kernel sources, else null."""
+    force_us = r["force_kernel_us"]
+    fbytes = force_kernel_bytes_per_atom(nbar) * n
+    achieved = fbytes / (force_us * 1e-6) / 1e9
+    kernel = "k_brick_force" if r["autotuned"].get("kernel") == 0 else "k_force"
+    t = FORCE_TRAFFIC.get(prec)
+    valid = (t is not None and workload == t["workload"] and kernel == t["kernel"]
+             and force_sources_hash() == t["sources_sha256_16"])
+    traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) if valid else None
+    alu = None
+    if valid and prec in FORCE_VALU_PER_WAVE:
+        lane_ops = FORCE_VALU_PER_WAVE[prec] * n / (force_us * 1e-6)
+        alu = {"achieved": lane_ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+               "frac": lane_ops / VALU_PEAK_LANE_OPS, "valu_instr_per_wave": FORCE_VALU_PER_WAVE[prec]}
+    step_b = step_bytes_per_atom(nbar, k)
+    return {
+        "bound": "hbm",
+        "kernel": f"{kernel} ({prec}: force pass + velocity Verlet)",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic_bytes / (force_us * 1e-6) / 1e9 if valid else None,
+        "traffic_bytes_per_launch": traffic_bytes,
+        "algorithmic_bytes_per_launch": fbytes,
+        "bytes_per_atom": force_kernel_bytes_per_atom(nbar),
+        "force_kernel_us": force_us,
+        "step_bytes_per_atom": step_b,
+        "step_frac": step_b * r["value"] / 1e9 / HBM_PEAK_GBS,
+        "measured_copy_GBs": copy_gbs,
+        "alu": alu,
+    }
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
 def timed_steps(sim, steps):
     """Milliseconds of one md_step(steps) call between HIP events on the
     caller's stream (barriers on both sides), and the wall time."""
@@ -96,15 +164,21 @@ def timed_steps(sim, steps):
 
 
 def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None, nvt=None,
-                  integrator="verlet"):
+                  integrator="verlet", energy_every=0, energy_ring=0):
     """A warmed-up timed run.  tune: options to apply (e.g. an autotuner's
     choice); graph replay is used unless per-kernel timing is requested.
-    nvt: (targets [R] K, thermostat masses [R] eV fs^2) for a Nose-Hoover run."""
+    nvt: (targets [R] K, thermostat masses [R] eV fs^2) for a Nose-Hoover run.
+    energy_every: reduce energies every that many steps into a ring of
+    energy_ring entries.  The timed call continues from the last warm-up
+    call (no reload and no force pass at its entry)."""
     kw = {} if nvt is None else {"nh_temperature": nvt[0], "nh_mass": nvt[1]}
     kw["integrator"] = integrator
-    sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode, **kw)
+    sim = md.Simulation(system, precision=precision, want_e_atom=False, nbr_mode=nbr_mode,
+                        energy_ring=energy_ring, **kw)
     for opt, val in (tune or {}).items():
         sim.set_option(opt, val)
+    if energy_every:
+        sim.set_option(md.MD_OPT_ENERGY_EVERY, energy_every)
     if not timing:
         sim.set_option(md.MD_OPT_USE_GRAPH, 1)
         # two warmup calls long enough to capture the graphs of both ping-pong
@@ -112,10 +186,10 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
         calls = [max(warmup, 4 * system.rebuild_every + 2)] * 2
     else:
         calls = [warmup]
+    sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)
     for w in calls:
         sim.step(w)
         sim.energy()
-    sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)
     if timing:
         sim.kernel_times(reset=True)
     ms, wall = timed_steps(sim, steps)
@@ -279,6 +353,10 @@ def main():
                     help="steps of the table versus explicit evaluation comparison (0 = skip)")
     ap.add_argument("--diffusion-steps", type=int, default=1000,
                     help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
+    ap.add_argument("--energy-steps", type=int, default=200,
+                    help="steps of the leg that reduces energies and the virial every step (0 = skip)")
+    ap.add_argument("--small-steps", type=int, default=100,
+                    help="steps of the 2000-atom FP64 configuration (0 = skip)")
     ap.add_argument("--copy-gbs-mib", type=int, default=1024,
                     help="size of the device copy whose bandwidth is reported beside the roofline (0 = skip)")
     ap.add_argument("--kernel", choices=["auto", "global"], default="auto",
@@ -438,7 +516,7 @@ def main():
     # knot sums, each precision with its autotuned kernel settings
     evaluator = {}
     if args.evaluator_steps > 0:
-        for prec in ("fp64", "mixed"):
+        for prec in ("fp64",):  # the term-by-term knot sums are FP64 only
             opts = choice_options(md, tuned[prec])
             rates = {}
             for ev, label in ((0, "table"), (1, "explicit")):
@@ -467,7 +545,7 @@ def main():
             w15[args.workload + "_fe15"] = s15
         for wname, s15 in w15.items():
             per = {"n_atoms": s15.n_atoms, "skin": s15.skin}
-            for prec in ("fp64", "mixed"):
+            for prec in ("fp64",):
                 opts = choice_options(md, tuned[prec])
                 rates = {}
                 for ev, label in ((0, "table"), (1, "explicit")):
@@ -559,40 +637,46 @@ def main():
             "repeat_ms_per_step": [x / args.steps for x in r["repeats"]],
             "median_value": (n * args.steps / (float(np.median(r["repeats"])) * 1e-3)) if r["repeats"] else None,
         }
+        rec[prec]["roofline"] = roofline_for(rec[prec], prec, nbar, n, system.rebuild_every, args.workload,
+                                             copy_gbs)
     gate_ok = mix_err <= 1e-5
-    head = rec["mixed"] if gate_ok else rec["fp64"]
-    force_us = head["force_kernel_us"]
-    fbytes = force_kernel_bytes_per_atom(nbar) * n
-    achieved = fbytes / (force_us * 1e-6) / 1e9
-    traffic = None
-    traffic_bytes = None
-    t = FORCE_TRAFFIC
-    if (gate_ok and args.workload == t["workload"] and force_sources_hash() == t["sources_sha256_16"]
-            and head.get("autotuned", {}).get("kernel") == 1):
-        traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
-        traffic = traffic_bytes / (force_us * 1e-6) / 1e9
-    alu = None
-    if (gate_ok and args.workload == t["workload"] and force_sources_hash() == t["sources_sha256_16"]
-            and head.get("autotuned", {}).get("kernel") == 1):
-        lane_ops = FORCE_VALU_PER_WAVE * n / (force_us * 1e-6)
-        alu = {"achieved": lane_ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
-               "frac": lane_ops / VALU_PEAK_LANE_OPS, "valu_instr_per_wave": FORCE_VALU_PER_WAVE}
-    roofline = {
-        "bound": "hbm",
-        "kernel": "k_force (force pass + velocity Verlet)",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS,
-        "traffic": traffic,
-        "traffic_bytes_per_launch": traffic_bytes,
-        "algorithmic_bytes_per_launch": fbytes,
-        "bytes_per_atom": force_kernel_bytes_per_atom(nbar),
-        "step_bytes_per_atom": step_bytes_per_atom(nbar, system.rebuild_every),
-        "step_frac": step_bytes_per_atom(nbar, system.rebuild_every) * head["value"] / 1e9 / HBM_PEAK_GBS,
-        "measured_copy_GBs": copy_gbs,
-        "alu": alu,
-    }
+    rec["mixed"]["gate"] = {"force_err_vs_fp64": mix_err, "bound": 1e-5, "ok": gate_ok}
+    rec["mixed"]["speedup_vs_fp64"] = rec["mixed"]["value"] / rec["fp64"]["value"]
+    head = rec["fp64"]
+    roofline = head["roofline"]
+
+    # energies, virial and pressure reduced on every step (device ring), the
+    # same workload and kernel settings as the headline, both precisions
+    every_step = {}
+    if args.energy_steps > 0:
+        for prec in ("fp64", "mixed"):
+            sim_e, ms_e, _, _, _ = run_precision(md, system, prec, args.energy_steps, args.warmup, timing=False,
+                                                 tune=choice_options(md, tuned[prec]), energy_every=1,
+                                                 energy_ring=args.energy_steps + 1024)
+            hist = sim_e.energy_history(max_entries=args.energy_steps + 1024)
+            every_step[prec] = {
+                "value": n * args.energy_steps / (ms_e * 1e-3), "ms_per_step": ms_e / args.energy_steps,
+                "vs_energy_at_call_end": (ms_e / args.energy_steps) / rec[prec]["ms_per_step"],
+                "entries_read": len(hist),
+                "pe_last_eV_per_atom": float(hist[-1].pe[0] / n) if hist else None,
+                "pressure_last_gpa": float(hist[-1].pressure_gpa[0]) if hist else None,
+            }
+            log(f"energies every step {prec}: {ms_e / args.energy_steps * 1e3:.1f} us/step")
+            del sim_e
+
+    # the small configuration: 2000-atom bcc Fe, FP64, 100 velocity-Verlet steps
+    small_rec = None
+    if args.small_steps > 0:
+        small = inputs.workload("bcc2000")
+        opts_s, ch_s = tune_options(md, small, "fp64")
+        sim_s, ms_s, _, en_s, _ = run_precision(md, small, "fp64", args.small_steps, args.warmup, timing=False,
+                                                tune=opts_s)
+        small_rec = {"workload": "bcc2000: bcc Fe 10^3 cells, 300 K, dt 1 fs, rebuild every 10",
+                     "n_atoms": small.n_atoms, "precision": "fp64", "steps": args.small_steps,
+                     "value": small.n_atoms * args.small_steps / (ms_s * 1e-3),
+                     "ms_per_step": ms_s / args.small_steps, "autotuned": ch_s}
+        log(f"bcc2000 fp64: {ms_s / args.small_steps * 1e3:.1f} us/step")
+        del sim_s
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -609,19 +693,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if gate_ok else "f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: bcc Fe 80^3 cells, 1% vacancies, N={n}, 600 K, "
                         f"rebuild every {system.rebuild_every}, dt {system.dt_fs} fs",
             "n_atoms": n,
             "mean_neighbours": nbar,
-            "precision": "mixed" if gate_ok else "fp64",
+            "precision": "fp64",
             "parallelism": "single GPU",
         },
         "mixed_force_err_vs_fp64": mix_err,
         "fp64": rec["fp64"],
         "mixed": rec["mixed"],
+        "energy_every_step": every_step,
+        "small_config": small_rec,
+        "paper_context": PAPER_CONTEXT,
         "larger_system": size_sweep,
         "barostat": barostat,
         "half_list_atomics": half,
@@ -686,6 +773,8 @@ def cpu_baseline(system, sim, pos, f_gpu, seconds):
         "value": s / dt,
         "unit": "atom-steps/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
+        "logical_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"forces of {s} random atoms of the same {system.n_atoms}-atom state, brute force O(N) each "
                   f"(O(N^2) algorithm), FP64, OpenMP; {dt:.1f} s",

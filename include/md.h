@@ -237,15 +237,38 @@ int md_build_neighbours(md_ctx *ctx, void *stream);
  * want_energy != 0 also the energies (read with md_energy) and e_atom. */
 int md_eam_forces(md_ctx *ctx, int want_energy, void *stream);
 
-/* Advances nsteps >= 1 velocity-Verlet steps from the caller's x, v; forces at
- * the starting positions are recomputed first.  Rebuilds the list whenever
- * the step index is a multiple of rebuild_every.  On completion x, v, f (and
- * e_atom) hold the final state and the energies of that state are ready. */
+/* Advances nsteps >= 1 velocity-Verlet steps from the caller's x, v.  Rebuilds
+ * the list whenever the step index is a multiple of rebuild_every.  On
+ * completion x, v, f (and e_atom) hold the final state and the energies of
+ * that state are ready.  A call that directly follows another md_step call
+ * continues from the state and forces that call left (no reload of x, v and
+ * no force pass at entry); after the caller writes x or v it must call
+ * md_state_changed, and any other call on the context (md_bind, md_set_option,
+ * md_eam_forces, md_build_neighbours, md_autotune) also makes the next md_step
+ * read x, v afresh and recompute the forces at the starting positions.  The
+ * Gear integrator and the barostat always start afresh.  With
+ * MD_OPT_ENERGY_EVERY = k > 0 every step whose index is a multiple of k also
+ * reduces PE, KE and the virial (paper, "Thermodynamic Quantities") into the
+ * ring read by md_energy_history. */
 int md_step(md_ctx *ctx, int32_t nsteps, void *stream);
+
+/* Declares that the caller has written the bound x, v (or other state arrays)
+ * since the last md_step: the next md_step reloads them and recomputes the
+ * forces before its first kick.  Host only; no device work. */
+int md_state_changed(md_ctx *ctx);
 
 /* Synchronises the stream, checks the device error flags and copies the
  * per-replica energies of the last evaluated state to out[0..R). */
 int md_energy(md_ctx *ctx, md_energies *out, void *stream);
+
+/* Per-step energies (paper, "Thermodynamic Quantities": the quantities are
+ * sampled along the run and averaged): the entries md_step appended to the
+ * device ring (MD_OPT_ENERGY_RING entries, MD_OPT_ENERGY_EVERY) since the last
+ * md_energy_history call or md_bind, oldest first.  out: host array of
+ * max_entries * R records, entry j of replica r at out[j * R + r], each with
+ * its step index in .step (entries older than the ring holds are skipped);
+ * *n_out receives the number of entries written.  Synchronises the stream. */
+int md_energy_history(md_ctx *ctx, md_energies *out, int64_t max_entries, int64_t *n_out, void *stream);
 
 /* Mean square displacement per replica and species (paper, "Self-diffusion
  * in iron": D = lim MSD / 6t, the MSD averaged over atoms), from the unwrapped
@@ -300,10 +323,18 @@ enum {
     MD_OPT_GRAPH_LAUNCHES = 12, /* read only: graph replays since md_create          */
     MD_OPT_TUNED_NS = 13,      /* read only: md_autotune's estimate of one step of
                                   the chosen configuration, ns                       */
-    MD_OPT_COMPACT = 14        /* mixed precision, global kernels, full list: 1 =
+    MD_OPT_COMPACT = 14,       /* mixed precision, global kernels, full list: 1 =
                                   gather 16-byte cell-relative fixed-point records
                                   (default), 0 = the FP64 position records; reads
                                   back whether compact records are in use            */
+    MD_OPT_ENERGY_EVERY = 15,  /* k > 0: every step whose index is a multiple of k
+                                  reduces PE, KE and the virial and appends them to
+                                  the energy ring (velocity-Verlet NVE only); 0 =
+                                  energies on the last step of each md_step only   */
+    MD_OPT_ENERGY_RING = 16    /* entries of the device energy ring (workspace
+                                  grows by entries * R * 96 bytes); set before
+                                  md_workspace_bytes and md_bind (MD_ERR_STATE
+                                  after md_bind).  Default 0: no ring                */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);

@@ -844,6 +844,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double vi
     }
 }
 
+// Per-step energies ("Thermodynamic Quantities", sampled every few steps):
+// the totals just reduced go to entry (count mod ring_len) of the ring, and the
+// count advances.  The entry index is read on the device, so a captured step
+// sequence appends to successive entries on every replay.  One workgroup.
+__global__ __launch_bounds__(kBlock) void k_energy_ring_push(Buffers b, int32_t n_replicas, int64_t ring_len)
+{
+    const int64_t count = __hip_atomic_load(b.ering_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t n = (int64_t)n_replicas * kEnergySlots;
+    double* dst = b.ering + (count % ring_len) * n;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) dst[i] = b.energies[i];
+    __syncthreads();
+    if (threadIdx.x == 0) b.ering_count[0] = count + 1;
+}
+
 // ---------------------------------------------------------------------------
 // Nose-Hoover thermostat (paper, "Thermostat NVTp").  The flow of a step is
 // split symmetrically: thermostat half step, velocity half kick, drift, forces,
@@ -922,7 +936,7 @@ __global__ __launch_bounds__(kBlock) void k_nh_update(Buffers b, int halves, dou
 // atoms v <- S v + (dt/2) f/m and x <- x + dt v; rigid atoms move on their
 // line and account the opening half of their power.  Writes pos[p^1] (and the
 // compact record of the new position).
-__global__ void k_nh_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double dt, int compact)
+__global__ void k_nh_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, double dt, int compact, int scaled)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -939,7 +953,7 @@ __global__ void k_nh_open(Buffers b, int p, int q, int64_t n_slots, PotArgs P, d
 #pragma unroll
         for (int a = 0; a < 3; ++a) xn[a] += dt * R.vp[a];
     } else {
-        const double S = b.nh_state[4 * (int64_t)r + 2];
+        const double S = scaled ? b.nh_state[4 * (int64_t)r + 2] : 1.0;
         const double acc = P.ns == 1 ? P.accel : G.accel[ty & 0x3F];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1666,7 +1680,9 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
     } else if (!fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
-        force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+        if (fl.energy)  // per-step energies
+            force_launch<R, S, NP, ND, EV, true, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+        else force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy == 3) {  // full-matrix barostat: closing kick, virial tensor
         force_launch<R, S, NP, ND, EV, 3, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy) {  // barostat: closing kick with the stress, forces kept
@@ -1706,7 +1722,8 @@ static void force_half_variant(const Buffers& b, int p, int q, const KernelShape
     } else if (!fl.close && fl.open) {
         integrate_half<S, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
-        integrate_half<S, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+        if (fl.energy) integrate_half<S, true, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+        else integrate_half<S, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {
         integrate_half<S, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else {
@@ -1762,10 +1779,10 @@ void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotAr
 }
 
 void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
-                    hipStream_t s)
+                    int scaled, hipStream_t s)
 {
     hipLaunchKernelGGL(k_nh_open, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, P, dt_fs,
-                       k.compact);
+                       k.compact, scaled);
 }
 
 void launch_pr_chunk_sums(const Buffers& b, const KernelShape& k, int n_terms, hipStream_t s)
@@ -1827,6 +1844,11 @@ void launch_gear_correct(const Buffers& b, int p, int q, const KernelShape& k, c
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s)
 {
     hipLaunchKernelGGL(k_nh_scale, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, st, energy);
+}
+
+void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t ring_len, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_energy_ring_push, dim3(1), dim3(kBlock), 0, s, b, k.n_replicas, ring_len);
 }
 
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)

@@ -636,7 +636,9 @@ static void brick_force_variant(const Buffers& b, int p, int q, const KernelShap
     } else if (!fl.close && fl.open) {
         brick_force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
     } else if (fl.close && fl.open) {
-        brick_force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
+        if (fl.energy)  // per-step energies
+            brick_force_launch<R, S, NP, ND, EV, true, true, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
+        else brick_force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, precision, dt_fs, st, s);
     } else if (!fl.writeback) {
         brick_force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, precision, dt_fs, st, s);
     } else {

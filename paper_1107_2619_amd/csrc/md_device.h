@@ -541,9 +541,9 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         const double p_half = -(f[0] * Rp.vp[0] + f[1] * Rp.vp[1] + f[2] * Rp.vp[2]) * 0.5 * dt;
         double acc = b.pwork[q][t];
         if (CLOSE) acc += p_half;
+        pw = acc;  // the work up to this state
         if (OPEN) acc += p_half;
         if (CLOSE || OPEN) b.pwork[q][t] = acc;
-        pw = acc;
         if (OPEN) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] += dt * Rp.vp[a];
@@ -585,9 +585,9 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
 #pragma unroll
         for (int k = 0; k < (ENERGY == 3 ? 6 : 3); ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
     }
-    if (!OPEN && !WRITEBACK) {
-        // thermostatted steps: the opening kick runs after the kinetic-energy
-        // reduction and reads the force from here
+    if (!OPEN) {
+        // kept for the opening kick that runs later: after the thermostat's
+        // kinetic-energy reduction, or at the start of the next md_step call
 #pragma unroll
         for (int a = 0; a < 3; ++a) b.fhalf[a][t] = f[a];
     }

@@ -198,6 +198,8 @@ struct Buffers {
     double *tab_force64, *tab_energy64, *tab_dens64;
     float *tab_force32, *tab_energy32, *tab_dens32;
     int32_t* flags;       // [F_COUNT]
+    double* ering;        // [ring_len][R][kEnergySlots] per-replica totals of the per-step energy steps
+    int64_t* ering_count; // entries appended since md_bind (entry i lives at i % ring_len)
 };
 
 struct KernelShape {
@@ -242,13 +244,18 @@ struct ForceFlags {
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
+// Appends the per-replica totals of the last reduction to the energy ring.
+void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t ring_len, hipStream_t s);
 // Nose-Hoover thermostat: kinetic energy per replica and `halves` thermostat
 // half steps of length dt/2 (launch_nh_update); then either the scaled opening
 // kick and drift (launch_nh_open) or the final scaling (launch_nh_scale).
 void launch_nh_update(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, int halves, double dt_fs,
                       hipStream_t s);
+// scaled = 1: the thermostat's velocity scale first (NVT); 0: the plain
+// opening kick and drift from the kept forces (an md_step call continuing
+// from the last one).
 void launch_nh_open(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
-                    hipStream_t s);
+                    int scaled, hipStream_t s);
 void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_state& st, int energy, hipStream_t s);
 // Brick path (kernels_brick.hip).
 void launch_gear_start(const Buffers& b, int q, const KernelShape& k, const PotArgs& P, hipStream_t s);

@@ -63,6 +63,16 @@ struct md_ctx {
     md_state st{};
     void* ws = nullptr;
     bool bound = false, have_slots = false, have_list = false, have_energy = false;
+    // md_step may continue from its own state: the internal positions and
+    // velocities are those it wrote back, and fhalf holds the forces of the
+    // final step (cleared by any call that could change either)
+    bool resume_ok = false;
+    // per-step energies: every energy_every-th step also reduces PE, KE and the
+    // virial and appends them to a device ring of ring_len entries
+    int32_t energy_every = 0;
+    int64_t ring_len = 0;
+    std::vector<int64_t> ring_steps;  // step index of every entry appended (host log)
+    int64_t ring_read = 0;            // entries already returned by md_energy_history
     Buffers buf{};
     int p = 0, q = 0;
     int64_t step = 0, built_at = -1, n_builds = 0, max_count = 0;
@@ -407,10 +417,12 @@ bool build_tables(md_ctx* c)
         for (int k = 0; k < nk; ++k) {
             if (amp[k] == 0.0) continue;
             const bool grid = on_grid(rk[k], w);
-            // bin of the knot: the bin it closes (grid) or the one it lies in
-            const int64_t kb = grid ? std::llround(rk[k] / w) - 1 : (int64_t)std::floor(rk[k] / w);
+            // a knot on the grid closes bin llround(rk / w) - 1 and is on across
+            // it and every bin below; a knot inside bin kb is on across the bins
+            // below kb and becomes a split term of bin kb
+            const int64_t kb = grid ? std::llround(rk[k] / w) : (int64_t)std::floor(rk[k] / w);
             const double D = rk[k] - base, a = amp[k];
-            if (kb > b) {  // switched on across the whole bin
+            if (b < kb) {  // switched on across the whole bin
                 out[0] += a * D * D * D;
                 out[1] += -3.0 * a * D * D;
                 out[2] += 3.0 * a * D;
@@ -458,7 +470,9 @@ void plan_workspace(md_ctx* c)
     size_t max_bricks = 0;
     for (int r = 0; r < c->R; ++r)
         max_bricks += (size_t)c->reps[r].nc[0] * c->reps[r].nc[1] * c->reps[r].nc[2];
-    const bool keep_f = c->nbr_mode == MD_NBR_HALF_ATOMIC || c->nvt || c->gear || c->pr;
+    // forces kept per slot: the half list's accumulators, the thermostat's,
+    // barostat's and Gear's kick, and the forces an md_step call resumes from
+    const bool keep_f = true;
     const size_t gear = c->gear ? Np * 8 : 0;
     std::vector<size_t> sizes = {
         Np * 32, Np * 32,                                    // pos[2]
@@ -512,6 +526,8 @@ void plan_workspace(md_ctx* c)
         c->pr ? (size_t)c->R * 16 : 0,                       // pr_param
         c->pr ? (size_t)c->R * (c->tri ? kPrtState : kPrState) * 8 : 0,  // pr_state
         c->pr ? Np / kWave * (c->tri ? 12 : 6) * 8 : 0,      // pr_partial
+        (size_t)c->ring_len * c->R * kEnergySlots * 8,       // ering
+        8,                                                   // ering_count
     };
     c->off.clear();
     size_t o = 0;
@@ -598,6 +614,8 @@ void bind_buffers(md_ctx* c)
     at(b.pr_param);
     at(b.pr_state);
     at(b.pr_partial);
+    at(b.ering);
+    at(b.ering_count);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -699,6 +717,12 @@ void reduce_energies(md_ctx* c, const KernelShape& k, hipStream_t s)
     // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
     launch_reduce_energies(c->buf, k, c->nbr_mode == MD_NBR_HALF_ATOMIC ? -1.0 : -0.5, s);
     c->have_energy = true;
+    // steps on the per-step energy schedule also append the totals to the ring
+    // (the device counter picks the entry, so graph replays append in turn)
+    if (c->ring_len > 0 && c->energy_every > 0 && c->step % c->energy_every == 0) {
+        launch_energy_ring_push(c->buf, k, c->ring_len, s);
+        c->ring_steps.push_back(c->step);
+    }
 }
 
 // Density and force passes.  reduce = false leaves the energy reduction to
@@ -729,7 +753,7 @@ void nh_boundary(md_ctx* c, int halves, hipStream_t s)
     const KernelShape k = shape(c);
     Timed tm(c, MD_KT_FORCE, s);
     launch_nh_update(c->buf, c->q, k, c->args, halves, c->dt_fs, s);
-    launch_nh_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, s);
+    launch_nh_open(c->buf, c->p, c->q, k, c->args, c->dt_fs, 1, s);
     c->p ^= 1;
 }
 
@@ -795,7 +819,8 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
             forces(c, ForceFlags{0, 1, 0, 0}, s);  // closing kick, forces kept
             nh_boundary(c, 2, s);
         } else {
-            forces(c, ForceFlags{0, 1, 1, 0}, s);
+            const int e = c->energy_every > 0 && c->step % c->energy_every == 0 ? 1 : 0;
+            forces(c, ForceFlags{e, 1, 1, 0}, s);
         }
     }
 }
@@ -834,6 +859,9 @@ bool replay_period(md_ctx* c, hipStream_t s)
         c->step = step0 + P;
         c->n_builds = builds0 + 2;
         c->built_at = c->step;
+        if (c->ring_len > 0 && c->energy_every > 0 && !c->nvt && !c->pr && !c->gear)
+            for (int64_t t = step0 + 1; t <= step0 + P; ++t)
+                if (t % c->energy_every == 0) c->ring_steps.push_back(t);
     }
     ++c->graph_launches;
     return hip_ok(c, hipEventRecord(c->graph_ev[0], s), "graph launch") &&
@@ -841,6 +869,70 @@ bool replay_period(md_ctx* c, hipStream_t s)
            hip_ok(c, hipGraphLaunch(c->graph_exec[key], gs), "graph launch") &&
            hip_ok(c, hipEventRecord(c->graph_ev[1], gs), "graph launch") &&
            hip_ok(c, hipStreamWaitEvent(s, c->graph_ev[1], 0), "graph launch");
+}
+
+// Per-replica quantities from the reduced totals v[kEnergySlots] of one
+// state (nh, pr: the thermostat and barostat states of all replicas, read only
+// with those enabled).
+void fill_energies(const md_ctx* c, int r, const double* v, const std::vector<double>& nh,
+                   const std::vector<double>& pr, int64_t step, md_energies& o)
+{
+    const int nps = c->tri ? kPrtState : kPrState;
+    std::memset(&o, 0, sizeof o);
+    const DevReplica& D = c->reps[r];
+    const bool has_rigid = c->n_mobile[r] < D.n_atoms;
+    const int64_t dof = has_rigid ? 3 * c->n_mobile[r] : 3 * c->n_mobile[r] - 3;
+    o.pe = v[E_PE];
+    o.ke = v[E_KE];
+    o.temperature = dof > 0 ? 2.0 * o.ke / ((double)dof * kBoltzmannEv) : 0.0;
+    if (c->tri) {
+        // the box matrix, its edge lengths and volume; with the barostat the
+        // energy P Omega + W tr(dh/dt^T dh/dt) / 2 + Omega0 tr((S - P) eps),
+        // eps = (h0^-T h^T h h0^-1 - 1) / 2 the strain from the bound box h0
+        const double* h = c->pr ? &pr[(size_t)nps * r] : &c->hmat[9 * (size_t)r];
+        std::memcpy(o.h, h, sizeof o.h);
+        for (int a = 0; a < 3; ++a) o.box[a] = std::sqrt(h[a] * h[a] + h[3 + a] * h[3 + a] + h[6 + a] * h[6 + a]);
+        o.volume = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) + h[2] * (h[3] * h[7] - h[4] * h[6]);
+        if (c->pr) {
+            const double* hd = &pr[(size_t)nps * r + 9];
+            const double* h0 = &c->hmat[9 * (size_t)r];
+            double kb = 0.0;
+            for (int e = 0; e < 9; ++e) kb += hd[e] * hd[e];
+            double h0i[9], f[9], eps[9];
+            invert3(h0, h0i);
+            for (int i = 0; i < 3; ++i)  // f = h h0^-1
+                for (int j = 0; j < 3; ++j) f[3 * i + j] = h[3 * i] * h0i[j] + h[3 * i + 1] * h0i[3 + j] + h[3 * i + 2] * h0i[6 + j];
+            for (int i = 0; i < 3; ++i)  // eps = (f^T f - 1) / 2
+                for (int j = 0; j < 3; ++j)
+                    eps[3 * i + j] = 0.5 * (f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j] - (i == j ? 1.0 : 0.0));
+            const double om0 = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
+                               h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
+            double el = 0.0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    el += (c->pr_S[9 * (size_t)r + 3 * i + j] - (i == j ? c->pr_P[r] : 0.0)) * eps[3 * j + i];
+            o.pr_energy = (c->pr_P[r] * o.volume + om0 * el) / kEvPerA3InGpa + 0.5 * c->pr_W[r] * kb;
+        }
+    } else {
+        for (int a = 0; a < 3; ++a) o.box[a] = c->pr ? pr[(size_t)kPrState * r + a] : D.box[a];
+        for (int a = 0; a < 3; ++a) o.h[4 * a] = o.box[a];
+        o.volume = o.box[0] * o.box[1] * o.box[2];
+        if (c->pr) {
+            const double* ld = &pr[(size_t)kPrState * r + 3];
+            o.pr_energy = c->pr_P[r] / kEvPerA3InGpa * o.volume + 0.5 * c->pr_W[r] * (ld[0] * ld[0] + ld[1] * ld[1] + ld[2] * ld[2]);
+        }
+    }
+    for (int k = 0; k < 6; ++k) o.virial[k] = v[E_W0 + k];
+    o.pressure_gpa = (2.0 * o.ke + o.virial[0] + o.virial[1] + o.virial[2]) / (3.0 * o.volume) * kEvPerA3InGpa;
+    o.piston_work = v[E_PW];
+    o.step = step;
+    o.n_atoms = D.n_atoms;
+    o.n_mobile = c->n_mobile[r];
+    if (c->nvt) {
+        const double Q = c->nh_gkt[2 * r], gkt = c->nh_gkt[2 * r + 1], pi = nh[4 * r], xi = nh[4 * r + 1];
+        o.nh_pi = pi;
+        o.nh_energy = 0.5 * Q * pi * pi + gkt * xi;
+    }
 }
 
 }  // namespace
@@ -1188,7 +1280,8 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         !hip_ok(c, hipMemcpy(c->buf.chunk_off, c->chunk_off.data(), c->chunk_off.size() * 4, hipMemcpyHostToDevice), "md_bind upload") ||
         (!c->chunk_rep.empty() &&
          !hip_ok(c, hipMemcpy(c->buf.chunk_rep, c->chunk_rep.data(), c->chunk_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
-        !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags"))
+        !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags") ||
+        !hip_ok(c, hipMemset(c->buf.ering_count, 0, 8), "md_bind energy ring"))
         return MD_ERR_DEVICE;
     if (c->table_ok &&
         (!hip_ok(c, hipMemcpy(c->buf.tab_force64, c->tf64.data(), c->tf64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
@@ -1278,6 +1371,9 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     }
     c->bound = true;
     c->gear_ready = false;
+    c->resume_ok = false;
+    c->ring_steps.clear();
+    c->ring_read = 0;
     c->drop_graphs();
     if (!build_cell_table(c)) return MD_ERR_DEVICE;
     c->have_slots = c->have_list = c->have_energy = false;
@@ -1294,6 +1390,7 @@ int md_build_neighbours(md_ctx* c, void* stream)
 {
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_build_neighbours: call md_bind first");
+    c->resume_ok = false;
     hipStream_t s = as_stream(stream);
     load_state(c, s, true);
     rebuild(c, s, false);
@@ -1304,6 +1401,7 @@ int md_eam_forces(md_ctx* c, int want_energy, void* stream)
 {
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_eam_forces: call md_bind first");
+    c->resume_ok = false;
     hipStream_t s = as_stream(stream);
     load_state(c, s, !c->have_list);
     if (!c->have_list) rebuild(c, s, false);
@@ -1317,10 +1415,23 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_step: call md_bind first");
     if (nsteps < 1) return fail(c, MD_ERR_ARG, "md_step: nsteps must be >= 1");
     hipStream_t s = as_stream(stream);
-    const bool build = !c->have_list || due(c);
-    load_state(c, s, build);
+    // continuing from the last md_step call (no md_state_changed, md_bind or
+    // other call in between): the internal state and the kept forces are
+    // current, so the step starts with the opening kick and drift alone
+    const bool resume = c->resume_ok && !c->gear && !c->pr && c->have_list && !due(c);
+    c->resume_ok = false;
+    const bool build = !resume && (!c->have_list || due(c));
+    if (!resume) load_state(c, s, build);
     if (build) rebuild(c, s, true);
-    if (c->gear) {
+    if (resume) {
+        if (c->nvt) {
+            nh_boundary(c, 1, s);  // thermostat half step, opening kick, drift
+        } else {
+            Timed tm(c, MD_KT_FORCE, s);
+            launch_nh_open(c->buf, c->p, c->q, shape(c), c->args, c->dt_fs, 0, s);  // opening kick, drift
+            c->p ^= 1;
+        }
+    } else if (c->gear) {
         if (!c->gear_ready) {
             forces(c, ForceFlags{0, 0, 0, 0}, s);  // f(x0): a = f/m, da/dt = 0
             launch_gear_start(c->buf, c->q, shape(c), c->args, s);
@@ -1385,7 +1496,9 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     } else {
         forces(c, ForceFlags{1, 1, 0, 1}, s);  // closing kick, energies, write back
     }
-    return check_launch(c);
+    const int rc = check_launch(c);
+    c->resume_ok = rc == MD_OK && !c->gear && !c->pr;
+    return rc;
 }
 
 int md_energy(md_ctx* c, md_energies* out, void* stream)
@@ -1408,65 +1521,7 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     std::vector<double> pr((size_t)c->R * nps, 0.0);
     if (c->pr && !hip_ok(c, hipMemcpy(pr.data(), c->buf.pr_state, pr.size() * 8, hipMemcpyDeviceToHost), "md_energy barostat"))
         return MD_ERR_DEVICE;
-    for (int r = 0; r < c->R; ++r) {
-        const double* v = e.data() + (size_t)r * kEnergySlots;
-        md_energies& o = out[r];
-        std::memset(&o, 0, sizeof o);
-        const DevReplica& D = c->reps[r];
-        const bool has_rigid = c->n_mobile[r] < D.n_atoms;
-        const int64_t dof = has_rigid ? 3 * c->n_mobile[r] : 3 * c->n_mobile[r] - 3;
-        o.pe = v[E_PE];
-        o.ke = v[E_KE];
-        o.temperature = dof > 0 ? 2.0 * o.ke / ((double)dof * kBoltzmannEv) : 0.0;
-        if (c->tri) {
-            // the box matrix, its edge lengths and volume; with the barostat the
-            // energy P Omega + W tr(dh/dt^T dh/dt) / 2 + Omega0 tr((S - P) eps),
-            // eps = (h0^-T h^T h h0^-1 - 1) / 2 the strain from the bound box h0
-            const double* h = c->pr ? &pr[(size_t)nps * r] : &c->hmat[9 * (size_t)r];
-            std::memcpy(o.h, h, sizeof o.h);
-            for (int a = 0; a < 3; ++a) o.box[a] = std::sqrt(h[a] * h[a] + h[3 + a] * h[3 + a] + h[6 + a] * h[6 + a]);
-            o.volume = h[0] * (h[4] * h[8] - h[5] * h[7]) - h[1] * (h[3] * h[8] - h[5] * h[6]) + h[2] * (h[3] * h[7] - h[4] * h[6]);
-            if (c->pr) {
-                const double* hd = &pr[(size_t)nps * r + 9];
-                const double* h0 = &c->hmat[9 * (size_t)r];
-                double kb = 0.0;
-                for (int e = 0; e < 9; ++e) kb += hd[e] * hd[e];
-                double h0i[9], f[9], eps[9];
-                invert3(h0, h0i);
-                for (int i = 0; i < 3; ++i)  // f = h h0^-1
-                    for (int j = 0; j < 3; ++j) f[3 * i + j] = h[3 * i] * h0i[j] + h[3 * i + 1] * h0i[3 + j] + h[3 * i + 2] * h0i[6 + j];
-                for (int i = 0; i < 3; ++i)  // eps = (f^T f - 1) / 2
-                    for (int j = 0; j < 3; ++j)
-                        eps[3 * i + j] = 0.5 * (f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j] - (i == j ? 1.0 : 0.0));
-                const double om0 = h0[0] * (h0[4] * h0[8] - h0[5] * h0[7]) - h0[1] * (h0[3] * h0[8] - h0[5] * h0[6]) +
-                                   h0[2] * (h0[3] * h0[7] - h0[4] * h0[6]);
-                double el = 0.0;
-                for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j)
-                        el += (c->pr_S[9 * (size_t)r + 3 * i + j] - (i == j ? c->pr_P[r] : 0.0)) * eps[3 * j + i];
-                o.pr_energy = (c->pr_P[r] * o.volume + om0 * el) / kEvPerA3InGpa + 0.5 * c->pr_W[r] * kb;
-            }
-        } else {
-            for (int a = 0; a < 3; ++a) o.box[a] = c->pr ? pr[(size_t)kPrState * r + a] : D.box[a];
-            for (int a = 0; a < 3; ++a) o.h[4 * a] = o.box[a];
-            o.volume = o.box[0] * o.box[1] * o.box[2];
-            if (c->pr) {
-                const double* ld = &pr[(size_t)kPrState * r + 3];
-                o.pr_energy = c->pr_P[r] / kEvPerA3InGpa * o.volume + 0.5 * c->pr_W[r] * (ld[0] * ld[0] + ld[1] * ld[1] + ld[2] * ld[2]);
-            }
-        }
-        for (int k = 0; k < 6; ++k) o.virial[k] = v[E_W0 + k];
-        o.pressure_gpa = (2.0 * o.ke + o.virial[0] + o.virial[1] + o.virial[2]) / (3.0 * o.volume) * kEvPerA3InGpa;
-        o.piston_work = v[E_PW];
-        o.step = c->step;
-        o.n_atoms = D.n_atoms;
-        o.n_mobile = c->n_mobile[r];
-        if (c->nvt) {
-            const double Q = c->nh_gkt[2 * r], gkt = c->nh_gkt[2 * r + 1], pi = nh[4 * r], xi = nh[4 * r + 1];
-            o.nh_pi = pi;
-            o.nh_energy = 0.5 * Q * pi * pi + gkt * xi;
-        }
-    }
+    for (int r = 0; r < c->R; ++r) fill_energies(c, r, e.data() + (size_t)r * kEnergySlots, nh, pr, c->step, out[r]);
     // a non-finite state first: it also trips the displacement checks
     for (int r = 0; r < c->R; ++r) {
         const double* v = e.data() + (size_t)r * kEnergySlots;
@@ -1496,6 +1551,41 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
                       flags[F_COMPACT], kCompactCells);
         return fail(c, MD_ERR_SKIN, msg);
     }
+    return MD_OK;
+}
+
+int md_energy_history(md_ctx* c, md_energies* out, int64_t max_entries, int64_t* n_out, void* stream)
+{
+    if (!c || !n_out || (max_entries > 0 && !out)) return fail(c, MD_ERR_ARG, "md_energy_history: NULL argument");
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_energy_history: call md_bind first");
+    *n_out = 0;
+    if (max_entries < 0) return fail(c, MD_ERR_ARG, "md_energy_history: max_entries must be >= 0");
+    if (c->ring_len == 0) return MD_OK;
+    if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_energy_history sync")) return MD_ERR_DEVICE;
+    const int64_t pushed = (int64_t)c->ring_steps.size();
+    // entries older than the ring holds were overwritten: skip them
+    c->ring_read = std::max(c->ring_read, pushed - c->ring_len);
+    const int64_t n = std::min(pushed - c->ring_read, max_entries);
+    const size_t per = (size_t)c->R * kEnergySlots;
+    std::vector<double> v(per);
+    const std::vector<double> none;
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t i = c->ring_read + j;
+        if (!hip_ok(c, hipMemcpy(v.data(), c->buf.ering + (size_t)(i % c->ring_len) * per, per * 8,
+                                 hipMemcpyDeviceToHost), "md_energy_history copy"))
+            return MD_ERR_DEVICE;
+        for (int r = 0; r < c->R; ++r)
+            fill_energies(c, r, v.data() + (size_t)r * kEnergySlots, none, none, c->ring_steps[i], out[j * c->R + r]);
+    }
+    c->ring_read += n;
+    *n_out = n;
+    return MD_OK;
+}
+
+int md_state_changed(md_ctx* c)
+{
+    if (!c) return MD_ERR_ARG;
+    c->resume_ok = false;
     return MD_OK;
 }
 
@@ -1559,7 +1649,22 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
 {
     if (!c) return MD_ERR_ARG;
     if (option != MD_OPT_TIMING) c->drop_graphs();  // captured launches hold the old settings
+    // options that change the list or the evaluation make the next md_step
+    // start afresh; timing, graph replay and the energy schedule do not
+    if (option != MD_OPT_TIMING && option != MD_OPT_USE_GRAPH && option != MD_OPT_ENERGY_EVERY) c->resume_ok = false;
     switch (option) {
+    case MD_OPT_ENERGY_EVERY:
+        if (value < 0 || value > (int64_t)1 << 30) return fail(c, MD_ERR_ARG, "energy_every must be 0..2^30");
+        if (value > 0 && (c->nvt || c->pr || c->gear))
+            return fail(c, MD_ERR_ARG, "per-step energies are for velocity-Verlet NVE runs");
+        c->energy_every = (int32_t)value;
+        return MD_OK;
+    case MD_OPT_ENERGY_RING:
+        if (c->bound) return fail(c, MD_ERR_STATE, "set the energy ring length before md_bind");
+        if (value < 0 || value > (int64_t)1 << 24) return fail(c, MD_ERR_ARG, "energy ring length must be 0..2^24");
+        c->ring_len = value;
+        plan_workspace(c);  // the ring lives in the workspace
+        return MD_OK;
     case MD_OPT_LANES_PER_ATOM:
         if (value != 0 && value != 1 && value != 2 && value != 4) return fail(c, MD_ERR_ARG, "lanes per atom must be 0 (automatic), 1, 2 or 4");
         c->lanes = (int32_t)value;
@@ -1622,6 +1727,7 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
 {
     if (!c) return MD_ERR_ARG;
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_autotune: call md_bind first");
+    c->resume_ok = false;
     if (trials < 1 || trials > 1000) return fail(c, MD_ERR_ARG, "md_autotune: trials must be 1..1000");
     if (c->timing) return fail(c, MD_ERR_STATE, "md_autotune: turn MD_OPT_TIMING off first");
     hipStream_t s = as_stream(stream);
@@ -1703,6 +1809,8 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
     case MD_OPT_BRICK_BLOCK: *value = c->brick_block; return MD_OK;
     case MD_OPT_HALO_CAP: *value = c->halo_cap; return MD_OK;
     case MD_OPT_HALO_OVERFLOWS: *value = c->halo_overflows; return MD_OK;
+    case MD_OPT_ENERGY_EVERY: *value = c->energy_every; return MD_OK;
+    case MD_OPT_ENERGY_RING: *value = c->ring_len; return MD_OK;
     default: return MD_ERR_ARG;
     }
 }

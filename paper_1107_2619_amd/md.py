@@ -37,12 +37,13 @@ MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_O
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
 MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS, MD_OPT_COMPACT = 12, 13, 14
+MD_OPT_ENERGY_EVERY, MD_OPT_ENERGY_RING = 15, 16
 KERNEL_GROUPS = ("build", "density", "force", "reduce")
 
 EXPORTED = [
     "md_create", "md_workspace_bytes", "md_bind", "md_build_neighbours", "md_eam_forces", "md_step",
     "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_autotune",
-    "md_msd", "md_msd_origin", "md_destroy", "md_last_error",
+    "md_msd", "md_msd_origin", "md_energy_history", "md_state_changed", "md_destroy", "md_last_error",
 ]
 
 
@@ -128,6 +129,8 @@ def library():
     lib.md_autotune.argtypes = [vp, i32, vp]
     lib.md_msd.argtypes = [vp, vp, vp, vp]
     lib.md_msd_origin.argtypes = [vp, vp]
+    lib.md_energy_history.argtypes = [vp, ctypes.POINTER(_Energies), i64, ctypes.POINTER(i64), vp]
+    lib.md_state_changed.argtypes = [vp]
     lib.md_destroy.argtypes = [vp]
     lib.md_destroy.restype = None
     lib.md_last_error.argtypes = [vp]
@@ -259,7 +262,7 @@ class Simulation:
     def __init__(self, system, *, precision="fp64", nbr_mode="full", max_neighbours=None, lanes_per_atom=0,
                  device="cuda:0", want_e_atom=True, rebuild_every=None, skin=None, nh_temperature=None,
                  nh_mass=None, integrator="verlet", pr_pressure_gpa=None, pr_mass=None, box_matrix=None,
-                 pr_stress_gpa=None):
+                 pr_stress_gpa=None, energy_ring=0):
         import torch
 
         self.torch = torch
@@ -275,6 +278,8 @@ class Simulation:
             nh_temperature=nh_temperature, nh_mass=nh_mass, integrator=integrator,
             pr_pressure_gpa=pr_pressure_gpa, pr_mass=pr_mass, box_matrix=box_matrix, pr_stress_gpa=pr_stress_gpa,
         )
+        if energy_ring:  # sizes the workspace, so before it is allocated
+            self.ctx.set_option(MD_OPT_ENERGY_RING, int(energy_ring))
         d = self.device
         f64 = dict(dtype=torch.float64, device=d)
         n = system.n_atoms
@@ -314,6 +319,11 @@ class Simulation:
         if vel is not None:
             v = t.as_tensor(np.asarray(vel, np.float64), device=self.device)
             self.vx.copy_(v[:, 0]), self.vy.copy_(v[:, 1]), self.vz.copy_(v[:, 2])
+        self.state_changed()
+
+    def state_changed(self):
+        """Tell the library the bound arrays were written (md_state_changed)."""
+        self.ctx._check(self.ctx.lib.md_state_changed(self.ctx.handle))
 
     def rebind(self):
         """Re-attach the same buffers (resets step counter, list and piston work)."""
@@ -341,6 +351,25 @@ class Simulation:
                         np.array([list(o.virial) for o in out]), int(out[0].step), g("n_atoms"), g("n_mobile"),
                         g("nh_pi"), g("nh_energy"), np.array([list(o.box) for o in out]), g("pr_energy"),
                         np.array([list(o.h) for o in out]).reshape(R, 3, 3))
+
+    def energy_history(self, max_entries=10000) -> list:
+        """Per-step energies appended since the last call (md_energy_history):
+        a list of Energies, one per sampled step, oldest first."""
+        R = self.ctx.n_replicas
+        out = (_Energies * (R * max_entries))()
+        n = ctypes.c_int64(0)
+        self.ctx._check(self.ctx.lib.md_energy_history(self.ctx.handle, out, int(max_entries), ctypes.byref(n),
+                                                       self.stream))
+        res = []
+        for j in range(n.value):
+            rec = out[j * R:(j + 1) * R]
+            g = lambda name: np.array([getattr(o, name) for o in rec])  # noqa: E731
+            res.append(Energies(g("pe"), g("ke"), g("temperature"), g("pressure_gpa"), g("volume"),
+                                g("piston_work"), np.array([list(o.virial) for o in rec]), int(rec[0].step),
+                                g("n_atoms"), g("n_mobile"), g("nh_pi"), g("nh_energy"),
+                                np.array([list(o.box) for o in rec]), g("pr_energy"),
+                                np.array([list(o.h) for o in rec]).reshape(R, 3, 3)))
+        return res
 
     def msd(self):
         """(msd [R, n_species] A^2, count [R, n_species]): mean square displacement

@@ -303,3 +303,23 @@ def test_box_matrix_validation(md):
     with pytest.raises(md.MDError) as e:
         md.Context(s.potential, s.atom_offset, s.box, [[1, 1, 0]], box_matrix=skew, **base)
     assert e.value.code == md.MD_ERR_ARG
+
+
+def test_energy_ring_options(md):
+    """The per-step energy ring sizes the workspace (set before md_bind); the
+    schedule is for velocity-Verlet NVE runs."""
+    c = _ctx(md)
+    base = c.workspace_bytes()
+    c.set_option(md.MD_OPT_ENERGY_RING, 1000)
+    assert c.get_option(md.MD_OPT_ENERGY_RING) == 1000
+    assert c.workspace_bytes() >= base + 1000 * 12 * 8 - 256
+    c.set_option(md.MD_OPT_ENERGY_EVERY, 5)
+    assert c.get_option(md.MD_OPT_ENERGY_EVERY) == 5
+    for opt, val in ((md.MD_OPT_ENERGY_RING, -1), (md.MD_OPT_ENERGY_EVERY, -2)):
+        with pytest.raises(md.MDError) as e:
+            c.set_option(opt, val)
+        assert e.value.code == md.MD_ERR_ARG
+    nvt = _ctx(md, nh_temperature=[300.0], nh_mass=[1e4])
+    with pytest.raises(md.MDError) as e:
+        nvt.set_option(md.MD_OPT_ENERGY_EVERY, 1)
+    assert e.value.code == md.MD_ERR_ARG
