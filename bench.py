@@ -181,9 +181,12 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
         sim.set_option(md.MD_OPT_ENERGY_EVERY, energy_every)
     if not timing:
         sim.set_option(md.MD_OPT_USE_GRAPH, 1)
-        # two warmup calls long enough to capture the graphs of both ping-pong
-        # states a call can start in (a graph spans two rebuild periods)
-        calls = [max(warmup, 4 * system.rebuild_every + 2)] * 2
+        # two warm-up calls long enough to capture the graphs of both ping-pong
+        # states a call can start in (a graph spans two rebuild periods), each a
+        # whole number of graph spans, so that the timed call starts on a span
+        # boundary and replays its steps from the graphs
+        span = 2 * system.rebuild_every
+        calls = [span * -(-max(warmup, 2 * span + 2) // span)] * 2
     else:
         calls = [warmup]
     sim.set_option(md.MD_OPT_TIMING, 1 if timing else 0)

@@ -312,7 +312,13 @@ enum {
                                   md_potential lists) */
     MD_OPT_KERNEL = 7,         /* 0 = LDS link-cell bricks (full list only),
                                   1 = one thread per atom with global gathers
-                                      (default)                                      */
+                                      (default),
+                                  2 = LDS bricks whose lists keep each pair of two
+                                      atoms of one brick once, both atoms' shares
+                                      summed in LDS in 64-bit fixed point (2^-40;
+                                      a share of 1024 or more is reported as
+                                      MD_ERR_NONFINITE); md_copy_neighbours then
+                                      returns those pairs once                     */
     MD_OPT_BRICK_DIMS = 8,     /* 0 = automatic, else bx + 10 by + 100 bz cells (1..4) */
     MD_OPT_BRICK_BLOCK = 9,    /* threads per brick workgroup: 64..1024             */
     MD_OPT_HALO_CAP = 10,      /* atoms one brick's LDS staging area holds (set

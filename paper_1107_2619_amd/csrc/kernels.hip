@@ -381,13 +381,6 @@ constexpr int kCandPasses = 4;
 
 __device__ __forceinline__ double select_shift(int s, double L) { return s == 1 ? L : (s == 2 ? -L : 0.0); }
 
-// Value of lane `l` (wave-uniform) of a double.
-__device__ __forceinline__ double bcast_lane(double v, int l)
-{
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
-}
 
 // Minimum image of one pair along the axes in `amb` (periodic axes with fewer
 // than three cells), with the entry's code field updated: the image shift in

@@ -9,291 +9,137 @@
 // halo around it, cell by cell in a fixed order, each halo cell shifted into
 // the brick's periodic frame.  The Verlet list of an atom then stores 16-bit
 // LDS indices into that staging order, which stays valid until the next cell
-// sort because cell contents only change there.  Every neighbour read of the
-// three passes is an LDS read: HBM/L2 see each halo atom once per workgroup
+// sort because cell contents only change there (staging order: the brick's
+// own atoms first, then the halo ring; brick_common.h).  Every neighbour read
+// of the three passes is an LDS read: HBM/L2 see each halo atom once per workgroup
 // (about 3-5 times the brick's own atoms) instead of one 128-byte line per
 // neighbour gather, and no periodic image is computed in the force loop.
-#include "md_device.h"
+#include <algorithm>
+
+#include "brick_common.h"
 
 namespace mdk {
 namespace {
 
-// Halo bookkeeping of the staged brick (LDS).
-struct Halo {
-    int32_t cnt[kHaloMax];        // atoms of halo cell h
-    int32_t start[kHaloMax + 1];  // first LDS index of halo cell h
-    int32_t cstart[kHaloMax];     // first slot of halo cell h
-    int32_t code[kHaloMax];       // periodic shift (2 bits per axis: 1 = +L, 2 = -L)
-    int32_t hx, hy, hz, H;        // halo extent per axis and cell count
-    int32_t cell0;                // first cell of the brick
-    int32_t own_begin, own_end;   // slot range of the brick's own atoms
-    int32_t total;                // atoms staged
-};
-
-__device__ __forceinline__ int brick_of_block()
-{
-    // same die-aware remap as the slot kernels: each die gets contiguous bricks
-    return (int)logical_block();
-}
-
-// Fill the halo table and the staged positions.  `with_w` also stages F'.
-// A brick whose halo exceeds `cap` stages nothing and is evaluated from global
-// memory through the halo table (halo_fetch); flags[F_HALO] counts such
-// bricks, a performance (not a correctness) signal.
-__device__ void stage_brick(const Buffers& b, const DevReplica& R, int lb, int p, bool with_w, int cap, Halo& M,
-                            double4* lpos, int32_t* record = nullptr)
-{
-    const int tid = threadIdx.x;
-    const int bx = lb % R.nbk[0], by = (lb / R.nbk[0]) % R.nbk[1], bz = lb / (R.nbk[0] * R.nbk[1]);
-    const int base[3] = {bx * R.bd[0], by * R.bd[1], bz * R.bd[2]};
-    int m[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) m[a] = min(R.bd[a], R.nc[a] - base[a]);
-    const int hx = m[0] + 2, hy = m[1] + 2, hz = m[2] + 2, H = hx * hy * hz;
-    if (tid == 0) {
-        M.hx = hx;
-        M.hy = hy;
-        M.hz = hz;
-        M.H = H;
-        M.cell0 = cell_index(R, base[0], base[1], base[2]);
-    }
-    for (int h = tid; h < H; h += blockDim.x) {
-        const int o[3] = {h % hx - 1, (h / hx) % hy - 1, h / (hx * hy) - 1};
-        int c[3], code = 0;
-        bool exists = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            c[a] = base[a] + o[a];
-            if (R.periodic_mask & (1 << a)) {
-                if (c[a] < 0) {
-                    c[a] += R.nc[a];
-                    code |= 2 << (2 * a);
-                } else if (c[a] >= R.nc[a]) {
-                    c[a] -= R.nc[a];
-                    code |= 1 << (2 * a);
-                }
-            } else if (c[a] < 0 || c[a] >= R.nc[a]) {
-                exists = false;
-            }
-        }
-        if (exists) {
-            const int cell = cell_index(R, c[0], c[1], c[2]);
-            M.cnt[h] = b.cell_count[cell];
-            M.cstart[h] = b.cell_start[cell];
-        } else {
-            M.cnt[h] = 0;
-            M.cstart[h] = 0;
-        }
-        M.code[h] = code;
-    }
-    __syncthreads();
-    if (tid < kWave) {
-        // exclusive scan of the halo counts by the first wavefront
-        int run = 0;
-        for (int h0 = 0; h0 < H; h0 += kWave) {
-            const int h = h0 + tid;
-            const int v = h < H ? M.cnt[h] : 0;
-            int incl = v;
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const int y = __shfl_up(incl, off, kWave);
-                if (tid >= off) incl += y;
-            }
-            if (h < H) M.start[h] = run + incl - v;
-            run += __shfl(incl, kWave - 1, kWave);
-        }
-        if (tid == 0) {
-            M.start[H] = run;
-            M.total = run;
-            const int last = M.cell0 + R.cpb - 1;
-            M.own_begin = b.cell_start[M.cell0];
-            M.own_end = b.cell_start[last] + b.cell_count[last];
-            if (run > cap) atomicAdd(&b.flags[F_HALO], 1);
-        }
-    }
-    __syncthreads();
-    const int total = M.total <= cap ? M.total : 0;
-    const double4* __restrict__ pos = b.pos[p];
-    for (int i = tid; i < total; i += blockDim.x) {
-        // halo cell of staged atom i: last h with start[h] <= i
-        int lo = 0, hi = H - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (M.start[mid] <= i) lo = mid;
-            else hi = mid - 1;
-        }
-        const int slot = M.cstart[lo] + (i - M.start[lo]);
-        double4 v = with_w ? pos[slot] : make_double4(0.0, 0.0, 0.0, 0.0);
-        if (!with_w) {
-            const double3 x = load_xyz(pos, slot);
-            v.x = x.x;
-            v.y = x.y;
-            v.z = x.z;
-        }
-        const int code = M.code[lo];
-        if (code) {
-            if (code & 3) v.x += (code & 1) ? R.box[0] : -R.box[0];
-            if (code & 12) v.y += (code & 4) ? R.box[1] : -R.box[1];
-            if (code & 48) v.z += (code & 16) ? R.box[2] : -R.box[2];
-        }
-        lpos[i] = v;
-        if (record) record[i] = slot | (code << kIndexBits);
-    }
-    __syncthreads();
-}
-
-// Fast staging from the record the list build left: staging position i holds
-// slot (src & kIndexMask) shifted by the periodic code (src >> kIndexBits).
-// One coalesced read of the record, one gather per atom, no halo search.
-__device__ void stage_recorded(const Buffers& b, const DevReplica& R, const int32_t* __restrict__ src, int total,
-                               int p, int q, bool with_w, double4* lpos, uint8_t* ltype)
-{
-    const double4* __restrict__ pos = b.pos[p];
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        const int e = src[i];
-        const int slot = e & kIndexMask, code = (unsigned)e >> kIndexBits;
-        double4 v;
-        if (with_w) {
-            v = pos[slot];
-        } else {
-            const double3 x = load_xyz(pos, slot);
-            v = make_double4(x.x, x.y, x.z, 0.0);
-        }
-        if (code) {
-            if (code & 3) v.x += (code & 1) ? R.box[0] : -R.box[0];
-            if (code & 12) v.y += (code & 4) ? R.box[1] : -R.box[1];
-            if (code & 48) v.z += (code & 16) ? R.box[2] : -R.box[2];
-        }
-        lpos[i] = v;
-        if (ltype) ltype[i] = b.type[q][slot];
-    }
-    __syncthreads();
-}
-
-// Halo cell and LDS index of an own atom (slot t) of the staged brick.
-__device__ __forceinline__ void own_index(const Buffers& b, const DevReplica& R, const Halo& M, int64_t t, int& h,
-                                          int& li)
-{
-    const int local = b.cell_sorted[t] - M.cell0;
-    const int lx = local % R.bd[0], ly = (local / R.bd[0]) % R.bd[1], lz = local / (R.bd[0] * R.bd[1]);
-    h = ((lz + 1) * M.hy + (ly + 1)) * M.hx + (lx + 1);
-    li = M.start[h] + (int)(t - M.cstart[h]);
-}
-
-// Slot and periodic shift code of staging position i (binary search over the
-// halo cells' first staging positions).
-__device__ __forceinline__ int halo_slot(const Halo& M, int i, int& code)
-{
-    int lo = 0, hi = M.H - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (M.start[mid] <= i) lo = mid;
-        else hi = mid - 1;
-    }
-    code = M.code[lo];
-    return M.cstart[lo] + (i - M.start[lo]);
-}
-
-// Staged atom i read from global memory: the path of a brick whose halo did
-// not fit the staging area (same values, same order, only slower).
-__device__ __forceinline__ double4 halo_fetch(const Buffers& b, const DevReplica& R, const Halo& M, int p, int i)
-{
-    int code;
-    const int slot = halo_slot(M, i, code);
-    double4 v = b.pos[p][slot];
-    if (code) {
-        if (code & 3) v.x += (code & 1) ? R.box[0] : -R.box[0];
-        if (code & 12) v.y += (code & 4) ? R.box[1] : -R.box[1];
-        if (code & 48) v.z += (code & 16) ? R.box[2] : -R.box[2];
-    }
-    return v;
-}
-
-__device__ __forceinline__ uint8_t halo_type(const Buffers& b, const Halo& M, int q, int i)
-{
-    int code;
-    return b.type[q][halo_slot(M, i, code)];
-}
-
 // ---------------------------------------------------------------------------
-// List build: every staged atom in the 27 halo cells around the atom's cell
-// with r < r_c + skin (paper, "The Neighbourlist calculation": the cell's
-// atoms against those of the cells around it).  Entries are staging (LDS) indices,
-// uint16, one row of `rowlen` (a multiple of 8) per atom, written 8 at a time.
-__global__ __launch_bounds__(1024) void k_brick_list(Buffers b, int p, int64_t n_slots, int32_t cap, double rlist2,
-                                                     int halo_cap, int rowlen)
+// List build (paper, "The Neighbourlist calculation": every atom of a link
+// cell against the atoms of the 27 cells around it, r < r_c + skin).  One
+// wavefront per own cell of the brick: its lanes hold up to 64 candidates at a
+// time from the 27 cells (staging order), and each atom of the cell is tested
+// against them in turn, the in-range lanes packed with a ballot.  Entries are
+// staging (LDS) indices, uint16, collected per atom in an LDS row and written
+// out once per cell: the cell's atoms are consecutive slots, so their rows are
+// one contiguous run of global memory.  half = 1 keeps a pair of two own
+// atoms once, in the row of the one with the smaller staging index (the pair
+// kernels then add its share to both atoms); pairs with a halo atom are kept
+// in full, since the other atom's brick keeps them too.  A brick keeps full
+// rows instead (brick_info.w = 0) when its halo did not fit the staging area
+// or it holds more than pair_slots own atoms (one pair-kernel round).
+constexpr int kListBlock = 1024;  // threads per list-build workgroup
+constexpr int kListPasses = 4;    // candidates per lane held in registers
+constexpr int kRowAtoms = 16;    // most atoms of one cell whose rows a wavefront collects at a time
+
+__global__ __launch_bounds__(kListBlock) void k_brick_list(Buffers b, int p, int64_t n_slots, int32_t cap,
+                                                           double rlist2, int halo_cap, int rowlen, int row_atoms,
+                                                           int half, int pair_slots)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     Halo& M = *reinterpret_cast<Halo*>(smem);
     double4* lpos = reinterpret_cast<double4*>(smem + ((sizeof(Halo) + 15) / 16) * 16);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, n_waves = blockDim.x / kWave;
+    uint16_t* rows = reinterpret_cast<uint16_t*>(lpos + halo_cap) + (size_t)wave * row_atoms * rowlen;
     const int brick = brick_of_block();
     const DevReplica& R = b.reps[b.brick_rep[brick]];
     stage_brick(b, R, brick - R.brick_off, p, false, halo_cap, M, lpos, b.stage_src + (int64_t)brick * halo_cap);
     const bool staged = M.total <= halo_cap;
-    if (threadIdx.x == 0) b.brick_info[brick] = make_int4(M.own_begin, M.own_end, M.total, 0);
+    const int n_own = M.own_end - M.own_begin;
+    half = half && staged && n_own <= pair_slots;
+    if (threadIdx.x == 0) b.brick_info[brick] = make_int4(M.own_begin, M.own_end, M.total, half);
+    for (int a = threadIdx.x; a < n_own; a += blockDim.x) b.own_li[M.own_begin + a] = (uint16_t)a;
     int most = 0;
-    for (int64_t t = M.own_begin + threadIdx.x; t < M.own_end; t += blockDim.x) {
-        int h, li;
-        own_index(b, R, M, t, h, li);
-        b.own_li[t] = (uint16_t)li;
-        const double4 xi = staged ? lpos[li] : halo_fetch(b, R, M, p, li);
-        int count = 0;
-        uint4* row = reinterpret_cast<uint4*>(b.nbr16 + t * (int64_t)rowlen);
-        uint32_t pk[4] = {0, 0, 0, 0};  // entries buffered until a 16-byte store
-        {
-            for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int hh = h + (dz * M.hy + dy) * M.hx + dx;
-                        const int beg = M.start[hh], end = beg + M.cnt[hh];
-#pragma unroll 4
-                        for (int i = beg; i < end; ++i) {
-                            if (i == li) continue;
-                            const double4 xj = staged ? lpos[i] : halo_fetch(b, R, M, p, i);
-                            const double ddx = xj.x - xi.x, ddy = xj.y - xi.y, ddz = xj.z - xi.z;
-                            if (ddx * ddx + ddy * ddy + ddz * ddz < rlist2) {
-                                if (count < cap) {
-                                    const int u = count & 7;
-                                    pk[u >> 1] |= (uint32_t)i << (16 * (u & 1));
-                                    if (u == 7) {
-                                        row[count >> 3] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-                                        pk[0] = pk[1] = pk[2] = pk[3] = 0;
-                                    }
-                                }
-                                ++count;
-                            }
-                        }
-                    }
+    const int n_cells = M.m[0] * M.m[1] * M.m[2];
+    for (int lc = wave; lc < n_cells; lc += n_waves) {
+        const int lx = lc % M.m[0], ly = (lc / M.m[0]) % M.m[1], lz = lc / (M.m[0] * M.m[1]);
+        const int h = ((lz + 1) * M.hy + (ly + 1)) * M.hx + (lx + 1);
+        const int n_cell = M.cnt[h], s_cell = M.start[h];
+        if (n_cell == 0) continue;
+        // lane k < 27: neighbour cell k of the stencil, its staging range
+        int nb_start = 0, nb_count = 0;
+        if (lane < 27) {
+            const int hh = h + ((lane / 9 - 1) * M.hy + (lane / 3 % 3 - 1)) * M.hx + (lane % 3 - 1);
+            nb_start = M.start[hh];
+            nb_count = M.cnt[hh];
         }
-        const int stored = count < cap ? count : cap;
-        if (stored & 7) row[stored >> 3] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-        b.ncount[t] = stored;
-        most = max(most, count);
+        int incl = nb_count;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        const int excl = incl - nb_count;
+        const int total = uniform(__shfl(incl, kWave - 1, kWave));
+        for (int i0 = 0; i0 < n_cell; i0 += row_atoms) {
+            const int nn = min(row_atoms, n_cell - i0);
+            // lane ii < nn holds atom i0 + ii of the cell; the tests broadcast it
+            const int l0 = s_cell + i0 + min(lane, nn - 1);
+            const double4 xl = staged ? lpos[l0] : halo_fetch(b, R, M, p, l0);
+            int my_count = 0;  // lane ii: entries of atom i0 + ii so far
+            for (int g0 = 0; g0 < total; g0 += kWave * kListPasses) {
+                // kListPasses candidates per lane: the stencil cell holding candidate
+                // m is the last k with excl_k <= m (lanes past the stencil hold
+                // excl = total, so k stays below 27)
+                double cx[kListPasses], cy[kListPasses], cz[kListPasses];
+                int ce[kListPasses];
+                bool live[kListPasses];
+#pragma unroll
+                for (int u = 0; u < kListPasses; ++u) {
+                    const int m0 = g0 + u * kWave + lane;
+                    const int m = min(m0, total - 1);
+                    int k = 0;
+#pragma unroll
+                    for (int step = kWave / 2; step > 0; step >>= 1)
+                        if (__shfl(excl, k + step, kWave) <= m) k += step;
+                    const int e = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
+                    const double4 xj = staged ? lpos[e] : halo_fetch(b, R, M, p, e);
+                    cx[u] = xj.x;
+                    cy[u] = xj.y;
+                    cz[u] = xj.z;
+                    ce[u] = e;
+                    live[u] = m0 < total;
+                }
+                for (int ii = 0; ii < nn; ++ii) {
+                    const int li = s_cell + i0 + ii;
+                    const double xi = bcast_lane(xl.x, ii), yi = bcast_lane(xl.y, ii), zi = bcast_lane(xl.z, ii);
+                    int base = __builtin_amdgcn_readlane(my_count, ii);
+#pragma unroll
+                    for (int u = 0; u < kListPasses; ++u) {
+                        const double dx = cx[u] - xi, dy = cy[u] - yi, dz = cz[u] - zi;
+                        bool take = live[u] && ce[u] != li && dx * dx + dy * dy + dz * dz < rlist2;
+                        if (half) take = take && (ce[u] >= n_own || ce[u] > li);
+                        const uint64_t mask = __ballot(take);
+                        if (mask == 0) continue;
+                        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+                        if (take && base + rank < cap) rows[ii * rowlen + base + rank] = (uint16_t)ce[u];
+                        base += __popcll(mask);
+                    }
+                    if (lane == ii) my_count = base;
+                }
+            }
+            // counts, and the rows of these atoms: one contiguous run of nn rows
+            const int64_t t0 = (int64_t)M.own_begin + s_cell + i0;
+            if (lane < nn) {
+                b.ncount[t0 + lane] = min(my_count, cap);
+                most = max(most, my_count);
+            }
+            const uint4* src = reinterpret_cast<const uint4*>(rows);
+            uint4* dst = reinterpret_cast<uint4*>(b.nbr16 + t0 * rowlen);
+            for (int c = lane; c < nn * rowlen / 8; c += kWave) dst[c] = src[c];
+        }
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) most = max(most, __shfl_xor(most, off, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && most > 0 && most > b.flags[F_MAX_COUNT])
-        atomicMax(&b.flags[F_MAX_COUNT], most);
-}
-
-// LDS layout of the density / force kernels: Halo | staged atoms | tables.
-__host__ __device__ inline size_t halo_bytes() { return (sizeof(Halo) + 15) / 16 * 16; }
-
-// Stage the species/rigid byte of every staged atom (several species, or
-// rigid pairs on energy steps).
-__device__ void stage_types(const Buffers& b, int q, const Halo& M, int cap, uint8_t* ltype)
-{
-    const int total = M.total <= cap ? M.total : 0;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        int lo = 0, hi = M.H - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (M.start[mid] <= i) lo = mid;
-            else hi = mid - 1;
-        }
-        ltype[i] = b.type[q][M.cstart[lo] + (i - M.start[lo])];
-    }
-    __syncthreads();
+    if (lane == 0 && most > 0 && most > b.flags[F_MAX_COUNT]) atomicMax(&b.flags[F_MAX_COUNT], most);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,52 +335,12 @@ __global__ __launch_bounds__(1024) void k_brick_list_to_slots(Buffers b, int64_t
     __shared__ Halo M;
     const int brick = brick_of_block();
     const DevReplica& R = b.reps[b.brick_rep[brick]];
-    // halo table only (no positions)
-    const int lb = brick - R.brick_off;
-    const int bx = lb % R.nbk[0], by = (lb / R.nbk[0]) % R.nbk[1], bz = lb / (R.nbk[0] * R.nbk[1]);
-    const int base[3] = {bx * R.bd[0], by * R.bd[1], bz * R.bd[2]};
-    int m[3];
-    for (int a = 0; a < 3; ++a) m[a] = min(R.bd[a], R.nc[a] - base[a]);
-    const int hx = m[0] + 2, hy = m[1] + 2, hz = m[2] + 2, H = hx * hy * hz;
-    if (threadIdx.x == 0) {
-        M.hx = hx;
-        M.hy = hy;
-        M.hz = hz;
-        M.H = H;
-        M.cell0 = cell_index(R, base[0], base[1], base[2]);
-        int run = 0;
-        for (int h = 0; h < H; ++h) {
-            const int o[3] = {h % hx - 1, (h / hx) % hy - 1, h / (hx * hy) - 1};
-            int c[3];
-            bool exists = true;
-            for (int a = 0; a < 3; ++a) {
-                c[a] = base[a] + o[a];
-                if (R.periodic_mask & (1 << a)) c[a] = (c[a] + R.nc[a]) % R.nc[a];
-                else if (c[a] < 0 || c[a] >= R.nc[a]) exists = false;
-            }
-            const int cell = exists ? cell_index(R, c[0], c[1], c[2]) : -1;
-            M.cnt[h] = exists ? b.cell_count[cell] : 0;
-            M.cstart[h] = exists ? b.cell_start[cell] : 0;
-            M.start[h] = run;
-            run += M.cnt[h];
-        }
-        M.start[H] = run;
-        const int last = M.cell0 + R.cpb - 1;
-        M.own_begin = b.cell_start[M.cell0];
-        M.own_end = b.cell_start[last] + b.cell_count[last];
-    }
-    __syncthreads();
+    halo_table(b, R, brick - R.brick_off, M);
     for (int64_t t = M.own_begin + threadIdx.x; t < M.own_end; t += blockDim.x) {
         const int n = b.ncount[t];
         for (int k = 0; k < n; ++k) {
-            const int i = b.nbr16[t * (int64_t)rowlen + k];
-            int lo = 0, hi = H - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (M.start[mid] <= i) lo = mid;
-                else hi = mid - 1;
-            }
-            b.nbr[(int64_t)k * n_slots + t] = M.cstart[lo] + (i - M.start[lo]);
+            int code;
+            b.nbr[(int64_t)k * n_slots + t] = halo_slot(M, b.nbr16[t * (int64_t)rowlen + k], code);
         }
     }
 }
@@ -556,12 +362,19 @@ size_t brick_lds_bytes(const KernelShape& k, const PotArgs& P, int precision, in
     return bytes;
 }
 
-void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, hipStream_t s)
+// half: pairs once, for bricks with at most pair_slots own atoms (pair_slots())
+void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half,
+                       int pair_slots, hipStream_t s)
 {
     (void)q;
-    const size_t lds = halo_bytes() + (size_t)k.halo_cap * sizeof(double4);
-    hipLaunchKernelGGL(k_brick_list, dim3(k.n_bricks), dim3(k.block), lds, s, b, p, k.n_slots, k.cap, rlist2,
-                       k.halo_cap, k.rowlen);
+    const size_t base = halo_bytes() + (size_t)k.halo_cap * sizeof(double4);
+    // rows collected per wavefront: as many atoms of a cell as the LDS left allows, up to kRowAtoms
+    const size_t per_atom = (size_t)(kListBlock / kWave) * k.rowlen * sizeof(uint16_t);
+    const int row_atoms = (int)std::max<int64_t>(
+        1, std::min<int64_t>(kRowAtoms, ((int64_t)k.lds_limit - (int64_t)base) / (int64_t)per_atom));
+    const size_t lds = base + (size_t)row_atoms * per_atom;
+    hipLaunchKernelGGL(k_brick_list, dim3(k.n_bricks), dim3(kListBlock), lds, s, b, p, k.n_slots, k.cap, rlist2,
+                       k.halo_cap, k.rowlen, row_atoms, half, pair_slots);
 }
 
 template <typename R, bool S, int ND, int EV, int L>

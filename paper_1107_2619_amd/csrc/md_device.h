@@ -28,6 +28,14 @@ inline int64_t blocks_for(int64_t n) { return (n + kBlock - 1) / kBlock; }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Value of lane `l` (wave-uniform) of a double.
+__device__ __forceinline__ double bcast_lane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // ---------------------------------------------------------------------------
 // Geometry helpers (paper, "Boundary conditions": minimum image along periodic
 // axes, plain differences along free ones; positions unwrapped).

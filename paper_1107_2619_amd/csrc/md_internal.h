@@ -29,6 +29,7 @@ constexpr int kEnergyTerms = 10;       // per-atom terms written on energy steps
 constexpr int kReduceChunk = 2048;
 constexpr int kChunkedSumWaves = 512;  // replicas above this many waves sum per chunk first     // slots per first-stage reduction chunk (one workgroup each)
 constexpr int kHaloMax = 216;          // halo cells of a brick: (4 + 2)^3 at most
+constexpr int kHaloTableBytes = 5120;  // LDS of a brick's halo table (bound checked where it is defined)
 constexpr int kBrickMaxDim = 4;
 
 // Neighbour-list entry: slot index in the low kIndexBits bits, the periodic
@@ -137,7 +138,10 @@ struct PotArgs {
 // F_HALO: brick passes whose halo did not fit the LDS staging area (those
 // read their neighbours from global memory instead).  F_COMPACT: atoms too far
 // outside their link cell for the compact mixed-mode record.
-enum FlagIndex { F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_PR_BOX = 5, F_COUNT = 8 };
+// F_RANGE: a pair term beyond the fixed-point range of the pair kernels' shared accumulators.
+enum FlagIndex {
+    F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_PR_BOX = 5, F_RANGE = 6, F_COUNT = 8
+};
 
 // Pointers into the workspace.
 struct Buffers {
@@ -219,6 +223,8 @@ struct KernelShape {
     int32_t rowlen;   // entries per brick-list row: cap rounded up to 8
     int32_t compact;  // mixed mode with compact records (global path): 1 orthorhombic, 2 sheared cells
     int32_t tri;      // 1 = box matrices (sheared cells)
+    int32_t lds_limit; // LDS bytes one workgroup may use
+    int32_t pairs;     // LDS bricks with each pair of two own atoms once (MD_OPT_KERNEL = 2)
     int32_t chunked;  // 1 = per-replica sums of the thermostat and barostat start with
                       // per-chunk sums (some replica spans more than kChunkedSumWaves waves)
 };
@@ -294,12 +300,25 @@ void launch_prt_close_scale(const Buffers& b, int q, const KernelShape& k, const
 // Launchers (kernels_analysis.hip).
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);
 
-void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, hipStream_t s);
+// Lanes per atom of the pair kernels: 1 or 2 (the brick setting, 4 taken as 2).
+inline int pair_lanes(const KernelShape& k) { return k.lanes >= 2 ? 2 : 1; }
+// half = 1: pairs of two own atoms of a brick once (the pair kernels); 0: every pair from both atoms
+void launch_brick_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half,
+                       int pair_slots, hipStream_t s);
 void launch_brick_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                           int energy, hipStream_t s);
 void launch_brick_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                         ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
 void launch_brick_list_to_slots(const Buffers& b, const KernelShape& k, hipStream_t s);
 size_t brick_lds_bytes(const KernelShape& k, const PotArgs& P, int precision, int pass, int energy);
+// Pair kernels (kernels_pairs.hip): the LDS-brick passes over lists that hold
+// each pair of two own atoms once, both atoms' shares accumulated in LDS.
+// Own atoms a pair-kernel brick can hold (LDS accumulators, one round of lanes);
+// bricks with more keep full lists.
+int pair_slots(const KernelShape& k, const PotArgs& P, int precision);
+void launch_pair_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
+                         int energy, hipStream_t s);
+void launch_pair_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
+                       ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
 
 }  // namespace mdk

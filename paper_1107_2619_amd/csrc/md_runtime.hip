@@ -47,7 +47,7 @@ struct md_ctx {
     int64_t N = 0, Np = 0;
     int32_t C = 0, C_alloc = 0, scan_nb = 0;
     // brick path
-    int32_t kernel_path = 1;  // 0 = LDS bricks, 1 = global gathers
+    int32_t kernel_path = 1;  // 0 = LDS bricks, 1 = global gathers, 2 = LDS bricks with pairs once
     int32_t brick_dims = 0;   // 0 = automatic, else bd[0] + 10 bd[1] + 100 bd[2]
     int32_t brick_block = 512;
     int32_t lds_limit = 65536;
@@ -180,7 +180,8 @@ KernelShape shape(const md_ctx* c)
     k.n_chunks = (int32_t)c->chunk_rep.size();
     k.n_bricks = (int32_t)c->brick_rep.size();
     // the barostat moves the bricks' box; the brick kernels take orthorhombic boxes only
-    k.brick = c->kernel_path == 0 && c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri;
+    k.brick = c->kernel_path != 1 && c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri;
+    k.pairs = k.brick && c->kernel_path == 2;
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
     k.rowlen = (c->cap + 7) / 8 * 8;
@@ -188,6 +189,7 @@ KernelShape shape(const md_ctx* c)
     if (k.compact && c->tri) k.compact = 2;  // fractional in-cell coordinates
     k.tri = c->tri ? 1 : 0;
     k.chunked = c->chunked_sums ? 1 : 0;
+    k.lds_limit = c->lds_limit;
     return k;
 }
 
@@ -221,7 +223,7 @@ void choose_bricks(md_ctx* c, int32_t dims)
                               : 0;
     // an explicit shape may use all the LDS a workgroup can have
     const int64_t budget = dims > 0 ? (int64_t)c->lds_limit : std::min<int64_t>(kLdsBudget, c->lds_limit);
-    const int64_t max_cap = std::max<int64_t>(64, std::min<int64_t>(65535, (budget - 4608 - (int64_t)tables) / 33));
+    const int64_t max_cap = std::max<int64_t>(64, std::min<int64_t>(65535, (budget - kHaloTableBytes - (int64_t)tables) / 33));
     static const int cand[][3] = {{4, 4, 4}, {4, 4, 3}, {4, 4, 2}, {4, 3, 2}, {4, 2, 2}, {3, 2, 2},
                                   {2, 2, 2}, {2, 2, 1}, {2, 1, 1}, {1, 1, 1}};
     int64_t cells = 0, bricks = 0;
@@ -692,7 +694,9 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
     launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
     c->p ^= 1;
     c->q ^= 1;
-    if (k.brick) launch_brick_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, s);
+    if (k.brick)
+        launch_brick_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, k.pairs,
+                          k.pairs ? pair_slots(k, c->args, c->precision) : 0, s);
     else launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
     if (c->pr) launch_pr_mark_build(c->buf, k, s);
     c->have_list = true;
@@ -734,12 +738,14 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
     {
         Timed tm(c, MD_KT_DENSITY, s);
         const int fe = fl.energy == 1;  // barostat steps (energy 2) need no embedding energies
-        if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
+        if (k.pairs) launch_pair_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
+        else if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
         else launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fe, s);
     }
     {
         Timed tm(c, MD_KT_FORCE, s);
-        if (k.brick) launch_brick_force(c->buf, c->p, c->q, k, c->args, c->precision, fl, c->dt_fs, c->st, s);
+        if (k.pairs) launch_pair_force(c->buf, c->p, c->q, k, c->args, c->precision, fl, c->dt_fs, c->st, s);
+        else if (k.brick) launch_brick_force(c->buf, c->p, c->q, k, c->args, c->precision, fl, c->dt_fs, c->st, s);
         else launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
     }
     if (fl.open) c->p ^= 1;
@@ -1528,6 +1534,9 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
         if (v[E_NONFINITE] != 0.0 || !std::isfinite(v[E_PE]) || !std::isfinite(v[E_KE]))
             return fail(c, MD_ERR_NONFINITE, "non-finite energy or force in replica " + std::to_string(r));
     }
+    if (flags[F_RANGE] > 0)
+        return fail(c, MD_ERR_NONFINITE, "a pair term exceeded the range of the pair kernels' fixed-point accumulators "
+                                         "(|share| >= 1024; atoms closer than the potential is meant for?)");
     if (flags[F_MAX_COUNT] > c->cap) {
         char msg[200];
         std::snprintf(msg, sizeof msg, "neighbour list overflow: an atom has %d entries, max_neighbours is %d (set it >= %d)",
@@ -1694,7 +1703,8 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
         c->evaluator = (int32_t)value;
         return MD_OK;
     case MD_OPT_KERNEL:
-        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "kernel path must be 0 (LDS bricks) or 1 (global gathers)");
+        if (value != 0 && value != 1 && value != 2)
+            return fail(c, MD_ERR_ARG, "kernel path must be 0 (LDS bricks), 1 (global gathers) or 2 (LDS bricks, pairs once)");
         if (value != c->kernel_path) {
             c->kernel_path = (int32_t)value;
             c->have_list = false;  // the two paths keep different list formats
@@ -1742,6 +1752,8 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     for (int32_t e : evals) {
         cands.push_back({1, 0, 0, 512, e});
         if (c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri)  // the brick kernels take fixed orthorhombic boxes
+            // (the pair kernels, MD_OPT_KERNEL = 2, are left out: their LDS
+            // atomics make them several times slower on this device)
             for (int32_t dims : {0, 444, 222})
                 for (int32_t lanes : {1, 2})
                     for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block, e});
@@ -1804,7 +1816,7 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
     case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
     case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;
     case MD_OPT_EVALUATOR: *value = (c->table_ok && c->evaluator == 0) ? 0 : 1; return MD_OK;
-    case MD_OPT_KERNEL: *value = shape(c).brick ? 0 : 1; return MD_OK;
+    case MD_OPT_KERNEL: *value = shape(c).brick ? (shape(c).pairs ? 2 : 0) : 1; return MD_OK;
     case MD_OPT_BRICK_DIMS: *value = c->reps.empty() ? 0 : c->reps[0].bd[0] + 10 * c->reps[0].bd[1] + 100 * c->reps[0].bd[2]; return MD_OK;
     case MD_OPT_BRICK_BLOCK: *value = c->brick_block; return MD_OK;
     case MD_OPT_HALO_CAP: *value = c->halo_cap; return MD_OK;
