@@ -282,6 +282,19 @@ int md_energy_history(md_ctx *ctx, md_energies *out, int64_t max_entries, int64_
  * (the call synchronises the stream). */
 int md_msd(md_ctx *ctx, double *msd, int64_t *count, void *stream);
 
+/* md_msd for callers that cannot allocate device memory or must not call the
+ * allocator (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the same kernels, with their per-chunk partial sums and
+ * per-replica results in a static device array of the library (1 MiB per GPU,
+ * held until the process ends) instead of the workspace; no hipMalloc or
+ * hipFree.  msd and count (not NULL here) as for md_msd.  MD_ERR_ARG when the
+ * bound system needs more than the array holds (about 8 doubles per
+ * 2048-atom chunk of every replica plus 8 + 2 S per replica, 2^17 in all).
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (other streams or threads) race and must be serialised by the caller.
+ * Synchronises the stream. */
+int md_msd_static(md_ctx *ctx, double *msd, int64_t *count, void *stream);
+
 /* Takes the positions in the bound state arrays as the new origin x0 of md_msd
  * (device copies enqueued on the stream; md_bind sets the origin as well). */
 int md_msd_origin(md_ctx *ctx, void *stream);

@@ -79,7 +79,26 @@ __global__ void k_msd_replicas(Buffers b, int n_replicas)
     b.msd_out[(int64_t)r * kMsdValues + MD_MAX_SPECIES + s] = cnt;
 }
 
+// Per-replica results in the caller's layout: msd[r * ns + s] and the counts
+// as int64 (for copies straight into the caller's host arrays).
+__global__ void k_msd_pack(const double* __restrict__ out, int n_replicas, int ns, double* __restrict__ msd,
+                           int64_t* __restrict__ count)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_replicas * ns) return;
+    const int r = t / ns, s = t % ns;
+    msd[t] = out[(int64_t)r * kMsdValues + s];
+    count[t] = (int64_t)out[(int64_t)r * kMsdValues + MD_MAX_SPECIES + s];
+}
+
 }  // namespace
+
+void launch_msd_pack(const double* out, int n_replicas, int ns, double* msd, int64_t* count, hipStream_t s)
+{
+    const int n = n_replicas * ns;
+    hipLaunchKernelGGL(k_msd_pack, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, out, n_replicas, ns, msd,
+                       count);
+}
 
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s)
 {

@@ -299,6 +299,8 @@ void launch_prt_close_scale(const Buffers& b, int q, const KernelShape& k, const
 
 // Launchers (kernels_analysis.hip).
 void launch_msd(const Buffers& b, const KernelShape& k, const md_state& st, hipStream_t s);
+// msd_out [R][2 MD_MAX_SPECIES] -> msd [R][ns], count [R][ns] (int64), on the device.
+void launch_msd_pack(const double* out, int n_replicas, int ns, double* msd, int64_t* count, hipStream_t s);
 
 // Lanes per atom of the pair kernels: 1 or 2 (the brick setting, 4 taken as 2).
 inline int pair_lanes(const KernelShape& k) { return k.lanes >= 2 ? 2 : 1; }

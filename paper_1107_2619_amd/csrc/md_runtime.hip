@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1637,6 +1638,72 @@ int md_msd(md_ctx* c, double* msd, int64_t* count, void* stream)
             msd[(size_t)r * ns + k] = out[(size_t)r * 2 * MD_MAX_SPECIES + k];
             if (count) count[(size_t)r * ns + k] = (int64_t)out[(size_t)r * 2 * MD_MAX_SPECIES + MD_MAX_SPECIES + k];
         }
+    return MD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Device scratch of md_msd_static: a file-scope array in every GPU's memory,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, so its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is used.
+namespace {
+constexpr size_t kScratchDoubles = (size_t)1 << 17;  // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device (nullptr and a message on failure).
+double* scratch_on_device(md_ctx* c)
+{
+    int dev = 0;
+    if (!hip_ok(c, hipGetDevice(&dev), "md_msd_static device")) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        c->err = "md_msd_static: device index beyond the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (!hip_ok(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "md_msd_static scratch address")) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int md_msd_static(md_ctx* c, double* msd, int64_t* count, void* stream)
+{
+    if (!c || !msd || !count) return fail(c, MD_ERR_ARG, "md_msd_static: NULL argument");
+    if (!c->bound) return fail(c, MD_ERR_STATE, "md_msd_static: call md_bind first");
+    const KernelShape k = shape(c);
+    const int ns = c->pot.ns;
+    // layout: chunk partials | per-replica sums | msd [R][ns] | count [R][ns]
+    const size_t n_part = (size_t)k.n_chunks * 2 * MD_MAX_SPECIES, n_out = (size_t)c->R * 2 * MD_MAX_SPECIES;
+    const size_t n_res = (size_t)c->R * ns;
+    if (n_part + n_out + 2 * n_res > kScratchDoubles)
+        return fail(c, MD_ERR_ARG, "md_msd_static: " + std::to_string(n_part + n_out + 2 * n_res) +
+                                       " scratch doubles needed, the static scratch holds " +
+                                       std::to_string(kScratchDoubles));
+    double* base = scratch_on_device(c);
+    if (!base) return MD_ERR_DEVICE;
+    hipStream_t s = as_stream(stream);
+    Buffers b = c->buf;  // the same kernels, their partials and results in the scratch
+    b.msd_partial = base;
+    b.msd_out = base + n_part;
+    double* d_msd = base + n_part + n_out;
+    int64_t* d_cnt = reinterpret_cast<int64_t*>(d_msd + n_res);
+    launch_msd(b, k, c->st, s);
+    launch_msd_pack(b.msd_out, c->R, ns, d_msd, d_cnt, s);
+    if (!hip_ok(c, hipGetLastError(), "md_msd_static launch") ||
+        !hip_ok(c, hipMemcpyAsync(msd, d_msd, n_res * 8, hipMemcpyDeviceToHost, s), "md_msd_static copy") ||
+        !hip_ok(c, hipMemcpyAsync(count, d_cnt, n_res * 8, hipMemcpyDeviceToHost, s), "md_msd_static copy") ||
+        !hip_ok(c, hipStreamSynchronize(s), "md_msd_static sync"))
+        return MD_ERR_DEVICE;
     return MD_OK;
 }
 

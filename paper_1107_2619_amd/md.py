@@ -43,7 +43,8 @@ KERNEL_GROUPS = ("build", "density", "force", "reduce")
 EXPORTED = [
     "md_create", "md_workspace_bytes", "md_bind", "md_build_neighbours", "md_eam_forces", "md_step",
     "md_energy", "md_copy_neighbours", "md_set_option", "md_get_option", "md_kernel_times", "md_autotune",
-    "md_msd", "md_msd_origin", "md_energy_history", "md_state_changed", "md_destroy", "md_last_error",
+    "md_msd", "md_msd_origin", "md_msd_static", "md_energy_history", "md_state_changed", "md_destroy",
+    "md_last_error",
 ]
 
 
@@ -129,6 +130,7 @@ def library():
     lib.md_autotune.argtypes = [vp, i32, vp]
     lib.md_msd.argtypes = [vp, vp, vp, vp]
     lib.md_msd_origin.argtypes = [vp, vp]
+    lib.md_msd_static.argtypes = [vp, vp, vp, vp]
     lib.md_energy_history.argtypes = [vp, ctypes.POINTER(_Energies), i64, ctypes.POINTER(i64), vp]
     lib.md_state_changed.argtypes = [vp]
     lib.md_destroy.argtypes = [vp]
@@ -378,6 +380,14 @@ class Simulation:
         out = np.zeros(shape)
         cnt = np.zeros(shape, np.int64)
         self.ctx._check(self.ctx.lib.md_msd(self.ctx.handle, out.ctypes.data, cnt.ctypes.data, self.stream))
+        return out, cnt
+
+    def msd_static(self):
+        """msd() through md_msd_static (no device allocation: static scratch)."""
+        shape = (self.ctx.n_replicas, self.ctx.n_species)
+        out = np.zeros(shape)
+        cnt = np.zeros(shape, np.int64)
+        self.ctx._check(self.ctx.lib.md_msd_static(self.ctx.handle, out.ctypes.data, cnt.ctypes.data, self.stream))
         return out, cnt
 
     def msd_origin(self):
