@@ -328,7 +328,7 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
 // periodic image (0 none, 1 +L, 2 -L); compact mixed mode: the unwrapped
 // link-cell offset plus one.  Axes with one or two periodic cells have no
 // unique image per cell; there the image is the minimum one of each pair.
-// Transposed layout nbr[k * Np + slot].  Overflow keeps counting, so the
+// Layout: groups of four entries per slot (nbr_at).  Overflow keeps counting, so the
 // required capacity can be reported.
 // Adjacency of every link cell, once per geometry: entry k of cell c is the
 // cell at offset (k % 3 - 1, k / 3 % 3 - 1, k / 9 - 1), or -1 where a free
@@ -429,9 +429,8 @@ __device__ __forceinline__ void test_candidates(int32_t* __restrict__ nbr, int64
             if (mask == 0) continue;
             const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-            // row `base` of atom i, then `rank` rows further
-            int32_t* row = nbr + ((int64_t)base * n_slots + i);
-            if (take && base + rank < cap) row[(uint32_t)rank * (uint32_t)n_slots] = e;
+            // entry base + rank of atom i
+            if (take && base + rank < cap) nbr[nbr_at(base + rank, i, n_slots)] = e;
             base += __popcll(mask);
         }
         if (lane == ii) my_count = base;
@@ -655,10 +654,12 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
         int e[kChunk];
         double3 xs[kChunk];
         int4 qs[kChunk];
+        static_assert(kChunk == 4, "one int4 list load per chunk");
+        {  // one 16-byte load of four entries; groups past cap are padding
+            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)(k0 >> 2) * n_slots + t];
+            const int v[kChunk] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const int v = nbr[(int64_t)(k0 + u) * n_slots + t];  // rows past cap are padding
-            e[u] = k0 + u < n ? v : (int)t;
+            for (int u = 0; u < kChunk; ++u) e[u] = k0 + u < n ? v[u] : (int)t;
         }
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
@@ -733,10 +734,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
         int e[kChunk];
         double4 ps[kChunk];
         int4 qs[kChunk];
+        static_assert(kChunk == 4, "one int4 list load per chunk");
+        {  // one 16-byte load of four entries; groups past cap are padding
+            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)(k0 >> 2) * n_slots + t];
+            const int v[kChunk] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            const int v = nbr[(int64_t)(k0 + u) * n_slots + t];  // rows past cap are padding
-            e[u] = k0 + u < n ? v : (int)t;
+            for (int u = 0; u < kChunk; ++u) e[u] = k0 + u < n ? v[u] : (int)t;
         }
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
@@ -1399,7 +1402,7 @@ __global__ __launch_bounds__(kBlock) void k_density_half(Buffers b, int p, int q
     const int n = b.ncount[t];
     double rho = 0.0;
     for (int k = 0; k < n; ++k) {
-        const int e = nbr[(int64_t)k * n_slots + t];
+        const int e = nbr[nbr_at(k, t, n_slots)];
         const int j = e & kIndexMask;
         const double3 xj = load_xyz(pos, j);
         double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
@@ -1465,7 +1468,7 @@ __global__ __launch_bounds__(kBlock) void k_force_half(Buffers b, int p, int q, 
     const int n = b.ncount[t];
     PairAcc A;
     for (int k = 0; k < n; ++k) {
-        const int e = nbr[(int64_t)k * n_slots + t];
+        const int e = nbr[nbr_at(k, t, n_slots)];
         const int j = e & kIndexMask;
         const double4 pj = pos[j];
         double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;

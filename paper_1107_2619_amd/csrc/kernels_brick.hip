@@ -340,7 +340,7 @@ __global__ __launch_bounds__(1024) void k_brick_list_to_slots(Buffers b, int64_t
         const int n = b.ncount[t];
         for (int k = 0; k < n; ++k) {
             int code;
-            b.nbr[(int64_t)k * n_slots + t] = halo_slot(M, b.nbr16[t * (int64_t)rowlen + k], code);
+            b.nbr[nbr_at(k, t, n_slots)] = halo_slot(M, b.nbr16[t * (int64_t)rowlen + k], code);
         }
     }
 }

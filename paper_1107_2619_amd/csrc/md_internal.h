@@ -36,7 +36,16 @@ constexpr int kBrickMaxDim = 4;
 // image shift (2 bits per axis) above.
 constexpr int kIndexBits = 26;
 constexpr int kIndexMask = (1 << kIndexBits) - 1;
-constexpr int kChunk = 4;  // neighbours whose loads are issued together
+constexpr int kChunk = 4;  // neighbours whose loads are issued together (one 16-byte list load)
+
+// Neighbour-list layout (global kernels): entry k of slot t at
+// nbr[((k / 4) Np + t) 4 + k % 4].  A slot's entries come in groups of four,
+// one 16-byte load per lane, and the groups of a wavefront's 64 slots are one
+// contiguous kilobyte.
+__host__ __device__ inline int64_t nbr_at(int k, int64_t t, int64_t n_slots)
+{
+    return ((int64_t)(k >> 2) * n_slots + t) * 4 + (k & 3);
+}
 constexpr int kForceStride = 6;  // coefficients per bin of the force table (phi', rho' quadratics)
 // Tables whose bins may hold one knot of each function inside (knots on no
 // common grid): every function's record also carries that knot's offset D

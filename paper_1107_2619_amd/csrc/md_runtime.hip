@@ -486,7 +486,7 @@ void plan_workspace(md_ctx* c)
         Np * 4, Np * 4, Np * 4, Np * 4, Np * 4, Np * 4,      // img[2][3]
         Np * 32,                                             // xbuild
         Np * 8,                                              // femb
-        Np * 4 * (size_t)(c->cap + kChunk),                  // nbr, transposed, kChunk padding rows
+        Np * 4 * (size_t)((c->cap + 2 * kChunk - 1) / kChunk * kChunk),  // nbr (nbr_at), a padding group
         Np * 4,                                              // ncount
         Np * 4,                                              // cell_of
         Np * 4,                                              // perm
@@ -1607,7 +1607,7 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
     if (shape(c).brick) launch_brick_list_to_slots(c->buf, shape(c), as_stream(stream));
     if (!hip_ok(c, hipStreamSynchronize(as_stream(stream)), "md_copy_neighbours sync")) return MD_ERR_DEVICE;
     const size_t Np = (size_t)c->Np;
-    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * (size_t)c->cap);
+    std::vector<int32_t> cnt(Np), ids(Np), nb(Np * (size_t)((c->cap + kChunk - 1) / kChunk * kChunk));
     if (!hip_ok(c, hipMemcpy(cnt.data(), c->buf.ncount, Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(ids.data(), c->buf.id[c->q], Np * 4, hipMemcpyDeviceToHost), "copy") ||
         !hip_ok(c, hipMemcpy(nb.data(), c->buf.nbr, nb.size() * 4, hipMemcpyDeviceToHost), "copy"))
@@ -1616,7 +1616,7 @@ int md_copy_neighbours(md_ctx* c, int32_t* counts, int32_t* list, int32_t cap, v
         const int32_t a = ids[t];
         if (a < 0) continue;
         counts[a] = cnt[t];
-        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[k * Np + t] & kIndexMask];
+        for (int k = 0; k < cnt[t]; ++k) list[(size_t)a * cap + k] = ids[nb[nbr_at(k, (int64_t)t, (int64_t)Np)] & kIndexMask];
     }
     return MD_OK;
 }
