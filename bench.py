@@ -206,7 +206,7 @@ def choice_options(md, ch):
     """The md_set_option settings of an autotuner choice."""
     return {md.MD_OPT_KERNEL: ch["kernel"], md.MD_OPT_BRICK_DIMS: ch["brick_dims"] if ch["kernel"] == 0 else 0,
             md.MD_OPT_LANES_PER_ATOM: ch["lanes"], md.MD_OPT_BRICK_BLOCK: ch["block"],
-            md.MD_OPT_EVALUATOR: ch["evaluator"]}
+            md.MD_OPT_EVALUATOR: ch["evaluator"], md.MD_OPT_NEIGHBOUR_CHUNK: ch.get("nchunk", 4)}
 
 
 def tune_options(md, system, precision):
@@ -362,6 +362,8 @@ def main():
                     help="steps of the 2000-atom FP64 configuration (0 = skip)")
     ap.add_argument("--copy-gbs-mib", type=int, default=1024,
                     help="size of the device copy whose bandwidth is reported beside the roofline (0 = skip)")
+    ap.add_argument("--nchunk", type=int, choices=[2, 4, 8], default=4,
+                    help="with --kernel global: neighbour records in flight per thread")
     ap.add_argument("--kernel", choices=["auto", "global"], default="auto",
                     help="main workload: autotuned configuration, or the global-gather kernels with tables")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -426,7 +428,8 @@ def main():
     tuned = {}
     for prec in ("fp64", "mixed"):
         if args.kernel == "global":  # fixed configuration (counter passes compare the same kernels)
-            ch = {"kernel": 1, "brick_dims": 0, "lanes": 1, "block": 512, "evaluator": 0, "step_us": None}
+            ch = {"kernel": 1, "brick_dims": 0, "lanes": 1, "block": 512, "evaluator": 0, "nchunk": args.nchunk,
+                  "step_us": None}
             opts = choice_options(md, ch)
             log(f"{prec}: global kernels, tables (no autotune)")
         else:

@@ -350,10 +350,14 @@ enum {
                                   reduces PE, KE and the virial and appends them to
                                   the energy ring (velocity-Verlet NVE only); 0 =
                                   energies on the last step of each md_step only   */
-    MD_OPT_ENERGY_RING = 16    /* entries of the device energy ring (workspace
+    MD_OPT_ENERGY_RING = 16,   /* entries of the device energy ring (workspace
                                   grows by entries * R * 96 bytes); set before
                                   md_workspace_bytes and md_bind (MD_ERR_STATE
                                   after md_bind).  Default 0: no ring                */
+    MD_OPT_NEIGHBOUR_CHUNK = 17 /* global kernels: neighbour records each thread
+                                  gathers before it evaluates them, 2, 4 (default)
+                                  or 8; md_autotune picks it.  Results do not
+                                  depend on it (same terms, same order)              */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);

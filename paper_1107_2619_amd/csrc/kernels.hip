@@ -622,7 +622,10 @@ __device__ __forceinline__ int4 record_load(__amdgpu_buffer_rsrc_t rs, int j)
 //
 // Density pass (Eq. Ucoh, the argument of F): rho_i = sum_j rho_{s_i s_j}(r_ij),
 // then F_i and F'_i.  The sum is accumulated in FP64 in both precision modes.
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, int CMP>
+//
+// NCH: neighbour records in flight per thread (2, 4 or 8; the autotuner picks
+// it): more hide more gather latency, fewer free registers for more waves.
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int CMP, int NCH>
 __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
                                                      int energy)
 {
@@ -650,40 +653,51 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
     const int si = b.type[q][t] & 0x3F;
     const int n = b.ncount[t];
     double rho = 0.0;
-    for (int k0 = 0; k0 < n; k0 += kChunk) {
-        int e[kChunk];
-        double3 xs[kChunk];
-        int4 qs[kChunk];
-        static_assert(kChunk == 4, "one int4 list load per chunk");
-        {  // one 16-byte load of four entries; groups past cap are padding
-            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)(k0 >> 2) * n_slots + t];
-            const int v[kChunk] = {v4.x, v4.y, v4.z, v4.w};
+    constexpr int GR = NCH >= kChunk ? NCH / kChunk : 1;  // list groups per iteration
+    constexpr int SUB = NCH >= kChunk ? 1 : kChunk / NCH;  // record batches per group
+    static_assert(kChunk == 4 && NCH * SUB == kChunk * GR, "one int4 list load per four entries");
+    for (int k0 = 0; k0 < n; k0 += kChunk * GR) {
+        int v[kChunk * GR];
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) e[u] = k0 + u < n ? v[u] : (int)t;
+        for (int g = 0; g < GR; ++g) {  // 16-byte loads of four entries; groups past cap are padding
+            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)((k0 >> 2) + g) * n_slots + t];
+            v[4 * g] = v4.x;
+            v[4 * g + 1] = v4.y;
+            v[4 * g + 2] = v4.z;
+            v[4 * g + 3] = v4.w;
         }
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
-            else xs[u] = load_xyz(pos, e[u] & kIndexMask);
-        }
+        for (int sb = 0; sb < SUB; ++sb) {
+            const int kb = k0 + sb * NCH;
+            if (kb >= n) break;
+            int e[NCH];
+            double3 xs[NCH];
+            int4 qs[NCH];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            if (k0 + u >= n) break;
-            const int code = (unsigned)e[u] >> kIndexBits;
-            double dx, dy, dz;
-            if (CMP) {
-                compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
-            } else {
-                dx = xs[u].x - xi.x;
-                dy = xs[u].y - xi.y;
-                dz = xs[u].z - xi.z;
-                if (code) apply_shift(bx, code, dx, dy, dz);
+            for (int u = 0; u < NCH; ++u) {
+                e[u] = kb + u < n ? v[sb * NCH + u] : (int)t;
+                if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
+                else xs[u] = load_xyz(pos, e[u] & kIndexMask);
             }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 < P.rc2)) continue;
-            const double r = r2 * inv_dist<R>(r2);
-            const int sj = SINGLE ? 0 : (b.type[q][e[u] & kIndexMask] & 0x3F);
-            rho += (double)density_term<R, SINGLE, NDK, EV>(P, G, tab, si, sj, r);
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                if (kb + u >= n) break;
+                const int code = (unsigned)e[u] >> kIndexBits;
+                double dx, dy, dz;
+                if (CMP) {
+                    compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
+                } else {
+                    dx = xs[u].x - xi.x;
+                    dy = xs[u].y - xi.y;
+                    dz = xs[u].z - xi.z;
+                    if (code) apply_shift(bx, code, dx, dy, dz);
+                }
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 < P.rc2)) continue;
+                const double r = r2 * inv_dist<R>(r2);
+                const int sj = SINGLE ? 0 : (b.type[q][e[u] & kIndexMask] & 0x3F);
+                rho += (double)density_term<R, SINGLE, NDK, EV>(P, G, tab, si, sj, r);
+            }
         }
     }
     double F, dF;
@@ -695,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
 
 // Force pass + velocity Verlet (global gathers).
 template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
-          int CMP>
+          int CMP, int NCH>
 __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
                                                    double dt, md_state st)
 {
@@ -730,46 +744,59 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
     const int n = b.ncount[t];
     const R fpi = CMP ? (R)__int_as_float(qi.w) : (R)pi.w;
     PairAcc A;
-    for (int k0 = 0; k0 < n; k0 += kChunk) {
-        int e[kChunk];
-        double4 ps[kChunk];
-        int4 qs[kChunk];
-        static_assert(kChunk == 4, "one int4 list load per chunk");
-        {  // one 16-byte load of four entries; groups past cap are padding
-            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)(k0 >> 2) * n_slots + t];
-            const int v[kChunk] = {v4.x, v4.y, v4.z, v4.w};
+    constexpr int GR = NCH >= kChunk ? NCH / kChunk : 1;  // list groups per iteration
+    constexpr int SUB = NCH >= kChunk ? 1 : kChunk / NCH;  // record batches per group
+    static_assert(kChunk == 4 && NCH * SUB == kChunk * GR, "one int4 list load per four entries");
+    for (int k0 = 0; k0 < n; k0 += kChunk * GR) {
+        int v[kChunk * GR];
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) e[u] = k0 + u < n ? v[u] : (int)t;
+        for (int g = 0; g < GR; ++g) {  // 16-byte loads of four entries; groups past cap are padding
+            const int4 v4 = reinterpret_cast<const int4*>(nbr)[(int64_t)((k0 >> 2) + g) * n_slots + t];
+            v[4 * g] = v4.x;
+            v[4 * g + 1] = v4.y;
+            v[4 * g + 2] = v4.z;
+            v[4 * g + 3] = v4.w;
         }
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
-            else ps[u] = pos[e[u] & kIndexMask];
-        }
+        for (int sb = 0; sb < SUB; ++sb) {
+            const int kb = k0 + sb * NCH;
+            if (kb >= n) break;
+            int e[NCH];
+            double4 ps[NCH];
+            int4 qs[NCH];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-            if (k0 + u >= n) break;
-            const int code = (unsigned)e[u] >> kIndexBits;
-            double dx, dy, dz;
-            R fpj;
-            if (CMP) {
-                compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
-                fpj = (R)__int_as_float(qs[u].w);
-            } else {
-                dx = ps[u].x - pi.x;
-                dy = ps[u].y - pi.y;
-                dz = ps[u].z - pi.z;
-                if (code) apply_shift(bx, code, dx, dy, dz);
-                fpj = (R)ps[u].w;
+            for (int u = 0; u < NCH; ++u) {
+                e[u] = kb + u < n ? v[sb * NCH + u] : (int)t;
+                if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
+                else ps[u] = pos[e[u] & kIndexMask];
             }
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 < P.rc2)) continue;
-            const double ri = inv_dist<R>(r2);
-            const double r = r2 * ri;
-            const uint8_t tj = (!SINGLE || ENERGY == 1) ? b.type[q][e[u] & kIndexMask] : 0;
-            R g, phi;
-            pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, fpj, g, phi);
-            accumulate<ENERGY>(A, (double)g * ri, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
+#pragma unroll
+            for (int u = 0; u < NCH; ++u) {
+                if (kb + u >= n) break;
+                const int code = (unsigned)e[u] >> kIndexBits;
+                double dx, dy, dz;
+                R fpj;
+                if (CMP) {
+                    compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
+                    fpj = (R)__int_as_float(qs[u].w);
+                } else {
+                    dx = ps[u].x - pi.x;
+                    dy = ps[u].y - pi.y;
+                    dz = ps[u].z - pi.z;
+                    if (code) apply_shift(bx, code, dx, dy, dz);
+                    fpj = (R)ps[u].w;
+                }
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (!(r2 < P.rc2)) continue;
+                const double ri = inv_dist<R>(r2);
+                const double r = r2 * ri;
+                // one species: j's type byte matters only for the virial of a rigid
+                // atom i (pairs of two rigid atoms stay out of it)
+                const uint8_t tj = (!SINGLE || (ENERGY == 1 && rigid_i)) ? b.type[q][e[u] & kIndexMask] : 0;
+                R g, phi;
+                pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, fpj, g, phi);
+                accumulate<ENERGY>(A, (double)g * ri, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
+            }
         }
     }
     atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK>(b, p, q, t, n_slots, Rp, P, G, dt, st, pi, ti, A);
@@ -1582,18 +1609,30 @@ void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipSt
     hipLaunchKernelGGL(k_compact_records, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, k.n_slots);
 }
 
+template <typename R, bool S, int NP, int ND, int EV, int CMP>
+static void density_chunked(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
+                            size_t lds, hipStream_t s)
+{
+    const dim3 grid(blocks_for(k.n_slots));
+    if (k.nchunk == 2)
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
+                           energy);
+    else if (k.nchunk == 8)
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 8>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
+                           energy);
+    else
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 4>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
+                           energy);
+}
+
 template <typename R, bool S, int NP, int ND, int EV>
 static void density_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                             hipStream_t s)
 {
     const size_t lds = (EV != EV_KNOTS && S) ? (size_t)P.nbt * value_stride(EV) * sizeof(R) : 0;
-    const dim3 grid(blocks_for(k.n_slots));
-    if (k.compact == 2)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
-    else if (k.compact)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
-    else
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, 0>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P, energy);
+    if (k.compact == 2) density_chunked<R, S, NP, ND, EV, 2>(b, p, q, k, P, energy, lds, s);
+    else if (k.compact) density_chunked<R, S, NP, ND, EV, 1>(b, p, q, k, P, energy, lds, s);
+    else density_chunked<R, S, NP, ND, EV, 0>(b, p, q, k, P, energy, lds, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>
@@ -1643,22 +1682,40 @@ void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const 
     }
 }
 
+// The neighbour chunk applies to the velocity-Verlet step kernels (with and
+// without energies) and to the plain force pass the autotuner times; the other
+// variants run once per call or per barostat step.
+template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W, int CMP>
+static void force_chunked(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                          const md_state& st, size_t lds, hipStream_t s)
+{
+    const dim3 grid(blocks_for(k.n_slots));
+    constexpr bool step = ((E == 0 || E == 1) && C && O && !W) || (E == 0 && !C && !O && !W);
+    if constexpr (step) {
+        if (k.nchunk == 2) {
+            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 2>), grid, dim3(kBlock), lds, s, b, p, q,
+                               k.n_slots, P, dt_fs, st);
+            return;
+        }
+        if (k.nchunk == 8) {
+            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 8>), grid, dim3(kBlock), lds, s, b, p, q,
+                               k.n_slots, P, dt_fs, st);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 4>), grid, dim3(kBlock), lds, s, b, p, q,
+                       k.n_slots, P, dt_fs, st);
+}
+
 template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W>
 static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                          const md_state& st, hipStream_t s)
 {
     const size_t lds =
         (EV != EV_KNOTS && S) ? (size_t)P.nbt * (force_stride(EV) + (E == 1 ? value_stride(EV) : 0)) * sizeof(R) : 0;
-    const dim3 grid(blocks_for(k.n_slots));
-    if (k.compact == 2)
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
-                           P, dt_fs, st);
-    else if (k.compact)
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 1>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots,
-                           P, dt_fs, st);
-    else
-        hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, 0>), grid, dim3(kBlock), lds, s, b, p, q,
-                           k.n_slots, P, dt_fs, st);
+    if (k.compact == 2) force_chunked<R, S, NP, ND, EV, E, C, O, W, 2>(b, p, q, k, P, dt_fs, st, lds, s);
+    else if (k.compact) force_chunked<R, S, NP, ND, EV, E, C, O, W, 1>(b, p, q, k, P, dt_fs, st, lds, s);
+    else force_chunked<R, S, NP, ND, EV, E, C, O, W, 0>(b, p, q, k, P, dt_fs, st, lds, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>

@@ -234,6 +234,7 @@ struct KernelShape {
     int32_t tri;      // 1 = box matrices (sheared cells)
     int32_t lds_limit; // LDS bytes one workgroup may use
     int32_t pairs;     // LDS bricks with each pair of two own atoms once (MD_OPT_KERNEL = 2)
+    int32_t nchunk;    // neighbour records in flight per thread in the global kernels: 2, 4 or 8
     int32_t chunked;  // 1 = per-replica sums of the thermostat and barostat start with
                       // per-chunk sums (some replica spans more than kChunkedSumWaves waves)
 };

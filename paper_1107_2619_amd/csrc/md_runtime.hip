@@ -49,6 +49,7 @@ struct md_ctx {
     int32_t C = 0, C_alloc = 0, scan_nb = 0;
     // brick path
     int32_t kernel_path = 1;  // 0 = LDS bricks, 1 = global gathers, 2 = LDS bricks with pairs once
+    int32_t nchunk = 4;       // neighbour records in flight per thread (global kernels)
     int32_t brick_dims = 0;   // 0 = automatic, else bd[0] + 10 bd[1] + 100 bd[2]
     int32_t brick_block = 512;
     int32_t lds_limit = 65536;
@@ -191,6 +192,7 @@ KernelShape shape(const md_ctx* c)
     k.tri = c->tri ? 1 : 0;
     k.chunked = c->chunked_sums ? 1 : 0;
     k.lds_limit = c->lds_limit;
+    k.nchunk = c->nchunk;
     return k;
 }
 
@@ -1756,6 +1758,10 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
             c->have_list = false;  // the list entries carry a different code
         }
         return MD_OK;
+    case MD_OPT_NEIGHBOUR_CHUNK:
+        if (value != 2 && value != 4 && value != 8) return fail(c, MD_ERR_ARG, "neighbour chunk must be 2, 4 or 8");
+        c->nchunk = (int32_t)value;
+        return MD_OK;
     case MD_OPT_TIMING:
         if (!value && !c->pending.empty()) return fail(c, MD_ERR_STATE, "read md_kernel_times before turning timing off");
         c->timing = value != 0;
@@ -1809,7 +1815,7 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     if (c->timing) return fail(c, MD_ERR_STATE, "md_autotune: turn MD_OPT_TIMING off first");
     hipStream_t s = as_stream(stream);
     struct Cand {
-        int32_t kernel, dims, lanes, block, evaluator;
+        int32_t kernel, dims, lanes, block, evaluator, nchunk;
     };
     // FP64 may take either evaluator (both meet its tolerance); mixed keeps the
     // current one, since its explicit FP32 knot sums do not
@@ -1817,13 +1823,13 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     if (c->precision == MD_FP64 && c->table_ok && c->explicit_ok) evals = {0, 1};
     std::vector<Cand> cands;
     for (int32_t e : evals) {
-        cands.push_back({1, 0, 0, 512, e});
+        for (int32_t nch : {4, 2, 8}) cands.push_back({1, 0, 0, 512, e, nch});
         if (c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri)  // the brick kernels take fixed orthorhombic boxes
             // (the pair kernels, MD_OPT_KERNEL = 2, are left out: their LDS
             // atomics make them several times slower on this device)
             for (int32_t dims : {0, 444, 222})
                 for (int32_t lanes : {1, 2})
-                    for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block, e});
+                    for (int32_t block : {512, 1024}) cands.push_back({0, dims, lanes, block, e, 4});
     }
     hipEvent_t ev[3];
     for (auto& e : ev)
@@ -1835,14 +1841,16 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
         if ((rc = md_set_option(c, MD_OPT_KERNEL, cd.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, cd.dims)) != MD_OK ||
             (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, cd.lanes)) != MD_OK ||
             (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_EVALUATOR, cd.evaluator)) != MD_OK)
+            (rc = md_set_option(c, MD_OPT_EVALUATOR, cd.evaluator)) != MD_OK ||
+            (rc = md_set_option(c, MD_OPT_NEIGHBOUR_CHUNK, cd.nchunk)) != MD_OK)
             break;
         ensure_slots(c, s);
         launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
         (void)hipEventRecord(ev[0], s);
         rebuild(c, s, false);
         (void)hipEventRecord(ev[1], s);
-        for (int32_t t = 0; t < trials; ++t) forces(c, ForceFlags{0, 0, 0, 1}, s);
+        // the plain force pass (forces kept in the slots, no state change)
+        for (int32_t t = 0; t < trials; ++t) forces(c, ForceFlags{0, 0, 0, 0}, s);
         (void)hipEventRecord(ev[2], s);
         if ((rc = check_launch(c)) != MD_OK) break;
         float t_build = 0.0f, t_force = 0.0f;
@@ -1863,7 +1871,8 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     if ((rc = md_set_option(c, MD_OPT_KERNEL, choice.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, choice.dims)) != MD_OK ||
         (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, choice.lanes)) != MD_OK ||
         (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, choice.block)) != MD_OK ||
-        (rc = md_set_option(c, MD_OPT_EVALUATOR, choice.evaluator)) != MD_OK)
+        (rc = md_set_option(c, MD_OPT_EVALUATOR, choice.evaluator)) != MD_OK ||
+        (rc = md_set_option(c, MD_OPT_NEIGHBOUR_CHUNK, choice.nchunk)) != MD_OK)
         return rc;
     c->tuned_us = best * 1e3;
     c->have_list = false;  // the next call builds the list of the chosen configuration
@@ -1890,6 +1899,7 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
     case MD_OPT_HALO_OVERFLOWS: *value = c->halo_overflows; return MD_OK;
     case MD_OPT_ENERGY_EVERY: *value = c->energy_every; return MD_OK;
     case MD_OPT_ENERGY_RING: *value = c->ring_len; return MD_OK;
+    case MD_OPT_NEIGHBOUR_CHUNK: *value = c->nchunk; return MD_OK;
     default: return MD_ERR_ARG;
     }
 }

@@ -37,7 +37,7 @@ MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_O
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
 MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS, MD_OPT_COMPACT = 12, 13, 14
-MD_OPT_ENERGY_EVERY, MD_OPT_ENERGY_RING = 15, 16
+MD_OPT_ENERGY_EVERY, MD_OPT_ENERGY_RING, MD_OPT_NEIGHBOUR_CHUNK = 15, 16, 17
 KERNEL_GROUPS = ("build", "density", "force", "reduce")
 
 EXPORTED = [
@@ -424,7 +424,7 @@ class Simulation:
         self.ctx._check(self.ctx.lib.md_autotune(self.ctx.handle, int(trials), self.stream))
         opts = {name: self.get_option(opt) for name, opt in (
             ("kernel", MD_OPT_KERNEL), ("brick_dims", MD_OPT_BRICK_DIMS), ("lanes", MD_OPT_LANES_PER_ATOM),
-            ("block", MD_OPT_BRICK_BLOCK), ("evaluator", MD_OPT_EVALUATOR))}
+            ("block", MD_OPT_BRICK_BLOCK), ("evaluator", MD_OPT_EVALUATOR), ("nchunk", MD_OPT_NEIGHBOUR_CHUNK))}
         opts["step_us"] = self.get_option(MD_OPT_TUNED_NS) / 1e3
         return opts
 

@@ -323,3 +323,16 @@ def test_energy_ring_options(md):
     with pytest.raises(md.MDError) as e:
         nvt.set_option(md.MD_OPT_ENERGY_EVERY, 1)
     assert e.value.code == md.MD_ERR_ARG
+
+
+def test_neighbour_chunk_option(md):
+    """The neighbour chunk of the global kernels takes 2, 4 or 8 (default 4)."""
+    c = _ctx(md)
+    assert c.get_option(md.MD_OPT_NEIGHBOUR_CHUNK) == 4
+    for v in (2, 8, 4):
+        c.set_option(md.MD_OPT_NEIGHBOUR_CHUNK, v)
+        assert c.get_option(md.MD_OPT_NEIGHBOUR_CHUNK) == v
+    for v in (0, 3, 16):
+        with pytest.raises(md.MDError) as e:
+            c.set_option(md.MD_OPT_NEIGHBOUR_CHUNK, v)
+        assert e.value.code == md.MD_ERR_ARG
