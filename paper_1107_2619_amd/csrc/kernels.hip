@@ -404,19 +404,23 @@ __device__ __forceinline__ void min_image_pair(const Box& bx, int amb, int compa
 }
 
 // Tests atoms s0 .. s0 + n - 1 (lane l holds atom s0 + l in xl) against the
-// candidates in registers and appends the in-range ones to their rows.
+// candidates in registers and appends the in-range ones to their rows.  The
+// rows are written through a raw buffer resource: the atom's row start is a
+// scalar byte offset and each lane adds its entry's 32-bit offset, so the
+// address costs three vector instructions (the list stays below 4 GiB).
 template <int P, bool AMB>
-__device__ __forceinline__ void test_candidates(int32_t* __restrict__ nbr, int64_t n_slots, int32_t cap, double rlist2,
-                                                int half_list, int compact, const Box& bx, int amb, int s0, int n,
-                                                const double3& xl, const double (&cx)[P], const double (&cy)[P],
-                                                const double (&cz)[P], const int (&ce)[P], const int (&cj)[P],
-                                                const bool (&live)[P], int& my_count)
+__device__ __forceinline__ void test_candidates(__amdgpu_buffer_rsrc_t lrs, uint32_t group_bytes, int32_t cap,
+                                                double rlist2, int half_list, int compact, const Box& bx, int amb,
+                                                int s0, int n, const double3& xl, const double (&cx)[P],
+                                                const double (&cy)[P], const double (&cz)[P], const int (&ce)[P],
+                                                const int (&cj)[P], const bool (&live)[P], int& my_count)
 {
     const int lane = threadIdx.x & (kWave - 1);
     for (int ii = 0; ii < n; ++ii) {
         const int i = s0 + ii;
         const double xi = bcast_lane(xl.x, ii), yi = bcast_lane(xl.y, ii), zi = bcast_lane(xl.z, ii);
         int base = __builtin_amdgcn_readlane(my_count, ii);
+        const uint32_t row = (uint32_t)i * 16u;  // entry k of atom i: row + (k / 4) group_bytes + 4 (k % 4)
 #pragma unroll
         for (int u = 0; u < P; ++u) {
             double dx = cx[u] - xi, dy = cy[u] - yi, dz = cz[u] - zi;
@@ -429,8 +433,10 @@ __device__ __forceinline__ void test_candidates(int32_t* __restrict__ nbr, int64
             if (mask == 0) continue;
             const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-            // entry base + rank of atom i
-            if (take && base + rank < cap) nbr[nbr_at(base + rank, i, n_slots)] = e;
+            // entry base + rank of atom i (the layout of nbr_at)
+            const uint32_t k = (uint32_t)(base + rank);
+            if (take && base + rank < cap)
+                __builtin_amdgcn_raw_buffer_store_b32(e, lrs, (k >> 2) * group_bytes + ((k & 3u) << 2), row, 0);
             base += __popcll(mask);
         }
         if (lane == ii) my_count = base;
@@ -484,7 +490,25 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
     const int excl = incl - nb_count;
     const int total = uniform(__shfl(incl, kWave - 1, kWave));
 
+    // candidate table of this wave: slot and codes of candidate m, written by
+    // the 27 lanes of the adjacent cells (lane k its own cell's run), read back
+    // by candidate index.  A wave's LDS operations complete in order, so the
+    // wave-scope fence suffices.  Larger stencils search the prefix instead.
+    __shared__ int2 cand_table[kBlock / kWave][kCandTable];
+    int2* tab = cand_table[threadIdx.x / kWave];
+    const bool tabled = total <= kCandTable;
+    if (tabled) {
+        const int wc = nb_wrap | (nb_code << 8);
+        for (int qq = 0; qq < nb_count; ++qq) tab[excl + qq] = make_int2(nb_start + qq, wc);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
     const double4* __restrict__ pos = b.pos[p];
+    const uint32_t group_bytes = (uint32_t)n_slots * 16u;
+    const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
+        b.nbr, (short)0, (int)(group_bytes * (uint32_t)((cap + 2 * kChunk - 1) / kChunk)), (int)kBufferWord3);
     for (int i0 = 0; i0 < n_own; i0 += kWave) {
         const int n_chunk = min(kWave, n_own - i0);
         // lane l holds atom s_own + i0 + l; the test loop broadcasts it
@@ -498,13 +522,22 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
             for (int u = 0; u < kCandPasses; ++u) {
                 const int m0 = g0 + u * kWave + lane;
                 const int m = min(m0, total - 1);
-                // the adjacent cell holding candidate m: the last k with excl_k <= m
-                int k = 0;
+                int j, w, code;
+                if (tabled) {
+                    const int2 tv = tab[m];
+                    j = tv.x;
+                    w = tv.y & 63;
+                    code = (tv.y >> 8) & 63;
+                } else {
+                    // the adjacent cell holding candidate m: the last k with excl_k <= m
+                    int k = 0;
 #pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1)
-                    if (__shfl(excl, k + step, kWave) <= m) k += step;
-                const int j = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
-                const int w = __shfl(nb_wrap, k, kWave);
+                    for (int step = kWave / 2; step > 0; step >>= 1)
+                        if (__shfl(excl, k + step, kWave) <= m) k += step;
+                    j = __shfl(nb_start, k, kWave) + (m - __shfl(excl, k, kWave));
+                    w = __shfl(nb_wrap, k, kWave);
+                    code = __shfl(nb_code, k, kWave);
+                }
                 const double3 xj = load_xyz(pos, j);
                 if (TRI) {  // the image cell's edge-vector shift
                     double dsh[3] = {0.0, 0.0, 0.0};
@@ -517,15 +550,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                     cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
                     cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
                 }
-                ce[u] = j | (__shfl(nb_code, k, kWave) << kIndexBits);
+                ce[u] = j | (code << kIndexBits);
                 cj[u] = j;
                 live[u] = m0 < total;
             }
             if (amb)
-                test_candidates<kCandPasses, true>(b.nbr, n_slots, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                test_candidates<kCandPasses, true>(lrs, group_bytes, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
                                                    n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
             else
-                test_candidates<kCandPasses, false>(b.nbr, n_slots, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                test_candidates<kCandPasses, false>(lrs, group_bytes, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
                                                     n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
         }
         // per-atom epilogue: count, overflow flag, compact record

@@ -21,6 +21,7 @@ constexpr double kEvPerA3InGpa = 160.217653;
 
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kBlock = 256;     // threads per workgroup (4 waves)
+constexpr int kCandTable = 512; // list build: candidates one wave's LDS table holds
 constexpr int kEnergySlots = 12;  // per-wave partial record, see EnergyIndex
 constexpr int kNumXcd = 8;      // MI355X: 8 accelerator dies, one L2 each
 

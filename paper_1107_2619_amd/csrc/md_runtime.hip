@@ -1223,6 +1223,9 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     c->C_alloc = (int32_t)std::max<int64_t>(cells_alloc, 1);
     c->scan_nb = (c->C_alloc + 1023) / 1024;
     if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
+    // the list kernels address the global list with 32-bit byte offsets
+    if ((uint64_t)c->Np * 16 * (uint64_t)((c->cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32))
+        return reject(MD_ERR_ARG, "neighbour list above 4 GiB: lower max_neighbours or split the system");
     c->rep_of_wave.assign(c->Np / kWave, 0);
     for (int r = 0; r < c->R; ++r) {
         const int64_t w0 = c->reps[r].slot_off / kWave;
