@@ -403,17 +403,30 @@ __device__ __forceinline__ void min_image_pair(const Box& bx, int amb, int compa
     if (amb & 4) min_image_axis(dz, bx.L[2], bx.iL[2], bx.nc[2], 2, compact, e);
 }
 
+// Where the list build writes.  Lists below 4 GiB are written through raw
+// buffer resources: the atom's row start is a scalar byte offset and each lane
+// adds its entry's 32-bit offset, so the address costs three vector
+// instructions; WIDE lists take 64-bit addresses.  With several species each
+// entry also gets its neighbour's type byte, in the same layout (four bytes
+// per group of four entries), so the force loop reads them with its entries
+// instead of gathering them one by one.
+struct ListOut {
+    __amdgpu_buffer_rsrc_t rs, ts;  // entries, type bytes
+    uint32_t group_bytes;           // n_slots * 16: one group of four entries of every slot
+    int32_t* nbr;
+    uint8_t* types;
+    int64_t n_slots;
+    int with_types;
+};
+
 // Tests atoms s0 .. s0 + n - 1 (lane l holds atom s0 + l in xl) against the
-// candidates in registers and appends the in-range ones to their rows.  The
-// rows are written through a raw buffer resource: the atom's row start is a
-// scalar byte offset and each lane adds its entry's 32-bit offset, so the
-// address costs three vector instructions (the list stays below 4 GiB).
-template <int P, bool AMB>
-__device__ __forceinline__ void test_candidates(__amdgpu_buffer_rsrc_t lrs, uint32_t group_bytes, int32_t cap,
-                                                double rlist2, int half_list, int compact, const Box& bx, int amb,
-                                                int s0, int n, const double3& xl, const double (&cx)[P],
-                                                const double (&cy)[P], const double (&cz)[P], const int (&ce)[P],
-                                                const int (&cj)[P], const bool (&live)[P], int& my_count)
+// candidates in registers and appends the in-range ones to their rows.
+template <int P, bool AMB, bool WIDE>
+__device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, double rlist2, int half_list,
+                                                int compact, const Box& bx, int amb, int s0, int n, const double3& xl,
+                                                const double (&cx)[P], const double (&cy)[P], const double (&cz)[P],
+                                                const int (&ce)[P], const int (&cj)[P], const int (&ct)[P],
+                                                const bool (&live)[P], int& my_count)
 {
     const int lane = threadIdx.x & (kWave - 1);
     for (int ii = 0; ii < n; ++ii) {
@@ -435,8 +448,18 @@ __device__ __forceinline__ void test_candidates(__amdgpu_buffer_rsrc_t lrs, uint
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
             // entry base + rank of atom i (the layout of nbr_at)
             const uint32_t k = (uint32_t)(base + rank);
-            if (take && base + rank < cap)
-                __builtin_amdgcn_raw_buffer_store_b32(e, lrs, (k >> 2) * group_bytes + ((k & 3u) << 2), row, 0);
+            if (take && base + rank < cap) {
+                if (WIDE) {
+                    const int64_t at = nbr_at(base + rank, i, L.n_slots);
+                    L.nbr[at] = e;
+                    if (L.with_types) L.types[at] = (uint8_t)ct[u];
+                } else {
+                    const uint32_t off = (k >> 2) * L.group_bytes + ((k & 3u) << 2);
+                    __builtin_amdgcn_raw_buffer_store_b32(e, L.rs, off, row, 0);
+                    if (L.with_types)  // byte offsets a quarter of the entry's
+                        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)ct[u], L.ts, off >> 2, row >> 2, 0);
+                }
+            }
             base += __popcll(mask);
         }
         if (lane == ii) my_count = base;
@@ -445,9 +468,10 @@ __device__ __forceinline__ void test_candidates(__amdgpu_buffer_rsrc_t lrs, uint
 
 // TRI: sheared cells (candidate shifts are edge-vector sums), a separate
 // instantiation so the orthorhombic build keeps its short candidate loop.
-template <bool TRI>
-__global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t n_slots, int32_t n_cells,
-                                                      int32_t cap, double rlist2, int half_list, int compact)
+template <bool TRI, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, int64_t n_slots, int32_t n_cells,
+                                                      int32_t cap, double rlist2, int half_list, int compact,
+                                                      int with_types)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int cell = uniform((int)(logical_block() * (kBlock / kWave) + threadIdx.x / kWave));
@@ -506,9 +530,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
     }
 
     const double4* __restrict__ pos = b.pos[p];
-    const uint32_t group_bytes = (uint32_t)n_slots * 16u;
-    const __amdgpu_buffer_rsrc_t lrs = __builtin_amdgcn_make_buffer_rsrc(
-        b.nbr, (short)0, (int)(group_bytes * (uint32_t)((cap + 2 * kChunk - 1) / kChunk)), (int)kBufferWord3);
+    // (WIDE: the buffer resources are unused; their sizes wrap harmlessly)
+    ListOut L;
+    L.group_bytes = (uint32_t)n_slots * 16u;
+    const uint32_t n_groups = (uint32_t)((cap + 2 * kChunk - 1) / kChunk);
+    L.rs = __builtin_amdgcn_make_buffer_rsrc(b.nbr, (short)0, (int)(L.group_bytes * n_groups), (int)kBufferWord3);
+    L.ts = __builtin_amdgcn_make_buffer_rsrc(b.ntype, (short)0, (int)(L.group_bytes / 4 * n_groups), (int)kBufferWord3);
+    L.nbr = b.nbr;
+    L.types = b.ntype;
+    L.n_slots = n_slots;
+    L.with_types = with_types;
     for (int i0 = 0; i0 < n_own; i0 += kWave) {
         const int n_chunk = min(kWave, n_own - i0);
         // lane l holds atom s_own + i0 + l; the test loop broadcasts it
@@ -516,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
         int my_count = 0;  // lane l: entries of that atom so far
         for (int g0 = 0; g0 < total; g0 += kWave * kCandPasses) {
             double cx[kCandPasses], cy[kCandPasses], cz[kCandPasses];
-            int ce[kCandPasses], cj[kCandPasses];
+            int ce[kCandPasses], cj[kCandPasses], ct[kCandPasses];
             bool live[kCandPasses];
 #pragma unroll
             for (int u = 0; u < kCandPasses; ++u) {
@@ -552,14 +583,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int64_t 
                 }
                 ce[u] = j | (code << kIndexBits);
                 cj[u] = j;
+                ct[u] = with_types ? b.type[q][j] : 0;
                 live[u] = m0 < total;
             }
             if (amb)
-                test_candidates<kCandPasses, true>(lrs, group_bytes, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
-                                                   n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
+                test_candidates<kCandPasses, true, WIDE>(L, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                                                         n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
             else
-                test_candidates<kCandPasses, false>(lrs, group_bytes, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
-                                                    n_chunk, xl, cx, cy, cz, ce, cj, live, my_count);
+                test_candidates<kCandPasses, false, WIDE>(L, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                                                          n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
         }
         // per-atom epilogue: count, overflow flag, compact record
         const int i = s_own + i0 + lane;
@@ -658,15 +690,18 @@ __device__ __forceinline__ int4 record_load(__amdgpu_buffer_rsrc_t rs, int j)
 //
 // NCH: neighbour records in flight per thread (2, 4 or 8; the autotuner picks
 // it): more hide more gather latency, fewer free registers for more waves.
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, int CMP, int NCH>
-__global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
-                                                     int energy)
+//
+// TL: several species with all their tables staged in LDS, in workgroups of
+// kTableBlock threads that share one copy (one species always stages its own).
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int CMP, int NCH, bool TL>
+__global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_density(Buffers b, int p, int q, int64_t n_slots,
+                                                                        PotArgs P, int energy)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const R* tab = tables<R>(b).dens;
-    if (EV != EV_KNOTS && SINGLE) {
+    if (EV != EV_KNOTS && (SINGLE || TL)) {
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tab, P.nbt * value_stride(EV));
+        lds_fill(s, tab, (SINGLE ? 1 : P.ns * P.ns) * P.nbt * value_stride(EV));
         __syncthreads();
         tab = s;
     }
@@ -699,6 +734,10 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
             v[4 * g + 2] = v4.z;
             v[4 * g + 3] = v4.w;
         }
+        uint32_t tv[GR];  // neighbour type bytes of the groups (several species)
+#pragma unroll
+        for (int g = 0; g < GR; ++g)
+            tv[g] = SINGLE ? 0u : reinterpret_cast<const uint32_t*>(b.ntype)[(int64_t)((k0 >> 2) + g) * n_slots + t];
 #pragma unroll
         for (int sb = 0; sb < SUB; ++sb) {
             const int kb = k0 + sb * NCH;
@@ -728,7 +767,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (!(r2 < P.rc2)) continue;
                 const double r = r2 * inv_dist<R>(r2);
-                const int sj = SINGLE ? 0 : (b.type[q][e[u] & kIndexMask] & 0x3F);
+                const int ku = sb * NCH + u;  // entry within the groups loaded
+                const int sj = SINGLE ? 0 : (int)((tv[ku >> 2] >> (8 * (ku & 3))) & 0x3F);
                 rho += (double)density_term<R, SINGLE, NDK, EV>(P, G, tab, si, sj, r);
             }
         }
@@ -742,21 +782,22 @@ __global__ __launch_bounds__(kBlock) void k_density(Buffers b, int p, int q, int
 
 // Force pass + velocity Verlet (global gathers).
 template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
-          int CMP, int NCH>
-__global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots, PotArgs P,
-                                                   double dt, md_state st)
+          int CMP, int NCH, bool TL>
+__global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots,
+                                                                      PotArgs P, double dt, md_state st)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Tabs<R> T = tables<R>(b);
     const R* tf = T.force;
     const R* te = T.energy;
-    if (EV != EV_KNOTS && SINGLE) {
+    if (EV != EV_KNOTS && (SINGLE || TL)) {
+        const int nf = (SINGLE ? 1 : P.ns * P.ns) * P.nbt * force_stride(EV);
         R* s = reinterpret_cast<R*>(smem);
-        lds_fill(s, tf, P.nbt * force_stride(EV));
-        if (ENERGY == 1) lds_fill(s + P.nbt * force_stride(EV), te, P.nbt * value_stride(EV));
+        lds_fill(s, tf, nf);
+        if (ENERGY == 1) lds_fill(s + nf, te, (SINGLE ? 1 : P.ns * P.ns) * P.nbt * value_stride(EV));
         __syncthreads();
         tf = s;
-        te = s + P.nbt * force_stride(EV);
+        te = s + nf;
     }
     const int64_t t = global_thread();
     if (t >= n_slots) return;
@@ -790,6 +831,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
             v[4 * g + 2] = v4.z;
             v[4 * g + 3] = v4.w;
         }
+        uint32_t tv[GR];  // neighbour type bytes of the groups (several species)
+#pragma unroll
+        for (int g = 0; g < GR; ++g)
+            tv[g] = SINGLE ? 0u : reinterpret_cast<const uint32_t*>(b.ntype)[(int64_t)((k0 >> 2) + g) * n_slots + t];
 #pragma unroll
         for (int sb = 0; sb < SUB; ++sb) {
             const int kb = k0 + sb * NCH;
@@ -825,7 +870,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Buffers b, int p, int q, int64
                 const double r = r2 * ri;
                 // one species: j's type byte matters only for the virial of a rigid
                 // atom i (pairs of two rigid atoms stay out of it)
-                const uint8_t tj = (!SINGLE || (ENERGY == 1 && rigid_i)) ? b.type[q][e[u] & kIndexMask] : 0;
+                const int ku = sb * NCH + u;  // entry within the groups loaded
+                const uint8_t tj = !SINGLE ? (uint8_t)(tv[ku >> 2] >> (8 * (ku & 3)))
+                                           : (ENERGY == 1 && rigid_i) ? b.type[q][e[u] & kIndexMask] : 0;
                 R g, phi;
                 pair_terms<R, SINGLE, NPK, NDK, EV, ENERGY>(P, G, tf, te, si, tj & 0x3F, r, fpi, fpj, g, phi);
                 accumulate<ENERGY>(A, (double)g * ri, dx, dy, dz, (double)phi, rigid_i && (tj & kRigidBit));
@@ -1622,14 +1669,12 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
                        hipStream_t s)
 {
-    (void)q;
     const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
-    if (k.tri)
-        hipLaunchKernelGGL(k_cell_list<true>, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap,
-                           rlist2, half_list, k.compact);
-    else
-        hipLaunchKernelGGL(k_cell_list<false>, dim3(blocks), dim3(kBlock), 0, s, b, p, k.n_slots, k.n_cells, k.cap,
-                           rlist2, half_list, k.compact);
+    const bool wide = (uint64_t)k.n_slots * 16 * (uint64_t)((k.cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32);
+    auto kern = k.tri ? (wide ? k_cell_list<true, true> : k_cell_list<true, false>)
+                      : (wide ? k_cell_list<false, true> : k_cell_list<false, false>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells, k.cap, rlist2,
+                       half_list, k.compact, k.list_types);
 }
 
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)
@@ -1642,30 +1687,45 @@ void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipSt
     hipLaunchKernelGGL(k_compact_records, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, k.n_slots);
 }
 
-template <typename R, bool S, int NP, int ND, int EV, int CMP>
+template <typename R, bool S, int NP, int ND, int EV, int CMP, bool TL>
 static void density_chunked(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                             size_t lds, hipStream_t s)
 {
-    const dim3 grid(blocks_for(k.n_slots));
+    const int block = TL ? kTableBlock : kBlock;
+    const dim3 grid((unsigned)((k.n_slots + block - 1) / block));
     if (k.nchunk == 2)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 2>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           energy);
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 2, TL>), grid, dim3(block), lds, s, b, p, q, k.n_slots,
+                           P, energy);
     else if (k.nchunk == 8)
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 8>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           energy);
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 8, TL>), grid, dim3(block), lds, s, b, p, q, k.n_slots,
+                           P, energy);
     else
-        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 4>), grid, dim3(kBlock), lds, s, b, p, q, k.n_slots, P,
-                           energy);
+        hipLaunchKernelGGL((k_density<R, S, NP, ND, EV, CMP, 4, TL>), grid, dim3(block), lds, s, b, p, q, k.n_slots,
+                           P, energy);
+}
+
+template <typename R, bool S, int NP, int ND, int EV, int CMP>
+static void density_tables(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
+                           hipStream_t s)
+{
+    // tables in LDS: always for one species, for several when they fit
+    const size_t bytes = EV != EV_KNOTS ? (size_t)(S ? 1 : P.ns * P.ns) * P.nbt * value_stride(EV) * sizeof(R) : 0;
+    if constexpr (!S && EV != EV_KNOTS) {
+        if (bytes <= (size_t)k.lds_limit) {
+            density_chunked<R, S, NP, ND, EV, CMP, true>(b, p, q, k, P, energy, bytes, s);
+            return;
+        }
+    }
+    density_chunked<R, S, NP, ND, EV, CMP, false>(b, p, q, k, P, energy, S ? bytes : 0, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>
 static void density_variant(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int energy,
                             hipStream_t s)
 {
-    const size_t lds = (EV != EV_KNOTS && S) ? (size_t)P.nbt * value_stride(EV) * sizeof(R) : 0;
-    if (k.compact == 2) density_chunked<R, S, NP, ND, EV, 2>(b, p, q, k, P, energy, lds, s);
-    else if (k.compact) density_chunked<R, S, NP, ND, EV, 1>(b, p, q, k, P, energy, lds, s);
-    else density_chunked<R, S, NP, ND, EV, 0>(b, p, q, k, P, energy, lds, s);
+    if (k.compact == 2) density_tables<R, S, NP, ND, EV, 2>(b, p, q, k, P, energy, s);
+    else if (k.compact) density_tables<R, S, NP, ND, EV, 1>(b, p, q, k, P, energy, s);
+    else density_tables<R, S, NP, ND, EV, 0>(b, p, q, k, P, energy, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>
@@ -1718,37 +1778,53 @@ void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const 
 // The neighbour chunk applies to the velocity-Verlet step kernels (with and
 // without energies) and to the plain force pass the autotuner times; the other
 // variants run once per call or per barostat step.
-template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W, int CMP>
+template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W, int CMP, bool TL>
 static void force_chunked(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                           const md_state& st, size_t lds, hipStream_t s)
 {
-    const dim3 grid(blocks_for(k.n_slots));
+    const int block = TL ? kTableBlock : kBlock;
+    const dim3 grid((unsigned)((k.n_slots + block - 1) / block));
     constexpr bool step = ((E == 0 || E == 1) && C && O && !W) || (E == 0 && !C && !O && !W);
     if constexpr (step) {
         if (k.nchunk == 2) {
-            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 2>), grid, dim3(kBlock), lds, s, b, p, q,
-                               k.n_slots, P, dt_fs, st);
+            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 2, TL>), grid, dim3(block), lds, s, b, p,
+                               q, k.n_slots, P, dt_fs, st);
             return;
         }
         if (k.nchunk == 8) {
-            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 8>), grid, dim3(kBlock), lds, s, b, p, q,
-                               k.n_slots, P, dt_fs, st);
+            hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 8, TL>), grid, dim3(block), lds, s, b, p,
+                               q, k.n_slots, P, dt_fs, st);
             return;
         }
     }
-    hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 4>), grid, dim3(kBlock), lds, s, b, p, q,
+    hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 4, TL>), grid, dim3(block), lds, s, b, p, q,
                        k.n_slots, P, dt_fs, st);
+}
+
+template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W, int CMP>
+static void force_tables(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
+                         const md_state& st, hipStream_t s)
+{
+    // tables in LDS: always for one species, for several when they fit
+    const size_t bytes = EV != EV_KNOTS ? (size_t)(S ? 1 : P.ns * P.ns) * P.nbt *
+                                              (force_stride(EV) + (E == 1 ? value_stride(EV) : 0)) * sizeof(R)
+                                        : 0;
+    if constexpr (!S && EV != EV_KNOTS) {
+        if (bytes <= (size_t)k.lds_limit) {
+            force_chunked<R, S, NP, ND, EV, E, C, O, W, CMP, true>(b, p, q, k, P, dt_fs, st, bytes, s);
+            return;
+        }
+    }
+    force_chunked<R, S, NP, ND, EV, E, C, O, W, CMP, false>(b, p, q, k, P, dt_fs, st, S ? bytes : 0, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV, int E, bool C, bool O, bool W>
 static void force_launch(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, double dt_fs,
                          const md_state& st, hipStream_t s)
 {
-    const size_t lds =
-        (EV != EV_KNOTS && S) ? (size_t)P.nbt * (force_stride(EV) + (E == 1 ? value_stride(EV) : 0)) * sizeof(R) : 0;
-    if (k.compact == 2) force_chunked<R, S, NP, ND, EV, E, C, O, W, 2>(b, p, q, k, P, dt_fs, st, lds, s);
-    else if (k.compact) force_chunked<R, S, NP, ND, EV, E, C, O, W, 1>(b, p, q, k, P, dt_fs, st, lds, s);
-    else force_chunked<R, S, NP, ND, EV, E, C, O, W, 0>(b, p, q, k, P, dt_fs, st, lds, s);
+    if (k.compact == 2) force_tables<R, S, NP, ND, EV, E, C, O, W, 2>(b, p, q, k, P, dt_fs, st, s);
+    else if (k.compact) force_tables<R, S, NP, ND, EV, E, C, O, W, 1>(b, p, q, k, P, dt_fs, st, s);
+    else force_tables<R, S, NP, ND, EV, E, C, O, W, 0>(b, p, q, k, P, dt_fs, st, s);
 }
 
 template <typename R, bool S, int NP, int ND, int EV>

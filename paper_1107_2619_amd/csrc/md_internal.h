@@ -22,6 +22,7 @@ constexpr double kEvPerA3InGpa = 160.217653;
 constexpr int kWave = 64;       // CDNA wavefront
 constexpr int kBlock = 256;     // threads per workgroup (4 waves)
 constexpr int kCandTable = 512; // list build: candidates one wave's LDS table holds
+constexpr int kTableBlock = 1024;  // global kernels with several species' tables in LDS
 constexpr int kEnergySlots = 12;  // per-wave partial record, see EnergyIndex
 constexpr int kNumXcd = 8;      // MI355X: 8 accelerator dies, one L2 each
 
@@ -166,6 +167,7 @@ struct Buffers {
     int4* cellxyz;        // [Np] link cell (cx, cy, cz) of each slot at the last build
     double* femb;         // [Np] F_i (energy steps)
     int32_t* nbr;         // [cap][Np] transposed list (global slots + shift code)
+    uint8_t* ntype;       // type byte of every list entry, same layout (several species)
     uint16_t* nbr16;      // [Np][rowlen] rows of staging (LDS) indices (brick path)
     int32_t* cell_sorted; // [Np] link cell of each slot after the sort
     int32_t* brick_rep;   // [n_bricks] replica of each brick
@@ -236,6 +238,7 @@ struct KernelShape {
     int32_t lds_limit; // LDS bytes one workgroup may use
     int32_t pairs;     // LDS bricks with each pair of two own atoms once (MD_OPT_KERNEL = 2)
     int32_t nchunk;    // neighbour records in flight per thread in the global kernels: 2, 4 or 8
+    int32_t list_types; // the global list also stores its entries' type bytes (several species)
     int32_t chunked;  // 1 = per-replica sums of the thermostat and barostat start with
                       // per-chunk sums (some replica spans more than kChunkedSumWaves waves)
 };

@@ -193,6 +193,7 @@ KernelShape shape(const md_ctx* c)
     k.chunked = c->chunked_sums ? 1 : 0;
     k.lds_limit = c->lds_limit;
     k.nchunk = c->nchunk;
+    k.list_types = c->single ? 0 : 1;
     return k;
 }
 
@@ -533,6 +534,7 @@ void plan_workspace(md_ctx* c)
         c->pr ? Np / kWave * (c->tri ? 12 : 6) * 8 : 0,      // pr_partial
         (size_t)c->ring_len * c->R * kEnergySlots * 8,       // ering
         8,                                                   // ering_count
+        c->single ? 0 : Np * (size_t)((c->cap + 2 * kChunk - 1) / kChunk * kChunk),  // ntype (several species)
     };
     c->off.clear();
     size_t o = 0;
@@ -621,6 +623,7 @@ void bind_buffers(md_ctx* c)
     at(b.pr_partial);
     at(b.ering);
     at(b.ering_count);
+    at(b.ntype);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -1223,9 +1226,6 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     c->C_alloc = (int32_t)std::max<int64_t>(cells_alloc, 1);
     c->scan_nb = (c->C_alloc + 1023) / 1024;
     if (c->scan_nb > 1024 * 64) return reject(MD_ERR_ARG, "too many link cells");
-    // the list kernels address the global list with 32-bit byte offsets
-    if ((uint64_t)c->Np * 16 * (uint64_t)((c->cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32))
-        return reject(MD_ERR_ARG, "neighbour list above 4 GiB: lower max_neighbours or split the system");
     c->rep_of_wave.assign(c->Np / kWave, 0);
     for (int r = 0; r < c->R; ++r) {
         const int64_t w0 = c->reps[r].slot_off / kWave;

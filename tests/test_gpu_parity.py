@@ -315,6 +315,26 @@ def test_neighbour_list_complete(md, orc):
         assert all(r[i, j] < rc + s.skin for j in listed)
 
 
+def test_list_above_4gib(md):
+    """A list whose allocation exceeds 4 GiB (128,000 atoms with room for 8,400
+    entries each) is written with 64-bit addresses instead of 32-bit buffer
+    offsets: the same entries in the same order, so 12 steps (one rebuild) agree
+    bit for bit with the default capacity."""
+    s = inputs.bcc_fe(40, temperature=300.0, seed=44, name="bcc_wide")
+    assert s.n_atoms * 16 * ((8400 + 7) // 4) >= 1 << 32
+    announce("list above 4 GiB")
+    out = []
+    for cap in (48, 8400):
+        sim = md.Simulation(s, max_neighbours=cap)
+        sim.set_option(md.MD_OPT_KERNEL, 1)
+        sim.step(12)
+        e = sim.energy()
+        out.append((sim.positions(), sim.forces(), e.pe))
+        del sim
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("precision,mode", [("fp64", "full"), ("mixed", "full"), ("fp64", "half")])
 def test_trajectory_100_steps(md, orc, precision, mode):
     """100 velocity-Verlet steps with list rebuilds every 10 steps against the
