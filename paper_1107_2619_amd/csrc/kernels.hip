@@ -781,11 +781,16 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_density(Buffers b
 }
 
 // Force pass + velocity Verlet (global gathers).
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK,
+//
+// EN = 4: the energies and virial of energy mode 1, summed per wavefront in the
+// kernel (the reduction then reads one record per 64 atoms).
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int EN, bool CLOSE, bool OPEN, bool WRITEBACK,
           int CMP, int NCH, bool TL>
 __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, int p, int q, int64_t n_slots,
                                                                       PotArgs P, double dt, md_state st)
 {
+    constexpr bool WSUM = EN == 4;
+    constexpr int ENERGY = WSUM ? 1 : EN;
     extern __shared__ __align__(16) unsigned char smem[];
     const Tabs<R> T = tables<R>(b);
     const R* tf = T.force;
@@ -802,7 +807,10 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, 
     const int64_t t = global_thread();
     if (t >= n_slots) return;
     const DevReplica& Rp = b.reps[uniform(b.rep_of_wave[t / kWave])];
-    if (t - Rp.slot_off >= Rp.n_atoms) return;
+    // slots past the replica's atoms: none in energy-sum mode, whose wavefront
+    // sums need every lane (those lanes add zeros)
+    const bool pad = t - Rp.slot_off >= Rp.n_atoms;
+    if (pad && !WSUM) return;
     const Box bx = load_box(Rp);
     const DevPotential& G = *b.pot;
     const double4* __restrict__ pos = b.pos[p];
@@ -815,7 +823,7 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, 
     const uint8_t ti = b.type[q][t];
     const int si = ti & 0x3F;
     const bool rigid_i = ti & kRigidBit;
-    const int n = b.ncount[t];
+    const int n = pad ? 0 : b.ncount[t];
     const R fpi = CMP ? (R)__int_as_float(qi.w) : (R)pi.w;
     PairAcc A;
     constexpr int GR = NCH >= kChunk ? NCH / kChunk : 1;  // list groups per iteration
@@ -879,8 +887,11 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, 
             }
         }
     }
-    atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK>(b, p, q, t, n_slots, Rp, P, G, dt, st, pi, ti, A);
-    if (CMP && OPEN) {
+    double wv[kEnergyTerms] = {};
+    if (!pad) atom_epilogue<SINGLE, ENERGY, CLOSE, OPEN, WRITEBACK, WSUM>(b, p, q, t, n_slots, Rp, P, G, dt, st, pi, ti,
+                                                                      A, wv);
+    if (WSUM) wave_sum_terms(b, t, wv);
+    if (CMP && OPEN && !pad) {
         // the compact record of the drifted position, for the next density pass
         const int4 c4 = b.cellxyz[t];
         const int c[3] = {c4.x, c4.y, c4.z};
@@ -926,6 +937,27 @@ __global__ __launch_bounds__(kBlock) void k_reduce_chunks(Buffers b, int64_t n_s
         for (int k = 0; k < kEnergyTerms; ++k) v[k] += b.eslot[(int64_t)k * n_slots + t];
     block_sum_terms(v, sh);
     if (threadIdx.x < kEnergyTerms) b.chunk_partial[(int64_t)c * kEnergySlots + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Stage 1 from per-wavefront sums: one wavefront per chunk sums its chunk's
+// (at most kReduceChunk / 64) wavefront records by an xor butterfly.
+__global__ __launch_bounds__(kWave) void k_reduce_wave_chunks(Buffers b)
+{
+    static_assert(kReduceChunk / kWave <= kWave, "one lane per wavefront record of a chunk");
+    const int c = blockIdx.x;
+    const int r = b.chunk_rep[c];
+    const DevReplica& R = b.reps[r];
+    const int64_t s0 = R.slot_off + (int64_t)(c - b.chunk_off[r]) * kReduceChunk;
+    const int64_t s1 = min(s0 + (int64_t)kReduceChunk, (int64_t)R.slot_off + R.n_atoms);
+    const int64_t w = s0 / kWave + threadIdx.x;
+    const bool live = w < (s1 + kWave - 1) / kWave;
+#pragma unroll
+    for (int k = 0; k < kEnergyTerms; ++k) {
+        double v = live ? b.wave_terms[w * kEnergyTerms + k] : 0.0;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+        if (threadIdx.x == 0) b.chunk_partial[(int64_t)c * kEnergySlots + k] = v;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double virial_scale)
@@ -1784,7 +1816,7 @@ static void force_chunked(const Buffers& b, int p, int q, const KernelShape& k, 
 {
     const int block = TL ? kTableBlock : kBlock;
     const dim3 grid((unsigned)((k.n_slots + block - 1) / block));
-    constexpr bool step = ((E == 0 || E == 1) && C && O && !W) || (E == 0 && !C && !O && !W);
+    constexpr bool step = ((E == 0 || E == 1 || E == 4) && C && O && !W) || (E == 0 && !C && !O && !W);
     if constexpr (step) {
         if (k.nchunk == 2) {
             hipLaunchKernelGGL((k_force<R, S, NP, ND, EV, E, C, O, W, CMP, 2, TL>), grid, dim3(block), lds, s, b, p,
@@ -1807,7 +1839,8 @@ static void force_tables(const Buffers& b, int p, int q, const KernelShape& k, c
 {
     // tables in LDS: always for one species, for several when they fit
     const size_t bytes = EV != EV_KNOTS ? (size_t)(S ? 1 : P.ns * P.ns) * P.nbt *
-                                              (force_stride(EV) + (E == 1 ? value_stride(EV) : 0)) * sizeof(R)
+                                              (force_stride(EV) + (E == 1 || E == 4 ? value_stride(EV) : 0)) *
+                                              sizeof(R)
                                         : 0;
     if constexpr (!S && EV != EV_KNOTS) {
         if (bytes <= (size_t)k.lds_limit) {
@@ -1842,7 +1875,9 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
     } else if (!fl.close && fl.open) {
         force_launch<R, S, NP, ND, EV, false, false, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (fl.close && fl.open) {
-        if (fl.energy)  // per-step energies
+        if (fl.energy == 4)  // per-step energies, summed per wavefront
+            force_launch<R, S, NP, ND, EV, 4, true, true, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (fl.energy)  // per-step energies
             force_launch<R, S, NP, ND, EV, true, true, true, false>(b, p, q, k, P, dt_fs, st, s);
         else force_launch<R, S, NP, ND, EV, false, true, true, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback && fl.energy == 3) {  // full-matrix barostat: closing kick, virial tensor
@@ -2016,6 +2051,12 @@ void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t rin
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)
 {
     if (k.n_chunks > 0) hipLaunchKernelGGL(k_reduce_chunks, dim3(k.n_chunks), dim3(kBlock), 0, s, b, k.n_slots);
+    hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale);
+}
+
+void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)
+{
+    if (k.n_chunks > 0) hipLaunchKernelGGL(k_reduce_wave_chunks, dim3(k.n_chunks), dim3(kWave), 0, s, b);
     hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale);
 }
 

@@ -533,11 +533,13 @@ __device__ __forceinline__ void accumulate(PairAcc& A, double s, double dx, doub
 // accumulate the work -f.v_p dt/2 per half step (trapezoid rule).  On energy
 // steps the atom's energy terms go to its slot of `eslot`; with WRITEBACK the
 // final state returns to the caller's arrays (caller order, unwrapped).
-template <bool SINGLE, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK>
+//
+// WSUM: the energy terms go to `wv` for a wavefront sum instead of `eslot`.
+template <bool SINGLE, int ENERGY, bool CLOSE, bool OPEN, bool WRITEBACK, bool WSUM = false>
 __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, int64_t t, int64_t n_slots,
                                               const DevReplica& Rp, const PotArgs& P, const DevPotential& G,
                                               double dt, const md_state& st, const double4& pi, uint8_t ti,
-                                              const PairAcc& A)
+                                              const PairAcc& A, double* wv = nullptr)
 {
     const int si = ti & 0x3F;
     const bool rigid_i = ti & kRigidBit;
@@ -588,7 +590,10 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         const int nonfinite = (!isfinite(pe) || !isfinite(ke) || !isfinite(f[0] + f[1] + f[2])) ? 1 : 0;
         const double vals[kEnergyTerms] = {pe, ke, A.w[0], A.w[1], A.w[2], A.w[3], A.w[4], A.w[5], pw, (double)nonfinite};
 #pragma unroll
-        for (int k = 0; k < kEnergyTerms; ++k) b.eslot[(int64_t)k * n_slots + t] = vals[k];
+        for (int k = 0; k < kEnergyTerms; ++k) {
+            if (WSUM) wv[k] = vals[k];
+            else b.eslot[(int64_t)k * n_slots + t] = vals[k];
+        }
     } else if (ENERGY == 2 || ENERGY == 3) {  // barostat steps: the virial diagonal, or the whole tensor
 #pragma unroll
         for (int k = 0; k < (ENERGY == 3 ? 6 : 3); ++k) b.eslot[(int64_t)(E_W0 + k) * n_slots + t] = A.w[k];
@@ -616,6 +621,20 @@ __device__ __forceinline__ void atom_epilogue(const Buffers& b, int p, int q, in
         }
         if (ENERGY == 1 && st.e_atom) st.e_atom[a] = pe;
     }
+}
+
+// Sum of each energy term over the wavefront (a wavefront never straddles two
+// replicas), by an xor butterfly: every lane ends with the same bits.  Lane 0
+// stores the sums of wavefront t / 64.  Called by all lanes of the wavefront.
+__device__ __forceinline__ void wave_sum_terms(const Buffers& b, int64_t t, double (&v)[kEnergyTerms])
+{
+#pragma unroll
+    for (int k = 0; k < kEnergyTerms; ++k)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int k = 0; k < kEnergyTerms; ++k) b.wave_terms[(t / kWave) * kEnergyTerms + k] = v[k];
 }
 
 }  // namespace

@@ -168,6 +168,7 @@ struct Buffers {
     double* femb;         // [Np] F_i (energy steps)
     int32_t* nbr;         // [cap][Np] transposed list (global slots + shift code)
     uint8_t* ntype;       // type byte of every list entry, same layout (several species)
+    double* wave_terms;   // [Np / 64][kEnergyTerms] per-wavefront energy sums (velocity-Verlet energy steps)
     uint16_t* nbr16;      // [Np][rowlen] rows of staging (LDS) indices (brick path)
     int32_t* cell_sorted; // [Np] link cell of each slot after the sort
     int32_t* brick_rep;   // [n_bricks] replica of each brick
@@ -257,13 +258,16 @@ void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                     int half_list, int energy, hipStream_t s);
 // energy: 0 none, 1 energies and virial, 2 the virial diagonal only (barostat),
-// 3 the whole virial tensor only (full-matrix barostat)
+// 3 the whole virial tensor only (full-matrix barostat), 4 energies and virial
+// summed per wavefront (velocity-Verlet energy steps of the global kernels)
 struct ForceFlags {
     int energy, close, open, writeback;
 };
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
 void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
+// The same totals from the per-wavefront sums of an energy step of the global kernels.
+void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
 // Appends the per-replica totals of the last reduction to the energy ring.
 void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t ring_len, hipStream_t s);
 // Nose-Hoover thermostat: kinetic energy per replica and `halves` thermostat

@@ -535,6 +535,7 @@ void plan_workspace(md_ctx* c)
         (size_t)c->ring_len * c->R * kEnergySlots * 8,       // ering
         8,                                                   // ering_count
         c->single ? 0 : Np * (size_t)((c->cap + 2 * kChunk - 1) / kChunk * kChunk),  // ntype (several species)
+        Np / kWave * kEnergyTerms * 8,                       // wave_terms
     };
     c->off.clear();
     size_t o = 0;
@@ -624,6 +625,7 @@ void bind_buffers(md_ctx* c)
     at(b.ering);
     at(b.ering_count);
     at(b.ntype);
+    at(b.wave_terms);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -721,11 +723,14 @@ void load_state(md_ctx* c, hipStream_t s, bool build_next)
     if (k.compact && c->have_list && !build_next) launch_compact_records(c->buf, c->p, k, s);
 }
 
-void reduce_energies(md_ctx* c, const KernelShape& k, hipStream_t s)
+// waves: the force pass summed the energy terms per wavefront (energy mode 4)
+void reduce_energies(md_ctx* c, const KernelShape& k, hipStream_t s, bool waves = false)
 {
     Timed tm(c, MD_KT_REDUCE, s);
     // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
-    launch_reduce_energies(c->buf, k, c->nbr_mode == MD_NBR_HALF_ATOMIC ? -1.0 : -0.5, s);
+    const double scale = c->nbr_mode == MD_NBR_HALF_ATOMIC ? -1.0 : -0.5;
+    if (waves) launch_reduce_waves(c->buf, k, scale, s);
+    else launch_reduce_energies(c->buf, k, scale, s);
     c->have_energy = true;
     // steps on the per-step energy schedule also append the totals to the ring
     // (the device counter picks the entry, so graph replays append in turn)
@@ -741,9 +746,13 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
 {
     const KernelShape k = shape(c);
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
+    // velocity-Verlet energy steps of the global kernels sum the energy terms
+    // per wavefront in the force pass (nothing else reads them per atom)
+    const bool waves = fl.energy == 1 && fl.close && fl.open && !fl.writeback && reduce && !k.brick && !half;
+    if (waves) fl.energy = 4;
     {
         Timed tm(c, MD_KT_DENSITY, s);
-        const int fe = fl.energy == 1;  // barostat steps (energy 2) need no embedding energies
+        const int fe = fl.energy == 1 || fl.energy == 4;  // barostat steps (energy 2, 3) need no embedding energies
         if (k.pairs) launch_pair_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
         else if (k.brick) launch_brick_density(c->buf, c->p, c->q, k, c->args, c->precision, fe, s);
         else launch_density(c->buf, c->p, c->q, k, c->args, c->precision, half, fe, s);
@@ -755,7 +764,7 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
         else launch_force(c->buf, c->p, c->q, k, c->args, c->precision, half, fl, c->dt_fs, c->st, s);
     }
     if (fl.open) c->p ^= 1;
-    if (fl.energy == 1 && reduce) reduce_energies(c, k, s);
+    if ((fl.energy == 1 || fl.energy == 4) && reduce) reduce_energies(c, k, s, waves);
 }
 
 // Thermostatted step boundary: kinetic energy, `halves` thermostat half steps,

@@ -135,3 +135,36 @@ def test_neighbour_chunk_is_bitwise_neutral(md, orc, precision):
             assert np.array_equal(a, b)
     ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), s.dt_fs, 30)
     assert np.max(np.abs(runs[0][0] - ref.pos)) < (1e-8 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_energy_ring_batched_equals_alone(md, precision):
+    """Per-step energies of the global kernels are summed per wavefront in the
+    force pass (a wavefront never straddles two replicas): every ring entry of
+    a replica inside a batch equals, bit for bit, that of the replica run alone,
+    and matches the sums of the per-atom path within rounding."""
+    s = inputs.fec_replicas(3, nmin=300, nmax=900, seed0=4960)
+    batch = md.Simulation(s, precision=precision, energy_ring=64)
+    batch.set_option(md.MD_OPT_KERNEL, 1)
+    batch.set_option(md.MD_OPT_ENERGY_EVERY, 1)
+    batch.step(25)
+    hist = batch.energy_history()
+    for r in range(s.n_replicas):
+        one = md.Simulation(s.replica(r), precision=precision, energy_ring=64)
+        one.set_option(md.MD_OPT_KERNEL, 1)
+        one.set_option(md.MD_OPT_ENERGY_EVERY, 1)
+        one.step(25)
+        h1 = one.energy_history()
+        assert [h.step for h in h1] == [h.step for h in hist]
+        for a, b in zip(h1, hist):
+            assert a.pe[0] == b.pe[r] and a.ke[0] == b.ke[r] and np.array_equal(a.virial[0], b.virial[r])
+    # the brick kernels keep the per-atom energy path: same totals within rounding
+    brick = md.Simulation(s, precision=precision, energy_ring=64)
+    brick.set_option(md.MD_OPT_KERNEL, 0)
+    brick.set_option(md.MD_OPT_ENERGY_EVERY, 1)
+    brick.step(25)
+    hb = brick.energy_history()
+    tol = 1e-10 if precision == "fp64" else 1e-6
+    for a, b in zip(hb, hist):
+        assert np.all(np.abs(a.pe - b.pe) <= tol * np.abs(a.pe))
+        assert np.all(np.abs(a.ke - b.ke) <= tol * np.abs(a.ke))
