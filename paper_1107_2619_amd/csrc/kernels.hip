@@ -960,10 +960,18 @@ __global__ __launch_bounds__(kWave) void k_reduce_wave_chunks(Buffers b)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double virial_scale)
+//
+// ring_len > 0: the totals also go to entry (count mod ring_len) of the energy
+// ring ("Thermodynamic Quantities", sampled every few steps).  Every workgroup
+// reads the count before it takes a ticket, and the last one to take a ticket
+// advances the count, so a captured step sequence appends to successive
+// entries on every replay.
+__global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double virial_scale, int64_t ring_len)
 {
     __shared__ double sh[kEnergyTerms][kBlock];
     const int r = blockIdx.x;
+    const int64_t count =
+        ring_len > 0 ? __hip_atomic_load(b.ering_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     double v[kEnergyTerms];
 #pragma unroll
     for (int k = 0; k < kEnergyTerms; ++k) v[k] = 0.0;
@@ -976,21 +984,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce_replicas(Buffers b, double vi
         double out = k < kEnergyTerms ? sh[k][0] : 0.0;
         if (k >= E_W0 && k < E_W0 + 6) out *= virial_scale;
         b.energies[(int64_t)r * kEnergySlots + k] = out;
+        if (ring_len > 0) b.ering[((count % ring_len) * gridDim.x + r) * kEnergySlots + k] = out;
     }
-}
-
-// Per-step energies ("Thermodynamic Quantities", sampled every few steps):
-// the totals just reduced go to entry (count mod ring_len) of the ring, and the
-// count advances.  The entry index is read on the device, so a captured step
-// sequence appends to successive entries on every replay.  One workgroup.
-__global__ __launch_bounds__(kBlock) void k_energy_ring_push(Buffers b, int32_t n_replicas, int64_t ring_len)
-{
-    const int64_t count = __hip_atomic_load(b.ering_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int64_t n = (int64_t)n_replicas * kEnergySlots;
-    double* dst = b.ering + (count % ring_len) * n;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) dst[i] = b.energies[i];
-    __syncthreads();
-    if (threadIdx.x == 0) b.ering_count[0] = count + 1;
+    if (ring_len > 0) {
+        __syncthreads();  // this replica's entry is written
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned long long done = atomicAdd(reinterpret_cast<unsigned long long*>(b.ering_count + 1), 1ull);
+            if (done == gridDim.x - 1) {
+                b.ering_count[1] = 0;
+                __hip_atomic_store(b.ering_count, count + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1870,6 +1876,7 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
         else if (!fl.writeback && fl.energy)  // barostat: the stress of the starting state, forces kept
             force_launch<R, S, NP, ND, EV, 2, false, false, false>(b, p, q, k, P, dt_fs, st, s);
         else if (!fl.writeback) force_launch<R, S, NP, ND, EV, false, false, false, false>(b, p, q, k, P, dt_fs, st, s);
+        else if (fl.energy == 4) force_launch<R, S, NP, ND, EV, 4, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else if (fl.energy) force_launch<R, S, NP, ND, EV, true, false, false, true>(b, p, q, k, P, dt_fs, st, s);
         else force_launch<R, S, NP, ND, EV, false, false, false, true>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.close && fl.open) {
@@ -1886,6 +1893,8 @@ static void force_variant(const Buffers& b, int p, int q, const KernelShape& k, 
         force_launch<R, S, NP, ND, EV, 2, true, false, false>(b, p, q, k, P, dt_fs, st, s);
     } else if (!fl.writeback) {
         force_launch<R, S, NP, ND, EV, false, true, false, false>(b, p, q, k, P, dt_fs, st, s);
+    } else if (fl.energy == 4) {  // the last step of a velocity-Verlet call
+        force_launch<R, S, NP, ND, EV, 4, true, false, true>(b, p, q, k, P, dt_fs, st, s);
     } else {
         force_launch<R, S, NP, ND, EV, true, true, false, true>(b, p, q, k, P, dt_fs, st, s);
     }
@@ -2043,21 +2052,19 @@ void launch_nh_scale(const Buffers& b, int q, const KernelShape& k, const md_sta
     hipLaunchKernelGGL(k_nh_scale, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, q, k.n_slots, st, energy);
 }
 
-void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t ring_len, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_energy_ring_push, dim3(1), dim3(kBlock), 0, s, b, k.n_replicas, ring_len);
-}
 
-void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)
+void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, int64_t ring_len,
+                            hipStream_t s)
 {
     if (k.n_chunks > 0) hipLaunchKernelGGL(k_reduce_chunks, dim3(k.n_chunks), dim3(kBlock), 0, s, b, k.n_slots);
-    hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale);
+    hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale, ring_len);
 }
 
-void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s)
+void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, int64_t ring_len,
+                         hipStream_t s)
 {
     if (k.n_chunks > 0) hipLaunchKernelGGL(k_reduce_wave_chunks, dim3(k.n_chunks), dim3(kWave), 0, s, b);
-    hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale);
+    hipLaunchKernelGGL(k_reduce_replicas, dim3(k.n_replicas), dim3(kBlock), 0, s, b, virial_scale, ring_len);
 }
 
 }  // namespace mdk

@@ -216,7 +216,8 @@ struct Buffers {
     float *tab_force32, *tab_energy32, *tab_dens32;
     int32_t* flags;       // [F_COUNT]
     double* ering;        // [ring_len][R][kEnergySlots] per-replica totals of the per-step energy steps
-    int64_t* ering_count; // entries appended since md_bind (entry i lives at i % ring_len)
+    int64_t* ering_count; // [2] entries appended since md_bind (entry i lives at i % ring_len),
+                          // then the reduction's workgroup ticket
 };
 
 struct KernelShape {
@@ -265,11 +266,12 @@ struct ForceFlags {
 };
 void launch_force(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,
                   int half_list, ForceFlags fl, double dt_fs, const md_state& st, hipStream_t s);
-void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
+// ring_len > 0: the totals also go to the next entry of the energy ring.
+void launch_reduce_energies(const Buffers& b, const KernelShape& k, double virial_scale, int64_t ring_len,
+                            hipStream_t s);
 // The same totals from the per-wavefront sums of an energy step of the global kernels.
-void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, hipStream_t s);
-// Appends the per-replica totals of the last reduction to the energy ring.
-void launch_energy_ring_push(const Buffers& b, const KernelShape& k, int64_t ring_len, hipStream_t s);
+void launch_reduce_waves(const Buffers& b, const KernelShape& k, double virial_scale, int64_t ring_len,
+                         hipStream_t s);
 // Nose-Hoover thermostat: kinetic energy per replica and `halves` thermostat
 // half steps of length dt/2 (launch_nh_update); then either the scaled opening
 // kick and drift (launch_nh_open) or the final scaling (launch_nh_scale).

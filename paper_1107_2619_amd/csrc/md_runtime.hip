@@ -533,7 +533,7 @@ void plan_workspace(md_ctx* c)
         c->pr ? (size_t)c->R * (c->tri ? kPrtState : kPrState) * 8 : 0,  // pr_state
         c->pr ? Np / kWave * (c->tri ? 12 : 6) * 8 : 0,      // pr_partial
         (size_t)c->ring_len * c->R * kEnergySlots * 8,       // ering
-        8,                                                   // ering_count
+        16,                                                  // ering_count, ticket
         c->single ? 0 : Np * (size_t)((c->cap + 2 * kChunk - 1) / kChunk * kChunk),  // ntype (several species)
         Np / kWave * kEnergyTerms * 8,                       // wave_terms
     };
@@ -729,15 +729,13 @@ void reduce_energies(md_ctx* c, const KernelShape& k, hipStream_t s, bool waves 
     Timed tm(c, MD_KT_REDUCE, s);
     // W = -sum over pairs of g d d / r: the full list sees each pair from both atoms
     const double scale = c->nbr_mode == MD_NBR_HALF_ATOMIC ? -1.0 : -0.5;
-    if (waves) launch_reduce_waves(c->buf, k, scale, s);
-    else launch_reduce_energies(c->buf, k, scale, s);
-    c->have_energy = true;
     // steps on the per-step energy schedule also append the totals to the ring
     // (the device counter picks the entry, so graph replays append in turn)
-    if (c->ring_len > 0 && c->energy_every > 0 && c->step % c->energy_every == 0) {
-        launch_energy_ring_push(c->buf, k, c->ring_len, s);
-        c->ring_steps.push_back(c->step);
-    }
+    const bool ring = c->ring_len > 0 && c->energy_every > 0 && c->step % c->energy_every == 0;
+    if (waves) launch_reduce_waves(c->buf, k, scale, ring ? c->ring_len : 0, s);
+    else launch_reduce_energies(c->buf, k, scale, ring ? c->ring_len : 0, s);
+    c->have_energy = true;
+    if (ring) c->ring_steps.push_back(c->step);
 }
 
 // Density and force passes.  reduce = false leaves the energy reduction to
@@ -746,9 +744,10 @@ void forces(md_ctx* c, ForceFlags fl, hipStream_t s, bool reduce = true)
 {
     const KernelShape k = shape(c);
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
-    // velocity-Verlet energy steps of the global kernels sum the energy terms
-    // per wavefront in the force pass (nothing else reads them per atom)
-    const bool waves = fl.energy == 1 && fl.close && fl.open && !fl.writeback && reduce && !k.brick && !half;
+    // energy steps of the global kernels whose totals are reduced right away
+    // (velocity Verlet, md_eam_forces) sum the energy terms per wavefront in the
+    // force pass; the thermostat, barostat and Gear steps rework them per atom
+    const bool waves = fl.energy == 1 && reduce && !k.brick && !half && (fl.writeback || (fl.close && fl.open));
     if (waves) fl.energy = 4;
     {
         Timed tm(c, MD_KT_DENSITY, s);
@@ -1302,7 +1301,7 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         (!c->chunk_rep.empty() &&
          !hip_ok(c, hipMemcpy(c->buf.chunk_rep, c->chunk_rep.data(), c->chunk_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
         !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags") ||
-        !hip_ok(c, hipMemset(c->buf.ering_count, 0, 8), "md_bind energy ring"))
+        !hip_ok(c, hipMemset(c->buf.ering_count, 0, 16), "md_bind energy ring"))
         return MD_ERR_DEVICE;
     if (c->table_ok &&
         (!hip_ok(c, hipMemcpy(c->buf.tab_force64, c->tf64.data(), c->tf64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
