@@ -324,9 +324,9 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
 // come out in candidate order.  Full list: every j != i with r < r_c + skin;
 // half list: only j with a larger slot index.
 //
-// Entries: slot | code << kIndexBits, 2 bits per axis.  FP64 mode: the
-// periodic image (0 none, 1 +L, 2 -L); compact mixed mode: the unwrapped
-// link-cell offset plus one.  Axes with one or two periodic cells have no
+// Entries: slot | code << kIndexBits, 2 bits per axis, and kInnerBit for a
+// pair closer than r_d + skin.  FP64 mode: the periodic image (0 none, 1 +L,
+// 2 -L); compact mixed mode: the unwrapped link-cell offset plus one.  Axes with one or two periodic cells have no
 // unique image per cell; there the image is the minimum one of each pair.
 // Layout: groups of four entries per slot (nbr_at).  Overflow keeps counting, so the
 // required capacity can be reported.
@@ -421,9 +421,10 @@ struct ListOut {
 
 // Tests atoms s0 .. s0 + n - 1 (lane l holds atom s0 + l in xl) against the
 // candidates in registers and appends the in-range ones to their rows.
-template <int P, bool AMB, bool WIDE>
-__device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, double rlist2, int half_list,
-                                                int compact, const Box& bx, int amb, int s0, int n, const double3& xl,
+template <int P, bool AMB, bool WIDE, bool SPLIT>
+__device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, double rlist2, double rdl2,
+                                                int half_list, int compact, const Box& bx, int amb, int s0, int n,
+                                                const double3& xl,
                                                 const double (&cx)[P], const double (&cy)[P], const double (&cz)[P],
                                                 const int (&ce)[P], const int (&cj)[P], const int (&ct)[P],
                                                 const bool (&live)[P], int& my_count)
@@ -441,6 +442,7 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
             if (AMB) min_image_pair(bx, amb, compact, dx, dy, dz, e);
             const double r2 = dx * dx + dy * dy + dz * dz;
             bool take = live[u] & (cj[u] != i) & (r2 < rlist2);
+            if (SPLIT && r2 < rdl2) e |= kInnerBit;  // (otherwise every candidate carries it)
             if (half_list) take = take & (cj[u] > i);
             const uint64_t mask = __ballot(take);
             if (mask == 0) continue;
@@ -468,10 +470,13 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
 
 // TRI: sheared cells (candidate shifts are edge-vector sums), a separate
 // instantiation so the orthorhombic build keeps its short candidate loop.
-template <bool TRI, bool WIDE>
+// SPLIT: mark the inner entries (r < r_d + skin); otherwise every entry is
+// inner (one precision's density pass gains nothing from the mark).
+// WT: several species (each entry's type byte is stored beside it).
+template <bool TRI, bool WIDE, bool SPLIT, bool WT>
 __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, int64_t n_slots, int32_t n_cells,
-                                                      int32_t cap, double rlist2, int half_list, int compact,
-                                                      int with_types)
+                                                      int32_t cap, double rlist2, double rdl2, int half_list,
+                                                      int compact)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int cell = uniform((int)(logical_block() * (kBlock / kWave) + threadIdx.x / kWave));
@@ -539,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, i
     L.nbr = b.nbr;
     L.types = b.ntype;
     L.n_slots = n_slots;
-    L.with_types = with_types;
+    L.with_types = WT;
     for (int i0 = 0; i0 < n_own; i0 += kWave) {
         const int n_chunk = min(kWave, n_own - i0);
         // lane l holds atom s_own + i0 + l; the test loop broadcasts it
@@ -581,16 +586,16 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, i
                     cy[u] = xj.y + select_shift((w >> 2) & 3, bx.L[1]);
                     cz[u] = xj.z + select_shift((w >> 4) & 3, bx.L[2]);
                 }
-                ce[u] = j | (code << kIndexBits);
+                ce[u] = j | (code << kIndexBits) | (SPLIT ? 0 : kInnerBit);
                 cj[u] = j;
-                ct[u] = with_types ? b.type[q][j] : 0;
+                ct[u] = WT ? b.type[q][j] : 0;
                 live[u] = m0 < total;
             }
             if (amb)
-                test_candidates<kCandPasses, true, WIDE>(L, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                test_candidates<kCandPasses, true, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb, s_own + i0,
                                                          n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
             else
-                test_candidates<kCandPasses, false, WIDE>(L, cap, rlist2, half_list, compact, bx, amb, s_own + i0,
+                test_candidates<kCandPasses, false, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb, s_own + i0,
                                                           n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
         }
         // per-atom epilogue: count, overflow flag, compact record
@@ -747,14 +752,19 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_density(Buffers b
             int4 qs[NCH];
 #pragma unroll
             for (int u = 0; u < NCH; ++u) {
+                // FP64: only inner entries (the others lie beyond every density
+                // cutoff); mixed-precision lists mark every entry inner
                 e[u] = kb + u < n ? v[sb * NCH + u] : (int)t;
-                if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
-                else xs[u] = load_xyz(pos, e[u] & kIndexMask);
+                if (sizeof(R) == 4 || e[u] < 0) {
+                    if (CMP) qs[u] = record_load(rs, e[u] & kIndexMask);
+                    else xs[u] = load_xyz(pos, e[u] & kIndexMask);
+                }
             }
 #pragma unroll
             for (int u = 0; u < NCH; ++u) {
                 if (kb + u >= n) break;
-                const int code = (unsigned)e[u] >> kIndexBits;
+                if (sizeof(R) == 8 && e[u] >= 0) continue;
+                const int code = ((unsigned)e[u] >> kIndexBits) & kCodeMask;
                 double dx, dy, dz;
                 if (CMP) {
                     compact_delta<CMP>(Rp, qb, qs[u], code, dx, dy, dz);
@@ -764,7 +774,7 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_density(Buffers b
                     dz = xs[u].z - xi.z;
                     if (code) apply_shift(bx, code, dx, dy, dz);
                 }
-                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 if (!(r2 < P.rc2)) continue;
                 const double r = r2 * inv_dist<R>(r2);
                 const int ku = sb * NCH + u;  // entry within the groups loaded
@@ -859,7 +869,7 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, 
 #pragma unroll
             for (int u = 0; u < NCH; ++u) {
                 if (kb + u >= n) break;
-                const int code = (unsigned)e[u] >> kIndexBits;
+                const int code = ((unsigned)e[u] >> kIndexBits) & kCodeMask;
                 double dx, dy, dz;
                 R fpj;
                 if (CMP) {
@@ -872,7 +882,7 @@ __global__ __launch_bounds__(TL ? kTableBlock : kBlock) void k_force(Buffers b, 
                     if (code) apply_shift(bx, code, dx, dy, dz);
                     fpj = (R)ps[u].w;
                 }
-                const double r2 = dx * dx + dy * dy + dz * dz;
+                const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 if (!(r2 < P.rc2)) continue;
                 const double ri = inv_dist<R>(r2);
                 const double r = r2 * ri;
@@ -1551,7 +1561,7 @@ __global__ __launch_bounds__(kBlock) void k_density_half(Buffers b, int p, int q
         const int j = e & kIndexMask;
         const double3 xj = load_xyz(pos, j);
         double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-        const int code = (unsigned)e >> kIndexBits;
+        const int code = ((unsigned)e >> kIndexBits) & kCodeMask;
         if (code) apply_shift(bx, code, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (!(r2 < P.rc2)) continue;
@@ -1617,7 +1627,7 @@ __global__ __launch_bounds__(kBlock) void k_force_half(Buffers b, int p, int q, 
         const int j = e & kIndexMask;
         const double4 pj = pos[j];
         double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-        const int code = (unsigned)e >> kIndexBits;
+        const int code = ((unsigned)e >> kIndexBits) & kCodeMask;
         if (code) apply_shift(bx, code, dx, dy, dz);
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (!(r2 < P.rc2)) continue;
@@ -1704,15 +1714,25 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots);
 }
 
-void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
-                       hipStream_t s)
+void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, double rdl2,
+                       int half_list, hipStream_t s)
 {
     const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
     const bool wide = (uint64_t)k.n_slots * 16 * (uint64_t)((k.cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32);
-    auto kern = k.tri ? (wide ? k_cell_list<true, true> : k_cell_list<true, false>)
-                      : (wide ? k_cell_list<false, true> : k_cell_list<false, false>);
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells, k.cap, rlist2,
-                       half_list, k.compact, k.list_types);
+    const bool split = k.split_list && !half_list && rdl2 < rlist2;
+    const int which = (k.tri ? 8 : 0) | (wide ? 4 : 0) | (split ? 2 : 0) | (k.list_types ? 1 : 0);
+    using Kern = void (*)(Buffers, int, int, int64_t, int32_t, int32_t, double, double, int, int);
+    static const Kern kerns[16] = {
+        k_cell_list<false, false, false, false>, k_cell_list<false, false, false, true>,
+        k_cell_list<false, false, true, false>,  k_cell_list<false, false, true, true>,
+        k_cell_list<false, true, false, false>,  k_cell_list<false, true, false, true>,
+        k_cell_list<false, true, true, false>,   k_cell_list<false, true, true, true>,
+        k_cell_list<true, false, false, false>,  k_cell_list<true, false, false, true>,
+        k_cell_list<true, false, true, false>,   k_cell_list<true, false, true, true>,
+        k_cell_list<true, true, false, false>,   k_cell_list<true, true, false, true>,
+        k_cell_list<true, true, true, false>,    k_cell_list<true, true, true, true>};
+    hipLaunchKernelGGL(kerns[which], dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells, k.cap, rlist2,
+                       half_list ? rlist2 : rdl2, half_list, k.compact);
 }
 
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)

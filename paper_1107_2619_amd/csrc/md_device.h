@@ -391,15 +391,15 @@ __device__ __forceinline__ double lane_sum(double v)
 
 // One pair's contribution to the density of the site atom (species si) from
 // a neighbour of species sj at distance r: rho_{si sj}(r).
-// Knot term inside a bin: amp (D - u)^2 (P = 2, derivative records) or
-// amp (D - u)^3 (P = 3, value records), zero for u >= D.
+// Knot term inside a bin, added to acc: amp (D - u)^2 (P = 2, derivative
+// records) or amp (D - u)^3 (P = 3, value records), zero for u >= D.  The
+// fused forms are explicit so that every kernel variant rounds alike.
 template <typename R, int PW>
-__device__ __forceinline__ R split_term(const R* c, R u)
+__device__ __forceinline__ R split_term(const R* c, R u, R acc)
 {
     R t = c[0] - u;
     t = t > R(0) ? t : R(0);
-    const R t2 = t * t;
-    return PW == 3 ? c[1] * t2 * t : c[1] * t2;
+    return PW == 3 ? fma(c[1] * t * t, t, acc) : fma(c[1] * t, t, acc);
 }
 
 template <typename R, bool SINGLE, int NDK, int EV>
@@ -412,7 +412,7 @@ __device__ __forceinline__ R density_term(const PotArgs& P, const DevPotential& 
         const R u = (R)fma(-(double)bin, P.w, r);
         const int ab = SINGLE ? 0 : si * G.ns + sj;
         const R* c = tab + ((int64_t)ab * P.nbt + bin) * VS;
-        if (EV == EV_SPLIT) return cubic(c, u) + split_term<R, 3>(c + 4, u);
+        if (EV == EV_SPLIT) return split_term<R, 3>(c + 4, u, cubic(c, u));
         return cubic(c, u);
     } else if (SINGLE) {
         const Coef<R> C1 = single_coef<R>(P);
@@ -427,8 +427,9 @@ __device__ __forceinline__ R density_term(const PotArgs& P, const DevPotential& 
 
 // g_ij = phi'_{ij}(r) + F'_i rho'_{ij}(r) + F'_j rho'_{ji}(r) and, on energy
 // steps, phi_{ij}(r).  Tables: tf = [ns*ns][nbt][kForceStride] derivative quadratics,
-// te = [ns*ns][nbt][4] value cubics.
-template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY>
+// te = [ns*ns][nbt][4] value cubics.  DENS = false: a pair beyond every density
+// cutoff, whose rho' terms vanish (the caller knows it from the list).
+template <typename R, bool SINGLE, int NPK, int NDK, int EV, int ENERGY, bool DENS = true>
 __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential& G, const R* tf, const R* te,
                                            int si, int sj, double r, R fpi, R fpj, R& g, R& phi)
 {
@@ -439,32 +440,38 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
         const R u = (R)fma(-(double)bin, P.w, r);
         if (SINGLE) {
             const R* c = tf + bin * FS;
-            R dphi = quadratic(c, u), drho = quadratic(c + 3, u);
-            if (EV == EV_SPLIT) {
-                dphi += split_term<R, 2>(c + 6, u);
-                drho += split_term<R, 2>(c + 8, u);
+            R dphi = quadratic(c, u);
+            if (EV == EV_SPLIT) dphi = split_term<R, 2>(c + 6, u, dphi);
+            g = dphi;
+            if (DENS) {  // explicit fused forms: every kernel variant rounds alike
+                R drho = quadratic(c + 3, u);
+                if (EV == EV_SPLIT) drho = split_term<R, 2>(c + 8, u, drho);
+                g = fma(fpi + fpj, drho, dphi);
             }
-            g = dphi + (fpi + fpj) * drho;
             if (ENERGY == 1) {
                 const R* e = te + bin * VS;
                 phi = cubic(e, u);
-                if (EV == EV_SPLIT) phi += split_term<R, 3>(e + 4, u);
+                if (EV == EV_SPLIT) phi = split_term<R, 3>(e + 4, u, phi);
             }
         } else {
             const int64_t ab = si * G.ns + sj, ba = sj * G.ns + si;
             const R* c = tf + (ab * P.nbt + bin) * FS;
-            const R* c2 = tf + (ba * P.nbt + bin) * FS;
-            R dphi = quadratic(c, u), dab = quadratic(c + 3, u), dba = quadratic(c2 + 3, u);
-            if (EV == EV_SPLIT) {
-                dphi += split_term<R, 2>(c + 6, u);
-                dab += split_term<R, 2>(c + 8, u);
-                dba += split_term<R, 2>(c2 + 8, u);
+            R dphi = quadratic(c, u);
+            if (EV == EV_SPLIT) dphi = split_term<R, 2>(c + 6, u, dphi);
+            g = dphi;
+            if (DENS) {
+                const R* c2 = tf + (ba * P.nbt + bin) * FS;
+                R dab = quadratic(c + 3, u), dba = quadratic(c2 + 3, u);
+                if (EV == EV_SPLIT) {
+                    dab = split_term<R, 2>(c + 8, u, dab);
+                    dba = split_term<R, 2>(c2 + 8, u, dba);
+                }
+                g = fma(fpi, dab, fma(fpj, dba, dphi));
             }
-            g = dphi + fpi * dab + fpj * dba;
             if (ENERGY == 1) {
                 const R* e = te + (ab * P.nbt + bin) * VS;
                 phi = cubic(e, u);
-                if (EV == EV_SPLIT) phi += split_term<R, 3>(e + 4, u);
+                if (EV == EV_SPLIT) phi = split_term<R, 3>(e + 4, u, phi);
             }
         }
     } else if (SINGLE) {
@@ -472,7 +479,7 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
         R dphi;
         if (ENERGY == 1) knot_both<R, NPK>(C1.pa, C1.pd, C1.pr, r, phi, dphi);
         else dphi = knot_deriv<R, NPK>(C1.pd, C1.pr, r);
-        g = dphi + (fpi + fpj) * knot_deriv<R, NDK>(C1.dd, C1.dr, r);
+        g = DENS ? fma(fpi + fpj, knot_deriv<R, NDK>(C1.dd, C1.dr, r), dphi) : dphi;
     } else {
         const int ab = si * G.ns + sj, ba = sj * G.ns + si;
         KnotSet<R, NPK> kp;
@@ -480,10 +487,13 @@ __device__ __forceinline__ void pair_terms(const PotArgs& P, const DevPotential&
         R dphi;
         if (ENERGY == 1) knot_both<R, NPK>(kp.a, kp.d, kp.r, r, phi, dphi);
         else dphi = knot_deriv<R, NPK>(kp.d, kp.r, r);
-        KnotSet<R, NDK> kab, kba;
-        load_knots<R, NDK>(G.dens_a[ab], G.dens_d[ab], G.dens_r[ab], kab);
-        load_knots<R, NDK>(G.dens_a[ba], G.dens_d[ba], G.dens_r[ba], kba);
-        g = dphi + fpi * knot_deriv<R, NDK>(kab.d, kab.r, r) + fpj * knot_deriv<R, NDK>(kba.d, kba.r, r);
+        g = dphi;
+        if (DENS) {
+            KnotSet<R, NDK> kab, kba;
+            load_knots<R, NDK>(G.dens_a[ab], G.dens_d[ab], G.dens_r[ab], kab);
+            load_knots<R, NDK>(G.dens_a[ba], G.dens_d[ba], G.dens_r[ba], kba);
+            g = fma(fpi, knot_deriv<R, NDK>(kab.d, kab.r, r), fma(fpj, knot_deriv<R, NDK>(kba.d, kba.r, r), g));
+        }
     }
 }
 

@@ -35,9 +35,14 @@ constexpr int kHaloTableBytes = 5120;  // LDS of a brick's halo table (bound che
 constexpr int kBrickMaxDim = 4;
 
 // Neighbour-list entry: slot index in the low kIndexBits bits, the periodic
-// image shift (2 bits per axis) above.
-constexpr int kIndexBits = 26;
+// image shift (2 bits per axis) in the six above, and in the global list the
+// sign bit set for an inner entry: a pair closer than r_d + skin at the build,
+// r_d the largest density knot.  The others stay beyond every density cutoff
+// until the next build, so the density pass gathers only inner entries.
+constexpr int kIndexBits = 25;
 constexpr int kIndexMask = (1 << kIndexBits) - 1;
+constexpr int kCodeMask = 63;
+constexpr int32_t kInnerBit = INT32_MIN;
 constexpr int kChunk = 4;  // neighbours whose loads are issued together (one 16-byte list load)
 
 // Neighbour-list layout (global kernels): entry k of slot t at
@@ -241,6 +246,8 @@ struct KernelShape {
     int32_t pairs;     // LDS bricks with each pair of two own atoms once (MD_OPT_KERNEL = 2)
     int32_t nchunk;    // neighbour records in flight per thread in the global kernels: 2, 4 or 8
     int32_t list_types; // the global list also stores its entries' type bytes (several species)
+    int32_t split_list; // the global list marks its inner entries (FP64: the density pass then
+                        // gathers only those)
     int32_t chunked;  // 1 = per-replica sums of the thermostat and barostat start with
                       // per-chunk sums (some replica spans more than kChunkedSumWaves waves)
 };
@@ -252,8 +259,9 @@ void launch_load_state(const Buffers& b, int p, int q, const md_state& st, const
                        hipStream_t s);
 void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double half_skin2,
                     int half_list, hipStream_t s);
-void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, int half_list,
-                       hipStream_t s);
+// rdl2 = (r_d + skin)^2 marks the inner entries (rlist2: every entry).
+void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, double rdl2,
+                       int half_list, hipStream_t s);
 void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s);
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

@@ -33,6 +33,7 @@ struct md_ctx {
     std::vector<double> box, origin, vp;
     std::vector<uint8_t> periodic;
     double skin = 0.0, dt_fs = 1.0, rc = 0.0, rlist = 0.0, t0_fs = 0.0;
+    double rd = 0.0;  // largest density knot: every density function vanishes beyond it
     // potential
     DevPotential pot{};
     bool single = false;
@@ -194,6 +195,9 @@ KernelShape shape(const md_ctx* c)
     k.lds_limit = c->lds_limit;
     k.nchunk = c->nchunk;
     k.list_types = c->single ? 0 : 1;
+    // FP64 density passes gather 24 bytes per neighbour and gain from skipping
+    // the outer entries; the 16-byte compact records of mixed precision do not
+    k.split_list = c->precision == MD_FP64 ? 1 : 0;
     return k;
 }
 
@@ -705,7 +709,12 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
     if (k.brick)
         launch_brick_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, k.pairs,
                           k.pairs ? pair_slots(k, c->args, c->precision) : 0, s);
-    else launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    else {
+        // inner entries: within r_d + skin, so a pair left out stays beyond r_d
+        // (every density function's last knot) until the next build
+        const double rdl = std::min(c->rd + c->skin, c->rlist);
+        launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, rdl * rdl, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    }
     if (c->pr) launch_pr_mark_build(c->buf, k, s);
     c->have_list = true;
     c->built_at = c->step;
@@ -1129,6 +1138,9 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
     if (!(rc > 0.0)) return reject(MD_ERR_POTENTIAL, "cutoff (largest knot) must be > 0");
     c->rc = rc;
     c->rlist = rc + c->skin;
+    c->rd = 0.0;
+    for (int ab = 0; ab < ns * ns; ++ab)
+        for (int k = 0; k < ndk; ++k) c->rd = std::max(c->rd, P.dens_r[ab][k]);
     P.rc = rc;
     P.rc2 = rc * rc;
     P.rlist2 = c->rlist * c->rlist;

@@ -185,15 +185,15 @@ def test_small_boxes_get_at_least_one_cell(md):
 
 
 def test_size_limits_rejected_on_host(md):
-    """More atom slots than a list entry can index (2^26), and link-cell grids
+    """More atom slots than a list entry can index (2^25), and link-cell grids
     beyond the supported count, are refused before any device work."""
     s = inputs.workload("bcc2000")
-    n = (1 << 26) + 1
+    n = (1 << 25) + 1
     with pytest.raises(md.MDError) as e:
         md.Context(s.potential, [0, n], [[300.0] * 3], [[1, 1, 1]], skin=0.3, max_neighbours=48)
     assert e.value.code == md.MD_ERR_ARG and "too large" in str(e.value)
     # one atom slot short of the limit is accepted (no device memory is touched)
-    md.Context(s.potential, [0, (1 << 26) - 64], [[300.0] * 3], [[1, 1, 1]], skin=0.3, max_neighbours=48)
+    md.Context(s.potential, [0, (1 << 25) - 64], [[300.0] * 3], [[1, 1, 1]], skin=0.3, max_neighbours=48)
 
 
 def test_options_round_trip_on_host(md):
