@@ -34,18 +34,23 @@ if ROOT not in sys.path:
 METRIC = "EAM atom-steps/s: mixed vs FP64 (force err ≤1e-5), batched vs one-by-one"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one launch of the mixed-mode force kernel on bcc1m, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of
-# 444 dispatches), each scaled by the reading for a plain 1 GiB device copy
-# (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
+# HBM bytes of one launch of the force kernel on bcc1m (FP64: knot sums, four
+# records in flight; mixed: tables, eight), from two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 185 dispatches), each
+# scaled by the reading for a plain 1 GiB device copy (FETCH_SIZE reads
+# 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {}  # precision -> {"fetch_kib", "write_kib", "fetch_scale", "write_scale",
-                   #                 "sources_sha256_16", "workload", "kernel"}
-# VALU instructions per wavefront of the same mixed force kernel (SQ_INSTS_VALU /
+FORCE_TRAFFIC = {  # precision -> counters of the step's force kernel (velocity-Verlet variant)
+    "fp64": {"fetch_kib": 103009, "write_kib": 55440, "fetch_scale": 2.0, "write_scale": 1.0,
+             "sources_sha256_16": "d0f9ee5b2139efb9", "workload": "bcc1m", "kernel": "k_force", "evaluator": 1},
+    "mixed": {"fetch_kib": 115740, "write_kib": 71280, "fetch_scale": 2.0, "write_scale": 1.0,
+              "sources_sha256_16": "d0f9ee5b2139efb9", "workload": "bcc1m", "kernel": "k_force", "evaluator": 0},
+}
+# VALU instructions per wavefront of the same force kernels (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
 # so this is also the lane-operations per atom of one launch.
-FORCE_VALU_PER_WAVE = {}  # precision -> VALU instructions per wave (64 atoms), same validity rule
+FORCE_VALU_PER_WAVE = {"fp64": 2055.9, "mixed": 1619.5}  # VALU instructions per wave (64 atoms), same rule
 # Lane-operation issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz (FP64 and unpacked FP32 issue at the same rate; packed FP32 is off).
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -106,6 +111,7 @@ def roofline_for(r, prec, nbar, n, k, workload, copy_gbs):
     kernel = "k_brick_force" if r["autotuned"].get("kernel") == 0 else "k_force"
     t = FORCE_TRAFFIC.get(prec)
     valid = (t is not None and workload == t["workload"] and kernel == t["kernel"]
+             and r["autotuned"].get("evaluator") == t.get("evaluator")
              and force_sources_hash() == t["sources_sha256_16"])
     traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) if valid else None
     alu = None
@@ -364,8 +370,12 @@ def main():
                     help="size of the device copy whose bandwidth is reported beside the roofline (0 = skip)")
     ap.add_argument("--nchunk", type=int, choices=[2, 4, 8], default=4,
                     help="with --kernel global: neighbour records in flight per thread")
-    ap.add_argument("--kernel", choices=["auto", "global"], default="auto",
-                    help="main workload: autotuned configuration, or the global-gather kernels with tables")
+    ap.add_argument("--nchunk-mixed", type=int, choices=[2, 4, 8], default=0,
+                    help="with --kernel global: the same for the mixed leg (0: as --nchunk)")
+    ap.add_argument("--fp64-evaluator", type=int, choices=[0, 1], default=0,
+                    help="with --kernel global or brick: the FP64 leg's evaluator (0 tables, 1 knot sums)")
+    ap.add_argument("--kernel", choices=["auto", "global", "brick"], default="auto",
+                    help="main workload: autotuned configuration, or the global-gather or LDS-brick kernels with tables")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run plain device-to-device copies of this size (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -427,11 +437,12 @@ def main():
     results = {}
     tuned = {}
     for prec in ("fp64", "mixed"):
-        if args.kernel == "global":  # fixed configuration (counter passes compare the same kernels)
-            ch = {"kernel": 1, "brick_dims": 0, "lanes": 1, "block": 512, "evaluator": 0, "nchunk": args.nchunk,
-                  "step_us": None}
+        if args.kernel in ("global", "brick"):  # fixed configuration (counter passes compare the same kernels)
+            ch = {"kernel": 1 if args.kernel == "global" else 0, "brick_dims": 444, "lanes": 1, "block": 1024,
+                  "evaluator": args.fp64_evaluator if prec == "fp64" else 0,
+                  "nchunk": args.nchunk if prec == "fp64" else (args.nchunk_mixed or args.nchunk), "step_us": None}
             opts = choice_options(md, ch)
-            log(f"{prec}: global kernels, tables (no autotune)")
+            log(f"{prec}: {args.kernel} kernels, {'knot sums' if ch['evaluator'] else 'tables'} (no autotune)")
         else:
             opts, ch = tune_options(md, system, prec)
         tuned[prec] = ch
@@ -702,8 +713,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: bcc Fe 80^3 cells, 1% vacancies, N={n}, 600 K, "
-                        f"rebuild every {system.rebuild_every}, dt {system.dt_fs} fs",
+            "workload": (f"{args.workload}: bcc Fe 80^3 cells, 1% vacancies, N={n}, 600 K, "
+                         if args.workload == "bcc1m" else
+                         f"{args.workload}: {system.n_replicas} replica(s), N={n}, ")
+                        + f"rebuild every {system.rebuild_every}, dt {system.dt_fs} fs",
             "n_atoms": n,
             "mean_neighbours": nbar,
             "precision": "fp64",
