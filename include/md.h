@@ -216,7 +216,8 @@ typedef struct {
 
 /* Validates the configuration and potential on the host (no device work)
  * and returns a new context in *out.  Box lengths on periodic axes must
- * exceed 2 (r_c + skin). */
+ * exceed 2 (r_c + skin).  At most 2^25 atom slots (each replica's atoms
+ * rounded up to 64; MD_ERR_ARG beyond). */
 int md_create(const md_config *cfg, const md_potential *pot, md_ctx **out);
 
 /* Bytes of device workspace md_bind needs for this context. */

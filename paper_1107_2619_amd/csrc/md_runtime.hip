@@ -1234,7 +1234,7 @@ int md_create(const md_config* cfg, const md_potential* pot, md_ctx** out)
         slot += (n + kWave - 1) / kWave * kWave;
         cells_alloc += worst;
         if (slot > (int64_t)kIndexMask || cells_alloc > (int64_t)INT32_MAX / 2)
-            return reject(MD_ERR_ARG, "system too large: at most 2^26 atom slots and 2^30 link cells");
+            return reject(MD_ERR_ARG, "system too large: at most 2^25 atom slots and 2^30 link cells");
     }
     c->Np = std::max<int64_t>(slot, kWave);
     for (const DevReplica& D : c->reps)
