@@ -316,7 +316,8 @@ enum {
                                   MD_OPT_TIMING).  Any md_set_option or md_bind
                                   drops the captured graphs.                         */
     MD_OPT_MAX_COUNT = 3,      /* read only: largest list length seen (at md_energy)  */
-    MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind                */
+    MD_OPT_N_BUILDS = 4,       /* read only: list builds since md_bind (automatic
+                                  ones as of the last md_energy)                     */
     MD_OPT_TIMING = 5,         /* 1 = bracket every kernel group with HIP events      */
     MD_OPT_EVALUATOR = 6,      /* 0 = exact local-polynomial tables (default), 1 =
                                   term-by-term knot sums (the paper's explicit
@@ -355,10 +356,23 @@ enum {
                                   grows by entries * R * 96 bytes); set before
                                   md_workspace_bytes and md_bind (MD_ERR_STATE
                                   after md_bind).  Default 0: no ring                */
-    MD_OPT_NEIGHBOUR_CHUNK = 17 /* global kernels: neighbour records each thread
+    MD_OPT_NEIGHBOUR_CHUNK = 17, /* global kernels: neighbour records each thread
                                   gathers before it evaluates them, 2, 4 (default)
                                   or 8; md_autotune picks it.  Results do not
                                   depend on it (same terms, same order)              */
+    MD_OPT_AUTO_REBUILD = 18   /* 1 = rebuild on displacement instead of every
+                                  rebuild_every steps ("The Neighbourlist
+                                  calculation": the list of r_c + skin stays
+                                  complete while no atom moves more than skin/2
+                                  from where it was at the build).  Before every
+                                  force evaluation of md_step and md_eam_forces
+                                  each replica with an atom past skin/2 is
+                                  re-sorted and gets a new list; the others keep
+                                  theirs, so a replica runs the same in a batch as
+                                  alone, and MD_ERR_SKIN does not occur.
+                                  rebuild_every is then unused.  Global kernels
+                                  only (MD_OPT_KERNEL reads 1); not with the
+                                  barostat (MD_ERR_ARG).  Default 0              */
 };
 int md_set_option(md_ctx *ctx, int32_t option, int64_t value);
 int md_get_option(const md_ctx *ctx, int32_t option, int64_t *value);

@@ -104,11 +104,18 @@ __device__ __forceinline__ int wave_run_add(int32_t* counter, int key)
 // ---------------------------------------------------------------------------
 // Rebuild stage 1 of 5: link cell of every atom, cell populations, and the skin
 // guard (net displacement since the previous build must stay below skin/2).
-__global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin2, int check_skin)
+// Every rebuild kernel takes `gate`: NULL for a build of all replicas, else
+// the automatic rebuild's flags, and then it leaves alone every replica r with
+// gate[1 + r] == 0 (slot ranges and link cells are per replica, so a kept
+// replica's slots, cells and list stay exactly as they are).
+__global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin2, int check_skin,
+                      const int32_t* __restrict__ gate)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
-    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
+    const int rep = uniform(b.rep_of_wave[t / kWave]);
+    if (gate && gate[1 + rep] == 0) return;  // (whole wavefronts: replicas are wave aligned)
+    const DevReplica& R = b.reps[rep];
     const bool valid = b.id[q][t] >= 0;
     const Box bx = load_box(R);
     const double3 x = load_xyz(b.pos[p], t);
@@ -116,7 +123,7 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
     cell_coords(bx, x.x, x.y, x.z, c);
     const int cell = valid ? cell_index(R, c[0], c[1], c[2]) : -1;
     b.cell_of[t] = cell;
-    wave_run_add(b.cell_count, cell);
+    wave_run_add(b.bin_count, cell);
     if (!valid) return;
     if (check_skin) {
         // displacement since the build, after mapping the build position into
@@ -147,8 +154,10 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
     }
 }
 
-// Rebuild stage 2: exclusive scan of cell populations, three phases (block scan, scan of block
-// sums, add), then shifted into slot numbering with the per-cell replica shift.
+// Rebuild stage 2: exclusive scan of cell populations in two phases (block scan, then
+// each block adds the sum of the block totals before it), shifted into slot numbering
+// with the per-cell replica shift.  The populations binned by stage 1 are taken over
+// (and their counters cleared for the next build); a kept replica's cells keep theirs.
 constexpr int kScanBlock = 1024;
 
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* sh, int32_t& total)
@@ -167,48 +176,55 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* sh, 
     return sh[tid] - v;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_local(Buffers b, int32_t n)
+__global__ __launch_bounds__(kScanBlock) void k_scan_local(Buffers b, int32_t n, const int32_t* __restrict__ gate)
 {
+    if (gate && gate[0] == 0) return;
     __shared__ int32_t sh[kScanBlock];
     const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    const int32_t v = i < n ? b.cell_count[i] : 0;
+    int32_t v = 0;
+    if (i < n) {
+        const int r = b.cell_rep[i];
+        if (gate && r >= 0 && gate[1 + r] == 0) {
+            v = b.cell_count[i];
+        } else {
+            v = b.bin_count[i];
+            b.cell_count[i] = v;
+            b.bin_count[i] = 0;
+            b.cell_cursor[i] = 0;
+        }
+    }
     int32_t total;
     const int32_t ex = block_exclusive_scan(v, sh, total);
     if (i < n) b.cell_start[i] = ex;
     if (threadIdx.x == 0) b.scan_blocks[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(Buffers b, int32_t nblocks)
+__global__ __launch_bounds__(kScanBlock) void k_scan_add(Buffers b, int32_t n, const int32_t* __restrict__ gate)
 {
-    // one workgroup; each thread owns a contiguous run of block sums
-    __shared__ int32_t sh[kScanBlock];
-    const int per = (nblocks + kScanBlock - 1) / kScanBlock;
-    const int beg = threadIdx.x * per;
+    if (gate && gate[0] == 0) return;
+    // the totals of the blocks before this one (integers: any order is exact)
+    __shared__ int32_t part[kScanBlock / kWave];
     int32_t run = 0;
-    for (int k = 0; k < per; ++k)
-        if (beg + k < nblocks) run += b.scan_blocks[beg + k];
-    int32_t total;
-    int32_t ex = block_exclusive_scan(run, sh, total);
-    for (int k = 0; k < per; ++k)
-        if (beg + k < nblocks) {
-            const int32_t v = b.scan_blocks[beg + k];
-            b.scan_blocks[beg + k] = ex;
-            ex += v;
-        }
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_add(Buffers b, int32_t n)
-{
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanBlock) run += b.scan_blocks[k];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) run += __shfl_xor(run, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = run;
+    __syncthreads();
+    int32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBlock / kWave; ++w) before += part[w];
     const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    if (i < n) b.cell_start[i] += b.scan_blocks[blockIdx.x] + b.cell_shift[i];
+    if (i < n) b.cell_start[i] += before + b.cell_shift[i];
+    if (gate && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&b.flags[F_AUTO_BUILDS], 1);
 }
 
 // Rebuild stage 3: place every atom in its cell's slot range (arbitrary order within
 // the cell, fixed by the next kernel).
-__global__ void k_scatter(Buffers b, int64_t n_slots)
+__global__ void k_scatter(Buffers b, int64_t n_slots, const int32_t* __restrict__ gate)
 {
     const int64_t t = global_thread();
     if (t >= n_slots) return;
+    if (gate && gate[1 + uniform(b.rep_of_wave[t / kWave])] == 0) return;
     const int c = b.cell_of[t];
     const int k = wave_run_add(b.cell_cursor, c);
     if (c >= 0) b.perm[b.cell_start[c] + k] = (int32_t)t;
@@ -216,10 +232,14 @@ __global__ void k_scatter(Buffers b, int64_t n_slots)
 
 // Rebuild stage 4: order each cell's members by caller index, making the slot order
 // (and so every later floating-point sum) independent of atomics' timing.
-__global__ void k_sort_cells(Buffers b, int q, int32_t n_cells)
+__global__ void k_sort_cells(Buffers b, int q, int32_t n_cells, const int32_t* __restrict__ gate)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
+    if (gate) {
+        const int r = b.cell_rep[c];
+        if (r < 0 || gate[1 + r] == 0) return;
+    }
     const int beg = b.cell_start[c], cnt = b.cell_count[c];
     int32_t* m = b.perm + beg;
     const int32_t* id = b.id[q];
@@ -236,11 +256,13 @@ __global__ void k_sort_cells(Buffers b, int q, int32_t n_cells)
 }
 
 // Rebuild stage 5: gather the whole atom state into the new slot order.
-__global__ void k_gather(Buffers b, int p, int q, int64_t n_slots)
+__global__ void k_gather(Buffers b, int p, int q, int64_t n_slots, const int32_t* __restrict__ gate)
 {
     const int64_t u = global_thread();
     if (u >= n_slots) return;
-    const DevReplica& R = b.reps[uniform(b.rep_of_wave[u / kWave])];
+    const int rep = uniform(b.rep_of_wave[u / kWave]);
+    if (gate && gate[1 + rep] == 0) return;
+    const DevReplica& R = b.reps[rep];
     const int pn = p ^ 1, qn = q ^ 1;
     if (u - R.slot_off < R.n_atoms) {
         const int32_t t = b.perm[u];
@@ -473,16 +495,20 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
 // SPLIT: mark the inner entries (r < r_d + skin); otherwise every entry is
 // inner (one precision's density pass gains nothing from the mark).
 // WT: several species (each entry's type byte is stored beside it).
+// gate: the automatic rebuild's replica flags (NULL: every replica).
+// copy_back: also copy each own atom's sorted state from (p, q) into
+// (p ^ 1, q ^ 1), the buffers an automatic rebuild keeps using.
 template <bool TRI, bool WIDE, bool SPLIT, bool WT>
 __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, int64_t n_slots, int32_t n_cells,
                                                       int32_t cap, double rlist2, double rdl2, int half_list,
-                                                      int compact)
+                                                      int compact, const int32_t* __restrict__ gate, int copy_back)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int cell = uniform((int)(logical_block() * (kBlock / kWave) + threadIdx.x / kWave));
     if (cell >= n_cells) return;
     const int r = uniform(b.cell_rep[cell]);
     if (r < 0) return;
+    if (gate && gate[1 + r] == 0) return;
     const int n_own = uniform(b.cell_count[cell]);
     if (n_own == 0) return;
     const int s_own = uniform(b.cell_start[cell]);
@@ -607,6 +633,25 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, i
                 int4 rq;
                 if (!compact_coords<TRI ? 2 : 1>(R, c, xl.x, xl.y, xl.z, rq)) atomicAdd(&b.flags[F_COMPACT], 1);
                 b.rec[0][i] = rq;
+            }
+            if (copy_back) {  // (no lane of this kernel reads the buffers written here)
+                const int pn = p ^ 1, qn = q ^ 1;
+                b.pos[pn][i] = pos[i];
+                b.id[qn][i] = b.id[q][i];
+                b.type[qn][i] = b.type[q][i];
+                b.pwork[qn][i] = b.pwork[q][i];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b.vel[qn][a][i] = b.vel[q][a][i];
+                    b.img[qn][a][i] = b.img[q][a][i];
+                }
+                if (b.acc[q][0]) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        b.acc[qn][a][i] = b.acc[q][a][i];
+                        b.jrk[qn][a][i] = b.jrk[q][a][i];
+                    }
+                }
             }
         }
         wave_max_flag(lane < n_chunk ? my_count : 0, &b.flags[F_MAX_COUNT]);
@@ -1697,31 +1742,59 @@ void launch_load_state(const Buffers& b, int p, int q, const md_state& st, const
 }
 
 void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double half_skin2,
-                    int half_list, hipStream_t s)
+                    int half_list, const int32_t* gate, hipStream_t s)
 {
-    // p, q: current buffers; the sorted state lands in p^1, q^1.
+    // p, q: current buffers; the sorted state lands in p^1, q^1.  The cell
+    // populations are binned into bin_count, which every build leaves zeroed.
     (void)half_list;
-    launch_fill_i32(b.cell_count, 0, k.n_cells, s);
-    launch_fill_i32(b.cell_cursor, 0, k.n_cells, s);
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots,
-                       half_skin2, half_skin2 >= 0.0 ? 1 : 0);
+                       half_skin2, half_skin2 >= 0.0 ? 1 : 0, gate);
     const int nb = (int)((k.n_cells + kScanBlock - 1) / kScanBlock);
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, b, nb);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells);
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, k.n_slots);
-    hipLaunchKernelGGL(k_sort_cells, dim3(blocks_for(k.n_cells)), dim3(kBlock), 0, s, b, q, k.n_cells);
-    hipLaunchKernelGGL(k_gather, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots);
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, k.n_slots, gate);
+    hipLaunchKernelGGL(k_sort_cells, dim3(blocks_for(k.n_cells)), dim3(kBlock), 0, s, b, q, k.n_cells, gate);
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, gate);
+}
+
+// Displacement check of the automatic rebuild: the same criterion as the skin
+// guard of scheduled builds (no atom may move more than skin/2 between builds
+// for a list of r_c + skin to hold every pair closer than r_c), tested at every
+// step before the list is used, per replica.  Block 0 also clears the flag set
+// of the next check (the rebuild kernels of the previous check, its readers,
+// ran before this kernel).
+__global__ void k_skin_check(Buffers b, int p, int64_t n_slots, int32_t n_rep, double guard2,
+                             int32_t* __restrict__ gate, int32_t* __restrict__ next)
+{
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i <= n_rep; i += blockDim.x) next[i] = 0;
+    const int64_t t = global_thread();
+    if (t >= n_slots) return;
+    const double3 x = load_xyz(b.pos[p], t);
+    const double3 x0 = load_xyz(b.xbuild, t);  // (empty slots: both zero)
+    const double dx = x.x - x0.x, dy = x.y - x0.y, dz = x.z - x0.z;
+    const bool far = fma(dx, dx, fma(dy, dy, dz * dz)) > guard2;
+    if (__ballot(far) != 0 && (threadIdx.x & (kWave - 1)) == 0) {
+        atomicOr(&gate[1 + b.rep_of_wave[t / kWave]], 1);
+        atomicOr(&gate[0], 1);
+    }
+}
+
+void launch_skin_check(const Buffers& b, int p, const KernelShape& k, double guard2, int32_t* gate,
+                       int32_t* next, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_skin_check, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, k.n_slots,
+                       k.n_replicas, guard2, gate, next);
 }
 
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, double rdl2,
-                       int half_list, hipStream_t s)
+                       int half_list, const int32_t* gate, int copy_back, hipStream_t s)
 {
     const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
     const bool wide = (uint64_t)k.n_slots * 16 * (uint64_t)((k.cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32);
     const bool split = k.split_list && !half_list && rdl2 < rlist2;
     const int which = (k.tri ? 8 : 0) | (wide ? 4 : 0) | (split ? 2 : 0) | (k.list_types ? 1 : 0);
-    using Kern = void (*)(Buffers, int, int, int64_t, int32_t, int32_t, double, double, int, int);
+    using Kern = void (*)(Buffers, int, int, int64_t, int32_t, int32_t, double, double, int, int, const int32_t*, int);
     static const Kern kerns[16] = {
         k_cell_list<false, false, false, false>, k_cell_list<false, false, false, true>,
         k_cell_list<false, false, true, false>,  k_cell_list<false, false, true, true>,
@@ -1732,7 +1805,7 @@ void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, dou
         k_cell_list<true, true, false, false>,   k_cell_list<true, true, false, true>,
         k_cell_list<true, true, true, false>,    k_cell_list<true, true, true, true>};
     hipLaunchKernelGGL(kerns[which], dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells, k.cap, rlist2,
-                       half_list ? rlist2 : rdl2, half_list, k.compact);
+                       half_list ? rlist2 : rdl2, half_list, k.compact, gate, copy_back);
 }
 
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)

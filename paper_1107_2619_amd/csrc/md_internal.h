@@ -155,8 +155,10 @@ struct PotArgs {
 // read their neighbours from global memory instead).  F_COMPACT: atoms too far
 // outside their link cell for the compact mixed-mode record.
 // F_RANGE: a pair term beyond the fixed-point range of the pair kernels' shared accumulators.
+// F_AUTO_BUILDS: builds the displacement check triggered (automatic rebuilds).
 enum FlagIndex {
-    F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_PR_BOX = 5, F_RANGE = 6, F_COUNT = 8
+    F_MAX_COUNT = 0, F_SKIN = 1, F_OUTSIDE = 2, F_HALO = 3, F_COMPACT = 4, F_PR_BOX = 5, F_RANGE = 6,
+    F_AUTO_BUILDS = 7, F_COUNT = 8
 };
 
 // Pointers into the workspace.
@@ -185,6 +187,7 @@ struct Buffers {
     int32_t* perm;        // [Np] new slot -> old slot
     int32_t* cell_start;  // [C]
     int32_t* cell_count;  // [C]
+    int32_t* bin_count;   // [C] atoms binned by the build in progress (zero between builds)
     int32_t* cell_cursor; // [C]
     int32_t* cell_shift;  // [C] slot_off - atom_off of the cell's replica
     int32_t* cell_rep;    // [C] replica of each link cell (-1: unused)
@@ -223,6 +226,8 @@ struct Buffers {
     double* ering;        // [ring_len][R][kEnergySlots] per-replica totals of the per-step energy steps
     int64_t* ering_count; // [2] entries appended since md_bind (entry i lives at i % ring_len),
                           // then the reduction's workgroup ticket
+    int32_t* gate;        // [2][R + 1] automatic rebuilds, two alternating sets: [0] some
+                          // replica moved past the guard, [1 + r] replica r did
 };
 
 struct KernelShape {
@@ -257,11 +262,22 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void launch_init_slots(const Buffers& b, int q, const md_state& st, const KernelShape& k, hipStream_t s);
 void launch_load_state(const Buffers& b, int p, int q, const md_state& st, const KernelShape& k,
                        hipStream_t s);
+// gate: NULL rebuilds every replica; otherwise only the replicas whose entry
+// gate[1 + r] is set (automatic rebuilds; every kernel exits at once for the
+// others).
 void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double half_skin2,
-                    int half_list, hipStream_t s);
+                    int half_list, const int32_t* gate, hipStream_t s);
 // rdl2 = (r_d + skin)^2 marks the inner entries (rlist2: every entry).
+// copy_back: the list is built from the sorted state in (p, q) and each own
+// atom's state is copied into (p ^ 1, q ^ 1) (automatic rebuilds, which keep
+// the ping-pong indices).
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, double rdl2,
-                       int half_list, hipStream_t s);
+                       int half_list, const int32_t* gate, int copy_back, hipStream_t s);
+// Displacement check of automatic rebuilds: sets gate[0] and gate[1 + r] when
+// an atom of replica r moved more than sqrt(guard2) since the last build, and
+// clears the other set `next` for the following check.
+void launch_skin_check(const Buffers& b, int p, const KernelShape& k, double guard2, int32_t* gate,
+                       int32_t* next, hipStream_t s);
 void launch_compact_records(const Buffers& b, int p, const KernelShape& k, hipStream_t s);
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s);
 void launch_density(const Buffers& b, int p, int q, const KernelShape& k, const PotArgs& P, int precision,

@@ -79,6 +79,13 @@ struct md_ctx {
     Buffers buf{};
     int p = 0, q = 0;
     int64_t step = 0, built_at = -1, n_builds = 0, max_count = 0;
+    // automatic rebuilds (MD_OPT_AUTO_REBUILD): a displacement check before
+    // every force evaluation and gated rebuild kernels instead of the fixed
+    // period; gate_sel picks the device flag set of the next check, auto_builds
+    // counts the triggered builds (as of the last md_energy)
+    bool auto_rebuild = false;
+    int gate_sel = 0;
+    int64_t auto_builds = 0;
     std::vector<int64_t> n_mobile;
     std::string err;
     // optional kernel timing: event pairs per group, resolved lazily
@@ -89,9 +96,11 @@ struct md_ctx {
     double kt_ms[MD_KT_COUNT] = {0, 0, 0, 0};
     int64_t kt_n[MD_KT_COUNT] = {0, 0, 0, 0};
     // HIP graph replay of md_step (MD_OPT_USE_GRAPH): one executable graph per
-    // ping-pong state (p + 2 q), each covering two list-rebuild periods
+    // ping-pong state (p + 2 q) and flag set of the automatic rebuild's checks,
+    // each covering two list-rebuild periods (kAutoGraphSteps steps with
+    // automatic rebuilds)
     bool use_graph = false;
-    hipGraphExec_t graph_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t graph_exec[8] = {};
     hipStream_t graph_stream = nullptr;
     hipEvent_t graph_ev[2] = {nullptr, nullptr};
     int64_t graph_launches = 0;
@@ -183,7 +192,8 @@ KernelShape shape(const md_ctx* c)
     k.n_chunks = (int32_t)c->chunk_rep.size();
     k.n_bricks = (int32_t)c->brick_rep.size();
     // the barostat moves the bricks' box; the brick kernels take orthorhombic boxes only
-    k.brick = c->kernel_path != 1 && c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri;
+    // (the automatic rebuild's gated build covers the global list only)
+    k.brick = c->kernel_path != 1 && c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri && !c->auto_rebuild;
     k.pairs = k.brick && c->kernel_path == 2;
     k.halo_cap = c->halo_cap;
     k.block = c->brick_block;
@@ -540,6 +550,8 @@ void plan_workspace(md_ctx* c)
         16,                                                  // ering_count, ticket
         c->single ? 0 : Np * (size_t)((c->cap + 2 * kChunk - 1) / kChunk * kChunk),  // ntype (several species)
         Np / kWave * kEnergyTerms * 8,                       // wave_terms
+        C * 4,                                               // bin_count (C_alloc)
+        2 * ((size_t)c->R + 1) * 4,                          // gate
     };
     c->off.clear();
     size_t o = 0;
@@ -630,6 +642,8 @@ void bind_buffers(md_ctx* c)
     at(b.ering_count);
     at(b.ntype);
     at(b.wave_terms);
+    at(b.bin_count);
+    at(b.gate);
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -703,7 +717,7 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
     const double guard = c->pr ? 0.4 * c->skin : 0.5 * c->skin;
     const double half_skin2 = (c->have_list && check_skin) ? guard * guard : -1.0;
     Timed tm(c, MD_KT_BUILD, s);
-    launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+    launch_rebuild(c->buf, c->p, c->q, k, half_skin2, c->nbr_mode == MD_NBR_HALF_ATOMIC, nullptr, s);
     c->p ^= 1;
     c->q ^= 1;
     if (k.brick)
@@ -713,12 +727,36 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
         // inner entries: within r_d + skin, so a pair left out stays beyond r_d
         // (every density function's last knot) until the next build
         const double rdl = std::min(c->rd + c->skin, c->rlist);
-        launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, rdl * rdl, c->nbr_mode == MD_NBR_HALF_ATOMIC, s);
+        launch_build_list(c->buf, c->p, c->q, k, c->rlist * c->rlist, rdl * rdl, c->nbr_mode == MD_NBR_HALF_ATOMIC,
+                          nullptr, 0, s);
     }
     if (c->pr) launch_pr_mark_build(c->buf, k, s);
     c->have_list = true;
     c->built_at = c->step;
     ++c->n_builds;
+}
+
+// Automatic rebuild ("The Neighbourlist calculation": the list must hold every
+// pair that comes within r_c before it is rebuilt): before a force evaluation,
+// each replica with an atom more than skin/2 from its position at the last
+// build is re-sorted and gets a new list; the others keep theirs.  The rebuild
+// kernels run every time and exit at once where nothing is flagged, so a
+// captured step needs no host decision.  The sorted state is gathered into the
+// other ping-pong buffers and copied back by the list kernel, which leaves the
+// buffer indices (fixed in a captured graph) as they were.
+void auto_check(md_ctx* c, hipStream_t s)
+{
+    const KernelShape k = shape(c);
+    const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
+    int32_t* gate = c->buf.gate + (size_t)c->gate_sel * (c->R + 1);
+    int32_t* next = c->buf.gate + (size_t)(c->gate_sel ^ 1) * (c->R + 1);
+    const double guard = 0.5 * c->skin;
+    const double rdl = std::min(c->rd + c->skin, c->rlist);
+    Timed tm(c, MD_KT_BUILD, s);
+    launch_skin_check(c->buf, c->p, k, guard * guard, gate, next, s);
+    launch_rebuild(c->buf, c->p, c->q, k, -1.0, half, gate, s);
+    launch_build_list(c->buf, c->p ^ 1, c->q ^ 1, k, c->rlist * c->rlist, rdl * rdl, half, gate, 1, s);
+    c->gate_sel ^= 1;
 }
 
 // Caller state -> internal slots at the start of every call.  Compact records
@@ -730,6 +768,16 @@ void load_state(md_ctx* c, hipStream_t s, bool build_next)
     ensure_slots(c, s);
     launch_load_state(c->buf, c->p, c->q, c->st, k, s);
     if (k.compact && c->have_list && !build_next) launch_compact_records(c->buf, c->p, k, s);
+}
+
+// Automatic rebuilds at the start of a call, after load_state(c, s, true): the
+// check on the caller's positions, then the compact records of the replicas
+// that kept their list.
+void check_loaded(md_ctx* c, hipStream_t s)
+{
+    auto_check(c, s);
+    const KernelShape k = shape(c);
+    if (k.compact) launch_compact_records(c->buf, c->p, k, s);
 }
 
 // waves: the force pass summed the energy terms per wavefront (energy mode 4)
@@ -786,7 +834,21 @@ void nh_boundary(md_ctx* c, int halves, hipStream_t s)
     c->p ^= 1;
 }
 
-bool due(const md_ctx* c) { return c->step % c->rebuild_every == 0 && c->built_at != c->step; }
+// A scheduled list build at this step (none with automatic rebuilds).
+bool due(const md_ctx* c) { return !c->auto_rebuild && c->step % c->rebuild_every == 0 && c->built_at != c->step; }
+
+// Before a force evaluation inside md_step: the scheduled build, or the
+// automatic rebuild's check.
+void before_forces(md_ctx* c, hipStream_t s)
+{
+    if (due(c)) rebuild(c, s, true);
+    else if (c->auto_rebuild) auto_check(c, s);
+}
+
+// Steps per captured graph: two rebuild periods (the pattern of scheduled
+// builds repeats), or a fixed span with automatic rebuilds.
+constexpr int64_t kAutoGraphSteps = 16;
+int64_t graph_period(const md_ctx* c) { return c->auto_rebuild ? kAutoGraphSteps : 2 * (int64_t)c->rebuild_every; }
 
 // Barostat step boundary: the stress tensor, the box half kicks (closing,
 // opening or both), and with `open` the box drift and the particles' opening
@@ -818,7 +880,7 @@ void pr_boundary(md_ctx* c, int close, int open, hipStream_t s)
 void gear_step(md_ctx* c, bool last, hipStream_t s)
 {
     ++c->step;
-    if (due(c)) rebuild(c, s, true);
+    before_forces(c, s);
     forces(c, last ? ForceFlags{1, 0, 0, 1} : ForceFlags{0, 0, 0, 0}, s, false);
     const KernelShape k = shape(c);
     {
@@ -839,7 +901,7 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
             continue;
         }
         ++c->step;
-        if (due(c)) rebuild(c, s, true);
+        before_forces(c, s);
         if (c->pr) {
             // closing kick and the virial (the whole tensor for a box matrix), forces kept
             forces(c, ForceFlags{c->tri ? 3 : 2, 1, 0, 0}, s, false);
@@ -857,12 +919,14 @@ void middle_steps(md_ctx* c, int64_t n, hipStream_t s)
 // Two rebuild periods of middle steps from a step that is a multiple of
 // 2 * rebuild_every, replayed from a captured graph.  Over such a span every
 // ping-pong index flips an even number of times and the rebuild pattern is
-// fixed, so one graph per (p, q) state serves every replay.  Capture runs the
-// host logic once (advancing the counters as a real run would) without
-// executing; a replay advances the counters by the same amounts.
+// fixed, so one graph per (p, q) state serves every replay.  With automatic
+// rebuilds the span is kAutoGraphSteps steps, each with its check (an even
+// number of checks: the flag set in use is the same at both ends).  Capture
+// runs the host logic once (advancing the counters as a real run would)
+// without executing; a replay advances the counters by the same amounts.
 bool replay_period(md_ctx* c, hipStream_t s)
 {
-    const int64_t P = 2 * (int64_t)c->rebuild_every;
+    const int64_t P = graph_period(c);
     if (!c->graph_stream) {
         if (!hip_ok(c, hipStreamCreateWithFlags(&c->graph_stream, hipStreamNonBlocking), "graph stream") ||
             !hip_ok(c, hipEventCreateWithFlags(&c->graph_ev[0], hipEventDisableTiming), "graph event") ||
@@ -870,7 +934,7 @@ bool replay_period(md_ctx* c, hipStream_t s)
             return false;
     }
     hipStream_t gs = c->graph_stream;
-    const int key = c->p + 2 * c->q;
+    const int key = c->p + 2 * c->q + 4 * c->gate_sel;
     const int64_t step0 = c->step, builds0 = c->n_builds;
     if (!c->graph_exec[key]) {
         hipGraph_t g = nullptr;
@@ -883,11 +947,14 @@ bool replay_period(md_ctx* c, hipStream_t s)
             c->graph_exec[key] = nullptr;
             return false;
         }
-        if (c->p + 2 * c->q != key) return fail(c, MD_ERR_STATE, "graph period changed the ping-pong state") == MD_OK;
+        if (c->p + 2 * c->q + 4 * c->gate_sel != key)
+            return fail(c, MD_ERR_STATE, "graph period changed the ping-pong state") == MD_OK;
     } else {
         c->step = step0 + P;
-        c->n_builds = builds0 + 2;
-        c->built_at = c->step;
+        if (!c->auto_rebuild) {
+            c->n_builds = builds0 + 2;
+            c->built_at = c->step;
+        }
         if (c->ring_len > 0 && c->energy_every > 0 && !c->nvt && !c->pr && !c->gear)
             for (int64_t t = step0 + 1; t <= step0 + P; ++t)
                 if (t % c->energy_every == 0) c->ring_steps.push_back(t);
@@ -1313,7 +1380,9 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
         (!c->chunk_rep.empty() &&
          !hip_ok(c, hipMemcpy(c->buf.chunk_rep, c->chunk_rep.data(), c->chunk_rep.size() * 4, hipMemcpyHostToDevice), "md_bind upload")) ||
         !hip_ok(c, hipMemset(c->buf.flags, 0, F_COUNT * 4), "md_bind flags") ||
-        !hip_ok(c, hipMemset(c->buf.ering_count, 0, 16), "md_bind energy ring"))
+        !hip_ok(c, hipMemset(c->buf.ering_count, 0, 16), "md_bind energy ring") ||
+        !hip_ok(c, hipMemset(c->buf.bin_count, 0, (size_t)c->C_alloc * 4), "md_bind cell counters") ||
+        !hip_ok(c, hipMemset(c->buf.gate, 0, 2 * ((size_t)c->R + 1) * 4), "md_bind rebuild flags"))
         return MD_ERR_DEVICE;
     if (c->table_ok &&
         (!hip_ok(c, hipMemcpy(c->buf.tab_force64, c->tf64.data(), c->tf64.size() * 8, hipMemcpyHostToDevice), "md_bind tables") ||
@@ -1413,6 +1482,8 @@ int md_bind(md_ctx* c, const md_state* st, void* workspace, size_t bytes)
     c->step = 0;
     c->built_at = -1;
     c->n_builds = 0;
+    c->auto_builds = 0;
+    c->gate_sel = 0;
     c->max_count = 0;
     c->err.clear();
     return MD_OK;
@@ -1435,8 +1506,9 @@ int md_eam_forces(md_ctx* c, int want_energy, void* stream)
     if (!c->bound) return fail(c, MD_ERR_STATE, "md_eam_forces: call md_bind first");
     c->resume_ok = false;
     hipStream_t s = as_stream(stream);
-    load_state(c, s, !c->have_list);
+    load_state(c, s, !c->have_list || c->auto_rebuild);
     if (!c->have_list) rebuild(c, s, false);
+    else if (c->auto_rebuild) check_loaded(c, s);
     forces(c, ForceFlags{want_energy ? 1 : 0, 0, 0, 1}, s);
     return check_launch(c);
 }
@@ -1453,8 +1525,9 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     const bool resume = c->resume_ok && !c->gear && !c->pr && c->have_list && !due(c);
     c->resume_ok = false;
     const bool build = !resume && (!c->have_list || due(c));
-    if (!resume) load_state(c, s, build);
+    if (!resume) load_state(c, s, build || c->auto_rebuild);
     if (build) rebuild(c, s, true);
+    else if (!resume && c->auto_rebuild) check_loaded(c, s);
     if (resume) {
         if (c->nvt) {
             nh_boundary(c, 1, s);  // thermostat half step, opening kick, drift
@@ -1483,7 +1556,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
     } else {
         forces(c, ForceFlags{0, 0, 1, 0}, s);  // f(x0), opening half kick, drift
     }
-    const int64_t P = 2 * (int64_t)c->rebuild_every;
+    const int64_t P = graph_period(c);
     int64_t left = nsteps - 1;  // middle steps
     while (left > 0) {
         if (c->use_graph && !c->timing && c->step % P == 0 && left >= P) {
@@ -1501,7 +1574,7 @@ int md_step(md_ctx* c, int32_t nsteps, void* stream)
         return check_launch(c);
     }
     ++c->step;
-    if (due(c)) rebuild(c, s, true);
+    before_forces(c, s);
     if (c->pr) {
         forces(c, ForceFlags{1, 1, 0, 1}, s, false);  // closing kick, energies, write back
         const KernelShape k = shape(c);
@@ -1546,6 +1619,7 @@ int md_energy(md_ctx* c, md_energies* out, void* stream)
     if (c->have_energy && !hip_ok(c, hipMemcpy(e.data(), c->buf.energies, e.size() * 8, hipMemcpyDeviceToHost), "md_energy copy"))
         return MD_ERR_DEVICE;
     c->max_count = flags[F_MAX_COUNT];
+    c->auto_builds = flags[F_AUTO_BUILDS];
     std::vector<double> nh((size_t)c->R * 4, 0.0);
     if (c->nvt && !hip_ok(c, hipMemcpy(nh.data(), c->buf.nh_state, nh.size() * 8, hipMemcpyDeviceToHost), "md_energy thermostat"))
         return MD_ERR_DEVICE;
@@ -1785,6 +1859,16 @@ int md_set_option(md_ctx* c, int32_t option, int64_t value)
         if (value != 2 && value != 4 && value != 8) return fail(c, MD_ERR_ARG, "neighbour chunk must be 2, 4 or 8");
         c->nchunk = (int32_t)value;
         return MD_OK;
+    case MD_OPT_AUTO_REBUILD: {
+        if (value != 0 && value != 1) return fail(c, MD_ERR_ARG, "auto_rebuild must be 0 or 1");
+        if (value != 0 && c->pr)
+            return fail(c, MD_ERR_ARG, "automatic rebuilds are not available under the barostat (its build guard "
+                                       "also bounds the box strain)");
+        const bool brick = shape(c).brick != 0;
+        c->auto_rebuild = value != 0;
+        if ((shape(c).brick != 0) != brick) c->have_list = false;  // the brick lists have their own format
+        return MD_OK;
+    }
     case MD_OPT_TIMING:
         if (!value && !c->pending.empty()) return fail(c, MD_ERR_STATE, "read md_kernel_times before turning timing off");
         c->timing = value != 0;
@@ -1847,7 +1931,8 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     std::vector<Cand> cands;
     for (int32_t e : evals) {
         for (int32_t nch : {4, 2, 8}) cands.push_back({1, 0, 0, 512, e, nch});
-        if (c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri)  // the brick kernels take fixed orthorhombic boxes
+        // the brick kernels take fixed orthorhombic boxes and scheduled builds
+        if (c->nbr_mode == MD_NBR_FULL && !c->pr && !c->tri && !c->auto_rebuild)
             // (the pair kernels, MD_OPT_KERNEL = 2, are left out: their LDS
             // atomics make them several times slower on this device)
             for (int32_t dims : {0, 444, 222})
@@ -1912,7 +1997,8 @@ int md_get_option(const md_ctx* c, int32_t option, int64_t* value)
     case MD_OPT_TUNED_NS: *value = (int64_t)(c->tuned_us * 1e3); return MD_OK;
     case MD_OPT_COMPACT: *value = shape(c).compact ? 1 : 0; return MD_OK;
     case MD_OPT_MAX_COUNT: *value = c->max_count; return MD_OK;
-    case MD_OPT_N_BUILDS: *value = c->n_builds; return MD_OK;
+    case MD_OPT_N_BUILDS: *value = c->n_builds + c->auto_builds; return MD_OK;
+    case MD_OPT_AUTO_REBUILD: *value = c->auto_rebuild ? 1 : 0; return MD_OK;
     case MD_OPT_TIMING: *value = c->timing ? 1 : 0; return MD_OK;
     case MD_OPT_EVALUATOR: *value = (c->table_ok && c->evaluator == 0) ? 0 : 1; return MD_OK;
     case MD_OPT_KERNEL: *value = shape(c).brick ? (shape(c).pairs ? 2 : 0) : 1; return MD_OK;

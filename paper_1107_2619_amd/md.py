@@ -37,7 +37,7 @@ MD_OPT_LANES_PER_ATOM, MD_OPT_USE_GRAPH, MD_OPT_MAX_COUNT, MD_OPT_N_BUILDS, MD_O
 MD_OPT_EVALUATOR = 6
 MD_OPT_KERNEL, MD_OPT_BRICK_DIMS, MD_OPT_BRICK_BLOCK, MD_OPT_HALO_CAP, MD_OPT_HALO_OVERFLOWS = 7, 8, 9, 10, 11
 MD_OPT_GRAPH_LAUNCHES, MD_OPT_TUNED_NS, MD_OPT_COMPACT = 12, 13, 14
-MD_OPT_ENERGY_EVERY, MD_OPT_ENERGY_RING, MD_OPT_NEIGHBOUR_CHUNK = 15, 16, 17
+MD_OPT_ENERGY_EVERY, MD_OPT_ENERGY_RING, MD_OPT_NEIGHBOUR_CHUNK, MD_OPT_AUTO_REBUILD = 15, 16, 17, 18
 KERNEL_GROUPS = ("build", "density", "force", "reduce")
 
 EXPORTED = [

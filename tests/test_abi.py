@@ -336,3 +336,28 @@ def test_neighbour_chunk_option(md):
         with pytest.raises(md.MDError) as e:
             c.set_option(md.MD_OPT_NEIGHBOUR_CHUNK, v)
         assert e.value.code == md.MD_ERR_ARG
+
+
+def test_auto_rebuild_option(md):
+    """Automatic rebuilds: 0 or 1 (default 0); the global kernels then run
+    whatever MD_OPT_KERNEL says; refused under the barostat."""
+    c = _ctx(md)
+    assert c.get_option(md.MD_OPT_AUTO_REBUILD) == 0
+    c.set_option(md.MD_OPT_KERNEL, 0)
+    assert c.get_option(md.MD_OPT_KERNEL) == 0
+    c.set_option(md.MD_OPT_AUTO_REBUILD, 1)
+    assert c.get_option(md.MD_OPT_AUTO_REBUILD) == 1
+    assert c.get_option(md.MD_OPT_KERNEL) == 1
+    c.set_option(md.MD_OPT_AUTO_REBUILD, 0)
+    assert c.get_option(md.MD_OPT_KERNEL) == 0
+    for v in (-1, 2):
+        with pytest.raises(md.MDError) as e:
+            c.set_option(md.MD_OPT_AUTO_REBUILD, v)
+        assert e.value.code == md.MD_ERR_ARG
+    s = inputs.bcc_fe(6, a=2.90)
+    pr = md.Context(s.potential, s.atom_offset, s.box, s.periodic, skin=0.3, max_neighbours=48,
+                    pr_pressure_gpa=[1.0], pr_mass=[1e4])
+    with pytest.raises(md.MDError) as e:
+        pr.set_option(md.MD_OPT_AUTO_REBUILD, 1)
+    assert e.value.code == md.MD_ERR_ARG
+    pr.set_option(md.MD_OPT_AUTO_REBUILD, 0)
