@@ -169,6 +169,9 @@ def timed_steps(sim, steps):
     return t0.elapsed_time(t1), time.perf_counter() - wall0
 
 
+AUTO_GRAPH_STEPS = 16  # steps per captured graph with automatic rebuilds (a library constant)
+
+
 def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full", tune=None, nvt=None,
                   integrator="verlet", energy_every=0, energy_ring=0):
     """A warmed-up timed run.  tune: options to apply (e.g. an autotuner's
@@ -191,7 +194,8 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
         # states a call can start in (a graph spans two rebuild periods), each a
         # whole number of graph spans, so that the timed call starts on a span
         # boundary and replays its steps from the graphs
-        span = 2 * system.rebuild_every
+        auto = bool((tune or {}).get(md.MD_OPT_AUTO_REBUILD, 0))
+        span = AUTO_GRAPH_STEPS if auto else 2 * system.rebuild_every
         calls = [span * -(-max(warmup, 2 * span + 2) // span)] * 2
     else:
         calls = [warmup]
@@ -201,8 +205,10 @@ def run_precision(md, system, precision, steps, warmup, timing, nbr_mode="full",
         sim.energy()
     if timing:
         sim.kernel_times(reset=True)
+    builds0 = sim.get_option(md.MD_OPT_N_BUILDS)
     ms, wall = timed_steps(sim, steps)
     en = sim.energy()
+    sim.timed_builds = sim.get_option(md.MD_OPT_N_BUILDS) - builds0
     kt = sim.kernel_times(reset=True) if timing else None
     sim.warmup_steps = sum(calls)
     return sim, ms, wall, en, kt
@@ -276,6 +282,37 @@ def batched_vs_one_by_one(md, system, name, steps, warmup, precision="mixed"):
         "autotuned": {k: v for k, v in ch.items()},
         "pe_per_atom_eV": float(np.sum(en.pe) / system.n_atoms),
     }
+
+
+def auto_rebuild_leg(md, system, name, steps, warmup, skins, precision, fixed=None):
+    """Automatic rebuilds (a rebuild of a replica whenever one of its atoms
+    moved more than skin/2, checked every step) at several skins, each
+    autotuned with the option on, beside the workload's fixed update period
+    (`fixed`: its atom-steps/s at its own skin and period)."""
+    runs = []
+    for skin in skins:
+        s2 = copy.copy(system)
+        s2.skin = skin
+        sim = md.Simulation(s2, precision=precision, want_e_atom=False)
+        sim.set_option(md.MD_OPT_AUTO_REBUILD, 1)
+        ch = sim.autotune(trials=3)
+        del sim
+        opts = {**choice_options(md, ch), md.MD_OPT_AUTO_REBUILD: 1}
+        sim, ms, _, en, _ = run_precision(md, s2, precision, steps, warmup, timing=False, tune=opts)
+        rate = system.n_atoms * steps / (ms * 1e-3)
+        runs.append({"skin": skin, "value": rate, "ms_per_step": ms / steps, "builds": sim.timed_builds,
+                     "steps_per_build": steps / max(sim.timed_builds, 1), "autotuned": ch,
+                     "temperature_K_mean": float(np.mean(en.temperature))})
+        log(f"{name} auto rebuild {precision} skin {skin}: {rate:.3e} atom-steps/s, {sim.timed_builds} builds "
+            f"in {steps} steps")
+        del sim
+    best = max(runs, key=lambda r: r["value"])
+    out = {"workload": name, "n_atoms": system.n_atoms, "n_replicas": system.n_replicas, "precision": precision,
+           "steps": steps, "runs": runs, "best_skin": best["skin"], "best": best["value"],
+           "fixed_period": {"skin": system.skin, "rebuild_every": system.rebuild_every, "value": fixed}}
+    if fixed:
+        out["best_vs_fixed"] = best["value"] / fixed
+    return out
 
 
 def nh_masses(system, tau_fs):
@@ -364,6 +401,10 @@ def main():
                     help="steps of the vacancy self-diffusion workload with MSD sampling (0 = skip)")
     ap.add_argument("--energy-steps", type=int, default=200,
                     help="steps of the leg that reduces energies and the virial every step (0 = skip)")
+    ap.add_argument("--auto-steps", type=int, default=100,
+                    help="steps of each automatic-rebuild run (batched workloads and the headline; 0 = skip)")
+    ap.add_argument("--auto-skins", default="0.3,0.4,0.5",
+                    help="skins of the automatic-rebuild runs of the batched workloads")
     ap.add_argument("--small-steps", type=int, default=100,
                     help="steps of the 2000-atom FP64 configuration (0 = skip)")
     ap.add_argument("--copy-gbs-mib", type=int, default=1024,
@@ -597,6 +638,17 @@ def main():
         batched.append(batched_vs_one_by_one(md, batched_sys["liquid4096"], "liquid4096", args.batched_steps,
                                              args.warmup, precision="fp64"))
 
+    # automatic rebuilds on the batched workloads at smaller skins than their
+    # fixed periods need, and on the headline workload at its own skin (FP64)
+    auto_rec = []
+    if args.auto_steps > 0:
+        skins = [float(x) for x in args.auto_skins.split(",") if x]
+        for w, system_b in batched_sys.items():
+            fixed = next((b["batched"] for b in batched if b["workload"] == w and b["precision"] == "mixed"), None)
+            auto_rec.append(auto_rebuild_leg(md, system_b, w, args.auto_steps, args.warmup, skins, "mixed", fixed))
+        auto_rec.append(auto_rebuild_leg(md, system, args.workload, args.auto_steps, args.warmup, [system.skin],
+                                         "fp64", n * args.steps / (results["fp64"]["ms"] * 1e-3)))
+
     diffusion = None
     if vacancy is not None:
         diffusion = diffusion_leg(md, vacancy, "vacancy192", args.diffusion_steps, args.warmup, 100)
@@ -735,6 +787,7 @@ def main():
         "table_vs_explicit_fe15": evaluator_fe15,
         "gear_predictor_corrector": gear,
         "batched_vs_one_by_one": batched,
+        "auto_rebuild": auto_rec,
         "nvt_batched": nvt_rec,
         "diffusion": diffusion,
         "piston_slab": piston_rec,

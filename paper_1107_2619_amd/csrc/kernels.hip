@@ -107,15 +107,21 @@ __device__ __forceinline__ int wave_run_add(int32_t* counter, int key)
 // Every rebuild kernel takes `gate`: NULL for a build of all replicas, else
 // the automatic rebuild's flags, and then it leaves alone every replica r with
 // gate[1 + r] == 0 (slot ranges and link cells are per replica, so a kept
-// replica's slots, cells and list stay exactly as they are).
-__global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin2, int check_skin,
-                      const int32_t* __restrict__ gate)
+// replica's slots, cells and list stay exactly as they are).  Gated builds run
+// at every step and mostly find nothing flagged: they launch a capped grid
+// whose threads stride over the elements (whole wavefronts per stride, as
+// replicas are wave aligned), so that such a launch ends at once; builds of
+// all replicas take one element per thread.
+constexpr int64_t kGatedBlocks = 2048;
+
+__device__ __forceinline__ bool replica_kept(const Buffers& b, const int32_t* gate, int64_t t)
 {
-    const int64_t t = global_thread();
-    if (t >= n_slots) return;
-    const int rep = uniform(b.rep_of_wave[t / kWave]);
-    if (gate && gate[1 + rep] == 0) return;  // (whole wavefronts: replicas are wave aligned)
-    const DevReplica& R = b.reps[rep];
+    return gate && gate[1 + uniform(b.rep_of_wave[t / kWave])] == 0;
+}
+
+__device__ __forceinline__ void bin_slot(const Buffers& b, int p, int q, int64_t t, double half_skin2, int check_skin)
+{
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[t / kWave])];
     const bool valid = b.id[q][t] >= 0;
     const Box bx = load_box(R);
     const double3 x = load_xyz(b.pos[p], t);
@@ -152,6 +158,15 @@ __global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin
             break;
         }
     }
+}
+
+__global__ void k_bin(Buffers b, int p, int q, int64_t n_slots, double half_skin2, int check_skin,
+                      const int32_t* __restrict__ gate)
+{
+    if (gate && gate[0] == 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = global_thread(); t < n_slots; t += stride)
+        if (!replica_kept(b, gate, t)) bin_slot(b, p, q, t, half_skin2, check_skin);
 }
 
 // Rebuild stage 2: exclusive scan of cell populations in two phases (block scan, then
@@ -222,18 +237,21 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(Buffers b, int32_t n, c
 // the cell, fixed by the next kernel).
 __global__ void k_scatter(Buffers b, int64_t n_slots, const int32_t* __restrict__ gate)
 {
-    const int64_t t = global_thread();
-    if (t >= n_slots) return;
-    if (gate && gate[1 + uniform(b.rep_of_wave[t / kWave])] == 0) return;
-    const int c = b.cell_of[t];
-    const int k = wave_run_add(b.cell_cursor, c);
-    if (c >= 0) b.perm[b.cell_start[c] + k] = (int32_t)t;
+    if (gate && gate[0] == 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = global_thread(); t < n_slots; t += stride) {
+        if (replica_kept(b, gate, t)) continue;
+        const int c = b.cell_of[t];
+        const int k = wave_run_add(b.cell_cursor, c);
+        if (c >= 0) b.perm[b.cell_start[c] + k] = (int32_t)t;
+    }
 }
 
 // Rebuild stage 4: order each cell's members by caller index, making the slot order
 // (and so every later floating-point sum) independent of atomics' timing.
 __global__ void k_sort_cells(Buffers b, int q, int32_t n_cells, const int32_t* __restrict__ gate)
 {
+    if (gate && gate[0] == 0) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     if (gate) {
@@ -256,13 +274,9 @@ __global__ void k_sort_cells(Buffers b, int q, int32_t n_cells, const int32_t* _
 }
 
 // Rebuild stage 5: gather the whole atom state into the new slot order.
-__global__ void k_gather(Buffers b, int p, int q, int64_t n_slots, const int32_t* __restrict__ gate)
+__device__ __forceinline__ void gather_slot(const Buffers& b, int p, int q, int64_t u)
 {
-    const int64_t u = global_thread();
-    if (u >= n_slots) return;
-    const int rep = uniform(b.rep_of_wave[u / kWave]);
-    if (gate && gate[1 + rep] == 0) return;
-    const DevReplica& R = b.reps[rep];
+    const DevReplica& R = b.reps[uniform(b.rep_of_wave[u / kWave])];
     const int pn = p ^ 1, qn = q ^ 1;
     if (u - R.slot_off < R.n_atoms) {
         const int32_t t = b.perm[u];
@@ -333,6 +347,14 @@ __global__ void k_gather(Buffers b, int p, int q, int64_t n_slots, const int32_t
             }
         }
     }
+}
+
+__global__ void k_gather(Buffers b, int p, int q, int64_t n_slots, const int32_t* __restrict__ gate)
+{
+    if (gate && gate[0] == 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = global_thread(); u < n_slots; u += stride)
+        if (!replica_kept(b, gate, u)) gather_slot(b, p, q, u);
 }
 
 // Verlet list from the link cells (paper, "The Neighbourlist calculation":
@@ -441,6 +463,8 @@ struct ListOut {
     int with_types;
 };
 
+typedef int int4v __attribute__((ext_vector_type(4)));
+
 // Tests atoms s0 .. s0 + n - 1 (lane l holds atom s0 + l in xl) against the
 // candidates in registers and appends the in-range ones to their rows.
 template <int P, bool AMB, bool WIDE, bool SPLIT>
@@ -452,6 +476,8 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
                                                 const bool (&live)[P], int& my_count)
 {
     const int lane = threadIdx.x & (kWave - 1);
+    // j != i (full list) or j > i (half list) as one unsigned compare of j - i - 1
+    const uint32_t lim = half_list ? 0x7FFFFFFFu : 0xFFFFFFFFu;
     for (int ii = 0; ii < n; ++ii) {
         const int i = s0 + ii;
         const double xi = bcast_lane(xl.x, ii), yi = bcast_lane(xl.y, ii), zi = bcast_lane(xl.z, ii);
@@ -463,10 +489,9 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
             int e = ce[u];
             if (AMB) min_image_pair(bx, amb, compact, dx, dy, dz, e);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            bool take = live[u] & (cj[u] != i) & (r2 < rlist2);
+            const bool take = live[u] & ((uint32_t)(cj[u] - (i + 1)) < lim) & (r2 < rlist2);
             if (SPLIT && r2 < rdl2) e |= kInnerBit;  // (otherwise every candidate carries it)
-            if (half_list) take = take & (cj[u] > i);
-            const uint64_t mask = __ballot(take);
+            const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
             if (mask == 0) continue;
             const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -499,13 +524,11 @@ __device__ __forceinline__ void test_candidates(const ListOut& L, int32_t cap, d
 // copy_back: also copy each own atom's sorted state from (p, q) into
 // (p ^ 1, q ^ 1), the buffers an automatic rebuild keeps using.
 template <bool TRI, bool WIDE, bool SPLIT, bool WT>
-__global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, int64_t n_slots, int32_t n_cells,
-                                                      int32_t cap, double rlist2, double rdl2, int half_list,
-                                                      int compact, const int32_t* __restrict__ gate, int copy_back)
+__device__ __forceinline__ void list_cell(const Buffers& b, int p, int q, int64_t n_slots, int cell, int32_t cap,
+                                          double rlist2, double rdl2, int half_list, int compact,
+                                          const int32_t* __restrict__ gate, int copy_back)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int cell = uniform((int)(logical_block() * (kBlock / kWave) + threadIdx.x / kWave));
-    if (cell >= n_cells) return;
     const int r = uniform(b.cell_rep[cell]);
     if (r < 0) return;
     if (gate && gate[1 + r] == 0) return;
@@ -618,11 +641,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, i
                 live[u] = m0 < total;
             }
             if (amb)
-                test_candidates<kCandPasses, true, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb, s_own + i0,
-                                                         n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
+                test_candidates<kCandPasses, true, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb,
+                                                                s_own + i0, n_chunk, xl, cx, cy, cz, ce, cj, ct, live,
+                                                                my_count);
             else
-                test_candidates<kCandPasses, false, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb, s_own + i0,
-                                                          n_chunk, xl, cx, cy, cz, ce, cj, ct, live, my_count);
+                test_candidates<kCandPasses, false, WIDE, SPLIT>(L, cap, rlist2, rdl2, half_list, compact, bx, amb,
+                                                                 s_own + i0, n_chunk, xl, cx, cy, cz, ce, cj, ct, live,
+                                                                 my_count);
         }
         // per-atom epilogue: count, overflow flag, compact record
         const int i = s_own + i0 + lane;
@@ -656,6 +681,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, i
         }
         wave_max_flag(lane < n_chunk ? my_count : 0, &b.flags[F_MAX_COUNT]);
     }
+}
+
+// One wavefront per link cell.  LOOP (gated builds): a capped grid, each
+// wavefront taking every `waves`-th cell (a wavefront's LDS operations
+// complete in order, so its candidate table is simply refilled for the next
+// cell); a separate instantiation, since the loop keeps more registers live.
+template <bool TRI, bool WIDE, bool SPLIT, bool WT, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_cell_list(Buffers b, int p, int q, int64_t n_slots, int32_t n_cells,
+                                                      int32_t cap, double rlist2, double rdl2, int half_list,
+                                                      int compact, const int32_t* __restrict__ gate, int copy_back)
+{
+    const int64_t w0 = logical_block() * (kBlock / kWave) + threadIdx.x / kWave;
+    if (!LOOP) {
+        if (w0 < n_cells)
+            list_cell<TRI, WIDE, SPLIT, WT>(b, p, q, n_slots, uniform((int)w0), cap, rlist2, rdl2, half_list,
+                                            compact, nullptr, 0);
+        return;
+    }
+    if (gate[0] == 0) return;
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t w = w0; w < n_cells; w += waves)
+        list_cell<TRI, WIDE, SPLIT, WT>(b, p, q, n_slots, uniform((int)w), cap, rlist2, rdl2, half_list, compact,
+                                        gate, copy_back);
 }
 
 // Compact records of all slots from the FP64 positions (mixed mode, at the
@@ -713,7 +761,6 @@ __device__ __forceinline__ int4 compact_base(const int4& q)
 
 // One 16-byte gather through a raw buffer resource: a single load
 // instruction with a 32-bit offset (out-of-range offsets read zero).
-typedef int int4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t record_rsrc(const int4* p, int64_t n)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<int4*>(p), (short)0, (int)(n * 16), (int)kBufferWord3);
@@ -1747,14 +1794,15 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
     // p, q: current buffers; the sorted state lands in p^1, q^1.  The cell
     // populations are binned into bin_count, which every build leaves zeroed.
     (void)half_list;
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots,
+    const int64_t slot_blocks = gate ? std::min<int64_t>(blocks_for(k.n_slots), kGatedBlocks) : blocks_for(k.n_slots);
+    hipLaunchKernelGGL(k_bin, dim3(slot_blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots,
                        half_skin2, half_skin2 >= 0.0 ? 1 : 0, gate);
     const int nb = (int)((k.n_cells + kScanBlock - 1) / kScanBlock);
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, k.n_slots, gate);
+    hipLaunchKernelGGL(k_scatter, dim3(slot_blocks), dim3(kBlock), 0, s, b, k.n_slots, gate);
     hipLaunchKernelGGL(k_sort_cells, dim3(blocks_for(k.n_cells)), dim3(kBlock), 0, s, b, q, k.n_cells, gate);
-    hipLaunchKernelGGL(k_gather, dim3(blocks_for(k.n_slots)), dim3(kBlock), 0, s, b, p, q, k.n_slots, gate);
+    hipLaunchKernelGGL(k_gather, dim3(slot_blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, gate);
 }
 
 // Displacement check of the automatic rebuild: the same criterion as the skin
@@ -1790,22 +1838,27 @@ void launch_skin_check(const Buffers& b, int p, const KernelShape& k, double gua
 void launch_build_list(const Buffers& b, int p, int q, const KernelShape& k, double rlist2, double rdl2,
                        int half_list, const int32_t* gate, int copy_back, hipStream_t s)
 {
-    const int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
+    int64_t blocks = ((int64_t)k.n_cells + kBlock / kWave - 1) / (kBlock / kWave);
+    if (gate) blocks = std::min<int64_t>(blocks, kGatedBlocks / 2);
     const bool wide = (uint64_t)k.n_slots * 16 * (uint64_t)((k.cap + 2 * kChunk - 1) / kChunk) >= ((uint64_t)1 << 32);
     const bool split = k.split_list && !half_list && rdl2 < rlist2;
     const int which = (k.tri ? 8 : 0) | (wide ? 4 : 0) | (split ? 2 : 0) | (k.list_types ? 1 : 0);
     using Kern = void (*)(Buffers, int, int, int64_t, int32_t, int32_t, double, double, int, int, const int32_t*, int);
-    static const Kern kerns[16] = {
-        k_cell_list<false, false, false, false>, k_cell_list<false, false, false, true>,
-        k_cell_list<false, false, true, false>,  k_cell_list<false, false, true, true>,
-        k_cell_list<false, true, false, false>,  k_cell_list<false, true, false, true>,
-        k_cell_list<false, true, true, false>,   k_cell_list<false, true, true, true>,
-        k_cell_list<true, false, false, false>,  k_cell_list<true, false, false, true>,
-        k_cell_list<true, false, true, false>,   k_cell_list<true, false, true, true>,
-        k_cell_list<true, true, false, false>,   k_cell_list<true, true, false, true>,
-        k_cell_list<true, true, true, false>,    k_cell_list<true, true, true, true>};
-    hipLaunchKernelGGL(kerns[which], dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells, k.cap, rlist2,
-                       half_list ? rlist2 : rdl2, half_list, k.compact, gate, copy_back);
+    // [gated][TRI WIDE SPLIT WT]
+    static const Kern kerns[2][16] = {
+#define MDK_LIST_ROW(G)                                                                                             \
+    {k_cell_list<false, false, false, false, G>, k_cell_list<false, false, false, true, G>,                        \
+     k_cell_list<false, false, true, false, G>,  k_cell_list<false, false, true, true, G>,                         \
+     k_cell_list<false, true, false, false, G>,  k_cell_list<false, true, false, true, G>,                         \
+     k_cell_list<false, true, true, false, G>,   k_cell_list<false, true, true, true, G>,                          \
+     k_cell_list<true, false, false, false, G>,  k_cell_list<true, false, false, true, G>,                         \
+     k_cell_list<true, false, true, false, G>,   k_cell_list<true, false, true, true, G>,                          \
+     k_cell_list<true, true, false, false, G>,   k_cell_list<true, true, false, true, G>,                          \
+     k_cell_list<true, true, true, false, G>,    k_cell_list<true, true, true, true, G>}
+        MDK_LIST_ROW(false), MDK_LIST_ROW(true)};
+#undef MDK_LIST_ROW
+    hipLaunchKernelGGL(kerns[gate ? 1 : 0][which], dim3(blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, k.n_cells,
+                       k.cap, rlist2, half_list ? rlist2 : rdl2, half_list, k.compact, gate, copy_back);
 }
 
 void launch_cell_table(const Buffers& b, const KernelShape& k, hipStream_t s)

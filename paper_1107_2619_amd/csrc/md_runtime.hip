@@ -736,6 +736,10 @@ void rebuild(md_ctx* c, hipStream_t s, bool check_skin)
     ++c->n_builds;
 }
 
+// Flag set `sel` of the automatic rebuild (two sets alternate: each check
+// writes one and clears the other, whose readers have run).
+int32_t* gate_set(md_ctx* c, int sel) { return c->buf.gate + (size_t)sel * (c->R + 1); }
+
 // Automatic rebuild ("The Neighbourlist calculation": the list must hold every
 // pair that comes within r_c before it is rebuilt): before a force evaluation,
 // each replica with an atom more than skin/2 from its position at the last
@@ -748,12 +752,11 @@ void auto_check(md_ctx* c, hipStream_t s)
 {
     const KernelShape k = shape(c);
     const int half = c->nbr_mode == MD_NBR_HALF_ATOMIC;
-    int32_t* gate = c->buf.gate + (size_t)c->gate_sel * (c->R + 1);
-    int32_t* next = c->buf.gate + (size_t)(c->gate_sel ^ 1) * (c->R + 1);
+    int32_t* gate = gate_set(c, c->gate_sel);
     const double guard = 0.5 * c->skin;
     const double rdl = std::min(c->rd + c->skin, c->rlist);
     Timed tm(c, MD_KT_BUILD, s);
-    launch_skin_check(c->buf, c->p, k, guard * guard, gate, next, s);
+    launch_skin_check(c->buf, c->p, k, guard * guard, gate, gate_set(c, c->gate_sel ^ 1), s);
     launch_rebuild(c->buf, c->p, c->q, k, -1.0, half, gate, s);
     launch_build_list(c->buf, c->p ^ 1, c->q ^ 1, k, c->rlist * c->rlist, rdl * rdl, half, gate, 1, s);
     c->gate_sel ^= 1;

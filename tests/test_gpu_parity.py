@@ -335,6 +335,25 @@ def test_list_above_4gib(md):
         assert np.array_equal(a, b)
 
 
+def test_large_list_above_4gib(md):
+    """64-bit list addresses at an ordinary capacity: 5,488,000 atoms with room
+    for 192 entries each pass 4 GiB and agree bit for bit, over 12 steps with
+    one rebuild, with the default capacity."""
+    s = inputs.bcc_fe(140, temperature=300.0, seed=45, name="bcc_wide_large")
+    assert s.n_atoms * 16 * ((192 + 7) // 4) >= 1 << 32
+    announce("large list above 4 GiB")
+    out = []
+    for cap in (48, 192):
+        sim = md.Simulation(s, max_neighbours=cap, want_e_atom=False)
+        sim.set_option(md.MD_OPT_KERNEL, 1)
+        sim.step(12)
+        e = sim.energy()
+        out.append((sim.positions(), sim.forces(), e.pe))
+        del sim
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("precision,mode", [("fp64", "full"), ("mixed", "full"), ("fp64", "half")])
 def test_trajectory_100_steps(md, orc, precision, mode):
     """100 velocity-Verlet steps with list rebuilds every 10 steps against the
