@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdeam.so")
-SOURCES = ["kernels.hip", "kernels_brick.hip", "kernels_pairs.hip", "kernels_analysis.hip", "kernels_box.hip",
+SOURCES = ["kernels.hip", "kernels_build.hip", "kernels_brick.hip", "kernels_pairs.hip", "kernels_analysis.hip", "kernels_box.hip",
            "md_runtime.hip"]
 ARCH = "gfx950"
 
