@@ -176,28 +176,27 @@ __global__ void k_scatter(Buffers b, int64_t n_slots, const int32_t* __restrict_
 }
 
 // Rebuild stage 4: order each cell's members by caller index, making the slot order
-// (and so every later floating-point sum) independent of atomics' timing.
-__global__ void k_sort_cells(Buffers b, int q, int32_t n_cells, const int32_t* __restrict__ gate)
+// (and so every later floating-point sum) independent of atomics' timing.  Every
+// member counts the members of its cell with a smaller caller index (indices are
+// distinct): that count is its place in the cell, and its old slot goes there in
+// perm_sorted.
+__global__ void k_sort_cells(Buffers b, int q, int64_t n_slots, const int32_t* __restrict__ gate)
 {
     if (gate && gate[0] == 0) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells) return;
-    if (gate) {
-        const int r = b.cell_rep[c];
-        if (r < 0 || gate[1 + r] == 0) return;
-    }
-    const int beg = b.cell_start[c], cnt = b.cell_count[c];
-    int32_t* m = b.perm + beg;
-    const int32_t* id = b.id[q];
-    for (int i = 1; i < cnt; ++i) {
-        const int32_t v = m[i];
-        const int32_t key = id[v];
-        int j = i - 1;
-        while (j >= 0 && id[m[j]] > key) {
-            m[j + 1] = m[j];
-            --j;
-        }
-        m[j + 1] = v;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int32_t* __restrict__ id = b.id[q];
+    for (int64_t u = global_thread(); u < n_slots; u += stride) {
+        const int rep = uniform(b.rep_of_wave[u / kWave]);
+        if (gate && gate[1 + rep] == 0) continue;
+        const DevReplica& R = b.reps[rep];
+        if (u - R.slot_off >= R.n_atoms) continue;  // slots past the replica's atoms
+        const int32_t t = b.perm[u];
+        const int c = b.cell_of[t];
+        const int beg = b.cell_start[c], cnt = b.cell_count[c];
+        const int32_t key = id[t];
+        int place = 0;
+        for (int j = 0; j < cnt; ++j) place += id[b.perm[beg + j]] < key ? 1 : 0;
+        b.perm_sorted[beg + place] = t;
     }
 }
 
@@ -207,7 +206,7 @@ __device__ __forceinline__ void gather_slot(const Buffers& b, int p, int q, int6
     const DevReplica& R = b.reps[uniform(b.rep_of_wave[u / kWave])];
     const int pn = p ^ 1, qn = q ^ 1;
     if (u - R.slot_off < R.n_atoms) {
-        const int32_t t = b.perm[u];
+        const int32_t t = b.perm_sorted[u];
         const double3 x = load_xyz(b.pos[p], t);
         double xw[3] = {x.x, x.y, x.z};
         // re-wrap atoms that left the primary box on a periodic axis
@@ -245,7 +244,6 @@ __device__ __forceinline__ void gather_slot(const Buffers& b, int p, int q, int6
         for (int a = 0; a < 3; ++a) b.vel[qn][a][u] = b.vel[q][a][t];
         b.id[qn][u] = b.id[q][t];
         b.type[qn][u] = b.type[q][t];
-        b.cell_sorted[u] = b.cell_of[t];
         b.pwork[qn][u] = b.pwork[q][t];
         if (b.acc[q][0]) {  // Gear integrator state travels with its atom
 #pragma unroll
@@ -266,7 +264,6 @@ __device__ __forceinline__ void gather_slot(const Buffers& b, int p, int q, int6
         b.id[qn][u] = -1;
         b.type[qn][u] = kEmptySlot;
         b.pwork[qn][u] = 0.0;
-        b.cell_sorted[u] = -1;
         if (b.acc[q][0]) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -648,7 +645,7 @@ void launch_rebuild(const Buffers& b, int p, int q, const KernelShape& k, double
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, b, k.n_cells, gate);
     hipLaunchKernelGGL(k_scatter, dim3(slot_blocks), dim3(kBlock), 0, s, b, k.n_slots, gate);
-    hipLaunchKernelGGL(k_sort_cells, dim3(blocks_for(k.n_cells)), dim3(kBlock), 0, s, b, q, k.n_cells, gate);
+    hipLaunchKernelGGL(k_sort_cells, dim3(slot_blocks), dim3(kBlock), 0, s, b, q, k.n_slots, gate);
     hipLaunchKernelGGL(k_gather, dim3(slot_blocks), dim3(kBlock), 0, s, b, p, q, k.n_slots, gate);
 }
 

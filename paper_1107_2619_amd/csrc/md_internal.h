@@ -177,7 +177,7 @@ struct Buffers {
     uint8_t* ntype;       // type byte of every list entry, same layout (several species)
     double* wave_terms;   // [Np / 64][kEnergyTerms] per-wavefront energy sums (velocity-Verlet energy steps)
     uint16_t* nbr16;      // [Np][rowlen] rows of staging (LDS) indices (brick path)
-    int32_t* cell_sorted; // [Np] link cell of each slot after the sort
+    int32_t* perm_sorted; // [Np] old slot of each new slot, cell members in caller-index order
     int32_t* brick_rep;   // [n_bricks] replica of each brick
     int4* brick_info;     // [n_bricks] own slot range [x, y) and halo atoms z at the last build
     int32_t* stage_src;   // [n_bricks][halo_cap] slot | shift code of each staging position

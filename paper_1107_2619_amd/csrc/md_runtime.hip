@@ -527,7 +527,7 @@ void plan_workspace(md_ctx* c)
         c->tf64.size() * 8, c->te64.size() * 8, c->td64.size() * 8,  // tables FP64
         c->tf32.size() * 4, c->te32.size() * 4, c->td32.size() * 4,  // tables FP32
         (Np * (size_t)((c->cap + 7) / 8 * 8) + 64) * 2,     // nbr16 rows (+ one padding row for prefetches)
-        Np * 4,                                              // cell_sorted
+        Np * 4,                                              // perm_sorted
         std::max<size_t>(max_bricks, 1) * 4,                 // brick_rep (bricks <= cells)
         std::max<size_t>(max_bricks, 1) * 16,                // brick_info
         stage_entries(c) * 4,                                // stage_src
@@ -613,7 +613,7 @@ void bind_buffers(md_ctx* c)
     at(b.tab_energy32);
     at(b.tab_dens32);
     at(b.nbr16);
-    at(b.cell_sorted);
+    at(b.perm_sorted);
     at(b.brick_rep);
     at(b.brick_info);
     at(b.stage_src);
