@@ -42,10 +42,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with (hash below); after
 # any change the bench reports null until the counters are taken again.
 FORCE_TRAFFIC = {  # precision -> counters of the step's force kernel (velocity-Verlet variant)
-    "fp64": {"fetch_kib": 103000, "write_kib": 55440, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256_16": "f38e79b74a48ff35", "workload": "bcc1m", "kernel": "k_force", "evaluator": 1},
-    "mixed": {"fetch_kib": 115728, "write_kib": 71280, "fetch_scale": 2.0, "write_scale": 1.0,
-              "sources_sha256_16": "f38e79b74a48ff35", "workload": "bcc1m", "kernel": "k_force", "evaluator": 0},
+    "fp64": {"fetch_kib": 103008, "write_kib": 55440, "fetch_scale": 2.0, "write_scale": 1.0,
+             "sources_sha256_16": "9f245d71b74f2274", "workload": "bcc1m", "kernel": "k_force", "evaluator": 1},
+    "mixed": {"fetch_kib": 115742, "write_kib": 71280, "fetch_scale": 2.0, "write_scale": 1.0,
+              "sources_sha256_16": "9f245d71b74f2274", "workload": "bcc1m", "kernel": "k_force", "evaluator": 0},
 }
 # VALU instructions per wavefront of the same force kernels (SQ_INSTS_VALU /
 # SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,

@@ -1945,40 +1945,43 @@ int md_autotune(md_ctx* c, int32_t trials, void* stream)
     hipEvent_t ev[3];
     for (auto& e : ev)
         if (!hip_ok(c, hipEventCreate(&e), "md_autotune events")) return MD_ERR_DEVICE;
-    double best = 1e300;
-    Cand choice = cands[0];
+    // two rounds over the candidates, each candidate scored by its faster round
+    // (one round alone mis-ranks close candidates now and then)
+    std::vector<double> cost_of(cands.size(), 1e300);
     int rc = MD_OK;
-    for (const Cand& cd : cands) {
-        if ((rc = md_set_option(c, MD_OPT_KERNEL, cd.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, cd.dims)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, cd.lanes)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_EVALUATOR, cd.evaluator)) != MD_OK ||
-            (rc = md_set_option(c, MD_OPT_NEIGHBOUR_CHUNK, cd.nchunk)) != MD_OK)
-            break;
-        ensure_slots(c, s);
-        launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
-        (void)hipEventRecord(ev[0], s);
-        rebuild(c, s, false);
-        (void)hipEventRecord(ev[1], s);
-        // the plain force pass (forces kept in the slots, no state change)
-        for (int32_t t = 0; t < trials; ++t) forces(c, ForceFlags{0, 0, 0, 0}, s);
-        (void)hipEventRecord(ev[2], s);
-        if ((rc = check_launch(c)) != MD_OK) break;
-        float t_build = 0.0f, t_force = 0.0f;
-        if (!hip_ok(c, hipEventSynchronize(ev[2]), "md_autotune") || !hip_ok(c, hipEventElapsedTime(&t_build, ev[0], ev[1]), "md_autotune") ||
-            !hip_ok(c, hipEventElapsedTime(&t_force, ev[1], ev[2]), "md_autotune")) {
-            rc = MD_ERR_DEVICE;
-            break;
-        }
-        // cost of one step: force passes plus the list build spread over its period
-        const double cost = t_force / trials + t_build / c->rebuild_every;
-        if (cost < best) {
-            best = cost;
-            choice = cd;
+    for (int round = 0; round < 2 && rc == MD_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Cand& cd = cands[ci];
+            if ((rc = md_set_option(c, MD_OPT_KERNEL, cd.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, cd.dims)) != MD_OK ||
+                (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, cd.lanes)) != MD_OK ||
+                (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, cd.block)) != MD_OK ||
+                (rc = md_set_option(c, MD_OPT_EVALUATOR, cd.evaluator)) != MD_OK ||
+                (rc = md_set_option(c, MD_OPT_NEIGHBOUR_CHUNK, cd.nchunk)) != MD_OK)
+                break;
+            ensure_slots(c, s);
+            launch_load_state(c->buf, c->p, c->q, c->st, shape(c), s);
+            (void)hipEventRecord(ev[0], s);
+            rebuild(c, s, false);
+            (void)hipEventRecord(ev[1], s);
+            // the plain force pass (forces kept in the slots, no state change)
+            for (int32_t t = 0; t < trials; ++t) forces(c, ForceFlags{0, 0, 0, 0}, s);
+            (void)hipEventRecord(ev[2], s);
+            if ((rc = check_launch(c)) != MD_OK) break;
+            float t_build = 0.0f, t_force = 0.0f;
+            if (!hip_ok(c, hipEventSynchronize(ev[2]), "md_autotune") || !hip_ok(c, hipEventElapsedTime(&t_build, ev[0], ev[1]), "md_autotune") ||
+                !hip_ok(c, hipEventElapsedTime(&t_force, ev[1], ev[2]), "md_autotune")) {
+                rc = MD_ERR_DEVICE;
+                break;
+            }
+            // cost of one step: force passes plus the list build spread over its period
+            cost_of[ci] = std::min(cost_of[ci], (double)t_force / trials + (double)t_build / c->rebuild_every);
         }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != MD_OK) return rc;
+    const size_t pick = (size_t)(std::min_element(cost_of.begin(), cost_of.end()) - cost_of.begin());
+    const Cand choice = cands[pick];
+    const double best = cost_of[pick];
     if ((rc = md_set_option(c, MD_OPT_KERNEL, choice.kernel)) != MD_OK || (rc = md_set_option(c, MD_OPT_BRICK_DIMS, choice.dims)) != MD_OK ||
         (rc = md_set_option(c, MD_OPT_LANES_PER_ATOM, choice.lanes)) != MD_OK ||
         (rc = md_set_option(c, MD_OPT_BRICK_BLOCK, choice.block)) != MD_OK ||
