@@ -34,23 +34,24 @@ if ROOT not in sys.path:
 METRIC = "EAM atom-steps/s: mixed vs FP64 (force err ≤1e-5), batched vs one-by-one"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one launch of the force kernel on bcc1m (FP64: knot sums, four
-# records in flight; mixed: tables, eight), from two rocprofv3 --pmc passes
-# (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 185 dispatches), each
-# scaled by the reading for a plain 1 GiB device copy (FETCH_SIZE reads
-# 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB -> x1.0).
-# Valid only for the kernel sources they were taken with (hash below); after
-# any change the bench reports null until the counters are taken again.
-FORCE_TRAFFIC = {  # precision -> counters of the step's force kernel (velocity-Verlet variant)
-    "fp64": {"fetch_kib": 103008, "write_kib": 55440, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256_16": "9f245d71b74f2274", "workload": "bcc1m", "kernel": "k_force", "evaluator": 1},
-    "mixed": {"fetch_kib": 115742, "write_kib": 71280, "fetch_scale": 2.0, "write_scale": 1.0,
-              "sources_sha256_16": "9f245d71b74f2274", "workload": "bcc1m", "kernel": "k_force", "evaluator": 0},
+# HBM bytes of one launch of the force kernel on bcc1m, per precision and
+# evaluator (the autotuner may pick either for FP64: FP64 knot sums or FP64
+# tables, four records in flight; mixed: tables, eight), from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean of 185
+# dispatches), each scaled by the reading for a plain 1 GiB device copy
+# (FETCH_SIZE reads 524,300 KiB -> x2.0; WRITE_SIZE reads 1,048,576 KiB ->
+# x1.0); and the VALU instructions per wavefront of the same kernels
+# (SQ_INSTS_VALU / SQ_WAVES: a wave carries 64 atoms, so this is also the
+# lane-operations per atom of one launch).  Valid only for the kernel sources
+# they were taken with (hash below); after any change the bench reports null
+# until the counters are taken again.
+_COUNTED = {"fetch_scale": 2.0, "write_scale": 1.0, "sources_sha256_16": "9f245d71b74f2274", "workload": "bcc1m",
+            "kernel": "k_force"}
+FORCE_TRAFFIC = {  # (precision, evaluator) -> counters of the step's force kernel (velocity-Verlet variant)
+    ("fp64", 1): {"fetch_kib": 103008, "write_kib": 55440, "valu_per_wave": 2055.9, **_COUNTED},
+    ("fp64", 0): {"fetch_kib": 102167, "write_kib": 55440, "valu_per_wave": 1444.4, **_COUNTED},
+    ("mixed", 0): {"fetch_kib": 115742, "write_kib": 71280, "valu_per_wave": 1619.5, **_COUNTED},
 }
-# VALU instructions per wavefront of the same force kernels (SQ_INSTS_VALU /
-# SQ_WAVES, rocprofv3 counters over the same sources): a wave carries 64 atoms,
-# so this is also the lane-operations per atom of one launch.
-FORCE_VALU_PER_WAVE = {"fp64": 2055.9, "mixed": 1619.5}  # VALU instructions per wave (64 atoms), same rule
 # Lane-operation issue peak of the vector ALUs: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz (FP64 and unpacked FP32 issue at the same rate; packed FP32 is off).
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -109,16 +110,15 @@ def roofline_for(r, prec, nbar, n, k, workload, copy_gbs):
     fbytes = force_kernel_bytes_per_atom(nbar) * n
     achieved = fbytes / (force_us * 1e-6) / 1e9
     kernel = "k_brick_force" if r["autotuned"].get("kernel") == 0 else "k_force"
-    t = FORCE_TRAFFIC.get(prec)
+    t = FORCE_TRAFFIC.get((prec, r["autotuned"].get("evaluator")))
     valid = (t is not None and workload == t["workload"] and kernel == t["kernel"]
-             and r["autotuned"].get("evaluator") == t.get("evaluator")
              and force_sources_hash() == t["sources_sha256_16"])
     traffic_bytes = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) if valid else None
     alu = None
-    if valid and prec in FORCE_VALU_PER_WAVE:
-        lane_ops = FORCE_VALU_PER_WAVE[prec] * n / (force_us * 1e-6)
+    if valid:
+        lane_ops = t["valu_per_wave"] * n / (force_us * 1e-6)
         alu = {"achieved": lane_ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
-               "frac": lane_ops / VALU_PEAK_LANE_OPS, "valu_instr_per_wave": FORCE_VALU_PER_WAVE[prec]}
+               "frac": lane_ops / VALU_PEAK_LANE_OPS, "valu_instr_per_wave": t["valu_per_wave"]}
     step_b = step_bytes_per_atom(nbar, k)
     return {
         "bound": "hbm",
