@@ -235,3 +235,48 @@ def test_auto_rebuild_sheared_cell(md, orc, precision):
                       origin=s.origin[0])
     assert sim.get_option(md.MD_OPT_N_BUILDS) >= 3
     _check(en, ref, sim.positions(), sim.forces(), precision, s.n_atoms)
+
+
+def test_auto_rebuild_piston_free_axis(md, orc):
+    """A rigid piston driven at 0.02 A/fs into a slab with a free z axis: the
+    moving rigid atoms trigger the rebuilds; trajectory and piston work against
+    the oracle."""
+    s = inputs.fcc_piston(nx=4, ny=4, nz=8, piston_cells=2, piston_speed_a_per_fs=0.02, steps=0)
+    s.skin = SKIN
+    announce("auto rebuild piston")
+    sim = _auto(md, s)
+    sim.step(60)
+    en = sim.energy()
+    ref = orc.run_verlet(s.pos, s.vel, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), s.dt_fs, 60,
+                         rigid=s.rigid, rigid_velocity=s.rigid_velocity[0])
+    assert sim.get_option(md.MD_OPT_N_BUILDS) >= 5  # 0.6 A of piston travel (dt 0.5 fs) over a 0.1 A guard
+    assert np.max(np.abs(sim.positions() - ref.pos)) < 1e-8
+    assert en.piston_work[0] == pytest.approx(ref.work[-1], rel=1e-8, abs=1e-10)
+
+
+def test_auto_rebuild_thermostatted_batch(md, orc):
+    """Per-replica Nose-Hoover thermostats on a batch with per-replica rebuilds:
+    each replica against the oracle's NVT run, and bitwise as alone."""
+    s = inputs.fec_replicas(2, nmin=300, nmax=700, tmin=600.0, tmax=1200.0, seed0=5400, skin=0.3)
+    kb = 8.617333262e-5
+    targets = [800.0, 1000.0]
+    q = []
+    for r in range(s.n_replicas):
+        n = int(s.atom_offset[r + 1] - s.atom_offset[r])
+        q.append((3 * n - 3) * kb * targets[r] * 50.0**2)
+    announce("auto rebuild thermostatted batch")
+    batch = _auto(md, s, nh_temperature=targets, nh_mass=q)
+    batch.step(50)
+    eb = batch.energy()
+    pos = batch.positions()
+    for r in range(s.n_replicas):
+        sub = s.replica(r)
+        a, b = int(s.atom_offset[r]), int(s.atom_offset[r + 1])
+        ref = orc.run_nh(sub.pos, sub.vel, sub.species, sub.box[0], sub.periodic[0], orc.Potential(sub.potential),
+                         sub.dt_fs, 50, targets[r], q[r])
+        assert np.max(np.abs(pos[a:b] - ref.pos)) < 1e-8
+        assert abs(eb.nh_pi[r] - ref.pi[-1]) <= 1e-8 * abs(ref.pi[-1]) + 1e-14
+        one = _auto(md, sub, nh_temperature=targets[r:r + 1], nh_mass=q[r:r + 1])
+        one.step(50)
+        one.energy()
+        assert np.array_equal(one.positions(), pos[a:b])
