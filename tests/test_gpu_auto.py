@@ -5,12 +5,14 @@ moves more than skin/2 from its position at the build).  Hot systems with a
 oracle's brute-force trajectories; the list's completeness at the current
 positions; per-replica rebuilds (a replica in a batch runs bitwise as alone);
 graph replay, split calls, the thermostat, Gear, half lists and sheared
-cells."""
+cells; and at the benchmark's sizes, where the gated build kernels stride over
+more slots and link cells than their capped grids hold, every atom against a
+fresh build at the final positions."""
 import numpy as np
 import pytest
 
 from paper_1107_2619_amd import inputs
-from tests.gpu_helpers import announce, force_error
+from tests.gpu_helpers import TOL, announce, energy_error, force_error
 
 pytestmark = pytest.mark.gpu
 
@@ -280,3 +282,64 @@ def test_auto_rebuild_thermostatted_batch(md, orc):
         one.step(50)
         one.energy()
         assert np.array_equal(one.positions(), pos[a:b])
+
+
+def _fresh_fp64(md, s, pos, vel):
+    """Forces and per-atom energies of a new FP64 context on the given state:
+    its list, link cells and slot order come from these positions alone
+    (the scheduled build, no automatic rebuild)."""
+    import copy
+
+    t = copy.copy(s)
+    t.pos, t.vel = pos, vel
+    sim = md.Simulation(t, precision="fp64")
+    sim.eam_forces(want_energy=True)
+    return sim.forces(), sim.atom_energies()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_auto_rebuild_full_size_crystal(md, orc, precision):
+    """The benchmark crystal (80^3 bcc cells, 1% vacancies, 1,013,760 atoms,
+    ~130k link cells) at 1200 K with a 0.2 A skin and graph replay: after 40
+    steps every atom's force and energy match a fresh FP64 build at the final
+    positions to the contract, and sampled atoms match the oracle."""
+    s = inputs.bcc_fe(80, temperature=1200.0, vacancy_frac=0.01, seed=2, skin=SKIN, rebuild_every=1000,
+                      name="bcc1m_hot")
+    announce(f"auto rebuild bcc1m at 1200 K {precision}")
+    sim = _auto(md, s, precision=precision)
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(40)
+    sim.energy()
+    builds = sim.get_option(md.MD_OPT_N_BUILDS)
+    pos, f, e = sim.positions(), sim.forces(), sim.atom_energies()
+    f_ref, e_ref = _fresh_fp64(md, s, pos, sim.velocities())
+    tol = TOL[precision]
+    ferr, eerr = force_error(f, f_ref), energy_error(e, e_ref)
+    sample = np.random.default_rng(4).choice(s.n_atoms, 16, replace=False)
+    ref = orc.forces_sampled(pos, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), sample)
+    rms = np.sqrt(np.mean(np.sum(f_ref**2, 1)))
+    oerr = np.max(np.linalg.norm(f[sample] - ref.f, axis=1)) / rms
+    announce(f"  {builds} builds, force err {ferr:.2e}, energy err {eerr:.2e}, oracle sample {oerr:.2e}")
+    assert builds >= 4
+    assert ferr <= tol["force"] and eerr <= tol["energy"]
+    assert oerr <= tol["force"]
+
+
+def test_auto_rebuild_full_size_batch(md):
+    """The Fe-C batch (256 replicas, 2.1 M atoms) in mixed precision with a
+    0.4 A skin and graph replay, as the benchmark's automatic-rebuild leg
+    runs it: the hot replicas rebuild on their own, and after 20 steps every
+    atom matches a fresh FP64 build at the final positions."""
+    s = inputs.workload("fec256", skin=0.4)
+    announce("auto rebuild fec256 mixed")
+    sim = _auto(md, s, precision="mixed")
+    sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+    sim.step(20)
+    sim.energy()
+    builds = sim.get_option(md.MD_OPT_N_BUILDS)
+    f, e = sim.forces(), sim.atom_energies()
+    f_ref, e_ref = _fresh_fp64(md, s, sim.positions(), sim.velocities())
+    ferr, eerr = force_error(f, f_ref), energy_error(e, e_ref)
+    announce(f"  {builds} builds, force err {ferr:.2e}, energy err {eerr:.2e}")
+    assert builds >= 3
+    assert ferr <= TOL["mixed"]["force"] and eerr <= TOL["mixed"]["energy"]
