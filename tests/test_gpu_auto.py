@@ -284,7 +284,7 @@ def test_auto_rebuild_thermostatted_batch(md, orc):
         assert np.array_equal(one.positions(), pos[a:b])
 
 
-def _fresh_fp64(md, s, pos, vel):
+def _fresh_fp64(md, s, pos, vel, **kw):
     """Forces and per-atom energies of a new FP64 context on the given state:
     its list, link cells and slot order come from these positions alone
     (the scheduled build, no automatic rebuild)."""
@@ -292,31 +292,46 @@ def _fresh_fp64(md, s, pos, vel):
 
     t = copy.copy(s)
     t.pos, t.vel = pos, vel
-    sim = md.Simulation(t, precision="fp64")
+    sim = md.Simulation(t, precision="fp64", **kw)
     sim.eam_forces(want_energy=True)
     return sim.forces(), sim.atom_energies()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_auto_rebuild_full_size_crystal(md, orc, precision):
+@pytest.mark.parametrize("precision,variant", [("fp64", "full"), ("mixed", "full"), ("fp64", "half"),
+                                               ("mixed", "sheared")])
+def test_auto_rebuild_full_size_crystal(md, orc, precision, variant):
     """The benchmark crystal (80^3 bcc cells, 1% vacancies, 1,013,760 atoms,
-    ~130k link cells) at 1200 K with a 0.2 A skin and graph replay: after 40
-    steps every atom's force and energy match a fresh FP64 build at the final
-    positions to the contract, and sampled atoms match the oracle."""
+    ~130k link cells) at 1200 K with a 0.2 A skin and graph replay; the full
+    list, the half list with atomics, and a sheared cell (the looping list
+    kernel with edge-vector shifts): after 40 steps every atom's force and
+    energy match a fresh FP64 build at the final positions to the contract,
+    and sampled atoms match the oracle."""
     s = inputs.bcc_fe(80, temperature=1200.0, vacancy_frac=0.01, seed=2, skin=SKIN, rebuild_every=1000,
                       name="bcc1m_hot")
-    announce(f"auto rebuild bcc1m at 1200 K {precision}")
-    sim = _auto(md, s, precision=precision)
+    kw, ref_kw = {}, {}
+    if variant == "half":
+        kw["nbr_mode"] = "half"
+    if variant == "sheared":
+        strain = np.array([[1.0, 0.03, -0.02], [0.01, 0.99, 0.04], [-0.03, 0.02, 1.01]])
+        h = strain @ np.diag(s.box[0])
+        s.pos = s.pos @ strain.T
+        kw["box_matrix"] = ref_kw["box_matrix"] = h
+    announce(f"auto rebuild bcc1m at 1200 K {precision} {variant}")
+    sim = _auto(md, s, precision=precision, **kw)
     sim.set_option(md.MD_OPT_USE_GRAPH, 1)
     sim.step(40)
     sim.energy()
     builds = sim.get_option(md.MD_OPT_N_BUILDS)
     pos, f, e = sim.positions(), sim.forces(), sim.atom_energies()
-    f_ref, e_ref = _fresh_fp64(md, s, pos, sim.velocities())
+    f_ref, e_ref = _fresh_fp64(md, s, pos, sim.velocities(), **ref_kw)
     tol = TOL[precision]
     ferr, eerr = force_error(f, f_ref), energy_error(e, e_ref)
     sample = np.random.default_rng(4).choice(s.n_atoms, 16, replace=False)
-    ref = orc.forces_sampled(pos, s.species, s.box[0], s.periodic[0], orc.Potential(s.potential), sample)
+    pot = orc.Potential(s.potential)
+    if variant == "sheared":
+        ref = orc.forces_sampled_tri(pos, s.species, kw["box_matrix"], pot, sample)
+    else:
+        ref = orc.forces_sampled(pos, s.species, s.box[0], s.periodic[0], pot, sample)
     rms = np.sqrt(np.mean(np.sum(f_ref**2, 1)))
     oerr = np.max(np.linalg.norm(f[sample] - ref.f, axis=1)) / rms
     announce(f"  {builds} builds, force err {ferr:.2e}, energy err {eerr:.2e}, oracle sample {oerr:.2e}")
