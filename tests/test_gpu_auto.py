@@ -358,3 +358,24 @@ def test_auto_rebuild_full_size_batch(md):
     announce(f"  {builds} builds, force err {ferr:.2e}, energy err {eerr:.2e}")
     assert builds >= 3
     assert ferr <= TOL["mixed"]["force"] and eerr <= TOL["mixed"]["energy"]
+
+
+def test_auto_rebuild_wide_list(md):
+    """The looping list kernel with 64-bit list addresses: a list allocation
+    above 4 GiB (128,000 atoms with room for 8,400 entries each, ~17,000 link
+    cells) agrees bit for bit with the default capacity over 30 graph-replayed
+    steps with automatic rebuilds at 1200 K."""
+    s = inputs.bcc_fe(40, temperature=1200.0, seed=44, skin=SKIN, rebuild_every=1000, name="bcc_wide_hot")
+    assert s.n_atoms * 16 * ((8400 + 7) // 4) >= 1 << 32
+    announce("auto rebuild, list above 4 GiB")
+    out = []
+    for cap in (48, 8400):
+        sim = _auto(md, s, max_neighbours=cap)
+        sim.set_option(md.MD_OPT_USE_GRAPH, 1)
+        sim.step(30)
+        e = sim.energy()
+        out.append((sim.positions(), sim.forces(), e.pe, sim.get_option(md.MD_OPT_N_BUILDS)))
+        del sim
+    assert out[0][3] == out[1][3] >= 3
+    for a, b in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(a, b)
