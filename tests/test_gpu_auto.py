@@ -379,3 +379,31 @@ def test_auto_rebuild_wide_list(md):
     assert out[0][3] == out[1][3] >= 3
     for a, b in zip(out[0][:3], out[1][:3]):
         assert np.array_equal(a, b)
+
+
+def test_auto_rebuild_full_size_gear(md):
+    """Gear's predictor-corrector state (acceleration and its derivative)
+    carried through the looping rebuilds of the 1,013,760-atom crystal at
+    1200 K: 40 graph-replayed steps with automatic rebuilds against the same
+    run rebuilt at every step (the two differ only in summation order)."""
+    import copy
+
+    s = inputs.bcc_fe(80, temperature=1200.0, vacancy_frac=0.01, seed=2, skin=SKIN, rebuild_every=1000,
+                      name="bcc1m_hot")
+    announce("auto rebuild bcc1m at 1200 K, Gear")
+    auto = _auto(md, s, integrator="gear3")
+    auto.set_option(md.MD_OPT_USE_GRAPH, 1)
+    auto.step(40)
+    auto.energy()
+    t = copy.copy(s)
+    t.rebuild_every = 1
+    every = md.Simulation(t, integrator="gear3")
+    every.set_option(md.MD_OPT_USE_GRAPH, 1)
+    every.step(40)
+    every.energy()
+    builds = auto.get_option(md.MD_OPT_N_BUILDS)
+    dx = np.max(np.abs(auto.positions() - every.positions()))
+    ferr = force_error(auto.forces(), every.forces())
+    announce(f"  {builds} builds, position diff {dx:.2e} A, force diff {ferr:.2e}")
+    assert 4 <= builds < every.get_option(md.MD_OPT_N_BUILDS)
+    assert dx < 1e-9 and ferr < 1e-9
