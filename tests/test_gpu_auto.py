@@ -407,3 +407,28 @@ def test_auto_rebuild_full_size_gear(md):
     announce(f"  {builds} builds, position diff {dx:.2e} A, force diff {ferr:.2e}")
     assert 4 <= builds < every.get_option(md.MD_OPT_N_BUILDS)
     assert dx < 1e-9 and ferr < 1e-9
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_auto_rebuild_energy_ring(md, orc, use_graph):
+    """Energies of every step (MD_OPT_ENERGY_EVERY = 1) with automatic
+    rebuilds, over 100 steps in calls of 7, 61 and 32, eager and
+    graph-replayed: each entry carries its step index and matches the
+    oracle's potential and kinetic energy of that step."""
+    s = _hot(seed=41)
+    announce(f"auto rebuild energy ring graph={use_graph}")
+    sim = _auto(md, s, precision="fp64", energy_ring=128)
+    sim.set_option(md.MD_OPT_ENERGY_EVERY, 1)
+    sim.set_option(md.MD_OPT_USE_GRAPH, use_graph)
+    hist = []
+    for n in (7, 61, 32):
+        sim.step(n)
+        hist += sim.energy_history()
+    ref = _verlet(orc, s, 100)
+    assert [h.step for h in hist] == list(range(1, 101))
+    pe = np.array([h.pe[0] for h in hist])
+    ke = np.array([h.ke[0] for h in hist])
+    assert np.max(np.abs(pe - ref.pe[1:]) / np.abs(ref.pe[1:])) < 1e-11
+    assert np.max(np.abs(ke - ref.ke[1:]) / np.abs(ref.ke[1:])) < 1e-11
+    sim.energy()  # (automatic builds are counted as of the last md_energy)
+    assert sim.get_option(md.MD_OPT_N_BUILDS) >= 3
